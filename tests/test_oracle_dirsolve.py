@@ -1,0 +1,97 @@
+"""Pins of the oracle's search-direction solve (CPU only).
+
+The min-norm problem min ||dw|| s.t. (A D) dw = f (eq. minnrmprob) has the closed-form
+solution pinv(A D) f for f in R(A D); the theorem of Sec. 3.5 says that the row-scaled
+AB-GMRES returns that unscaled min-norm solution, also for rank-deficient A.  The GMRES
+residual estimate must equal the true residual, and the flexible final step must agree
+with the literal one (B applied to V y) because the inner-iteration preconditioner is a
+fixed linear map.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07491_amd import synth
+
+
+def _problem(m, n, seed, dup=0, density=0.4):
+    rng = np.random.default_rng(seed)
+    lp = synth.tiny_lp(m, n, seed, density=density, n_dup=dup) if m <= 6 else None
+    if lp is None:
+        lp = synth.sparse_lp(m - dup, n, 4, dup, seed=seed)
+    A = lp.to_dense()
+    d = rng.uniform(0.2, 2.0, lp.n)
+    AD = A * d
+    f = AD @ rng.standard_normal(lp.n)          # f in R(A D)
+    return lp, A, d, AD, f
+
+
+CASES = [
+    dict(krylov=oracle.ABGMRES, inner=oracle.NESOR, ell=2, flexible=0),
+    dict(krylov=oracle.ABGMRES, inner=oracle.NESOR, ell=2, flexible=1),
+    dict(krylov=oracle.ABGMRES, inner=oracle.NESOR, ell=1, flexible=0, omega=1.5),
+    dict(krylov=oracle.ABGMRES, inner=oracle.CIMMINO, ell=2, flexible=1),
+    dict(krylov=oracle.ABGMRES, inner=oracle.NESSOR, ell=1, flexible=0),
+    dict(krylov=oracle.CGNE, inner=oracle.NESSOR, ell=1),
+    dict(krylov=oracle.MRNE, inner=oracle.NESSOR, ell=1),
+    dict(krylov=oracle.CGNE, inner=oracle.NESSOR, ell=3, omega=1.2),
+    dict(krylov=oracle.MRNE, inner=oracle.NESSOR, ell=3, omega=0.9),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+@pytest.mark.parametrize("shape", [(6, 11, 0), (6, 12, 2), (30, 70, 3)])
+def test_dirsolve_is_min_norm_solution(case, shape):
+    m, n, dup = shape
+    lp, A, d, AD, f = _problem(m, n, seed=m + n + dup, dup=dup)
+    kmax = 20 * lp.m if case["krylov"] != oracle.ABGMRES else 0
+    opts = oracle.solver_opts(kmax=kmax, **case)
+    dw, dy, info = oracle.dirsolve(lp, d, f, 1e-13, opts)
+    ref = np.linalg.pinv(AD) @ f
+    sv = np.linalg.svd(AD, compute_uv=False)
+    kappa = sv[0] / sv[sv > sv[0] * 1e-12][-1]
+    assert np.linalg.norm(dw - ref) <= 1e-11 * kappa * np.linalg.norm(ref)
+    # dw = (A D)^T dy exactly in exact arithmetic: dw lies in R((A D)^T)
+    np.testing.assert_allclose(AD.T @ dy, dw, rtol=1e-8, atol=1e-9 * np.abs(dw).max())
+    assert not info["failed"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_gmres_estimate_is_true_residual_and_flexible_equals_literal(seed):
+    lp, A, d, AD, f = _problem(40, 90, seed, dup=2)
+    for k in (1, 3, 7, 15):
+        o1 = oracle.solver_opts(kmax=k, flexible=0)
+        o2 = oracle.solver_opts(kmax=k, flexible=1)
+        dw1, dy1, i1 = oracle.dirsolve(lp, d, f, 0.0, o1)
+        dw2, dy2, i2 = oracle.dirsolve(lp, d, f, 0.0, o2)
+        assert i1["iters"] == k and i2["iters"] == k
+        # |gamma_{k+1}| is the residual of the k-th iterate
+        assert abs(i1["res_est"] - i1["res_true"]) <= 1e-9 * i1["beta"]
+        assert abs(i2["res_est"] - i2["res_true"]) <= 1e-9 * i2["beta"]
+        np.testing.assert_allclose(dw1, dw2, rtol=1e-9, atol=1e-10 * np.abs(dw1).max())
+        np.testing.assert_allclose(dy1, dy2, rtol=1e-8, atol=1e-9 * np.abs(dy1).max())
+        # GMRES minimises the residual over the Krylov space: monotone in k
+        if k > 1:
+            assert i1["res_est"] <= prev * (1 + 1e-12)
+        prev = i1["res_est"]
+
+
+def test_dirsolve_zero_rhs_and_failure_flag():
+    lp, A, d, AD, f = _problem(20, 50, 5)
+    dw, dy, info = oracle.dirsolve(lp, d, np.zeros(lp.m), 1e-8)
+    assert info["iters"] == 0 and not np.any(dw) and not np.any(dy)
+    dw, dy, info = oracle.dirsolve(lp, d, f, 1e-12, oracle.solver_opts(kmax=2))
+    assert info["iters"] == 2 and info["failed"] == 1
+
+
+def test_scaled_equals_unscaled_minimum_norm():
+    """Lemma/Theorem of Sec. 3.5: the row scaling does not change the min-norm solution,
+    even for badly scaled rows (here rows multiplied by 10^+-4)."""
+    lp, A, d, AD, f = _problem(25, 60, 8, dup=2)
+    rng = np.random.default_rng(0)
+    sc = 10.0 ** rng.uniform(-4, 4, lp.m)
+    A2 = A * sc[:, None]
+    lp2 = synth.from_dense(A2, np.zeros(lp.m), np.zeros(lp.n))
+    dw1, _, _ = oracle.dirsolve(lp, d, f, 1e-13)
+    dw2, _, _ = oracle.dirsolve(lp2, d, f * sc, 1e-13)
+    np.testing.assert_allclose(dw1, dw2, rtol=1e-8, atol=1e-9 * np.abs(dw1).max())
