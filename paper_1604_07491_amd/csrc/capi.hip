@@ -1,0 +1,643 @@
+// C ABI of the library: validation, problem set-up, and the entry points declared in
+// include/lpk.h.  Host inputs are validated before any HIP call.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lpk_impl.h"
+
+namespace lpk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+lp_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+    return LP_EDEVICE;
+}
+
+static lp_status fail(lp_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+// Krylov basis capacity: m (Sec. 4.2) unless the options cap it, and at most what fits in
+// a 16 GiB budget for the basis and multiplier vectors
+static int64_t plan_kmax(int64_t m, const lp_options& o) {
+    int64_t k = m;
+    if (o.krylov_max_iter > 0) k = std::min<int64_t>(k, o.krylov_max_iter);
+    const int64_t budget = (int64_t)16 << 30;
+    const int64_t cap = std::max<int64_t>(8, budget / (16 * (m + 1)));
+    return std::max<int64_t>(1, std::min(k, cap));
+}
+
+struct Sizes {
+    uint64_t bytes = 0;
+    void add(int64_t count, int64_t elem) {
+        if (count <= 0) count = 1;
+        bytes += ((uint64_t)count * (uint64_t)elem + 255) & ~(uint64_t)255;
+    }
+};
+
+static uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
+    Sizes z;
+    const bool mixed = o.precision == LP_MIXED;
+    const int64_t kmax = plan_kmax(m, o);
+    const GsPlan gs = gs_plan(m);
+    z.add(m + 1, 4); z.add(nnz, 4); z.add(nnz, 8); z.add(n + 1, 4); z.add(nnz, 4); z.add(nnz, 8);
+    z.add(nnz, 8); z.add(nnz, 8);
+    if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
+    z.add(m, 4);
+    for (int i = 0; i < 13; ++i) z.add(m, 8);    // m-vectors
+    for (int i = 0; i < 12; ++i) z.add(n, 8);    // n-vectors
+    z.add(n, 4); z.add(m, 4);                     // z32, r32
+    z.add(m * (kmax + 1), 8); z.add(m * (kmax + 1), 8);   // V, P
+    z.add((kmax + 1) * (kmax + 1), 8);                      // H
+    for (int i = 0; i < 5; ++i) z.add(kmax + 2, 8);
+    z.add((int64_t)gs.nchunks * (kmax + 1), 8);
+    z.add(m / 4 + 8, 8);
+    z.add(8 * 1024, 8); z.add(8, 8);
+    z.add(1, sizeof(KrylovCtl));
+    return z.bytes;
+}
+
+static lp_status validate(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                          const double* val) {
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    if (m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
+    if (nnz < 1 || nnz >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31))
+        return fail(LP_EDIM, "nnz and n must be below 2^31");
+    if (!rp || !ci || !val) return fail(LP_EINVAL, "NULL CSR array");
+    if (rp[0] != 0 || rp[m] != nnz) return fail(LP_EINVAL, "row_ptr must start at 0 and end at nnz");
+    std::vector<char> colseen((size_t)n, 0);
+    for (int64_t i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(LP_EINVAL, "row_ptr is decreasing at row " + std::to_string(i));
+        if (rp[i + 1] == rp[i]) return fail(LP_EINVAL, "row " + std::to_string(i) + " is empty");
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = ci[k];
+            if (j < 0 || j >= n) return fail(LP_EINVAL, "column index out of range in row " + std::to_string(i));
+            if (k > rp[i] && ci[k - 1] >= j)
+                return fail(LP_EINVAL, "column indices not strictly increasing in row " + std::to_string(i));
+            if (!std::isfinite(val[k])) return fail(LP_ENONFINITE, "non-finite entry in A");
+            colseen[j] = 1;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        if (!colseen[j]) return fail(LP_EINVAL, "column " + std::to_string(j) + " is empty");
+    return LP_OK;
+}
+
+static lp_status check_vec(const double* v, int64_t len, const char* name) {
+    if (!v) return fail(LP_EINVAL, std::string("NULL ") + name);
+    for (int64_t i = 0; i < len; ++i)
+        if (!std::isfinite(v[i])) return fail(LP_ENONFINITE, std::string("non-finite entry in ") + name);
+    return LP_OK;
+}
+
+static lp_status check_device() {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(LP_EDEVICE, "no HIP device available");
+    return LP_OK;
+}
+
+// copy a caller array (host or device per device_io) into a host vector
+template <typename T>
+static lp_status fetch(const T* src, int64_t count, bool dev, std::vector<T>& out) {
+    out.resize((size_t)std::max<int64_t>(count, 0));
+    if (count <= 0) return LP_OK;
+    if (dev) LPK_HIP(hipMemcpy(out.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+    else memcpy(out.data(), src, sizeof(T) * count);
+    return LP_OK;
+}
+
+static void destroy(lp_problem* p) {
+    if (!p) return;
+    prof_release(p);
+    p->arena.release();
+    if (p->host_out) (void)hipHostFree(p->host_out);
+    if (p->host_ctl) (void)hipHostFree(p->host_ctl);
+    delete p;
+}
+
+// set-up from host arrays that have passed validation
+static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, const double* val,
+                       const double* b, const double* c) {
+    const int64_t m = p->m, n = p->n, nnz = p->nnz;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    // colouring and the permuted CSR
+    std::vector<int32_t> colour((size_t)m);
+    p->perm.resize((size_t)m);
+    const int32_t ncol = greedy_colour(m, n, rp, ci, colour.data(), p->perm.data());
+    std::vector<int32_t> prp((size_t)m + 1), pci((size_t)nnz);
+    std::vector<double> pa((size_t)nnz), pb((size_t)m);
+    prp[0] = 0;
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t i = p->perm[t];
+        const int64_t len = rp[i + 1] - rp[i];
+        memcpy(&pci[prp[t]], ci + rp[i], sizeof(int32_t) * len);
+        memcpy(&pa[prp[t]], val + rp[i], sizeof(double) * len);
+        prp[t + 1] = (int32_t)(prp[t] + len);
+        pb[t] = b[i];
+    }
+    // colour ranges and lanes per row for each colour
+    p->colours.clear();
+    int64_t t0 = 0;
+    for (int32_t cl = 0; cl < ncol; ++cl) {
+        int64_t t1 = t0;
+        while (t1 < m && colour[p->perm[t1]] == cl) ++t1;
+        Colour C;
+        C.r0 = (int32_t)t0;
+        C.r1 = (int32_t)t1;
+        C.g = lanes_for((double)(prp[t1] - prp[t0]) / (double)std::max<int64_t>(1, t1 - t0));
+        C.nnz = prp[t1] - prp[t0];
+        p->colours.push_back(C);
+        t0 = t1;
+    }
+    // CSC of the permuted matrix (row indices in the permuted numbering, ascending)
+    std::vector<int32_t> pcp((size_t)n + 1, 0), pri((size_t)nnz);
+    std::vector<double> pac((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) pcp[pci[k] + 1]++;
+    for (int64_t j = 0; j < n; ++j) pcp[j + 1] += pcp[j];
+    {
+        std::vector<int32_t> fillp(pcp.begin(), pcp.end() - 1);
+        for (int64_t t = 0; t < m; ++t)
+            for (int32_t k = prp[t]; k < prp[t + 1]; ++k) {
+                const int32_t pos = fillp[pci[k]]++;
+                pri[pos] = (int32_t)t;
+                pac[pos] = pa[k];
+            }
+    }
+    p->g_csr = lanes_for((double)nnz / (double)m);
+    p->g_csc = lanes_for((double)nnz / (double)n);
+    double nb = 0.0, nc = 0.0;
+    for (int64_t i = 0; i < m; ++i) nb += b[i] * b[i];
+    for (int64_t j = 0; j < n; ++j) nc += c[j] * c[j];
+    p->norm_b = std::sqrt(nb);
+    p->norm_c = std::sqrt(nc);
+
+    // device memory
+    DevArena& A = p->arena;
+    p->kmax = plan_kmax(m, p->opt);
+    p->ldv = m;
+    p->ldh = p->kmax + 1;
+    p->gs = gs_plan(m);
+    p->rp = A.alloc<int32_t>(m + 1);
+    p->ci = A.alloc<int32_t>(nnz);
+    p->a = A.alloc<double>(nnz);
+    p->cp = A.alloc<int32_t>(n + 1);
+    p->ri = A.alloc<int32_t>(nnz);
+    p->ac = A.alloc<double>(nnz);
+    p->ah = A.alloc<double>(nnz);
+    p->ahc = A.alloc<double>(nnz);
+    if (mixed) {
+        p->ah32 = A.alloc<float>(nnz);
+        p->ahc32 = A.alloc<float>(nnz);
+    }
+    p->perm_d = A.alloc<int32_t>(m);
+    double** mv[] = {&p->b, &p->y, &p->rho, &p->rpv, &p->dya, &p->dyc, &p->f, &p->dyh, &p->dtmp_m,
+                     &p->pcol, &p->u, &p->fhU, &p->r64};
+    for (double** q : mv) *q = A.alloc<double>(m);
+    double** nv[] = {&p->c, &p->x, &p->s, &p->d, &p->rdv, &p->tn, &p->dxa, &p->dsa, &p->dw,
+                     &p->dtmp_n, &p->z64, &p->dapi};
+    for (double** q : nv) *q = A.alloc<double>(n);
+    p->z32 = A.alloc<float>(n);
+    p->r32 = A.alloc<float>(m);
+    p->V = A.alloc<double>(m * (p->kmax + 1));
+    p->P = A.alloc<double>(m * (p->kmax + 1));
+    p->H = A.alloc<double>((p->kmax + 1) * (p->kmax + 1));
+    p->cs = A.alloc<double>(p->kmax + 2);
+    p->sn = A.alloc<double>(p->kmax + 2);
+    p->gam = A.alloc<double>(p->kmax + 2);
+    p->ykr = A.alloc<double>(p->kmax + 2);
+    p->h2 = A.alloc<double>(p->kmax + 2);
+    p->gpart = A.alloc<double>((int64_t)p->gs.nchunks * (p->kmax + 1));
+    p->spart = A.alloc<double>(m / 4 + 8);
+    p->red.maxblk = 1024;
+    p->red.part = A.alloc<double>(8 * 1024);
+    p->red.out = A.alloc<double>(8);
+    p->ctl = A.alloc<KrylovCtl>(1);
+    if (A.failed) return fail(LP_ENOMEM, "device allocation failed");
+    if (hipHostMalloc((void**)&p->host_out, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&p->host_ctl, sizeof(KrylovCtl), hipHostMallocDefault) != hipSuccess)
+        return fail(LP_ENOMEM, "pinned host allocation failed");
+    hipStream_t st = p->st;
+    LPK_HIP(hipMemcpyAsync(p->rp, prp.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->ci, pci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->a, pa.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->cp, pcp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->ri, pri.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->ac, pac.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->perm_d, p->perm.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->b, pb.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->c, c, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemsetAsync(p->H, 0, sizeof(double) * (p->kmax + 1) * (p->kmax + 1), st));
+    LPK_HIP(hipStreamSynchronize(st));
+    p->ist.eps_in = p->opt.eps_in0;
+    return LP_OK;
+}
+
+static lp_status check_options(const lp_options& o) {
+    if (o.precision != LP_FP64 && o.precision != LP_MIXED) return fail(LP_EINVAL, "unknown precision");
+    if (o.krylov != LP_ABGMRES) return fail(LP_EINVAL, "only AB-GMRES is available on the device");
+    if (o.inner != LP_NESOR && o.inner != LP_CIMMINO)
+        return fail(LP_EINVAL, "inner iterations must be NE-SOR or Cimmino for a sparse problem");
+    if (o.inner_sweeps < 1 || o.inner_sweeps > 64) return fail(LP_EINVAL, "inner_sweeps must be in [1, 64]");
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LP_EINVAL, "omega must be in (0, 2)");
+    if (!(o.eta >= 0.9 && o.eta < 1.0)) return fail(LP_EINVAL, "eta must be in [0.9, 1)");
+    if (o.ipm_max_iter < 0) return fail(LP_EINVAL, "ipm_max_iter must be >= 0");
+    if (!(o.eps_in_min > 0.0 && o.eps_in_min <= o.eps_in_max)) return fail(LP_EINVAL, "bad eps_in range");
+    return LP_OK;
+}
+
+static lp_status copy_out(lp_problem* p, const double* dev, double* dst, int64_t len) {
+    const hipMemcpyKind k = p->opt.device_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    LPK_HIP(hipMemcpyAsync(dst, dev, sizeof(double) * len, k, p->st));
+    return LP_OK;
+}
+
+static lp_status copy_in(lp_problem* p, const double* src, double* dev, int64_t len) {
+    const hipMemcpyKind k = p->opt.device_io ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    LPK_HIP(hipMemcpyAsync(dev, src, sizeof(double) * len, k, p->st));
+    return LP_OK;
+}
+
+}  // namespace lpk
+
+using namespace lpk;
+
+extern "C" {
+
+lp_status lp_options_default(lp_options* o) {
+    if (!o) return fail(LP_EINVAL, "NULL options");
+    memset(o, 0, sizeof(*o));
+    o->precision = LP_FP64;
+    o->krylov = LP_ABGMRES;
+    o->inner = LP_NESOR;
+    o->inner_sweeps = 2;
+    o->omega = 1.0;
+    o->omega_c = 0.0;
+    o->krylov_max_iter = 0;
+    o->ipm_max_iter = 99;
+    o->start = 0;
+    o->eps_out = 1e-8;
+    o->eta = 0.9995;
+    o->phi = 1e-5;
+    o->sigma_max = 0.208;
+    o->eps_in0 = 1e-6;
+    o->eps_in_min = 1e-14;
+    o->eps_in_max = 1e-4;
+    o->init_tol = 1e-10;
+    o->backtrack = 0.95;
+    o->max_backtrack = 200;
+    o->device_io = 0;
+    o->stream = nullptr;
+    o->poll_every = 0;
+    o->use_graphs = 0;
+    return LP_OK;
+}
+
+lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                    const int32_t* col_idx, const double* val, const double* b, const double* c,
+                    const lp_options* o, lp_problem** out) {
+    g_err.clear();
+    if (!out) return fail(LP_EINVAL, "NULL out");
+    *out = nullptr;
+    lp_options opt;
+    if (o) opt = *o;
+    else lp_options_default(&opt);
+    lp_status rc = check_options(opt);
+    if (rc != LP_OK) return rc;
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    if (m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
+    if (!row_ptr || !col_idx || !val || !b || !c) return fail(LP_EINVAL, "NULL input array");
+    std::vector<int64_t> hrp;
+    std::vector<int32_t> hci;
+    std::vector<double> hval, hb, hc;
+    const bool dev = opt.device_io != 0;
+    if (dev) {
+        rc = check_device();
+        if (rc != LP_OK) return rc;
+        if ((rc = fetch(row_ptr, m + 1, true, hrp)) != LP_OK) return rc;
+        if (hrp[m] < 1 || hrp[m] >= ((int64_t)1 << 31)) return fail(LP_EDIM, "nnz must be in [1, 2^31)");
+        if ((rc = fetch(col_idx, hrp[m], true, hci)) != LP_OK) return rc;
+        if ((rc = fetch(val, hrp[m], true, hval)) != LP_OK) return rc;
+        if ((rc = fetch(b, m, true, hb)) != LP_OK) return rc;
+        if ((rc = fetch(c, n, true, hc)) != LP_OK) return rc;
+        row_ptr = hrp.data();
+        col_idx = hci.data();
+        val = hval.data();
+        b = hb.data();
+        c = hc.data();
+    }
+    rc = validate(m, n, nnz, row_ptr, col_idx, val);
+    if (rc != LP_OK) return rc;
+    if ((rc = check_vec(b, m, "b")) != LP_OK) return rc;
+    if ((rc = check_vec(c, n, "c")) != LP_OK) return rc;
+    if (!dev && (rc = check_device()) != LP_OK) return rc;
+    lp_problem* p = new (std::nothrow) lp_problem();
+    if (!p) return fail(LP_ENOMEM, "host allocation failed");
+    p->m = m;
+    p->n = n;
+    p->nnz = nnz;
+    p->opt = opt;
+    p->st = (hipStream_t)opt.stream;
+    (void)hipGetDevice(&p->device);
+    rc = setup(p, row_ptr, col_idx, val, b, c);
+    if (rc != LP_OK) {
+        destroy(p);
+        return rc;
+    }
+    *out = p;
+    return LP_OK;
+}
+
+lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
+                          const double* c, const lp_options* o, lp_problem** out) {
+    g_err.clear();
+    if (!out) return fail(LP_EINVAL, "NULL out");
+    *out = nullptr;
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    if (m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
+    if (lda < n) return fail(LP_EINVAL, "lda < n");
+    if (!A || !b || !c) return fail(LP_EINVAL, "NULL input array");
+    if (m * n >= ((int64_t)1 << 31)) return fail(LP_EDIM, "m * n must be below 2^31");
+    lp_options opt;
+    if (o) opt = *o;
+    else lp_options_default(&opt);
+    const bool dev = opt.device_io != 0;
+    std::vector<double> hA;
+    std::vector<double> hb, hc;
+    lp_status rc;
+    if (dev) {
+        if ((rc = check_device()) != LP_OK) return rc;
+        hA.resize((size_t)(m * lda));
+        LPK_HIP(hipMemcpy(hA.data(), A, sizeof(double) * m * lda, hipMemcpyDeviceToHost));
+        if ((rc = fetch(b, m, true, hb)) != LP_OK) return rc;
+        if ((rc = fetch(c, n, true, hc)) != LP_OK) return rc;
+        A = hA.data();
+        b = hb.data();
+        c = hc.data();
+    }
+    // every entry is kept, zero or not: the dense matrix as a full CSR
+    std::vector<int64_t> rp((size_t)m + 1);
+    std::vector<int32_t> ci((size_t)(m * n));
+    std::vector<double> val((size_t)(m * n));
+    for (int64_t i = 0; i < m; ++i) {
+        rp[i] = i * n;
+        for (int64_t j = 0; j < n; ++j) {
+            ci[i * n + j] = (int32_t)j;
+            val[i * n + j] = A[i * lda + j];
+        }
+    }
+    rp[m] = m * n;
+    lp_options o2 = opt;
+    o2.device_io = 0;
+    rc = lp_create(m, n, m * n, rp.data(), ci.data(), val.data(), b, c, &o2, out);
+    if (rc == LP_OK) {
+        (*out)->opt.device_io = opt.device_io;
+        (*out)->dense = true;
+    }
+    return rc;
+}
+
+void lp_destroy(lp_problem* p) { destroy(p); }
+
+lp_status ipm_step(lp_problem* p, lp_iter_info* info) {
+    g_err.clear();
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    lp_iter_info L{};
+    lp_status rc;
+    if (!p->have_point) {
+        if (p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
+        rc = ipm_init_point(p);
+        if (rc != LP_OK) return rc;
+    }
+    rc = ipm_iterate(p, &L);
+    p->log.push_back(L);
+    if (info) *info = L;
+    return rc;
+}
+
+lp_status lp_solve(lp_problem* p, lp_result* r) {
+    g_err.clear();
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    const auto t0 = std::chrono::steady_clock::now();
+    p->log.clear();
+    p->krylov_total = 0;
+    p->last_iters = 0;
+    lp_status rc = LP_OK;
+    if (p->opt.start == 0 || !p->have_point) {
+        if (p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
+        rc = ipm_init_point(p);
+        if (rc != LP_OK) return rc;
+    } else {
+        p->ist.eps_in = p->opt.eps_in0;
+        p->ist.k = 0;
+        p->ist.fail_prev = 0;
+    }
+    lp_iter_info L{};
+    int32_t k = 0;
+    lp_status status = LP_NOT_CONVERGED;
+    for (k = 0; k <= p->opt.ipm_max_iter; ++k) {
+        if (k == p->opt.ipm_max_iter) {
+            // the final point is only evaluated
+            L = lp_iter_info{};
+            rc = ipm_evaluate(p, &L);
+            if (rc != LP_OK) return rc;
+            status = L.converged ? LP_OK : LP_NOT_CONVERGED;
+            p->log.push_back(L);
+            break;
+        }
+        L = lp_iter_info{};
+        rc = ipm_iterate(p, &L);
+        p->log.push_back(L);
+        if (rc != LP_OK) {
+            status = rc;
+            break;
+        }
+        if (L.converged) {
+            status = LP_OK;
+            break;
+        }
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (r) {
+        memset(r, 0, sizeof(*r));
+        r->status = status;
+        r->iters = k;
+        r->gamma = L.gamma;
+        r->gamma_rel = L.gamma_rel;
+        r->pobj = L.pobj;
+        r->dobj = L.dobj;
+        r->rp_rel = L.rp_rel;
+        r->rd_rel = L.rd_rel;
+        r->gap_rel = L.gap_rel;
+        r->krylov_iters = p->krylov_total;
+        r->seconds = secs;
+    }
+    return status;
+}
+
+lp_status direction_solve(lp_problem* p, const double* d, const double* f, double tol, double* dw,
+                          double* dy, lp_krylov_info* ki) {
+    g_err.clear();
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    if (!f || !dw) return fail(LP_EINVAL, "NULL f or dw");
+    if (!(tol >= 0.0)) return fail(LP_EINVAL, "tol must be >= 0");
+    const int64_t m = p->m, n = p->n;
+    lp_status rc;
+    if (!p->opt.device_io) {
+        if ((rc = check_vec(f, m, "f")) != LP_OK) return rc;
+        if (d) {
+            if ((rc = check_vec(d, n, "d")) != LP_OK) return rc;
+            for (int64_t j = 0; j < n; ++j)
+                if (!(d[j] > 0.0)) return fail(LP_EINVAL, "d must be positive");
+        }
+    }
+    hipStream_t st = p->st;
+    const double* dd;
+    if (d) {
+        if ((rc = copy_in(p, d, p->dapi, n)) != LP_OK) return rc;
+        dd = p->dapi;
+    } else {
+        if (!p->have_point) return fail(LP_EINVAL, "no current iterate: pass d");
+        ipm_scaling(st, n, p->x, p->s, nullptr, p->dapi, nullptr);
+        dd = p->dapi;
+    }
+    rc = build_scaling(p, dd);
+    if (rc != LP_OK) return rc;
+    if ((rc = copy_in(p, f, p->dtmp_m, m)) != LP_OK) return rc;
+    gather(st, m, p->dtmp_m, p->perm_d, p->f);
+    rc = krylov_solve(p, p->f, tol, p->dw, p->dyh, ki);
+    if (rc != LP_OK) return rc;
+    if ((rc = copy_out(p, p->dw, dw, n)) != LP_OK) return rc;
+    if (dy) {
+        div_by(st, m, p->dyh, p->rho, p->dyc);
+        scatter(st, m, p->dyc, p->perm_d, p->dtmp_m);
+        if ((rc = copy_out(p, p->dtmp_m, dy, m)) != LP_OK) return rc;
+    }
+    LPK_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+lp_status lp_get_state(const lp_problem* pc, double* x, double* y, double* s, lp_ipm_state* stt) {
+    g_err.clear();
+    lp_problem* p = const_cast<lp_problem*>(pc);
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    lp_status rc;
+    if (x && (rc = copy_out(p, p->x, x, p->n)) != LP_OK) return rc;
+    if (s && (rc = copy_out(p, p->s, s, p->n)) != LP_OK) return rc;
+    if (y) {
+        scatter(p->st, p->m, p->y, p->perm_d, p->dtmp_m);
+        if ((rc = copy_out(p, p->dtmp_m, y, p->m)) != LP_OK) return rc;
+    }
+    LPK_HIP(hipStreamSynchronize(p->st));
+    if (stt) *stt = p->ist;
+    return LP_OK;
+}
+
+lp_status lp_set_state(lp_problem* p, const double* x, const double* y, const double* s,
+                       const lp_ipm_state* stt) {
+    g_err.clear();
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    if (!x || !y || !s) return fail(LP_EINVAL, "NULL x, y or s");
+    lp_status rc;
+    if (!p->opt.device_io) {
+        if ((rc = check_vec(x, p->n, "x")) != LP_OK) return rc;
+        if ((rc = check_vec(s, p->n, "s")) != LP_OK) return rc;
+        if ((rc = check_vec(y, p->m, "y")) != LP_OK) return rc;
+        for (int64_t j = 0; j < p->n; ++j)
+            if (!(x[j] > 0.0) || !(s[j] > 0.0)) return fail(LP_EINVAL, "x and s must be positive");
+    }
+    if ((rc = copy_in(p, x, p->x, p->n)) != LP_OK) return rc;
+    if ((rc = copy_in(p, s, p->s, p->n)) != LP_OK) return rc;
+    if ((rc = copy_in(p, y, p->dtmp_m, p->m)) != LP_OK) return rc;
+    gather(p->st, p->m, p->dtmp_m, p->perm_d, p->y);
+    if (p->opt.device_io) {
+        min2(p->st, p->red, p->n, p->x, p->s);
+        double mins[2];
+        if ((rc = sync_read(p, p->red.out, mins, 2)) != LP_OK) return rc;
+        if (!(mins[0] > 0.0) || !(mins[1] > 0.0)) return fail(LP_EINVAL, "x and s must be positive");
+    }
+    LPK_HIP(hipStreamSynchronize(p->st));
+    if (stt) {
+        p->ist = *stt;
+    } else {
+        p->ist.eps_in = p->opt.eps_in0;
+        p->ist.k = 0;
+        p->ist.fail_prev = 0;
+    }
+    p->have_point = true;
+    return LP_OK;
+}
+
+lp_status lp_get_log(const lp_problem* p, lp_iter_info* info, int32_t cap, int32_t* n_out) {
+    if (!p || !n_out) return fail(LP_EINVAL, "NULL argument");
+    const int32_t cnt = (int32_t)p->log.size();
+    *n_out = cnt;
+    if (info)
+        for (int32_t i = 0; i < cnt && i < cap; ++i) info[i] = p->log[i];
+    return LP_OK;
+}
+
+lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options* o, uint64_t* bytes) {
+    if (!bytes) return fail(LP_EINVAL, "NULL bytes");
+    if (m < 1 || n < 1 || m > n || nnz < 1 || nnz >= ((int64_t)1 << 31)) return fail(LP_EDIM, "bad dimensions");
+    lp_options opt;
+    if (o) opt = *o;
+    else lp_options_default(&opt);
+    *bytes = footprint(m, n, nnz, opt);
+    return LP_OK;
+}
+
+lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, int32_t cap) {
+    if (!p || !ncolours) return fail(LP_EINVAL, "NULL argument");
+    *ncolours = (int32_t)p->colours.size();
+    if (sizes)
+        for (int32_t c = 0; c < *ncolours && c < cap; ++c) sizes[c] = p->colours[c].r1 - p->colours[c].r0;
+    return LP_OK;
+}
+
+lp_status lp_colour_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                         int32_t* colour, int32_t* perm, int32_t* ncolours) {
+    g_err.clear();
+    if (!row_ptr || !col_idx || !colour || !perm || !ncolours) return fail(LP_EINVAL, "NULL argument");
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    if (row_ptr[0] != 0) return fail(LP_EINVAL, "row_ptr[0] != 0");
+    for (int64_t i = 0; i < m; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(LP_EINVAL, "row_ptr decreasing");
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col_idx[k] < 0 || col_idx[k] >= n) return fail(LP_EINVAL, "column index out of range");
+    }
+    *ncolours = greedy_colour(m, n, row_ptr, col_idx, colour, perm);
+    return LP_OK;
+}
+
+const char* lp_status_str(lp_status s) {
+    switch (s) {
+        case LP_OK: return "LP_OK";
+        case LP_EINVAL: return "LP_EINVAL";
+        case LP_EDIM: return "LP_EDIM";
+        case LP_ENONFINITE: return "LP_ENONFINITE";
+        case LP_ENOMEM: return "LP_ENOMEM";
+        case LP_ETOOBIG: return "LP_ETOOBIG";
+        case LP_EDEVICE: return "LP_EDEVICE";
+        case LP_NOT_CONVERGED: return "LP_NOT_CONVERGED";
+        case LP_DIVERGED: return "LP_DIVERGED";
+        case LP_KRYLOV_MAXIT: return "LP_KRYLOV_MAXIT";
+    }
+    return "LP_UNKNOWN";
+}
+
+const char* lp_last_error(void) { return g_err.c_str(); }
+
+const char* lp_version(void) { return "lpk 0.1 (gfx950)"; }
+
+}  // extern "C"

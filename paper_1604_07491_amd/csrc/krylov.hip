@@ -1,0 +1,197 @@
+// The search-direction solve on the device: AB-GMRES right-preconditioned by inner
+// iterations (Sec. 3.2) on the row-scaled min-norm problem (Sec. 3.5).
+//
+// Differences from the paper's CPU layout, all exact in exact arithmetic:
+//  * flexible final step: the multiplier vectors p_k of every preconditioner application
+//    are kept (P = [p_1 .. p_k]) and the solution is dw = A_hat^T (P y); z_k = A_hat^T p_k
+//    is recomputed in FP64, so the Arnoldi relation and dw in R(A_hat^T) hold to FP64 even
+//    when the sweeps run in FP32.  The multipliers also give dy = diag(rho)^-1 P y with no
+//    extra matrix-vector product.
+//  * classical Gram-Schmidt applied twice in place of modified Gram-Schmidt (Sec. 3.2 uses
+//    MGS); both orthogonalise to working precision, CGS2 in two reductions per pass.
+//  * the Hessenberg least-squares problem is kept in QR form by Givens rotations on the
+//    device; the host only polls the convergence flag every few iterations.
+#include <algorithm>
+
+#include "lpk_impl.h"
+
+namespace lpk {
+
+lp_status sync_read(lp_problem* p, const double* dev, double* host, int count) {
+    LPK_HIP(hipMemcpyAsync(p->host_out, dev, sizeof(double) * count, hipMemcpyDeviceToHost, p->st));
+    LPK_HIP(hipStreamSynchronize(p->st));
+    for (int i = 0; i < count; ++i) host[i] = p->host_out[i];
+    return LP_OK;
+}
+
+static lp_status read_ctl(lp_problem* p, KrylovCtl* out) {
+    LPK_HIP(hipMemcpyAsync(p->host_ctl, p->ctl, sizeof(KrylovCtl), hipMemcpyDeviceToHost, p->st));
+    LPK_HIP(hipStreamSynchronize(p->st));
+    *out = *p->host_ctl;
+    return LP_OK;
+}
+
+// rho, A_hat (CSR, CSC; FP32 copies in mixed mode) for D = diag(d) (d NULL: D = I), and
+// the Cimmino step 1/lambda when it is not fixed by the options
+lp_status build_scaling(lp_problem* p, const double* d_dev) {
+    hipStream_t st = p->st;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    const bool cim = p->opt.inner == LP_CIMMINO;
+    scale_rows(st, p->g_csr, (int)p->m, p->rp, p->ci, p->a, d_dev, p->rho, p->ah, mixed ? p->ah32 : nullptr);
+    scale_cols(st, (int)p->n, p->cp, p->ri, p->ac, d_dev, p->rho, p->ahc, (mixed && cim) ? p->ahc32 : nullptr);
+    LPK_HIP(hipGetLastError());
+    if (cim) {
+        if (p->opt.omega_c > 0.0) {
+            p->omega_c = p->opt.omega_c;
+        } else {
+            // 20 power iterations on A_hat A_hat^T from e / sqrt(m): lambda = ||A_hat A_hat^T v||
+            double* v = p->dtmp_m;
+            fill(st, p->m, 1.0 / std::sqrt((double)p->m), v);
+            for (int it = 0; it < 20; ++it) {
+                spmv_f64(st, p->g_csc, (int)p->n, p->cp, p->ri, p->ahc, v, p->dtmp_n, EPI_PLAIN, nullptr, nullptr, nullptr);
+                spmv_f64(st, p->g_csr, (int)p->m, p->rp, p->ci, p->ah, p->dtmp_n, v, EPI_PLAIN, nullptr, nullptr, nullptr);
+                sumsq(st, p->red, p->m, v);
+                if (it + 1 < 20) vec_scale_by_norm(st, p->red, p->m, v, 0);
+            }
+            double l2;
+            lp_status rc = sync_read(p, p->red.out, &l2, 1);
+            if (rc != LP_OK) return rc;
+            const double lam = std::sqrt(l2);
+            p->omega_c = lam > 0.0 ? 1.0 / lam : 1.0;
+        }
+    }
+    p->scaled_for_d = false;
+    return LP_OK;
+}
+
+// enqueue Krylov iteration `it` of the current solve (every kernel returns at once once
+// ctl->done is set).  Each launch carries its algorithmic bytes for the profiler: every
+// input and output it must move, each once.
+static void enqueue_iteration(lp_problem* p, int64_t it) {
+    hipStream_t st = p->st;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    const int64_t m = p->m, n = p->n, ldv = p->ldv, nnz = p->nnz;
+    const int32_t* skip = &p->ctl->done;
+    const int ell = std::max(1, (int)p->opt.inner_sweeps);
+    const double sv = mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
+    if (p->opt.inner == LP_CIMMINO) {
+        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, p->ctl);
+        for (int sw = 0; sw < ell; ++sw) {
+            const int first = sw == 0;
+            {
+                const double by = first ? m * (8.0 + sv + 16.0)
+                                        : nnz * (sv + 4.0) + n * sv + m * (4.0 + 8.0 + sv + 16.0);
+                Prof pr(p, LP_K_SWEEP, it, by);
+                if (mixed)
+                    cimmino_residual_f32(st, p->g_csr, (int)m, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->omega_c, p->r32, first, p->ctl);
+                else
+                    cimmino_residual_f64(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->omega_c, p->r64, first, p->ctl);
+            }
+            if (sw + 1 < ell) {
+                const double by = nnz * (sv + 4.0) + m * sv + n * (4.0 + sv * (first ? 1.0 : 2.0));
+                Prof pr(p, LP_K_SWEEP, it, by);
+                if (mixed)
+                    cimmino_zupdate_f32(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc32, p->r32, p->z32, p->omega_c, first, p->ctl);
+                else
+                    cimmino_zupdate_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->r64, p->z64, p->omega_c, first, p->ctl);
+            }
+        }
+    } else {
+        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, mixed ? nullptr : p->z64, mixed ? p->z32 : nullptr, p->ctl);
+        const int nc = (int)p->colours.size();
+        for (int sw = 0; sw < ell; ++sw) {
+            for (int c = 0; c < nc; ++c) {
+                const Colour& cl = p->colours[c];
+                const int wz = !(sw + 1 == ell && c + 1 == nc);
+                const double by = cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) +
+                                  (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
+                Prof pr(p, LP_K_SWEEP, it, by);
+                if (mixed)
+                    nesor_colour_f32(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->opt.omega, p->ctl, wz);
+                else
+                    nesor_colour_f64(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->opt.omega, p->ctl, wz);
+            }
+        }
+    }
+    // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k
+    copy_pcol(st, m, p->P, ldv, p->pcol, p->ctl);
+    {
+        Prof pr(p, LP_K_SPMV_CSC, it, nnz * 12.0 + m * 8.0 + n * 8.0 + (n + 1) * 4.0);
+        spmv_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->pcol, p->z64, EPI_PLAIN, nullptr, nullptr, skip);
+    }
+    {
+        Prof pr(p, LP_K_SPMV_CSR, it, nnz * 12.0 + n * 8.0 + m * 8.0 + (m + 1) * 4.0);
+        spmv_f64(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->u, EPI_PLAIN, nullptr, nullptr, skip);
+    }
+    // CGS2 + Givens; the host iteration index equals the device one while the solve runs
+    const int64_t ldp = p->kmax + 1;
+    const double kk = (double)(it + 1), nch = (double)p->gs.nchunks;
+    {
+        Prof pr(p, LP_K_GS_DOTS, it, kk * m * 8.0 + m * 8.0 + nch * kk * 8.0);
+        gs_dots(st, p->gs, m, p->V, ldv, p->u, p->gpart, ldp, p->ctl);
+    }
+    gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 0, p->ctl);
+    {
+        Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * kk * 8.0 + kk * 8.0);
+        gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 0, p->ctl);
+    }
+    gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 1, p->ctl);
+    {
+        Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * 8.0 + kk * 8.0);
+        gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 1, p->ctl);
+    }
+    gs_finish(st, p->gs, p->gpart, p->H, p->ldh, p->cs, p->sn, p->gam, p->ctl);
+}
+
+lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* dw, double* dyh,
+                       lp_krylov_info* ki) {
+    hipStream_t st = p->st;
+    const int64_t m = p->m, n = p->n;
+    int64_t kmax = p->kmax;
+    if (p->opt.krylov_max_iter > 0) kmax = std::min<int64_t>(kmax, p->opt.krylov_max_iter);
+    const int64_t sid = p->solve_id++;
+    if ((int64_t)p->solve_iters.size() <= sid) p->solve_iters.resize(sid + 1, 0);
+    int nb = 0;
+    krylov_init_rhs(st, m, f_dev, p->rho, p->fhU, p->u, p->red.part, &nb);
+    krylov_init_ctl(st, m, p->red.part, nb, p->fhU, p->V, tol, (int)kmax, p->ctl, p->gam);
+    LPK_HIP(hipGetLastError());
+    KrylovCtl hc;
+    int64_t enq = 0;
+    int batch;
+    if (p->opt.poll_every > 0) batch = p->opt.poll_every;
+    else batch = p->last_iters > 2 ? (int)(p->last_iters - 1) : 4;
+    for (;;) {
+        const int64_t todo = std::min<int64_t>(batch, kmax - enq);
+        for (int64_t i = 0; i < todo; ++i) enqueue_iteration(p, enq + i);
+        enq += todo;
+        LPK_HIP(hipGetLastError());
+        lp_status rc = read_ctl(p, &hc);
+        if (rc != LP_OK) return rc;
+        if (hc.done || enq >= kmax) break;
+        if (p->opt.poll_every <= 0) batch = std::max(2, std::min(32, batch < 8 ? 4 : batch / 2));
+    }
+    // dyh = P y with R y = gamma; dw = A_hat^T dyh; true residual ||f_hat - A_hat dw||
+    krylov_backsolve(st, p->H, p->ldh, p->gam, p->ykr, p->ctl);
+    krylov_combine(st, m, p->P, p->ldv, p->ykr, dyh, p->ctl);
+    spmv_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, dyh, dw, EPI_PLAIN, nullptr, nullptr, nullptr);
+    const int nbr = spmv_f64_nrm(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, dw, p->dtmp_m, EPI_B_MINUS, p->fhU, p->spart);
+    krylov_true_res(st, p->spart, nbr, p->ctl);
+    LPK_HIP(hipGetLastError());
+    lp_status rc = read_ctl(p, &hc);
+    if (rc != LP_OK) return rc;
+    if (ki) {
+        ki->iters = hc.iters;
+        ki->beta = hc.beta;
+        ki->res_est = hc.res;
+        ki->res_true = hc.res_true;
+        ki->failed = hc.failed;
+        ki->pad0 = 0;
+    }
+    p->solve_iters[sid] = hc.iters;
+    if (p->prof_recs.size() > 200000) prof_collect(p);
+    p->last_iters = hc.iters;
+    p->krylov_total += hc.iters;
+    return LP_OK;
+}
+
+}  // namespace lpk

@@ -162,11 +162,13 @@ def transport_lp(n_src: int = 300, n_snk: int = 300, seed: int = 1) -> LP:
     """
     rng = np.random.default_rng(seed)
     supply = rng.integers(50, 151, size=n_src).astype(np.float64)
-    while True:
+    for _ in range(10000):
         dem = rng.integers(50, 151, size=n_snk - 1).astype(np.float64)
         last = supply.sum() - dem.sum()
         if last >= 1:
             break
+    else:
+        raise ValueError("supplies and demands cannot be balanced for these sizes")
     demand = np.concatenate([dem, [last]])
     cost = rng.integers(1, 101, size=n_src * n_snk).astype(np.float64)
     m, n = n_src + n_snk, n_src * n_snk

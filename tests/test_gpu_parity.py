@@ -1,0 +1,157 @@
+"""Parity of the HIP library (through the C ABI) with the CPU FP64 oracle.  GPU only.
+
+Tolerances: at a fixed number of Krylov iterations both sides compute the same GMRES
+iterate in exact arithmetic; they differ by rounding only (sparse-product summation order,
+fused multiply-add on the GPU, CGS2 against MGS), bounded here by 1e-9 relative.  Converged
+solves are compared with the min-norm solution.  Mixed precision (FP32 inner sweeps) only
+changes the preconditioner, so a converged mixed solve still meets the same min-norm
+solution to the solve tolerance.  End to end, every solve must reach gamma_rel <= 1e-8
+and the objective of the oracle within 1e-7 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1604_07491_amd as lpk
+from paper_1604_07491_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a.cpu() if hasattr(a, "cpu") else a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _case(name):
+    if name == "config0":
+        return synth.config(0)
+    if name == "ragged":
+        return synth.sparse_lp(331, 777, 5, 4, seed=21)
+    if name == "longrows":     # rows longer than the register-staged length
+        return synth.basis_pursuit_lp(40, 300, 3, seed=4)
+    if name == "transport":
+        return synth.transport_lp(31, 29, seed=8)
+    raise ValueError(name)
+
+
+def _dir_problem(lp, seed=0):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.2, 2.0, lp.n)
+    w = rng.standard_normal(lp.n)
+    f = oracle.csr_mv(lp, d * w)          # f in R(A D)
+    return d, f
+
+
+@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport"])
+@pytest.mark.parametrize("k", [1, 4, 13])
+def test_direction_solve_fixed_iterations(name, k):
+    lp = _case(name)
+    d, f = _dir_problem(lp, k)
+    print(f"case {name} k={k} m={lp.m} n={lp.n}", flush=True)
+    with lpk.from_lp(lp, lpk.options(krylov_max_iter=k)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
+    order = oracle.ORDER_NATURAL if name == "longrows" else oracle.ORDER_COLOUR
+    odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, order=order))
+    assert info["iters"] == oinfo["iters"] == min(k, lp.m)
+    assert _rel(dw, odw) <= 1e-9
+    assert _rel(dy, ody) <= 1e-9
+    assert abs(info["res_est"] - oinfo["res_est"]) <= 1e-9 * oinfo["beta"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "transport"])
+def test_direction_solve_converged_is_min_norm(name, precision):
+    lp = _case(name)
+    d, f = _dir_problem(lp, 3)
+    print(f"case {name} {precision}", flush=True)
+    with lpk.from_lp(lp, lpk.options(precision=precision)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
+    AD = lp.to_dense() * d
+    ref = np.linalg.pinv(AD) @ f
+    assert not info["failed"]
+    assert _rel(dw, ref) <= 1e-8
+    # dw = (A D)^T dy
+    assert _rel(AD.T @ np.asarray(dy), ref) <= 1e-8
+    assert info["res_true"] <= 2e-12 * info["beta"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cimmino_direction_solve(precision):
+    lp = _case("config0")
+    d, f = _dir_problem(lp, 5)
+    for k in (1, 6):
+        with lpk.from_lp(lp, lpk.options(krylov_max_iter=k, inner="cimmino", precision=precision)) as p:
+            dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
+        odw, ody, _ = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, inner=oracle.CIMMINO))
+        tol = 1e-9 if precision == "fp64" else 1e-4
+        assert _rel(dw, odw) <= tol and _rel(dy, ody) <= tol
+    with lpk.from_lp(lp, lpk.options(inner="cimmino", precision=precision)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
+    ref = np.linalg.pinv(lp.to_dense() * d) @ f
+    assert _rel(dw, ref) <= 1e-8
+
+
+def test_ipm_step_from_a_given_point():
+    lp = synth.config(0)
+    x, y, s = lp.x0.copy(), lp.y0.copy(), lp.s0.copy()
+    with lpk.from_lp(lp, lpk.options(start=1)) as p:
+        for it in range(3):
+            lpk.lp_set_state(p, x, y, s, dict(eps_in=1e-6 * 0.75 ** it if it else 1e-6, k=it, fail_prev=0))
+            info = lpk.ipm_step(p)
+            gx, gy, gs, st = lpk.lp_get_state(p)
+            ost = oracle.new_state(1e-6 * 0.75 ** it if it else 1e-6)
+            ost.k = it
+            ox, oy, os_ = x.copy(), y.copy(), s.copy()
+            rc, done, L = oracle.ipm_iterate(lp, ox, oy, os_, ost)
+            assert rc == 0 and not done
+            assert info["k_af"] == L["k_af"] and info["k_cc"] == L["k_cc"]
+            assert abs(info["alpha_p"] - L["alpha_p"]) <= 1e-9 and abs(info["alpha_d"] - L["alpha_d"]) <= 1e-9
+            assert _rel(gx, ox) <= 1e-9 and _rel(gs, os_) <= 1e-9 and _rel(gy, oy) <= 1e-8
+            x, y, s = ox, oy, os_
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_lp_solve_end_to_end(cfg, precision):
+    lp = synth.config(cfg)
+    print(f"config {cfg} {precision}", flush=True)
+    o = oracle.ipm(lp)
+    assert o["status"] == oracle.OK
+    with lpk.from_lp(lp, lpk.options(precision=precision)) as p:
+        r = lpk.lp_solve(p)
+        x, y, s, _ = lpk.lp_get_state(p)
+    print(f"gpu iters {r['iters']} krylov {r['krylov_iters']} {r['seconds']:.3f}s gamma_rel {r['gamma_rel']:.2e} "
+          f"pobj {r['pobj']!r} oracle iters {o['iters']} pobj {o['pobj']!r}", flush=True)
+    assert r["status"] == lpk.LP_OK
+    assert r["gamma_rel"] <= 1e-8
+    assert abs(r["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+    assert abs(r["dobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+    A = lp.to_dense() if lp.n <= 2000 else None
+    if A is not None:
+        assert np.linalg.norm(A @ x - lp.b) <= 1e-8 * max(1, np.linalg.norm(lp.b))
+    assert np.all(np.asarray(x) > 0) and np.all(np.asarray(s) > 0)
+
+
+def test_single_row_and_device_io():
+    import torch
+    lp = synth.from_dense(np.array([[1.0, 2.0, 1.0, 3.0]]), np.array([2.0]), np.array([1.0, 1.0, 2.0, 1.0]))
+    o = oracle.ipm(lp)
+    with lpk.from_lp(lp, device=True) as p:
+        r = lpk.lp_solve(p)
+        x, y, s, _ = lpk.lp_get_state(p)
+    assert isinstance(x, torch.Tensor) and x.is_cuda
+    assert r["status"] == lpk.LP_OK and abs(r["pobj"] - o["pobj"]) <= 1e-8 * max(1, abs(o["pobj"]))
+
+
+def test_errors_on_device():
+    lp = synth.config(0)
+    with lpk.from_lp(lp) as p:
+        with pytest.raises(lpk.LpError) as e:
+            lpk.direction_solve(p, -np.ones(lp.n), lp.b, 1e-8)
+        assert e.value.status == lpk.LP_EINVAL
+        with pytest.raises(lpk.LpError):
+            lpk.direction_solve(p, None, lp.b, 1e-8)   # no iterate yet
+        r = lpk.lp_solve(lpk.from_lp(lp, lpk.options(ipm_max_iter=2)))
+        assert r["status"] == lpk.LP_NOT_CONVERGED
