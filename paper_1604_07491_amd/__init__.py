@@ -113,6 +113,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1604_07491_amd/build.py")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # the library bind to that one runtime, so torch's device pointers and streams are
+        # valid in the library and both see the GPU
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -215,6 +219,10 @@ def lp_create(m, n, row_ptr, col_idx, val, b, c, opts: Optional[Options] = None,
     """``lp_create`` of the C ABI (introduction: min c^T x s.t. A x = b, x >= 0)."""
     o = opts if opts is not None else options(**kw)
     keep = []
+    if not o.stream:
+        import torch
+        if torch.cuda.is_available():
+            o.stream = torch.cuda.current_stream().cuda_stream
     if _is_torch(val):
         import torch
         o.device_io = 1

@@ -61,6 +61,7 @@ static uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o
     z.add((kmax + 1) * (kmax + 1), 8);                      // H
     for (int i = 0; i < 5; ++i) z.add(kmax + 2, 8);
     z.add((int64_t)gs.nchunks * (kmax + 1), 8);
+    if (gs_fusable(gs, kmax)) z.add((int64_t)gs.nchunks * (kmax + 1), 8);
     z.add(m / 4 + 8, 8);
     z.add(8 * 1024, 8); z.add(8, 8);
     z.add(1, sizeof(KrylovCtl));
@@ -120,6 +121,9 @@ static lp_status fetch(const T* src, int64_t count, bool dev, std::vector<T>& ou
 static void destroy(lp_problem* p) {
     if (!p) return;
     prof_release(p);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
     p->arena.release();
     if (p->host_out) (void)hipHostFree(p->host_out);
     if (p->host_ctl) (void)hipHostFree(p->host_ctl);
@@ -218,6 +222,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->ykr = A.alloc<double>(p->kmax + 2);
     p->h2 = A.alloc<double>(p->kmax + 2);
     p->gpart = A.alloc<double>((int64_t)p->gs.nchunks * (p->kmax + 1));
+    p->gs_fused = gs_fusable(p->gs, p->kmax);
+    if (p->gs_fused) p->gpart2 = A.alloc<double>((int64_t)p->gs.nchunks * (p->kmax + 1));
     p->spart = A.alloc<double>(m / 4 + 8);
     p->red.maxblk = 1024;
     p->red.part = A.alloc<double>(8 * 1024);
@@ -299,7 +305,7 @@ lp_status lp_options_default(lp_options* o) {
     o->device_io = 0;
     o->stream = nullptr;
     o->poll_every = 0;
-    o->use_graphs = 0;
+    o->use_graphs = 1;
     return LP_OK;
 }
 

@@ -21,6 +21,7 @@ struct KrylovCtl {
     double res;         // |gamma_{k+1}|
     double inv_h;       // 1 / h_{k+1,k} of the last completed iteration
     double res_true;    // ||f_hat - A_hat dw||
+    double omega_c;     // Cimmino step of the current scaling
 };
 
 enum Epilogue : int {
@@ -38,6 +39,11 @@ void spmv_f64(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_
 void spmv_f32(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
               const float* val, const float* x, float* out, int epi, const double* b1,
               const int32_t* skip);
+// out = A x with x = column ctl->k of the column-major X (leading dimension ldx); skipped
+// once ctl->done is set
+void spmv_f64_col(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
+                  const double* val, const double* X, int64_t ldx, double* out,
+                  const KrylovCtl* ctl);
 // same with the sum of squares of out accumulated into per-block partials part[nblk]
 int spmv_f64_nrm(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
                  const double* val, const double* x, double* out, int epi, const double* b1,
@@ -91,6 +97,12 @@ void gs_reduce(hipStream_t st, const GsPlan& pl, const double* part, int64_t ldp
 void gs_update(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
                double* u, const double* h, double* part, int64_t ldp, int mode,
                const KrylovCtl* ctl);
+// update with the reduction of the previous pass's partials pin fused in (each block sums
+// them; block 0 writes column k of H): usable while gs_fusable
+bool gs_fusable(const GsPlan& pl, int64_t kmax);
+void gs_update_fused(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
+                     double* u, const double* pin, double* part, int64_t ldp, int mode,
+                     double* H, int64_t ldh, const KrylovCtl* ctl);
 // norm finish + Givens + convergence; single block
 void gs_finish(hipStream_t st, const GsPlan& pl, const double* part, double* H, int64_t ldh,
                double* cs, double* sn, double* gam, KrylovCtl* ctl);
@@ -99,7 +111,7 @@ void gs_finish(hipStream_t st, const GsPlan& pl, const double* part, double* H, 
 void krylov_init_rhs(hipStream_t st, int64_t m, const double* f, const double* rho, double* fh,
                      double* U, double* part, int* nblk_out);
 void krylov_init_ctl(hipStream_t st, int64_t m, const double* part, int nblk, const double* fh,
-                     double* V, double tol, int kmax, KrylovCtl* ctl, double* gam);
+                     double* V, double tol, int kmax, KrylovCtl* ctl, double* gam, double omega_c);
 // back substitution R y = gamma(1:iters) (single block)
 void krylov_backsolve(hipStream_t st, const double* H, int64_t ldh, const double* gam,
                       double* y, KrylovCtl* ctl);

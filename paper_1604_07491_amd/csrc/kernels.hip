@@ -71,9 +71,12 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int nrows, const int32_t* __rest
                                                 int epi, const double* __restrict__ b1,
                                                 const double* __restrict__ b2,
                                                 const int32_t* __restrict__ skip,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part,
+                                                const KrylovCtl* __restrict__ xcol,
+                                                int64_t xld) {
     __shared__ double sh[BLOCK / 64];
     if (skip && *skip) return;
+    if (xcol) x += (int64_t)xcol->k * xld;   // x is column k of a column-major array
     using A = TV;
     const int tid = blockIdx.x * BLOCK + threadIdx.x;
     const int row = tid / G, lane = tid & (G - 1);
@@ -101,10 +104,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int nrows, const int32_t* __rest
 template <typename TV, typename TX, typename TO>
 static int launch_spmv(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
                        const TV* val, const TX* x, TO* out, int epi, const double* b1,
-                       const double* b2, const int32_t* skip, double* part) {
+                       const double* b2, const int32_t* skip, double* part,
+                       const KrylovCtl* xcol = nullptr, int64_t xld = 0) {
     const unsigned grid = cdiv((int64_t)nrows * g, BLOCK);
     if (grid == 0) return 0;
-#define LPK_SPMV(G) hipLaunchKernelGGL((k_spmv<G, TV, TX, TO>), dim3(grid), dim3(BLOCK), 0, st, nrows, ptr, idx, val, x, out, epi, b1, b2, skip, part)
+#define LPK_SPMV(G) hipLaunchKernelGGL((k_spmv<G, TV, TX, TO>), dim3(grid), dim3(BLOCK), 0, st, nrows, ptr, idx, val, x, out, epi, b1, b2, skip, part, xcol, xld)
     switch (g) {
         case 1: LPK_SPMV(1); break;
         case 2: LPK_SPMV(2); break;
@@ -127,6 +131,12 @@ void spmv_f32(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_
               const float* val, const float* x, float* out, int epi, const double* b1,
               const int32_t* skip) {
     launch_spmv<float, float, float>(st, g, nrows, ptr, idx, val, x, out, epi, b1, nullptr, skip, nullptr);
+}
+void spmv_f64_col(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
+                  const double* val, const double* X, int64_t ldx, double* out,
+                  const KrylovCtl* ctl) {
+    launch_spmv<double, double, double>(st, g, nrows, ptr, idx, val, X, out, EPI_PLAIN, nullptr, nullptr,
+                                        &ctl->done, nullptr, ctl, ldx);
 }
 int spmv_f64_nrm(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
                  const double* val, const double* x, double* out, int epi, const double* b1,
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_cim_res(int m, const int32_t* __restr
     if (lane == 0) {
         const T rr = (T)V[k * ldv + row] - sum;
         r[row] = rr;
-        P[k * ldv + row] += w * (double)rr;
+        P[k * ldv + row] += ctl->omega_c * (double)rr;
     }
 }
 
@@ -265,7 +275,8 @@ __global__ __launch_bounds__(BLOCK) void k_cim_z(int n, const int32_t* __restric
     const int s = cptr[col], e = cptr[col + 1];
     for (int kk = s + lane; kk < e; kk += G) sum += cval[kk] * r[ridx[kk]];
     sum = sg_sum<G>(sum);
-    if (lane == 0) z[col] = first ? (T)w * sum : z[col] + (T)w * sum;
+    const T wc = (T)ctl->omega_c;
+    if (lane == 0) z[col] = first ? wc * sum : z[col] + wc * sum;
 }
 
 #define LPK_SWITCH_G(MACRO)            \
@@ -403,18 +414,40 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_dots(int64_t m, const doub
     }
 }
 
+constexpr int GS_HLDS = 2048;   // coefficients staged in LDS by the fused reduction
+
 template <int RPL>
 __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(int64_t m, const double* __restrict__ V,
                                                              int64_t ldv, double* __restrict__ u,
                                                              const double* __restrict__ h,
                                                              double* __restrict__ part, int64_t ldp,
                                                              int mode,
-                                                             const KrylovCtl* __restrict__ ctl) {
+                                                             const KrylovCtl* __restrict__ ctl,
+                                                             const double* __restrict__ pin,
+                                                             int nchunks, double* __restrict__ H,
+                                                             int64_t ldh) {
     __shared__ double red[GS_WAVES][64 * RPL];
     __shared__ double unew[64 * RPL];
     __shared__ double sh[GS_WAVES];
+    __shared__ double hl[GS_HLDS];
     if (ctl->done) return;
     const int k = ctl->k;
+    if (pin) {
+        // fused reduction of the previous pass's dot partials (every block, fixed order);
+        // mode 0 follows pass 1 (column k of H = h), mode 1 follows pass 2 (H += h)
+        for (int j = threadIdx.x; j <= k; j += blockDim.x) {
+            double sj = 0.0;
+            for (int c = 0; c < nchunks; ++c) sj += pin[(int64_t)c * ldp + j];
+            hl[j] = sj;
+            if (blockIdx.x == 0) {
+                double* hk = H + (int64_t)k * ldh;
+                if (mode == 0) hk[j] = sj;
+                else hk[j] += sj;
+            }
+        }
+        __syncthreads();
+        h = hl;
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * 64 * RPL;
     double acc[RPL];
@@ -486,9 +519,23 @@ void gs_dots(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64
 void gs_update(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
                double* u, const double* h, double* part, int64_t ldp, int mode,
                const KrylovCtl* ctl) {
-#define LPK_GU(R) hipLaunchKernelGGL((k_gs_update<R>), dim3(pl.nchunks), dim3(64 * GS_WAVES), 0, st, m, V, ldv, u, h, part, ldp, mode, ctl)
+    const double* pin = nullptr;
+    double* H = nullptr;
+    int64_t ldh = 0;
+#define LPK_GU(R) hipLaunchKernelGGL((k_gs_update<R>), dim3(pl.nchunks), dim3(64 * GS_WAVES), 0, st, m, V, ldv, u, h, part, ldp, mode, ctl, pin, pl.nchunks, H, ldh)
     LPK_SWITCH_RPL(LPK_GU)
 #undef LPK_GU
+}
+
+bool gs_fusable(const GsPlan& pl, int64_t kmax) { return pl.nchunks <= 32 && kmax + 1 <= GS_HLDS; }
+
+void gs_update_fused(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
+                     double* u, const double* pin, double* part, int64_t ldp, int mode,
+                     double* H, int64_t ldh, const KrylovCtl* ctl) {
+    const double* h = nullptr;
+#define LPK_GUF(R) hipLaunchKernelGGL((k_gs_update<R>), dim3(pl.nchunks), dim3(64 * GS_WAVES), 0, st, m, V, ldv, u, h, part, ldp, mode, ctl, pin, pl.nchunks, H, ldh)
+    LPK_SWITCH_RPL(LPK_GUF)
+#undef LPK_GUF
 }
 
 // h[j] = sum over chunks of part[c, j] (fixed order).  Pass 1 (accumulate == 0) stores
@@ -533,13 +580,16 @@ __global__ __launch_bounds__(BLOCK) void k_gs_finish(int nchunks, const double* 
     const int k = ctl->k;
     const double hn = sqrt(nrm2);
     double* hk = H + (int64_t)k * ldh;
-    hk[k + 1] = hn;
+    // earlier rotations on column k; the rotated entry i+1 is carried in a register, so
+    // the loads of cs, sn and hk do not wait on the previous step
+    double carry = hk[0];
+#pragma unroll 8
     for (int i = 0; i < k; ++i) {
-        const double a = hk[i], b = hk[i + 1];
-        hk[i] = cs[i] * a + sn[i] * b;
-        hk[i + 1] = -sn[i] * a + cs[i] * b;
+        const double b = hk[i + 1], c = cs[i], s = sn[i];
+        hk[i] = c * carry + s * b;
+        carry = -s * carry + c * b;
     }
-    const double a = hk[k], b = hk[k + 1];
+    const double a = carry, b = hn;
     const double r = hypot(a, b);
     if (r == 0.0) {
         ctl->done = 1;
@@ -610,7 +660,7 @@ void krylov_init_rhs(hipStream_t st, int64_t m, const double* f, const double* r
 __global__ __launch_bounds__(BLOCK) void k_init_ctl(int nblk, const double* __restrict__ part,
                                                     double tol, int kmax,
                                                     KrylovCtl* __restrict__ ctl,
-                                                    double* __restrict__ gam) {
+                                                    double* __restrict__ gam, double omega_c) {
     __shared__ double sh[BLOCK / 64];
     double q = 0.0;
     for (int c = threadIdx.x; c < nblk; c += BLOCK) q += part[c];
@@ -627,15 +677,16 @@ __global__ __launch_bounds__(BLOCK) void k_init_ctl(int nblk, const double* __re
     ctl->res_true = beta;
     ctl->inv_h = beta > 0.0 ? 1.0 / beta : 0.0;
     ctl->done = (beta == 0.0 || kmax <= 0) ? 1 : 0;
+    ctl->omega_c = omega_c;
     gam[0] = beta;
 }
 
 void krylov_init_ctl(hipStream_t st, int64_t m, const double* part, int nblk, const double* fh,
-                     double* V, double tol, int kmax, KrylovCtl* ctl, double* gam) {
+                     double* V, double tol, int kmax, KrylovCtl* ctl, double* gam, double omega_c) {
     (void)m;
     (void)fh;
     (void)V;
-    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(BLOCK), 0, st, nblk, part, tol, kmax, ctl, gam);
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(BLOCK), 0, st, nblk, part, tol, kmax, ctl, gam, omega_c);
 }
 
 // R y = gamma(1:iters), R = upper triangle of the rotated Hessenberg matrix (column-major)

@@ -114,10 +114,9 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
         }
     }
     // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k
-    copy_pcol(st, m, p->P, ldv, p->pcol, p->ctl);
     {
         Prof pr(p, LP_K_SPMV_CSC, it, nnz * 12.0 + m * 8.0 + n * 8.0 + (n + 1) * 4.0);
-        spmv_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->pcol, p->z64, EPI_PLAIN, nullptr, nullptr, skip);
+        spmv_f64_col(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->P, ldv, p->z64, p->ctl);
     }
     {
         Prof pr(p, LP_K_SPMV_CSR, it, nnz * 12.0 + n * 8.0 + m * 8.0 + (m + 1) * 4.0);
@@ -130,17 +129,51 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
         Prof pr(p, LP_K_GS_DOTS, it, kk * m * 8.0 + m * 8.0 + nch * kk * 8.0);
         gs_dots(st, p->gs, m, p->V, ldv, p->u, p->gpart, ldp, p->ctl);
     }
-    gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 0, p->ctl);
-    {
-        Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * kk * 8.0 + kk * 8.0);
-        gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 0, p->ctl);
-    }
-    gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 1, p->ctl);
-    {
-        Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * 8.0 + kk * 8.0);
-        gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 1, p->ctl);
+    if (p->gs_fused) {
+        // each update block reduces the previous pass's partials itself (few chunks)
+        {
+            Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + 2.0 * nch * kk * 8.0);
+            gs_update_fused(st, p->gs, m, p->V, ldv, p->u, p->gpart, p->gpart2, ldp, 0, p->H, p->ldh, p->ctl);
+        }
+        {
+            Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * kk * 8.0 + nch * 8.0);
+            gs_update_fused(st, p->gs, m, p->V, ldv, p->u, p->gpart2, p->gpart, ldp, 1, p->H, p->ldh, p->ctl);
+        }
+    } else {
+        gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 0, p->ctl);
+        {
+            Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * kk * 8.0 + kk * 8.0);
+            gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 0, p->ctl);
+        }
+        gs_reduce(st, p->gs, p->gpart, ldp, p->H, p->ldh, p->h2, 1, p->ctl);
+        {
+            Prof pr(p, LP_K_GS_UPDATE, it, kk * m * 8.0 + 16.0 * m + nch * 8.0 + kk * 8.0);
+            gs_update(st, p->gs, m, p->V, ldv, p->u, p->h2, p->gpart, ldp, 1, p->ctl);
+        }
     }
     gs_finish(st, p->gs, p->gpart, p->H, p->ldh, p->cs, p->sn, p->gam, p->ctl);
+}
+
+// capture `iters` Krylov iterations once per problem; every kernel argument is fixed
+// (the iteration index, the done flag and the Cimmino step live in device memory), so
+// the same executable graph serves every iteration of every solve
+static lp_status build_graph(lp_problem* p, int iters) {
+    if (!p->cap_st) LPK_HIP(hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
+    hipStream_t keep = p->st;
+    const uint32_t mask = p->prof_mask;
+    p->prof_mask = 0;
+    p->st = p->cap_st;
+    hipError_t e = hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < iters; ++i) enqueue_iteration(p, -1);
+        e = hipStreamEndCapture(p->cap_st, &p->graph);
+    }
+    p->st = keep;
+    p->prof_mask = mask;
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    LPK_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+    p->graph_iters = iters;
+    return LP_OK;
 }
 
 lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* dw, double* dyh,
@@ -153,8 +186,13 @@ lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* d
     if ((int64_t)p->solve_iters.size() <= sid) p->solve_iters.resize(sid + 1, 0);
     int nb = 0;
     krylov_init_rhs(st, m, f_dev, p->rho, p->fhU, p->u, p->red.part, &nb);
-    krylov_init_ctl(st, m, p->red.part, nb, p->fhU, p->V, tol, (int)kmax, p->ctl, p->gam);
+    krylov_init_ctl(st, m, p->red.part, nb, p->fhU, p->V, tol, (int)kmax, p->ctl, p->gam, p->omega_c);
     LPK_HIP(hipGetLastError());
+    const bool use_graph = p->opt.use_graphs && p->prof_mask == 0;
+    if (use_graph && !p->graph_exec) {
+        lp_status grc = build_graph(p, 8);
+        if (grc != LP_OK) return grc;
+    }
     KrylovCtl hc;
     int64_t enq = 0;
     int batch;
@@ -162,8 +200,14 @@ lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* d
     else batch = p->last_iters > 2 ? (int)(p->last_iters - 1) : 4;
     for (;;) {
         const int64_t todo = std::min<int64_t>(batch, kmax - enq);
-        for (int64_t i = 0; i < todo; ++i) enqueue_iteration(p, enq + i);
-        enq += todo;
+        if (use_graph) {
+            const int64_t launches = (todo + p->graph_iters - 1) / p->graph_iters;
+            for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(p->graph_exec, st));
+            enq += launches * p->graph_iters;
+        } else {
+            for (int64_t i = 0; i < todo; ++i) enqueue_iteration(p, enq + i);
+            enq += todo;
+        }
         LPK_HIP(hipGetLastError());
         lp_status rc = read_ctl(p, &hc);
         if (rc != LP_OK) return rc;

@@ -103,6 +103,13 @@ struct lp_problem {
     float *z32 = nullptr, *r32 = nullptr;
     double *r64 = nullptr;
     double* gpart = nullptr;                        // (nchunks) x (kmax+1) CGS partials
+    double* gpart2 = nullptr;                       // second buffer for the fused passes
+    bool gs_fused = false;
+    // captured Krylov iterations (replayed with hipGraphLaunch)
+    hipStream_t cap_st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_iters = 0;
     double* spart = nullptr;                        // per-block partials of a CSR product
     double* dapi = nullptr;                         // D given to direction_solve
     double norm_b = 0.0, norm_c = 0.0;
