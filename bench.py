@@ -29,7 +29,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="transport_300x300",
-                    choices=["transport_300x300", "sparse_200x500"])
+                    choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "cimmino"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -45,11 +45,15 @@ def main():
     import paper_1604_07491_amd as lpk
     from paper_1604_07491_amd import synth
 
-    lp = synth.config(1) if args.workload == "transport_300x300" else synth.config(0)
+    lp = {"transport_300x300": lambda: synth.config(1), "sparse_200x500": lambda: synth.config(0),
+          "basis_pursuit_1024x16384": lambda: synth.config(2)}[args.workload]()
     torch.cuda.set_device(0)
     dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
     opts = lpk.options(precision=args.precision, inner=args.inner)
-    p = lpk.lp_create(lp.m, lp.n, dev(lp.row_ptr), dev(lp.col_idx), dev(lp.val), dev(lp.b), dev(lp.c), opts)
+    if lp.dense is not None:
+        p = lpk.lp_create_dense(dev(lp.dense), dev(lp.b), dev(lp.c), opts)
+    else:
+        p = lpk.lp_create(lp.m, lp.n, dev(lp.row_ptr), dev(lp.col_idx), dev(lp.val), dev(lp.b), dev(lp.c), opts)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -83,7 +87,7 @@ def main():
         traffic = tr.get(dom)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and lp.dense is None:
         import oracle
         tc = time.perf_counter()
         o = oracle.ipm(lp)
@@ -121,8 +125,9 @@ def main():
                      "bytes_per_launch": bytes_launch},
         "kernel_classes": {k: {"launches": v["launches"], "ms_total": v["ms_total"],
                                "us_per_launch": v["ms_total"] * 1e3 / max(v["launches"], 1),
-                               "GBps": (v["bytes_total"] / (v["ms_total"] / 1e3) / 1e9) if v["ms_total"] > 0 else 0}
-                           for k, v in stats.items()},
+                               "GBps": (v["bytes_total"] / (v["ms_total"] / 1e3) / 1e9) if v["ms_total"] > 0 else 0,
+                               "TFLOPs": (v["flops_total"] / (v["ms_total"] / 1e3) / 1e12) if v["ms_total"] > 0 else 0}
+                           for k, v in stats.items() if v["launches"] > 0},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

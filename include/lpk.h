@@ -206,7 +206,8 @@ typedef enum {
     LP_K_SPMV_CSC = 2,       /* z = A_hat^T p of the Krylov loop (FP64)                     */
     LP_K_GS_DOTS = 3,        /* Gram-Schmidt dot products V^T u                             */
     LP_K_GS_UPDATE = 4,      /* Gram-Schmidt update u -= V h (with the next dots or norm)   */
-    LP_K_COUNT = 5
+    LP_K_GRAM = 5,           /* dense path: G = A_hat A_hat^T with FP64 matrix cores        */
+    LP_K_COUNT = 6
 } lp_kernel_class;
 
 typedef struct {
@@ -215,6 +216,7 @@ typedef struct {
     int64_t launches;        /* launches that did work (skipped launches are not counted)  */
     double ms_total;         /* sum of HIP-event durations of those launches              */
     double bytes_total;      /* algorithmic bytes: each input and output moved once       */
+    double flops_total;      /* algorithmic floating-point operations                     */
     char name[32];
 } lp_kernel_stat;
 

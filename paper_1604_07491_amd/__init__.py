@@ -65,10 +65,11 @@ class IpmState(C.Structure):
 
 class KernelStat(C.Structure):
     _fields_ = [("cls", C.c_int32), ("pad0", C.c_int32), ("launches", C.c_int64),
-                ("ms_total", C.c_double), ("bytes_total", C.c_double), ("name", C.c_char * 32)]
+                ("ms_total", C.c_double), ("bytes_total", C.c_double), ("flops_total", C.c_double),
+                ("name", C.c_char * 32)]
 
 
-LP_K_SWEEP, LP_K_SPMV_CSR, LP_K_SPMV_CSC, LP_K_GS_DOTS, LP_K_GS_UPDATE, LP_K_COUNT = 0, 1, 2, 3, 4, 5
+LP_K_SWEEP, LP_K_SPMV_CSR, LP_K_SPMV_CSC, LP_K_GS_DOTS, LP_K_GS_UPDATE, LP_K_GRAM, LP_K_COUNT = 0, 1, 2, 3, 4, 5, 6
 
 
 class Result(C.Structure):
@@ -349,4 +350,5 @@ def lp_profile_read(p: Problem):
     n = C.c_int32(0)
     _check(lib().lp_profile_read(p.h, arr, LP_K_COUNT, C.byref(n)), "lp_profile_read")
     return {arr[i].name.decode(): dict(launches=arr[i].launches, ms_total=arr[i].ms_total,
-                                       bytes_total=arr[i].bytes_total) for i in range(n.value)}
+                                       bytes_total=arr[i].bytes_total, flops_total=arr[i].flops_total)
+            for i in range(n.value)}

@@ -135,10 +135,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
                        const double* b, const double* c) {
     const int64_t m = p->m, n = p->n, nnz = p->nnz;
     const bool mixed = p->opt.precision == LP_MIXED;
-    // colouring and the permuted CSR
+    // colouring and the permuted CSR (a dense A is a complete conflict graph: colour =
+    // row, the natural order)
     std::vector<int32_t> colour((size_t)m);
     p->perm.resize((size_t)m);
-    const int32_t ncol = greedy_colour(m, n, rp, ci, colour.data(), p->perm.data());
+    int32_t ncol;
+    if (p->dense) {
+        for (int64_t i = 0; i < m; ++i) colour[i] = p->perm[i] = (int32_t)i;
+        ncol = (int32_t)m;
+    } else {
+        ncol = greedy_colour(m, n, rp, ci, colour.data(), p->perm.data());
+    }
     std::vector<int32_t> prp((size_t)m + 1), pci((size_t)nnz);
     std::vector<double> pa((size_t)nnz), pb((size_t)m);
     prp[0] = 0;
@@ -229,6 +236,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->red.part = A.alloc<double>(8 * 1024);
     p->red.out = A.alloc<double>(8);
     p->ctl = A.alloc<KrylovCtl>(1);
+    if (p->gsor) {
+        p->G = A.alloc<double>(m * m);
+        p->Xinv = A.alloc<double>(m * m);
+        p->Rblk = A.alloc<double>(64 * m);
+        if (p->opt.inner_sweeps > 1) {
+            p->Tmat = A.alloc<double>(m * m);
+            p->Cmat = A.alloc<double>(m * m);
+            if (p->opt.inner_sweeps > 2) p->Tmat2 = A.alloc<double>(m * m);
+        }
+        if (mixed) p->C32 = A.alloc<float>(m * m);
+    }
     if (A.failed) return fail(LP_ENOMEM, "device allocation failed");
     if (hipHostMalloc((void**)&p->host_out, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&p->host_ctl, sizeof(KrylovCtl), hipHostMallocDefault) != hipSuccess)
@@ -249,11 +267,11 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     return LP_OK;
 }
 
-static lp_status check_options(const lp_options& o) {
+static lp_status check_options(const lp_options& o, bool dense) {
     if (o.precision != LP_FP64 && o.precision != LP_MIXED) return fail(LP_EINVAL, "unknown precision");
     if (o.krylov != LP_ABGMRES) return fail(LP_EINVAL, "only AB-GMRES is available on the device");
-    if (o.inner != LP_NESOR && o.inner != LP_CIMMINO)
-        return fail(LP_EINVAL, "inner iterations must be NE-SOR or Cimmino for a sparse problem");
+    if (o.inner != LP_NESOR && o.inner != LP_CIMMINO && !(dense && o.inner == LP_GSOR))
+        return fail(LP_EINVAL, "inner iterations must be NE-SOR or Cimmino (or G-SOR for a dense A)");
     if (o.inner_sweeps < 1 || o.inner_sweeps > 64) return fail(LP_EINVAL, "inner_sweeps must be in [1, 64]");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LP_EINVAL, "omega must be in (0, 2)");
     if (!(o.eta >= 0.9 && o.eta < 1.0)) return fail(LP_EINVAL, "eta must be in [0.9, 1)");
@@ -309,16 +327,16 @@ lp_status lp_options_default(lp_options* o) {
     return LP_OK;
 }
 
-lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
-                    const int32_t* col_idx, const double* val, const double* b, const double* c,
-                    const lp_options* o, lp_problem** out) {
+static lp_status create_impl(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                             const int32_t* col_idx, const double* val, const double* b,
+                             const double* c, const lp_options* o, bool dense, lp_problem** out) {
     g_err.clear();
     if (!out) return fail(LP_EINVAL, "NULL out");
     *out = nullptr;
     lp_options opt;
     if (o) opt = *o;
     else lp_options_default(&opt);
-    lp_status rc = check_options(opt);
+    lp_status rc = check_options(opt, dense);
     if (rc != LP_OK) return rc;
     if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
     if (m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
@@ -353,6 +371,13 @@ lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
     p->n = n;
     p->nnz = nnz;
     p->opt = opt;
+    p->dense = dense;
+    // a dense A runs NE-SOR as SOR on the Gram matrix (the same iteration in exact arithmetic)
+    p->gsor = dense && (opt.inner == LP_NESOR || opt.inner == LP_GSOR);
+    if (p->gsor && m > 8192) {
+        delete p;
+        return fail(LP_ETOOBIG, "the Gram-matrix path needs m <= 8192");
+    }
     p->st = (hipStream_t)opt.stream;
     (void)hipGetDevice(&p->device);
     rc = setup(p, row_ptr, col_idx, val, b, c);
@@ -362,6 +387,16 @@ lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
     }
     *out = p;
     return LP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                    const int32_t* col_idx, const double* val, const double* b, const double* c,
+                    const lp_options* o, lp_problem** out) {
+    return create_impl(m, n, nnz, row_ptr, col_idx, val, b, c, o, false, out);
 }
 
 lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
@@ -405,11 +440,8 @@ lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, co
     rp[m] = m * n;
     lp_options o2 = opt;
     o2.device_io = 0;
-    rc = lp_create(m, n, m * n, rp.data(), ci.data(), val.data(), b, c, &o2, out);
-    if (rc == LP_OK) {
-        (*out)->opt.device_io = opt.device_io;
-        (*out)->dense = true;
-    }
+    rc = create_impl(m, n, m * n, rp.data(), ci.data(), val.data(), b, c, &o2, true, out);
+    if (rc == LP_OK) (*out)->opt.device_io = opt.device_io;
     return rc;
 }
 

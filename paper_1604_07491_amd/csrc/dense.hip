@@ -1,0 +1,270 @@
+// Dense-panel path for problems created from a dense A (basis pursuit).
+//
+// Once per interior-point step the Gram matrix G = A_hat A_hat^T (m x m) of the unit-row
+// A_hat is formed with FP64 matrix cores.  The inner iterations are then SOR on
+// G p = v in natural row order, which in exact arithmetic is NE-SOR on the rows of A_hat
+// (Sec. 3.4: the row update d_i = omega (g_i - alpha_i . z) with z = A_hat^T p is
+// omega (g_i - G_i . p)), and the Krylov operator u = A_hat A_hat^T p is the product G p.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace lpk {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+static inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------------------------
+// G = A A^T for a dense row-major A (m x n, leading dimension lda).  A block computes one
+// 64 x 64 tile (tile row bi <= tile column bj; the mirrored tile is written too, so G is
+// exactly symmetric).  Each of the 4 waves owns a 32 x 32 quarter as 2 x 2 tiles of
+// v_mfma_f64_16x16x4: lane l supplies a = A[r0 + l%16][k + l/16] and
+// b = A[c0 + l%16][k + l/16]; result register r of lane l is D[l/16 + 4r][l%16].
+constexpr int GT = 64;      // tile edge
+constexpr int GKC = 32;     // k chunk staged in LDS
+constexpr int GKP = GKC + 1;
+
+__global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __restrict__ A,
+                                              int64_t lda, double* __restrict__ G,
+                                              float* __restrict__ G32, int nb) {
+    const int bi = blockIdx.x % nb, bj = blockIdx.x / nb;
+    if (bi > bj) return;
+    __shared__ double As[GT][GKP];
+    __shared__ double Bs[GT][GKP];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;   // wave quarter inside the tile
+    const int r0 = bi * GT, c0 = bj * GT;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = 0; k0 < n; k0 += GKC) {
+        // stage 64 x 32 of the row block and of the column block (zero padded)
+#pragma unroll
+        for (int q = 0; q < (GT * GKC) / 256; ++q) {
+            const int e = tid + q * 256;
+            const int rr = e / GKC, kk = e % GKC;
+            const int64_t kg = k0 + kk;
+            const int ra = r0 + rr, rb = c0 + rr;
+            As[rr][kk] = (ra < m && kg < n) ? A[(int64_t)ra * lda + kg] : 0.0;
+            Bs[rr][kk] = (rb < m && kg < n) ? A[(int64_t)rb * lda + kg] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GKC; kk += 4) {
+            const int kl = kk + (lane >> 4);
+            const double a0 = As[wr + (lane & 15)][kl];
+            const double a1 = As[wr + 16 + (lane & 15)][kl];
+            const double b0 = Bs[wc + (lane & 15)][kl];
+            const double b1 = Bs[wc + 16 + (lane & 15)][kl];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
+                const int j = c0 + wc + 16 * b + (lane & 15);
+                if (i < m && j < m) {
+                    const double v = acc[a][b][r];
+                    G[(int64_t)i * m + j] = v;
+                    G[(int64_t)j * m + i] = v;
+                    if (G32) {
+                        G32[(int64_t)i * m + j] = (float)v;
+                        G32[(int64_t)j * m + i] = (float)v;
+                    }
+                }
+            }
+}
+
+void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32) {
+    const int nb = (int)cdiv_u(m, GT);
+    hipLaunchKernelGGL(k_gram, dim3(nb * nb), dim3(256), 0, st, m, n, A, lda, G, G32, nb);
+}
+
+// ------------------------------------------------------------------------------------
+// u = G p_k (p_k = column ctl->k of P), one wave per row of the dense symmetric G
+__global__ __launch_bounds__(256) void k_gemv_col(int m, const double* __restrict__ G,
+                                                  const double* __restrict__ P, int64_t ldv,
+                                                  double* __restrict__ u,
+                                                  const KrylovCtl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const double* __restrict__ p = P + (int64_t)ctl->k * ldv;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= m) return;
+    const double* __restrict__ gi = G + (int64_t)i * m;
+    double acc = 0.0;
+    for (int j = lane; j < m; j += 64) acc += gi[j] * p[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) u[i] = acc;
+}
+
+void gemv_col(hipStream_t st, int m, const double* G, const double* P, int64_t ldv, double* u,
+              const KrylovCtl* ctl) {
+    hipLaunchKernelGGL(k_gemv_col, dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, G, P, ldv, u, ctl);
+}
+
+// ------------------------------------------------------------------------------------
+// D = alpha (A B) + beta E + F + diag_one * [row + r0 == col], all row-major (FP64
+// MFMA, 64 x 64 tiles, k chunks of 32 staged in LDS).  A: M x K (lda), B: K x N (ldb).
+// E, F may be NULL.  Used for the explicit inner-iteration preconditioner of the dense
+// path.
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
+                                              const double* __restrict__ A, int64_t lda,
+                                              const double* __restrict__ B, int64_t ldb,
+                                              double beta, const double* __restrict__ E,
+                                              const double* __restrict__ F, int64_t lde,
+                                              double* __restrict__ D, int64_t ldd, int diag_r0,
+                                              int nbn) {
+    __shared__ double As[GT][GKP];
+    __shared__ double Bs[GT][GKP];   // Bs[col][k]
+    const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int r0 = bm * GT, c0 = bn * GT;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += GKC) {
+#pragma unroll
+        for (int q = 0; q < (GT * GKC) / 256; ++q) {
+            const int e = tid + q * 256;
+            // A tile: row rr, k kk (consecutive threads along k)
+            const int rr = e / GKC, kk = e % GKC;
+            const int ra = r0 + rr, ka = k0 + kk;
+            As[rr][kk] = (ra < M && ka < K) ? A[(int64_t)ra * lda + ka] : 0.0;
+            // B tile: k kb, column cc (consecutive threads along the column)
+            const int kb = e / GT, cc = e % GT;
+            const int kg = k0 + kb, cg = c0 + cc;
+            Bs[cc][kb] = (kg < K && cg < N) ? B[(int64_t)kg * ldb + cg] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GKC; kk += 4) {
+            const int kl = kk + (lane >> 4);
+            const double a0 = As[wr + (lane & 15)][kl];
+            const double a1 = As[wr + 16 + (lane & 15)][kl];
+            const double b0 = Bs[wc + (lane & 15)][kl];
+            const double b1 = Bs[wc + 16 + (lane & 15)][kl];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
+                const int j = c0 + wc + 16 * b + (lane & 15);
+                if (i < M && j < N) {
+                    double v = alpha * acc[a][b][r];
+                    if (E) v += beta * E[(int64_t)i * lde + j];
+                    if (F) v += F[(int64_t)i * lde + j];
+                    if (diag_r0 >= 0 && i + diag_r0 == j) v += 1.0;
+                    D[(int64_t)i * ldd + j] = v;
+                }
+            }
+}
+
+void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, const double* E, const double* F,
+              int64_t lde, double* D, int64_t ldd, int diag_r0) {
+    if (M <= 0 || N <= 0) return;
+    const int nbm = (int)cdiv_u(M, GT), nbn = (int)cdiv_u(N, GT);
+    hipLaunchKernelGGL(k_gemm, dim3(nbm * nbn), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, E,
+                       F, lde, D, ldd, diag_r0, nbn);
+}
+
+// Forward substitution with the diagonal block of M = I/omega + tril(G, -1) (rows
+// [r0, r0+b) of the m x m G): X[r0 + i, j] = omega (R[i, j] - sum_{t<i} G[r0+i, r0+t] X[r0+t, j])
+// for every column j < ncols; one thread per column, the block of G in LDS.
+__global__ __launch_bounds__(256) void k_trsm_diag(int m, int r0, int b, const double* __restrict__ G,
+                                                   const double* __restrict__ R, int64_t ldr,
+                                                   double* __restrict__ X, double omega,
+                                                   int ncols) {
+    __shared__ double gb[64][65];
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int i = e / 64, t = e % 64;
+        gb[i][t] = (i < b && t < b) ? G[(int64_t)(r0 + i) * m + r0 + t] : 0.0;
+    }
+    __syncthreads();
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= ncols) return;
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        double s = 0.0;
+        if (i < b) {
+            s = R[(int64_t)i * ldr + j];
+#pragma unroll
+            for (int t = 0; t < i; ++t) s -= gb[i][t] * x[t];
+            s *= omega;
+        }
+        x[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+        if (i < b) X[(int64_t)(r0 + i) * m + j] = x[i];
+}
+
+void trsm_diag(hipStream_t st, int m, int r0, int b, const double* G, const double* R, int64_t ldr,
+               double* X, double omega, int ncols) {
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv_u(ncols, 256)), dim3(256), 0, st, m, r0, b, G, R, ldr, X, omega, ncols);
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(int64_t len, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) b[i] = (float)a[i];
+}
+void to_f32(hipStream_t st, int64_t len, const double* a, float* b) {
+    if (len > 0) hipLaunchKernelGGL(k_to_f32, dim3(cdiv_u(len, 256)), dim3(256), 0, st, len, a, b);
+}
+
+// p_k = C v_k (C: m x m row-major, precision T), v_k = column ctl->k of V, into P[:,k];
+// one wave per row
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_c(int m, const T* __restrict__ C, const double* __restrict__ V,
+                                                 double* __restrict__ P, int64_t ldv,
+                                                 const KrylovCtl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int64_t k = ctl->k;
+    const double* __restrict__ v = V + k * ldv;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= m) return;
+    const T* __restrict__ ci = C + (int64_t)i * m;
+    T acc = 0;
+    for (int j = lane; j < m; j += 64) acc += ci[j] * (T)v[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) P[k * ldv + i] = (double)acc;
+}
+
+void apply_c_f64(hipStream_t st, int m, const double* C, const double* V, double* P, int64_t ldv,
+                 const KrylovCtl* ctl) {
+    hipLaunchKernelGGL((k_apply_c<double>), dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, C, V, P, ldv, ctl);
+}
+void apply_c_f32(hipStream_t st, int m, const float* C, const double* V, double* P, int64_t ldv,
+                 const KrylovCtl* ctl) {
+    hipLaunchKernelGGL((k_apply_c<float>), dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, C, V, P, ldv, ctl);
+}
+
+}  // namespace lpk

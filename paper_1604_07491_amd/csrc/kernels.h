@@ -120,6 +120,25 @@ void krylov_combine(hipStream_t st, int64_t m, const double* P, int64_t ldv, con
                     double* dyh, const KrylovCtl* ctl);
 void krylov_true_res(hipStream_t st, const double* part, int nblk, KrylovCtl* ctl);
 
+// dense path: G = A A^T by FP64 MFMA (A dense row-major), u = G p_k
+void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32);
+void gemv_col(hipStream_t st, int m, const double* G, const double* P, int64_t ldv, double* u,
+              const KrylovCtl* ctl);
+
+// dense GEMM D = alpha A B + beta E + F (+1 on the diagonal shifted by diag_r0 >= 0)
+void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, const double* E, const double* F,
+              int64_t lde, double* D, int64_t ldd, int diag_r0);
+// X[r0:r0+b, 0:ncols] = forward substitution with I/omega + tril(G[r0:r0+b, r0:r0+b], -1)
+void trsm_diag(hipStream_t st, int m, int r0, int b, const double* G, const double* R, int64_t ldr,
+               double* X, double omega, int ncols);
+void to_f32(hipStream_t st, int64_t len, const double* a, float* b);
+// P[:,k] = C V[:,k]
+void apply_c_f64(hipStream_t st, int m, const double* C, const double* V, double* P, int64_t ldv,
+                 const KrylovCtl* ctl);
+void apply_c_f32(hipStream_t st, int m, const float* C, const double* V, double* P, int64_t ldv,
+                 const KrylovCtl* ctl);
+
 // generic reductions: partial results per block, then a fixed-order finish
 struct Red {
     double* part;       // [nq * maxblk]

@@ -31,6 +31,47 @@ static lp_status read_ctl(lp_problem* p, KrylovCtl* out) {
     return LP_OK;
 }
 
+// Dense path, once per scaling: G = A_hat A_hat^T (MFMA), then the inner-iteration
+// preconditioner in the matrix form of Sec. 3.1/3.2, C<l> = sum_{i<l} H^i M^-1 with the SOR
+// splitting M = I/omega + tril(G, -1) (unit diagonal, Sec. 3.5) and H = I - M^-1 G:
+//   X = M^-1 by block forward substitution (64-row blocks: R = I - G[B, <B] X[<B, :] by
+//   GEMM, then the diagonal block's substitution), C_1 = X, C_{i+1} = X + C_i - X (G C_i).
+// l SOR sweeps from zero apply exactly this C to v, so each Krylov iteration needs only
+// p = C v and u = G p.
+static lp_status build_dense_preconditioner(lp_problem* p) {
+    hipStream_t st = p->st;
+    const int m = (int)p->m;
+    const int64_t mm = (int64_t)m * m;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    const double om = p->opt.omega;
+    const int ell = std::max(1, (int)p->opt.inner_sweeps);
+    const double nbt = (double)((m + 63) / 64);
+    double fl = 2.0 * (double)p->n * 64.0 * 64.0 * nbt * (nbt + 1.0) / 2.0;     // Gram tiles
+    fl += (double)m * m * m / 3.0 * 2.0 + (ell - 1) * 4.0 * (double)m * m * m;   // M^-1 and C
+    Prof pr(p, LP_K_GRAM, -1, 8.0 * (double)m * p->n + 8.0 * mm * (3.0 + 3.0 * (ell - 1)), fl);
+    gram_f64(st, m, p->n, p->ah, p->n, p->G, nullptr);
+    fill(st, mm, 0.0, p->Xinv);
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const int b = std::min(64, m - r0), ncols = r0 + b;
+        // R = I[B, :] - G[B, 0:r0] X[0:r0, 0:ncols]   (K = 0 for the first block: R = I)
+        gemm_f64(st, b, ncols, r0, -1.0, p->G + (int64_t)r0 * m, m, p->Xinv, m, 0.0, nullptr, nullptr, m,
+                 p->Rblk, m, r0);
+        trsm_diag(st, m, r0, b, p->G, p->Rblk, m, p->Xinv, om, ncols);
+    }
+    const double* Ccur = p->Xinv;
+    double* bufs[2] = {p->Cmat, p->Tmat2};
+    for (int i = 1; i < ell; ++i) {
+        double* Cn = bufs[(i - 1) & 1];
+        gemm_f64(st, m, m, m, 1.0, p->G, m, Ccur, m, 0.0, nullptr, nullptr, m, p->Tmat, m, -1);
+        gemm_f64(st, m, m, m, -1.0, p->Xinv, m, p->Tmat, m, 1.0, p->Xinv, Ccur, m, Cn, m, -1);
+        Ccur = Cn;
+    }
+    p->Capply = Ccur;
+    if (mixed) to_f32(st, mm, Ccur, p->C32);
+    LPK_HIP(hipGetLastError());
+    return LP_OK;
+}
+
 // rho, A_hat (CSR, CSC; FP32 copies in mixed mode) for D = diag(d) (d NULL: D = I), and
 // the Cimmino step 1/lambda when it is not fixed by the options
 lp_status build_scaling(lp_problem* p, const double* d_dev) {
@@ -39,6 +80,11 @@ lp_status build_scaling(lp_problem* p, const double* d_dev) {
     const bool cim = p->opt.inner == LP_CIMMINO;
     scale_rows(st, p->g_csr, (int)p->m, p->rp, p->ci, p->a, d_dev, p->rho, p->ah, mixed ? p->ah32 : nullptr);
     scale_cols(st, (int)p->n, p->cp, p->ri, p->ac, d_dev, p->rho, p->ahc, (mixed && cim) ? p->ahc32 : nullptr);
+    // dense path: the CSR values of a dense A are A_hat row-major; G = A_hat A_hat^T
+    if (p->gsor) {
+        lp_status rc = build_dense_preconditioner(p);
+        if (rc != LP_OK) return rc;
+    }
     LPK_HIP(hipGetLastError());
     if (cim) {
         if (p->opt.omega_c > 0.0) {
@@ -74,7 +120,22 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
     const int32_t* skip = &p->ctl->done;
     const int ell = std::max(1, (int)p->opt.inner_sweeps);
     const double sv = mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
-    if (p->opt.inner == LP_CIMMINO) {
+    if (p->gsor) {
+        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, p->ctl);
+        {
+            // l SOR sweeps on G p = v_k, applied as p = C<l> v_k
+            Prof pr(p, LP_K_SWEEP, it, (double)m * m * sv + 16.0 * m);
+            if (mixed)
+                apply_c_f32(st, (int)m, p->C32, p->V, p->P, ldv, p->ctl);
+            else
+                apply_c_f64(st, (int)m, p->Capply, p->V, p->P, ldv, p->ctl);
+        }
+        {
+            // u = A_hat A_hat^T p_k = G p_k
+            Prof pr(p, LP_K_SPMV_CSR, it, 8.0 * m * m + 16.0 * m);
+            gemv_col(st, (int)m, p->G, p->P, ldv, p->u, p->ctl);
+        }
+    } else if (p->opt.inner == LP_CIMMINO) {
         krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, p->ctl);
         for (int sw = 0; sw < ell; ++sw) {
             const int first = sw == 0;
@@ -113,12 +174,12 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
             }
         }
     }
-    // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k
-    {
+    // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k (dense path: u = G p_k above)
+    if (!p->gsor) {
         Prof pr(p, LP_K_SPMV_CSC, it, nnz * 12.0 + m * 8.0 + n * 8.0 + (n + 1) * 4.0);
         spmv_f64_col(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->P, ldv, p->z64, p->ctl);
     }
-    {
+    if (!p->gsor) {
         Prof pr(p, LP_K_SPMV_CSR, it, nnz * 12.0 + n * 8.0 + m * 8.0 + (m + 1) * 4.0);
         spmv_f64(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->u, EPI_PLAIN, nullptr, nullptr, skip);
     }

@@ -67,6 +67,7 @@ struct ProfRec {
     int64_t solve;      // which Krylov solve it belongs to
     int64_t iter;       // host-side iteration index inside that solve (-1: not a loop kernel)
     double bytes;
+    double flops;
     hipEvent_t a, b;
 };
 
@@ -78,6 +79,11 @@ struct lp_problem {
     hipStream_t st = nullptr;
     int device = 0;
     bool dense = false;
+    bool gsor = false;                              // dense: SOR on the Gram matrix
+    double* G = nullptr;                            // m x m Gram matrix A_hat A_hat^T
+    double *Xinv = nullptr, *Tmat = nullptr, *Tmat2 = nullptr, *Cmat = nullptr, *Rblk = nullptr;
+    const double* Capply = nullptr;                 // the preconditioner matrix C<l>
+    float* C32 = nullptr;
 
     // host-side structure
     std::vector<int32_t> perm;        // permuted row t is original row perm[t]
@@ -134,7 +140,7 @@ struct lp_problem {
     std::vector<hipEvent_t> prof_pool;
     std::vector<int64_t> solve_iters;               // iterations of each profiled solve
     int64_t prof_launch[LP_K_COUNT] = {0};
-    double prof_ms[LP_K_COUNT] = {0}, prof_bytes[LP_K_COUNT] = {0};
+    double prof_ms[LP_K_COUNT] = {0}, prof_bytes[LP_K_COUNT] = {0}, prof_flops[LP_K_COUNT] = {0};
 };
 
 namespace lpk {
@@ -154,7 +160,7 @@ lp_status sync_read(lp_problem* p, const double* dev, double* host, int count);
 struct Prof {
     lp_problem* p;
     int idx = -1;
-    Prof(lp_problem* pp, int cls, int64_t iter, double bytes);
+    Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops = 0.0);
     ~Prof();
 };
 lp_status prof_collect(lp_problem* p);

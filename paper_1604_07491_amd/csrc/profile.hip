@@ -9,7 +9,7 @@
 
 namespace lpk {
 
-static const char* kClassName[LP_K_COUNT] = {"sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update"};
+static const char* kClassName[LP_K_COUNT] = {"sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update", "gram"};
 
 static hipEvent_t take_event(lp_problem* p) {
     if (!p->prof_pool.empty()) {
@@ -22,13 +22,14 @@ static hipEvent_t take_event(lp_problem* p) {
     return e;
 }
 
-Prof::Prof(lp_problem* pp, int cls, int64_t iter, double bytes) : p(pp) {
+Prof::Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops) : p(pp) {
     if (!(p->prof_mask & (1u << cls))) return;
     ProfRec r;
     r.cls = cls;
     r.solve = p->solve_id;
     r.iter = iter;
     r.bytes = bytes;
+    r.flops = flops;
     r.a = take_event(p);
     r.b = take_event(p);
     if (!r.a || !r.b) return;
@@ -56,6 +57,7 @@ lp_status prof_collect(lp_problem* p) {
                 p->prof_launch[r.cls] += 1;
                 p->prof_ms[r.cls] += ms;
                 p->prof_bytes[r.cls] += r.bytes;
+                p->prof_flops[r.cls] += r.flops;
             }
         }
         p->prof_pool.push_back(r.a);
@@ -92,6 +94,7 @@ lp_status lp_profile(lp_problem* p, uint32_t mask) {
         p->prof_launch[c] = 0;
         p->prof_ms[c] = 0.0;
         p->prof_bytes[c] = 0.0;
+        p->prof_flops[c] = 0.0;
     }
     return LP_OK;
 }
@@ -107,6 +110,7 @@ lp_status lp_profile_read(lp_problem* p, lp_kernel_stat* st, int32_t cap, int32_
         st[c].launches = p->prof_launch[c];
         st[c].ms_total = p->prof_ms[c];
         st[c].bytes_total = p->prof_bytes[c];
+        st[c].flops_total = p->prof_flops[c];
         strncpy(st[c].name, kClassName[c], sizeof(st[c].name) - 1);
     }
     return LP_OK;

@@ -158,3 +158,68 @@ def test_errors_on_device():
             lpk.direction_solve(p, None, lp.b, 1e-8)   # no iterate yet
         r = lpk.lp_solve(lpk.from_lp(lp, lpk.options(ipm_max_iter=2)))
         assert r["status"] == lpk.LP_NOT_CONVERGED
+
+
+# ------------------------------------------------------------------ dense (Gram) path
+def _dense_case(m, N, k, seed):
+    return synth.basis_pursuit_lp(m, N, k, seed=seed)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(40, 150), (150, 350), (64, 200)])
+@pytest.mark.parametrize("k", [1, 5, 12])
+def test_dense_gram_direction_solve_fixed_iterations(shape, k, precision):
+    """SOR on G = A_hat A_hat^T (MFMA Gram, blocked single-workgroup sweep, ragged last
+    block) against the oracle's NE-SOR in natural row order at a fixed iteration count."""
+    m, N = shape
+    lp = _dense_case(m, N, 3, seed=m + N)
+    d, f = _dir_problem(lp, k)
+    print(f"dense {m}x{2 * N} k={k} {precision}", flush=True)
+    with lpk.lp_create_dense(lp.dense, lp.b, lp.c, lpk.options(krylov_max_iter=k, precision=precision)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
+    odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, order=oracle.ORDER_NATURAL))
+    assert info["iters"] == oinfo["iters"]
+    tol = 1e-9 if precision == "fp64" else 2e-4
+    assert _rel(dw, odw) <= tol
+    AD = lp.dense * d
+    assert _rel(AD.T @ np.asarray(dy), AD.T @ ody) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dense_gram_converged_min_norm(precision):
+    lp = _dense_case(150, 350, 3, seed=9)
+    d, f = _dir_problem(lp, 2)
+    with lpk.lp_create_dense(lp.dense, lp.b, lp.c, lpk.options(precision=precision)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
+    ref = np.linalg.pinv(lp.dense * d) @ f
+    assert not info["failed"] and _rel(dw, ref) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dense_lp_solve_vs_oracle(precision):
+    lp = _dense_case(128, 1024, 8, seed=3)
+    o = oracle.ipm(lp, oracle.ipm_opts(solver=oracle.solver_opts(order=oracle.ORDER_NATURAL)))
+    with lpk.lp_create_dense(lp.dense, lp.b, lp.c, lpk.options(precision=precision)) as p:
+        r = lpk.lp_solve(p)
+    print(f"dense lp {precision}: iters {r['iters']} krylov {r['krylov_iters']} {r['seconds']:.3f}s "
+          f"pobj {r['pobj']!r} oracle {o['pobj']!r}", flush=True)
+    assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
+    assert abs(r["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+    assert abs(r["pobj"] - lp.meta["k"]) <= 1e-7 * lp.meta["k"]     # ||x_true||_1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config2_basis_pursuit_full_size(precision):
+    """1024 x 16384 basis pursuit at full size: the optimum is ||x_true||_1 = 64 (closed
+    form); the recovered signal is x_true."""
+    lp = synth.config(2)
+    with lpk.lp_create_dense(lp.dense, lp.b, lp.c, lpk.options(precision=precision)) as p:
+        r = lpk.lp_solve(p)
+        x, y, s, _ = lpk.lp_get_state(p)
+    print(f"config 2 {precision}: iters {r['iters']} krylov {r['krylov_iters']} {r['seconds']:.3f}s "
+          f"pobj {r['pobj']!r} gamma_rel {r['gamma_rel']:.2e}", flush=True)
+    assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
+    assert abs(r["pobj"] - 64.0) <= 1e-7 * 64.0
+    N = lp.meta["N"]
+    xr = np.asarray(x)[:N] - np.asarray(x)[N:]
+    assert np.abs(xr - lp.meta["x_true"]).max() < 1e-5
