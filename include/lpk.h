@@ -229,6 +229,19 @@ lp_status lp_profile(lp_problem* p, uint32_t mask);
  * entries into st; the count in *n_out).  Synchronises the stream.                    */
 lp_status lp_profile_read(lp_problem* p, lp_kernel_stat* st, int32_t cap, int32_t* n_out);
 
+/* Mean duration of one launch of kernel class cls (LP_K_SWEEP: one application of the
+ * inner-iteration preconditioner; LP_K_SPMV_CSR / LP_K_SPMV_CSC: the Krylov loop's two
+ * products; LP_K_GRAM: the dense path's Gram and preconditioner build, timed per launch
+ * of its kernels), from `reps` back-to-back replays of its launches captured with the
+ * current A_hat, between two HIP events on the problem's stream.  Also returns the
+ * algorithmic bytes and flops per launch (as in lp_kernel_stat) and the launches in one
+ * group (e.g. colours x sweeps).  Needs a scaling: run ipm_step, lp_solve or
+ * direction_solve first.  Overwrites column 0 of the Krylov workspace.
+ * Errors: LP_EINVAL, LP_EDEVICE.                                                        */
+lp_status lp_time_kernel(lp_problem* p, int32_t cls, int32_t reps, double* us_per_launch,
+                         double* bytes_per_launch, double* flops_per_launch,
+                         int32_t* launches_per_group);
+
 /* Human-readable name of a status code (static storage).                               */
 const char* lp_status_str(lp_status s);
 

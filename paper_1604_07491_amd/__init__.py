@@ -79,7 +79,19 @@ class Result(C.Structure):
                [("krylov_iters", C.c_int64), ("seconds", C.c_double)]
 
 
-# every entry point declared in include/lpk.h, with its ctypes signature
+class ServerOptions(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_skip", C.c_int32), ("hbm_budget", C.c_uint64),
+                ("solver", Options)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("iters", C.c_int32),
+                ("pobj", C.c_double), ("dobj", C.c_double), ("gamma_rel", C.c_double),
+                ("krylov_iters", C.c_int64), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("footprint", C.c_uint64)]
+
+
+# every entry point declared in include/lpk.h and include/lpk_server.h, with its signature
 _P = C.c_void_p
 SIGNATURES = {
     "lp_options_default": (C.c_int, [C.POINTER(Options)]),
@@ -100,6 +112,18 @@ SIGNATURES = {
     "lp_colour_rows": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
     "lp_profile": (C.c_int, [_P, C.c_uint32]),
     "lp_profile_read": (C.c_int, [_P, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
+    "lp_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.POINTER(Result)]),
+    "lp_server_options_default": (C.c_int, [C.POINTER(ServerOptions)]),
+    "lp_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(C.c_void_p)]),
+    "lp_server_submit": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P, _P,
+                                   C.POINTER(C.c_uint64)]),
+    "lp_server_poll": (C.c_int, [_P, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)]),
+    "lp_server_wait": (C.c_int, [_P, C.c_int32, C.c_double]),
+    "lp_server_result": (C.c_int, [_P, C.c_uint64, _P, _P, _P]),
+    "lp_server_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lp_server_destroy": (C.c_int, [_P]),
+    "lp_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "lp_status_str": (C.c_char_p, [C.c_int]),
     "lp_last_error": (C.c_char_p, []),
     "lp_version": (C.c_char_p, []),
@@ -352,3 +376,76 @@ def lp_profile_read(p: Problem):
     return {arr[i].name.decode(): dict(launches=arr[i].launches, ms_total=arr[i].ms_total,
                                        bytes_total=arr[i].bytes_total, flops_total=arr[i].flops_total)
             for i in range(n.value)}
+
+
+def lp_solve_batch(problems, workers: int):
+    """Solve created problems concurrently (one thread and HIP stream per worker)."""
+    arr = (C.c_void_p * len(problems))(*[p.h.value for p in problems])
+    res = (Result * max(1, len(problems)))()
+    _check(lib().lp_solve_batch(arr, len(problems), int(workers), res), "lp_solve_batch")
+    return [_dict(res[i]) for i in range(len(problems))]
+
+
+class Server:
+    """The request server of include/lpk_server.h (continuous admission by HBM footprint)."""
+
+    def __init__(self, slots=8, max_skip=8, hbm_budget=0, solver: Optional[Options] = None, **kw):
+        o = ServerOptions()
+        lib().lp_server_options_default(C.byref(o))
+        o.slots, o.max_skip, o.hbm_budget = int(slots), int(max_skip), int(hbm_budget)
+        o.solver = solver if solver is not None else options(**kw)
+        h = C.c_void_p(None)
+        _check(lib().lp_server_create(C.byref(o), C.byref(h)), "lp_server_create")
+        self.h = h
+        self.sizes = {}
+
+    def submit(self, lp) -> int:
+        t = C.c_uint64(0)
+        arrs = [np.ascontiguousarray(lp.row_ptr, np.int64), np.ascontiguousarray(lp.col_idx, np.int32),
+                np.ascontiguousarray(lp.val, np.float64), np.ascontiguousarray(lp.b, np.float64),
+                np.ascontiguousarray(lp.c, np.float64)]
+        _check(lib().lp_server_submit(self.h, lp.m, lp.n, int(arrs[0][-1]), *[a.ctypes.data for a in arrs],
+                                      C.byref(t)), "lp_server_submit")
+        self.sizes[t.value] = (lp.m, lp.n)
+        return t.value
+
+    def wait(self, count: int, timeout: float = 600.0) -> bool:
+        return lib().lp_server_wait(self.h, int(count), float(timeout)) == LP_OK
+
+    def poll(self, cap: int = 4096):
+        arr = (Completion * cap)()
+        n = C.c_int32(0)
+        _check(lib().lp_server_poll(self.h, arr, cap, C.byref(n)), "lp_server_poll")
+        return [_dict(arr[i]) for i in range(n.value)]
+
+    def result(self, ticket: int):
+        m, n = self.sizes[ticket]
+        x, y, s = np.zeros(n), np.zeros(m), np.zeros(n)
+        _check(lib().lp_server_result(self.h, C.c_uint64(ticket), x.ctypes.data, y.ctypes.data, s.ctypes.data),
+               "lp_server_result")
+        return x, y, s
+
+    def stats(self):
+        b, q, r = C.c_uint64(0), C.c_int32(0), C.c_int32(0)
+        _check(lib().lp_server_stats(self.h, C.byref(b), C.byref(q), C.byref(r)), "lp_server_stats")
+        return dict(bytes_in_use=b.value, queued=q.value, running=r.value)
+
+    def close(self):
+        if self.h:
+            lib().lp_server_destroy(self.h)
+            self.h = C.c_void_p(None)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def lp_time_kernel(p: Problem, cls: int, reps: int = 200):
+    """Replay-timed mean launch duration (us) and algorithmic bytes/flops per launch."""
+    us, by, fl, nl = C.c_double(0), C.c_double(0), C.c_double(0), C.c_int32(0)
+    _check(lib().lp_time_kernel(p.h, int(cls), int(reps), C.byref(us), C.byref(by), C.byref(fl), C.byref(nl)),
+           "lp_time_kernel")
+    return dict(us_per_launch=us.value, bytes_per_launch=by.value, flops_per_launch=fl.value,
+                launches_per_group=nl.value)

@@ -45,7 +45,7 @@ struct Sizes {
     }
 };
 
-static uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
+uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
     const bool mixed = o.precision == LP_MIXED;
     const int64_t kmax = plan_kmax(m, o);
@@ -64,6 +64,7 @@ static uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o
     if (gs_fusable(gs, kmax)) z.add((int64_t)gs.nchunks * (kmax + 1), 8);
     z.add(m / 4 + 8, 8);
     z.add(8 * 1024, 8); z.add(8, 8);
+    z.add(1, sizeof(KrylovCtl));
     z.add(1, sizeof(KrylovCtl));
     return z.bytes;
 }
@@ -99,6 +100,14 @@ static lp_status check_vec(const double* v, int64_t len, const char* name) {
     for (int64_t i = 0; i < len; ++i)
         if (!std::isfinite(v[i])) return fail(LP_ENONFINITE, std::string("non-finite entry in ") + name);
     return LP_OK;
+}
+
+lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                          const double* val, const double* b, const double* c) {
+    lp_status rc = validate(m, n, nnz, rp, ci, val);
+    if (rc != LP_OK) return rc;
+    if ((rc = check_vec(b, m, "b")) != LP_OK) return rc;
+    return check_vec(c, n, "c");
 }
 
 static lp_status check_device() {
@@ -236,6 +245,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->red.part = A.alloc<double>(8 * 1024);
     p->red.out = A.alloc<double>(8);
     p->ctl = A.alloc<KrylovCtl>(1);
+    p->tctl = A.alloc<KrylovCtl>(1);
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);
         p->Xinv = A.alloc<double>(m * m);

@@ -110,33 +110,28 @@ lp_status build_scaling(lp_problem* p, const double* d_dev) {
     return LP_OK;
 }
 
-// enqueue Krylov iteration `it` of the current solve (every kernel returns at once once
-// ctl->done is set).  Each launch carries its algorithmic bytes for the profiler: every
-// input and output it must move, each once.
-static void enqueue_iteration(lp_problem* p, int64_t it) {
+// enqueue one application of the inner-iteration preconditioner to column k of V (k and
+// the done flag from ctl), with the start-of-iteration preparation when with_prep.  Each
+// launch carries its algorithmic bytes for the profiler: every input and output it must
+// move, each once.
+void enqueue_precond(lp_problem* p, KrylovCtl* ctl, int64_t it, bool with_prep) {
     hipStream_t st = p->st;
     const bool mixed = p->opt.precision == LP_MIXED;
     const int64_t m = p->m, n = p->n, ldv = p->ldv, nnz = p->nnz;
-    const int32_t* skip = &p->ctl->done;
     const int ell = std::max(1, (int)p->opt.inner_sweeps);
     const double sv = mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
     if (p->gsor) {
-        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, p->ctl);
+        if (with_prep) krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, ctl);
         {
             // l SOR sweeps on G p = v_k, applied as p = C<l> v_k
             Prof pr(p, LP_K_SWEEP, it, (double)m * m * sv + 16.0 * m);
             if (mixed)
-                apply_c_f32(st, (int)m, p->C32, p->V, p->P, ldv, p->ctl);
+                apply_c_f32(st, (int)m, p->C32, p->V, p->P, ldv, ctl);
             else
-                apply_c_f64(st, (int)m, p->Capply, p->V, p->P, ldv, p->ctl);
-        }
-        {
-            // u = A_hat A_hat^T p_k = G p_k
-            Prof pr(p, LP_K_SPMV_CSR, it, 8.0 * m * m + 16.0 * m);
-            gemv_col(st, (int)m, p->G, p->P, ldv, p->u, p->ctl);
+                apply_c_f64(st, (int)m, p->Capply, p->V, p->P, ldv, ctl);
         }
     } else if (p->opt.inner == LP_CIMMINO) {
-        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, p->ctl);
+        if (with_prep) krylov_prep(st, m, n, p->V, p->u, p->P, ldv, nullptr, nullptr, ctl);
         for (int sw = 0; sw < ell; ++sw) {
             const int first = sw == 0;
             {
@@ -144,21 +139,21 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
                                         : nnz * (sv + 4.0) + n * sv + m * (4.0 + 8.0 + sv + 16.0);
                 Prof pr(p, LP_K_SWEEP, it, by);
                 if (mixed)
-                    cimmino_residual_f32(st, p->g_csr, (int)m, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->omega_c, p->r32, first, p->ctl);
+                    cimmino_residual_f32(st, p->g_csr, (int)m, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->omega_c, p->r32, first, ctl);
                 else
-                    cimmino_residual_f64(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->omega_c, p->r64, first, p->ctl);
+                    cimmino_residual_f64(st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->omega_c, p->r64, first, ctl);
             }
             if (sw + 1 < ell) {
                 const double by = nnz * (sv + 4.0) + m * sv + n * (4.0 + sv * (first ? 1.0 : 2.0));
                 Prof pr(p, LP_K_SWEEP, it, by);
                 if (mixed)
-                    cimmino_zupdate_f32(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc32, p->r32, p->z32, p->omega_c, first, p->ctl);
+                    cimmino_zupdate_f32(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc32, p->r32, p->z32, p->omega_c, first, ctl);
                 else
-                    cimmino_zupdate_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->r64, p->z64, p->omega_c, first, p->ctl);
+                    cimmino_zupdate_f64(st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->r64, p->z64, p->omega_c, first, ctl);
             }
         }
     } else {
-        krylov_prep(st, m, n, p->V, p->u, p->P, ldv, mixed ? nullptr : p->z64, mixed ? p->z32 : nullptr, p->ctl);
+        if (with_prep) krylov_prep(st, m, n, p->V, p->u, p->P, ldv, mixed ? nullptr : p->z64, mixed ? p->z32 : nullptr, ctl);
         const int nc = (int)p->colours.size();
         for (int sw = 0; sw < ell; ++sw) {
             for (int c = 0; c < nc; ++c) {
@@ -168,11 +163,25 @@ static void enqueue_iteration(lp_problem* p, int64_t it) {
                                   (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
                 Prof pr(p, LP_K_SWEEP, it, by);
                 if (mixed)
-                    nesor_colour_f32(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->opt.omega, p->ctl, wz);
+                    nesor_colour_f32(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah32, p->z32, p->V, p->P, ldv, p->opt.omega, ctl, wz);
                 else
-                    nesor_colour_f64(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->opt.omega, p->ctl, wz);
+                    nesor_colour_f64(st, cl.g, cl.r0, cl.r1, p->rp, p->ci, p->ah, p->z64, p->V, p->P, ldv, p->opt.omega, ctl, wz);
             }
         }
+    }
+}
+
+// enqueue Krylov iteration `it` of the current solve (every kernel returns at once once
+// ctl->done is set)
+static void enqueue_iteration(lp_problem* p, int64_t it) {
+    hipStream_t st = p->st;
+    const int64_t m = p->m, n = p->n, ldv = p->ldv, nnz = p->nnz;
+    const int32_t* skip = &p->ctl->done;
+    enqueue_precond(p, p->ctl, it, true);
+    if (p->gsor) {
+        // u = A_hat A_hat^T p_k = G p_k
+        Prof pr(p, LP_K_SPMV_CSR, it, 8.0 * m * m + 16.0 * m);
+        gemv_col(st, (int)m, p->G, p->P, ldv, p->u, p->ctl);
     }
     // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k (dense path: u = G p_k above)
     if (!p->gsor) {
@@ -300,3 +309,100 @@ lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* d
 }
 
 }  // namespace lpk
+
+using namespace lpk;
+
+// ------------------------------------------------------------------------------------
+// Timing replay: the launches of one kernel class, captured once with a control block at
+// k = 0 and replayed back-to-back between two events on the problem's stream.
+extern "C" lp_status lp_time_kernel(lp_problem* p, int32_t cls, int32_t reps, double* us_per_launch,
+                                    double* bytes_per_launch, double* flops_per_launch,
+                                    int32_t* launches_per_group) {
+    if (!p || reps < 1 || !us_per_launch) return LP_EINVAL;
+    if (!p->have_point) {
+        set_error("no scaling yet: run ipm_step, lp_solve or direction_solve first");
+        return LP_EINVAL;
+    }
+    if (cls == LP_K_GRAM && !p->gsor) {
+        set_error("no dense Gram path for this problem");
+        return LP_EINVAL;
+    }
+    if (cls != LP_K_SWEEP && cls != LP_K_SPMV_CSR && cls != LP_K_SPMV_CSC && cls != LP_K_GRAM) {
+        set_error("timing replay covers the sweep, the two sparse products and the Gram build");
+        return LP_EINVAL;
+    }
+    hipStream_t st = p->st;
+    // control block for the replay: k = 0, not done, the current Cimmino step
+    KrylovCtl t{};
+    t.kmax = 1;
+    t.omega_c = p->omega_c;
+    *p->host_ctl = t;
+    LPK_HIP(hipMemcpyAsync(p->tctl, p->host_ctl, sizeof(KrylovCtl), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    if (!p->cap_st) LPK_HIP(hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
+    const uint32_t mask = p->prof_mask;
+    p->prof_mask = 0;
+    double bytes = 0.0, flops = 0.0;
+    int64_t launches = 0;
+    p->count_bytes = &bytes;
+    p->count_flops = &flops;
+    p->count_launch = &launches;
+    p->count_cls = cls;
+    hipStream_t keep = p->st;
+    p->st = p->cap_st;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const int64_t m = p->m, n = p->n, nnz = p->nnz;
+        if (cls == LP_K_SWEEP) {
+            enqueue_precond(p, p->tctl, -1, false);
+        } else if (cls == LP_K_SPMV_CSC) {
+            Prof pr(p, LP_K_SPMV_CSC, -1, nnz * 12.0 + m * 8.0 + n * 8.0 + (n + 1) * 4.0);
+            spmv_f64_col(p->st, p->g_csc, (int)n, p->cp, p->ri, p->ahc, p->P, p->ldv, p->z64, p->tctl);
+        } else if (cls == LP_K_SPMV_CSR) {
+            if (p->gsor) {
+                Prof pr(p, LP_K_SPMV_CSR, -1, 8.0 * m * m + 16.0 * m);
+                gemv_col(p->st, (int)m, p->G, p->P, p->ldv, p->u, p->tctl);
+            } else {
+                Prof pr(p, LP_K_SPMV_CSR, -1, nnz * 12.0 + n * 8.0 + m * 8.0 + (m + 1) * 4.0);
+                spmv_f64(p->st, p->g_csr, (int)m, p->rp, p->ci, p->ah, p->z64, p->u, EPI_PLAIN, nullptr, nullptr,
+                         &p->tctl->done);
+            }
+        } else {
+            (void)build_dense_preconditioner(p);
+        }
+        e = hipStreamEndCapture(p->cap_st, &g);
+    }
+    p->st = keep;
+    p->prof_mask = mask;
+    p->count_bytes = nullptr;
+    p->count_flops = nullptr;
+    p->count_launch = nullptr;
+    if (e != hipSuccess) return hip_fail(e, "timing capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "timing graph instantiate");
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    LPK_HIP(hipEventCreate(&a));
+    LPK_HIP(hipEventCreate(&b));
+    LPK_HIP(hipGraphLaunch(ex, st));   // warm
+    LPK_HIP(hipEventRecord(a, st));
+    for (int32_t r = 0; r < reps; ++r) LPK_HIP(hipGraphLaunch(ex, st));
+    LPK_HIP(hipEventRecord(b, st));
+    LPK_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    LPK_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    const double per = launches > 0 ? (double)launches : 1.0;
+    *us_per_launch = (double)ms * 1e3 / ((double)reps * per);
+    if (bytes_per_launch) *bytes_per_launch = bytes / per;
+    if (flops_per_launch) *flops_per_launch = flops / per;
+    if (launches_per_group) *launches_per_group = (int32_t)launches;
+    return LP_OK;
+}

@@ -26,6 +26,12 @@ lp_status hip_fail(hipError_t e, const char* what);
 int32_t greedy_colour(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci,
                       int32_t* colour, int32_t* perm);
 
+// device bytes lp_create allocates for these sizes and options
+uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o);
+// host validation of lp_create's inputs (no device call)
+lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                          const double* val, const double* b, const double* c);
+
 // lanes per row for a row-dot over rows of mean length len
 int lanes_for(double len);
 
@@ -135,6 +141,11 @@ struct lp_problem {
     int64_t last_iters = 0;                         // hint for the polling period
     // profiler
     uint32_t prof_mask = 0;
+    lpk::KrylovCtl* tctl = nullptr;                 // control block of timing replays
+    double* count_bytes = nullptr;                  // host-side accounting of one capture
+    double* count_flops = nullptr;
+    int64_t* count_launch = nullptr;
+    int count_cls = -1;
     int64_t solve_id = 0;
     std::vector<lpk::ProfRec> prof_recs;
     std::vector<hipEvent_t> prof_pool;

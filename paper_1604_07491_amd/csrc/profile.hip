@@ -23,6 +23,11 @@ static hipEvent_t take_event(lp_problem* p) {
 }
 
 Prof::Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops) : p(pp) {
+    if (p->count_launch && cls == p->count_cls) {
+        *p->count_launch += 1;
+        *p->count_bytes += bytes;
+        *p->count_flops += flops;
+    }
     if (!(p->prof_mask & (1u << cls))) return;
     ProfRec r;
     r.cls = cls;

@@ -1,0 +1,85 @@
+"""Concurrent solves and the request server (GPU).
+
+Every solve's arithmetic is independent of what else runs on the device, so a result must
+be bitwise identical alone and in the concurrent mix.  Admission must keep the summed
+footprint of running requests within the budget, reject requests that can never fit, and
+still complete every accepted request."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1604_07491_amd as lpk
+from paper_1604_07491_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(count, seed0=50):
+    lps = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        mb = int(rng.integers(60, 240))
+        lps.append(synth.sparse_lp(mb, int(mb * rng.uniform(2.0, 3.0)), int(rng.integers(4, 8)), 2, seed=seed0 + i))
+    return lps
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_results_identical_alone_and_in_mix(precision):
+    lps = _mix(6)
+    alone = []
+    for lp in lps:
+        with lpk.from_lp(lp, lpk.options(precision=precision)) as p:
+            r = lpk.lp_solve(p)
+            alone.append((r, lpk.lp_get_state(p)[:3]))
+    probs = [lpk.from_lp(lp, lpk.options(precision=precision)) for lp in lps]
+    res = lpk.lp_solve_batch(probs, workers=3)
+    for i, p in enumerate(probs):
+        x, y, s, _ = lpk.lp_get_state(p)
+        r0, (x0, y0, s0) = alone[i]
+        assert res[i]["status"] == lpk.LP_OK and res[i]["iters"] == r0["iters"]
+        assert res[i]["krylov_iters"] == r0["krylov_iters"]
+        assert np.array_equal(x, x0) and np.array_equal(y, y0) and np.array_equal(s, s0)
+        p.close()
+    # and each agrees with the oracle's optimum
+    for lp, (r0, _) in zip(lps[:3], alone[:3]):
+        o = oracle.ipm(lp)
+        assert abs(r0["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+
+
+def test_server_admission_and_results():
+    lps = _mix(10, seed0=80)
+    alone = {}
+    for i, lp in enumerate(lps[:4]):
+        with lpk.from_lp(lp) as p:
+            lpk.lp_solve(p)
+            alone[i] = lpk.lp_get_state(p)[0]
+    fps = [lpk.lp_footprint_bytes(lp.m, lp.n, lp.nnz) for lp in lps]
+    budget = int(2.5 * max(fps))          # at most two or three resident at once
+    big = synth.sparse_lp(1500, 3500, 6, 2, seed=7)   # never fits this budget
+    assert lpk.lp_footprint_bytes(big.m, big.n, big.nnz) > budget
+    with lpk.Server(slots=4, max_skip=2, hbm_budget=budget) as srv:
+        tickets = [srv.submit(lp) for lp in lps]
+        tbig = srv.submit(big)
+        bad = lps[0]
+        with pytest.raises(lpk.LpError):
+            rp = bad.row_ptr.copy(); rp[3] = rp[2]
+            srv.submit(synth.LP(bad.m, bad.n, rp, bad.col_idx, bad.val, bad.b, bad.c))
+        assert srv.wait(len(tickets) + 1, 300.0)
+        done = {c["ticket"]: c for c in srv.poll()}
+        assert set(done) == set(tickets) | {tbig}
+        assert done[tbig]["status"] == lpk.LP_ETOOBIG
+        for t in tickets:
+            assert done[t]["status"] == lpk.LP_OK and done[t]["gamma_rel"] <= 1e-8
+        # the running set never exceeded the budget
+        ev = sorted([(done[t]["t_start"], done[t]["footprint"]) for t in tickets] +
+                    [(done[t]["t_done"], -done[t]["footprint"]) for t in tickets], key=lambda e: (e[0], e[1]))
+        cur = peak = 0
+        for _, f in ev:
+            cur += f
+            peak = max(peak, cur)
+        assert peak <= budget
+        for i in range(4):
+            x, y, s = srv.result(tickets[i])
+            assert np.array_equal(x, alone[i])
+        with pytest.raises(lpk.LpError):
+            srv.result(tickets[0])      # released after the first fetch
