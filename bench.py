@@ -1,16 +1,19 @@
 """Benchmark: interior-point LP solves per second on one MI355X.
 
-One step solves a batch of B LPs of the workload's shape (distinct seeds; the first is
-the workload LP itself) to a relative duality gap of 1e-8, with W solves in flight (one
-worker thread and HIP stream each; their kernels overlap on the device).  Inputs are
-created on the device before the timed region (torch tensors handed to lp_create), so
-`value` excludes host-to-device copies.  Prints one JSON line:
+One step solves B LPs of the workload's shape (distinct seeds; the first is the workload
+LP itself) to a relative duality gap of 1e-8, up to W of them in lockstep (lp_solve_batch:
+each phase of an interior-point iteration is one launch for the whole batch; a finished
+LP leaves and a waiting one joins).  Inputs are created on the device before the timed
+region (torch tensors handed to lp_create), so `value` excludes host-to-device copies.
+Prints one JSON line:
 
   value         LPs solved per second over the K timed steps (all B x K solves)
-  p50_ms/p99_ms per-solve latency inside the timed steps (wall time of each lp_solve)
-  roofline      the dominant kernel class of a profiled solve, timed by lp_time_kernel:
-                its launches replayed back-to-back between two HIP events on the
-                library's stream; achieved = algorithmic bytes per launch / mean duration
+  p50_ms/p99_ms per-LP latency inside the timed steps (joining the batch to leaving it)
+  roofline      the dominant kernel class of a profiled solve, timed for the batch as it
+                runs (lp_time_batch_kernel: one launch covers all W LPs) by replaying its
+                launches back-to-back between two HIP events on the library's stream;
+                achieved = algorithmic bytes per launch (summed over the W LPs) / mean
+                launch duration
   cpu_baseline  the CPU FP64 oracle on the workload LP (one full solve, one core)
 """
 import argparse
@@ -48,7 +51,7 @@ def main():
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
                              "sparse_120000x434580"])
     ap.add_argument("--batch", type=int, default=32, help="LPs per step")
-    ap.add_argument("--workers", type=int, default=4, help="solves in flight")
+    ap.add_argument("--width", type=int, default=32, help="LPs in lockstep")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "cimmino"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -57,9 +60,6 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    # one hardware queue per stream in flight (HIP's default is 4), set before HIP starts
-    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.workers)))
-
     import numpy as np
     import torch
 
@@ -80,12 +80,12 @@ def main():
     print(f"created {len(probs)} LPs of {args.workload}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        lpk.lp_solve_batch(probs, args.workers)
+        lpk.lp_solve_batch(probs, args.width)
     torch.cuda.synchronize()
     lat, res = [], []
     t0 = time.perf_counter()
     for step in range(args.steps):
-        out = lpk.lp_solve_batch(probs, args.workers)
+        out = lpk.lp_solve_batch(probs, args.width)
         res += out
         lat += [r["seconds"] for r in out]
         print(f"step {step} done", file=sys.stderr, flush=True)
@@ -106,15 +106,21 @@ def main():
               "gram": lpk.LP_K_GRAM}
     timed = {k: v for k, v in stats.items() if k in cls_id and v["launches"] > 0}
     dom = max(timed, key=lambda k: timed[k]["ms_total"])
-    tk = lpk.lp_time_kernel(p0, cls_id[dom], reps=200 if dom != "gram" else 5)
+    # the dominant class for the batch as it runs in the timed steps
+    width = min(args.width, len(probs))
+    tk = lpk.lp_time_batch_kernel(probs[:width], cls_id[dom], reps=200 if dom != "gram" else 5)
     achieved = tk["bytes_per_launch"] / (tk["us_per_launch"] * 1e-6) / 1e9
+    t1 = lpk.lp_time_kernel(p0, cls_id[dom], reps=200 if dom != "gram" else 5)
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         traffic = json.load(open(args.traffic)).get(args.workload, {}).get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "us_per_launch": tk["us_per_launch"],
                 "bytes_per_launch": tk["bytes_per_launch"], "launches_per_group": tk["launches_per_group"],
-                "timing": "lp_time_kernel replay, 200 x group, HIP events on the library stream"}
+                "lps_per_launch": width,
+                "timing": "lp_time_batch_kernel replay, 200 x group, HIP events on the library stream",
+                "single_lp": {"us_per_launch": t1["us_per_launch"], "bytes_per_launch": t1["bytes_per_launch"],
+                              "achieved": t1["bytes_per_launch"] / (t1["us_per_launch"] * 1e-6) / 1e9}}
     extra = {}
     if "gram" in timed:
         tg = lpk.lp_time_kernel(p0, lpk.LP_K_GRAM, reps=5)
@@ -155,7 +161,7 @@ def main():
         "krylov_iters": r0["krylov_iters"],
         "gamma_rel": r0["gamma_rel"],
         "config": {"workload": args.workload, "m": lps[0].m, "n": lps[0].n, "nnz": lps[0].nnz,
-                   "lps_per_step": len(probs), "solves_in_flight": args.workers,
+                   "lps_per_step": len(probs), "lps_in_lockstep": args.width,
                    "precision": args.precision, "inner": args.inner, "krylov": "AB-GMRES",
                    "inner_sweeps": 2, "omega": 1.0},
         "roofline": roofline,

@@ -1,13 +1,15 @@
 /*
- * lpk serving: many LPs solved concurrently on one MI355X.
+ * lpk serving: many LPs solved together on one MI355X.
  *
  * Each LP is the problem statement of lpk.h (the paper's primal-dual pair) solved by the
  * same interior-point method.  A single LP of moderate size leaves most of the GPU idle
  * (every Krylov iteration is a short chain of dependent kernels), so throughput comes
- * from running several at once: each concurrent solve has its own worker thread and its
- * own HIP stream (default priority), and the device overlaps their kernels.  A solve's
- * arithmetic does not depend on what else runs, so every result is bitwise the same
- * alone and in the mix.
+ * from solving many at once in lockstep: the LPs of a batch run the same phase of their
+ * own interior-point iteration together, and each phase is one kernel launch covering all
+ * of them (one workgroup row per LP).  An LP that finishes leaves the batch at the end of
+ * an iteration and a waiting one joins; it computes its starting point during the next
+ * iteration.  Every reduction of an LP is partitioned by that LP's own sizes, so its
+ * result is bitwise the same alone and in any batch.
  *
  * Conventions as in lpk.h: every call returns an lp_status, nothing aborts, host arrays
  * are copied at the call.
@@ -21,17 +23,28 @@
 extern "C" {
 #endif
 
-/* Solve `count` already-created problems with up to `workers` solves in flight (one
- * thread and one HIP stream per worker; each problem's own stream is restored after its
- * solve).  results[i] receives lp_solve's result for problems[i].  Returns LP_OK when
- * every solve ran (check results[i].status), else the first error.  Errors: LP_EINVAL
- * (NULL arrays, count < 0, workers < 1), LP_EDEVICE.                                     */
-lp_status lp_solve_batch(lp_problem** problems, int32_t count, int32_t workers, lp_result* results);
+/* Solve `count` already-created problems, up to `width` of them in lockstep.  Problems
+ * that share precision, inner iterations, sweeps and layout (sparse / dense) form one
+ * group; groups run one after the other, each on a stream of its own (every problem's
+ * stream is synchronised first).  results[i] receives lp_solve's result for problems[i]
+ * (seconds: from joining the batch to leaving it).  Returns LP_OK when every solve ran
+ * (check results[i].status), else the first error.  Errors: LP_EINVAL (NULL arrays,
+ * count < 0, width < 1), LP_EDEVICE.                                                      */
+lp_status lp_solve_batch(lp_problem** problems, int32_t count, int32_t width, lp_result* results);
+
+/* lp_time_kernel for a batch: the launches of kernel class cls for all `count` problems
+ * together (one launch covers every problem), replayed `reps` times between two HIP
+ * events.  bytes and flops are summed over the problems.  The problems must share
+ * precision, inner iterations, sweeps and layout, and each needs a scaling (a solve ran).
+ * Errors: LP_EINVAL, LP_EDEVICE.                                                          */
+lp_status lp_time_batch_kernel(lp_problem** problems, int32_t count, int32_t cls, int32_t reps,
+                               double* us_per_launch, double* bytes_per_launch,
+                               double* flops_per_launch, int32_t* launches_per_group);
 
 typedef struct lp_server lp_server;
 
 typedef struct {
-    int32_t slots;           /* concurrent solves (worker threads and streams) [8]          */
+    int32_t slots;           /* LPs in the lockstep batch, [1, 256] [32]                    */
     int32_t max_skip;        /* FIFO with bounded skip: later requests that may start ahead
                                 of a head request that does not fit yet [8]                */
     uint64_t hbm_budget;     /* device bytes the admitted problems may hold together, by

@@ -124,6 +124,9 @@ SIGNATURES = {
     "lp_server_destroy": (C.c_int, [_P]),
     "lp_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "lp_time_batch_kernel": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]),
     "lp_status_str": (C.c_char_p, [C.c_int]),
     "lp_last_error": (C.c_char_p, []),
     "lp_version": (C.c_char_p, []),
@@ -378,18 +381,19 @@ def lp_profile_read(p: Problem):
             for i in range(n.value)}
 
 
-def lp_solve_batch(problems, workers: int):
-    """Solve created problems concurrently (one thread and HIP stream per worker)."""
+def lp_solve_batch(problems, width: int):
+    """Solve created problems, up to `width` of them in lockstep (one launch per phase)."""
     arr = (C.c_void_p * len(problems))(*[p.h.value for p in problems])
     res = (Result * max(1, len(problems)))()
-    _check(lib().lp_solve_batch(arr, len(problems), int(workers), res), "lp_solve_batch")
+    _check(lib().lp_solve_batch(arr, len(problems), int(width), res), "lp_solve_batch")
     return [_dict(res[i]) for i in range(len(problems))]
 
 
 class Server:
-    """The request server of include/lpk_server.h (continuous admission by HBM footprint)."""
+    """The request server of include/lpk_server.h (lockstep batch, continuous admission by
+    HBM footprint)."""
 
-    def __init__(self, slots=8, max_skip=8, hbm_budget=0, solver: Optional[Options] = None, **kw):
+    def __init__(self, slots=32, max_skip=8, hbm_budget=0, solver: Optional[Options] = None, **kw):
         o = ServerOptions()
         lib().lp_server_options_default(C.byref(o))
         o.slots, o.max_skip, o.hbm_budget = int(slots), int(max_skip), int(hbm_budget)
@@ -447,5 +451,15 @@ def lp_time_kernel(p: Problem, cls: int, reps: int = 200):
     us, by, fl, nl = C.c_double(0), C.c_double(0), C.c_double(0), C.c_int32(0)
     _check(lib().lp_time_kernel(p.h, int(cls), int(reps), C.byref(us), C.byref(by), C.byref(fl), C.byref(nl)),
            "lp_time_kernel")
+    return dict(us_per_launch=us.value, bytes_per_launch=by.value, flops_per_launch=fl.value,
+                launches_per_group=nl.value)
+
+
+def lp_time_batch_kernel(problems, cls: int, reps: int = 200):
+    """lp_time_kernel over a batch: one launch covers every problem; bytes/flops summed."""
+    arr = (C.c_void_p * len(problems))(*[p.h.value for p in problems])
+    us, by, fl, nl = C.c_double(0), C.c_double(0), C.c_double(0), C.c_int32(0)
+    _check(lib().lp_time_batch_kernel(arr, len(problems), int(cls), int(reps), C.byref(us), C.byref(by),
+                                      C.byref(fl), C.byref(nl)), "lp_time_batch_kernel")
     return dict(us_per_launch=us.value, bytes_per_launch=by.value, flops_per_launch=fl.value,
                 launches_per_group=nl.value)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,23 +50,23 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
     const bool mixed = o.precision == LP_MIXED;
     const int64_t kmax = plan_kmax(m, o);
-    const GsPlan gs = gs_plan(m);
+    const int64_t nchunks = (m + 64 * gs_rpl_for(m) - 1) / (64 * gs_rpl_for(m));
     z.add(m + 1, 4); z.add(nnz, 4); z.add(nnz, 8); z.add(n + 1, 4); z.add(nnz, 4); z.add(nnz, 8);
     z.add(nnz, 8); z.add(nnz, 8);
     if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
-    z.add(m, 4);
-    for (int i = 0; i < 13; ++i) z.add(m, 8);    // m-vectors
-    for (int i = 0; i < 12; ++i) z.add(n, 8);    // n-vectors
+    z.add(m, 4);                                  // permutation
+    z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
+    for (int i = 0; i < 12; ++i) z.add(m, 8);    // m-vectors
+    for (int i = 0; i < 11; ++i) z.add(n, 8);    // n-vectors
     z.add(n, 4); z.add(m, 4);                     // z32, r32
     z.add(m * (kmax + 1), 8); z.add(m * (kmax + 1), 8);   // V, P
     z.add((kmax + 1) * (kmax + 1), 8);                      // H
     for (int i = 0; i < 5; ++i) z.add(kmax + 2, 8);
-    z.add((int64_t)gs.nchunks * (kmax + 1), 8);
-    if (gs_fusable(gs, kmax)) z.add((int64_t)gs.nchunks * (kmax + 1), 8);
-    z.add(m / 4 + 8, 8);
-    z.add(8 * 1024, 8); z.add(8, 8);
-    z.add(1, sizeof(KrylovCtl));
-    z.add(1, sizeof(KrylovCtl));
+    z.add(nchunks * (kmax + 1), 8);
+    if (gs_fusable(nchunks, kmax)) z.add(nchunks * (kmax + 1), 8);
+    // the problem's batch of one: descriptor, control words, parameters, partials
+    z.add(1, sizeof(Inst)); z.add(1, sizeof(Slot)); z.add(1, sizeof(Param));
+    z.add((int64_t)RED_NQ * RED_MAXBLK, 8);
     return z.bytes;
 }
 
@@ -129,13 +130,7 @@ static lp_status fetch(const T* src, int64_t count, bool dev, std::vector<T>& ou
 
 static void destroy(lp_problem* p) {
     if (!p) return;
-    prof_release(p);
-    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
-    p->arena.release();
-    if (p->host_out) (void)hipHostFree(p->host_out);
-    if (p->host_ctl) (void)hipHostFree(p->host_ctl);
+    if (p->st) (void)hipStreamSynchronize(p->st);
     delete p;
 }
 
@@ -207,7 +202,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->kmax = plan_kmax(m, p->opt);
     p->ldv = m;
     p->ldh = p->kmax + 1;
-    p->gs = gs_plan(m);
+    p->rpl = gs_rpl_for(m);
+    p->nchunks = (int)((m + 64 * p->rpl - 1) / (64 * p->rpl));
     p->rp = A.alloc<int32_t>(m + 1);
     p->ci = A.alloc<int32_t>(nnz);
     p->a = A.alloc<double>(nnz);
@@ -221,12 +217,12 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         p->ahc32 = A.alloc<float>(nnz);
     }
     p->perm_d = A.alloc<int32_t>(m);
-    double** mv[] = {&p->b, &p->y, &p->rho, &p->rpv, &p->dya, &p->dyc, &p->f, &p->dyh, &p->dtmp_m,
-                     &p->pcol, &p->u, &p->fhU, &p->r64};
-    for (double** q : mv) *q = A.alloc<double>(m);
-    double** nv[] = {&p->c, &p->x, &p->s, &p->d, &p->rdv, &p->tn, &p->dxa, &p->dsa, &p->dw,
-                     &p->dtmp_n, &p->z64, &p->dapi};
-    for (double** q : nv) *q = A.alloc<double>(n);
+    p->cstart = A.alloc<int32_t>((int64_t)p->colours.size() + 1);
+    p->cg = A.alloc<int32_t>((int64_t)p->colours.size());
+    const int mv[] = {V_Y, V_RHO, V_RP, V_DYA, V_DYC, V_F, V_DYH, V_TMPM, V_B, V_FH, V_U, V_R64};
+    for (int q : mv) p->vec[q] = A.alloc<double>(m);
+    const int nv[] = {V_X, V_S, V_D, V_RD, V_TN, V_DXA, V_DSA, V_DW, V_TMPN, V_C, V_Z64};
+    for (int q : nv) p->vec[q] = A.alloc<double>(n);
     p->z32 = A.alloc<float>(n);
     p->r32 = A.alloc<float>(m);
     p->V = A.alloc<double>(m * (p->kmax + 1));
@@ -237,15 +233,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->gam = A.alloc<double>(p->kmax + 2);
     p->ykr = A.alloc<double>(p->kmax + 2);
     p->h2 = A.alloc<double>(p->kmax + 2);
-    p->gpart = A.alloc<double>((int64_t)p->gs.nchunks * (p->kmax + 1));
-    p->gs_fused = gs_fusable(p->gs, p->kmax);
-    if (p->gs_fused) p->gpart2 = A.alloc<double>((int64_t)p->gs.nchunks * (p->kmax + 1));
-    p->spart = A.alloc<double>(m / 4 + 8);
-    p->red.maxblk = 1024;
-    p->red.part = A.alloc<double>(8 * 1024);
-    p->red.out = A.alloc<double>(8);
-    p->ctl = A.alloc<KrylovCtl>(1);
-    p->tctl = A.alloc<KrylovCtl>(1);
+    p->gpart = A.alloc<double>((int64_t)p->nchunks * (p->kmax + 1));
+    if (gs_fusable(p->nchunks, p->kmax)) p->gpart2 = A.alloc<double>((int64_t)p->nchunks * (p->kmax + 1));
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);
         p->Xinv = A.alloc<double>(m * m);
@@ -258,10 +247,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         if (mixed) p->C32 = A.alloc<float>(m * m);
     }
     if (A.failed) return fail(LP_ENOMEM, "device allocation failed");
-    if (hipHostMalloc((void**)&p->host_out, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&p->host_ctl, sizeof(KrylovCtl), hipHostMallocDefault) != hipSuccess)
-        return fail(LP_ENOMEM, "pinned host allocation failed");
     hipStream_t st = p->st;
+    p->h_cstart.resize(p->colours.size() + 1);
+    p->h_cg.resize(p->colours.size());
+    for (size_t cl = 0; cl < p->colours.size(); ++cl) {
+        p->h_cstart[cl] = p->colours[cl].r0;
+        p->h_cg[cl] = p->colours[cl].g;
+    }
+    p->h_cstart[p->colours.size()] = (int32_t)m;
+    LPK_HIP(hipMemcpyAsync(p->cstart, p->h_cstart.data(), sizeof(int32_t) * p->h_cstart.size(), hipMemcpyHostToDevice, st));
+    if (!p->h_cg.empty())
+        LPK_HIP(hipMemcpyAsync(p->cg, p->h_cg.data(), sizeof(int32_t) * p->h_cg.size(), hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->rp, prp.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->ci, pci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->a, pa.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
@@ -269,8 +265,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     LPK_HIP(hipMemcpyAsync(p->ri, pri.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->ac, pac.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->perm_d, p->perm.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-    LPK_HIP(hipMemcpyAsync(p->b, pb.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-    LPK_HIP(hipMemcpyAsync(p->c, c, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->vec[V_B], pb.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(p->vec[V_C], c, sizeof(double) * n, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemsetAsync(p->H, 0, sizeof(double) * (p->kmax + 1) * (p->kmax + 1), st));
     LPK_HIP(hipStreamSynchronize(st));
     p->ist.eps_in = p->opt.eps_in0;
@@ -457,80 +453,63 @@ lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, co
 
 void lp_destroy(lp_problem* p) { destroy(p); }
 
+// run the problem alone (its batch of one) until it leaves the engine or `ticks` ticks ran
+static lp_status run_solo(lp_problem* p, bool from_point, int32_t limit_k, int ticks, Engine::Member* out) {
+    Batch* b = nullptr;
+    lp_status rc = solo_batch(p, &b);
+    if (rc != LP_OK) return rc;
+    Engine E;
+    E.attach(b);
+    const int s = E.join(p, from_point, limit_k);
+    if (s < 0) return fail(LP_EINVAL, "no slot");
+    for (int t = 0; (ticks <= 0 || t < ticks) && E.any_live(); ++t) {
+        rc = E.tick();
+        if (rc != LP_OK) return rc;
+    }
+    *out = E.mem[s];
+    return LP_OK;
+}
+
 lp_status ipm_step(lp_problem* p, lp_iter_info* info) {
     g_err.clear();
     if (!p) return fail(LP_EINVAL, "NULL problem");
-    lp_iter_info L{};
     lp_status rc;
+    Engine::Member mb;
     if (!p->have_point) {
         if (p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
-        rc = ipm_init_point(p);
+        // the starting point takes one tick of its own
+        rc = run_solo(p, false, INT32_MAX, 1, &mb);
         if (rc != LP_OK) return rc;
+        if (mb.state == Engine::DONE) return mb.status;
     }
-    rc = ipm_iterate(p, &L);
-    p->log.push_back(L);
-    if (info) *info = L;
-    return rc;
+    rc = run_solo(p, true, INT32_MAX, 1, &mb);
+    if (rc != LP_OK) return rc;
+    if (info) *info = mb.L;
+    return mb.state == Engine::DONE && mb.status == LP_DIVERGED ? LP_DIVERGED : LP_OK;
 }
 
 lp_status lp_solve(lp_problem* p, lp_result* r) {
     g_err.clear();
     if (!p) return fail(LP_EINVAL, "NULL problem");
-    const auto t0 = std::chrono::steady_clock::now();
+    const double t0 = now_seconds();
     p->log.clear();
     p->krylov_total = 0;
-    p->last_iters = 0;
-    lp_status rc = LP_OK;
-    if (p->opt.start == 0 || !p->have_point) {
-        if (p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
-        rc = ipm_init_point(p);
-        if (rc != LP_OK) return rc;
-    } else {
+    bool from_point = false;
+    if (p->opt.start != 0) {
+        if (!p->have_point) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
         p->ist.eps_in = p->opt.eps_in0;
         p->ist.k = 0;
         p->ist.fail_prev = 0;
+        from_point = true;
     }
-    lp_iter_info L{};
-    int32_t k = 0;
-    lp_status status = LP_NOT_CONVERGED;
-    for (k = 0; k <= p->opt.ipm_max_iter; ++k) {
-        if (k == p->opt.ipm_max_iter) {
-            // the final point is only evaluated
-            L = lp_iter_info{};
-            rc = ipm_evaluate(p, &L);
-            if (rc != LP_OK) return rc;
-            status = L.converged ? LP_OK : LP_NOT_CONVERGED;
-            p->log.push_back(L);
-            break;
-        }
-        L = lp_iter_info{};
-        rc = ipm_iterate(p, &L);
-        p->log.push_back(L);
-        if (rc != LP_OK) {
-            status = rc;
-            break;
-        }
-        if (L.converged) {
-            status = LP_OK;
-            break;
-        }
-    }
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    Engine::Member mb;
+    lp_status rc = run_solo(p, from_point, p->opt.ipm_max_iter, 0, &mb);
+    if (rc != LP_OK) return rc;
     if (r) {
-        memset(r, 0, sizeof(*r));
-        r->status = status;
-        r->iters = k;
-        r->gamma = L.gamma;
-        r->gamma_rel = L.gamma_rel;
-        r->pobj = L.pobj;
-        r->dobj = L.dobj;
-        r->rp_rel = L.rp_rel;
-        r->rd_rel = L.rd_rel;
-        r->gap_rel = L.gap_rel;
-        r->krylov_iters = p->krylov_total;
-        r->seconds = secs;
+        fill_result(mb, r);
+        r->seconds = now_seconds() - t0;
     }
-    return status;
+    return mb.status;
 }
 
 lp_status direction_solve(lp_problem* p, const double* d, const double* f, double tol, double* dw,
@@ -549,28 +528,39 @@ lp_status direction_solve(lp_problem* p, const double* d, const double* f, doubl
                 if (!(d[j] > 0.0)) return fail(LP_EINVAL, "d must be positive");
         }
     }
-    hipStream_t st = p->st;
-    const double* dd;
+    if (!d && !p->have_point) return fail(LP_EINVAL, "no current iterate: pass d");
+    Batch* b = nullptr;
+    if ((rc = solo_batch(p, &b)) != LP_OK) return rc;
+    hipStream_t st = b->st;
+    Param& pr = b->h_param[0];
     if (d) {
-        if ((rc = copy_in(p, d, p->dapi, n)) != LP_OK) return rc;
-        dd = p->dapi;
+        if ((rc = copy_in(p, d, p->vec[V_D], n)) != LP_OK) return rc;
     } else {
-        if (!p->have_point) return fail(LP_EINVAL, "no current iterate: pass d");
-        ipm_scaling(st, n, p->x, p->s, nullptr, p->dapi, nullptr);
-        dd = p->dapi;
+        // D = diag(sqrt(x/s)) of the current iterate
+        pr.mode = MD_RUN;
+        if ((rc = b->put_params()) != LP_OK) return rc;
+        b_scaling(b->L);
     }
-    rc = build_scaling(p, dd);
-    if (rc != LP_OK) return rc;
-    if ((rc = copy_in(p, f, p->dtmp_m, m)) != LP_OK) return rc;
-    gather(st, m, p->dtmp_m, p->perm_d, p->f);
-    rc = krylov_solve(p, p->f, tol, p->dw, p->dyh, ki);
-    if (rc != LP_OK) return rc;
-    if ((rc = copy_out(p, p->dw, dw, n)) != LP_OK) return rc;
+    pr.mode = MD_API;
+    pr.scal[SC_TOL] = tol;
+    if (p->opt.inner == LP_CIMMINO && !p->gsor) {
+        if (p->opt.omega_c > 0.0) pr.scal[SC_OMC] = p->opt.omega_c;
+        else pr.mode |= MD_POW;
+    }
+    if ((rc = b->put_params()) != LP_OK) return rc;
+    if ((rc = scale_batch(*b, MD_API)) != LP_OK) return rc;
+    if ((rc = copy_in(p, f, p->vec[V_TMPM], m)) != LP_OK) return rc;
+    gather(st, m, p->vec[V_TMPM], p->perm_d, p->vec[V_F]);
+    std::vector<lp_krylov_info> info;
+    if ((rc = krylov_batch(*b, MD_API, &info)) != LP_OK) return rc;
+    if (ki) *ki = info[0];
+    if ((rc = copy_out(p, p->vec[V_DW], dw, n)) != LP_OK) return rc;
     if (dy) {
-        div_by(st, m, p->dyh, p->rho, p->dyc);
-        scatter(st, m, p->dyc, p->perm_d, p->dtmp_m);
-        if ((rc = copy_out(p, p->dtmp_m, dy, m)) != LP_OK) return rc;
+        b_div_rho(b->L, V_DYC, V_DYH, MD_API);
+        scatter(st, m, p->vec[V_DYC], p->perm_d, p->vec[V_TMPM]);
+        if ((rc = copy_out(p, p->vec[V_TMPM], dy, m)) != LP_OK) return rc;
     }
+    LPK_HIP(hipGetLastError());
     LPK_HIP(hipStreamSynchronize(st));
     return LP_OK;
 }
@@ -580,11 +570,11 @@ lp_status lp_get_state(const lp_problem* pc, double* x, double* y, double* s, lp
     lp_problem* p = const_cast<lp_problem*>(pc);
     if (!p) return fail(LP_EINVAL, "NULL problem");
     lp_status rc;
-    if (x && (rc = copy_out(p, p->x, x, p->n)) != LP_OK) return rc;
-    if (s && (rc = copy_out(p, p->s, s, p->n)) != LP_OK) return rc;
+    if (x && (rc = copy_out(p, p->vec[V_X], x, p->n)) != LP_OK) return rc;
+    if (s && (rc = copy_out(p, p->vec[V_S], s, p->n)) != LP_OK) return rc;
     if (y) {
-        scatter(p->st, p->m, p->y, p->perm_d, p->dtmp_m);
-        if ((rc = copy_out(p, p->dtmp_m, y, p->m)) != LP_OK) return rc;
+        scatter(p->st, p->m, p->vec[V_Y], p->perm_d, p->vec[V_TMPM]);
+        if ((rc = copy_out(p, p->vec[V_TMPM], y, p->m)) != LP_OK) return rc;
     }
     LPK_HIP(hipStreamSynchronize(p->st));
     if (stt) *stt = p->ist;
@@ -604,15 +594,22 @@ lp_status lp_set_state(lp_problem* p, const double* x, const double* y, const do
         for (int64_t j = 0; j < p->n; ++j)
             if (!(x[j] > 0.0) || !(s[j] > 0.0)) return fail(LP_EINVAL, "x and s must be positive");
     }
-    if ((rc = copy_in(p, x, p->x, p->n)) != LP_OK) return rc;
-    if ((rc = copy_in(p, s, p->s, p->n)) != LP_OK) return rc;
-    if ((rc = copy_in(p, y, p->dtmp_m, p->m)) != LP_OK) return rc;
-    gather(p->st, p->m, p->dtmp_m, p->perm_d, p->y);
+    if ((rc = copy_in(p, x, p->vec[V_X], p->n)) != LP_OK) return rc;
+    if ((rc = copy_in(p, s, p->vec[V_S], p->n)) != LP_OK) return rc;
+    if ((rc = copy_in(p, y, p->vec[V_TMPM], p->m)) != LP_OK) return rc;
+    gather(p->st, p->m, p->vec[V_TMPM], p->perm_d, p->vec[V_Y]);
     if (p->opt.device_io) {
-        min2(p->st, p->red, p->n, p->x, p->s);
-        double mins[2];
-        if ((rc = sync_read(p, p->red.out, mins, 2)) != LP_OK) return rc;
-        if (!(mins[0] > 0.0) || !(mins[1] > 0.0)) return fail(LP_EINVAL, "x and s must be positive");
+        Batch* b = nullptr;
+        if ((rc = solo_batch(p, &b)) != LP_OK) return rc;
+        b->h_param[0].mode = MD_API;
+        if ((rc = b->put_params()) != LP_OK) return rc;
+        b_min2(b->L, MD_API);
+        const int ops[2] = {1, 1};
+        b_red_finish(b->L, 2, ops, MD_API, 0);
+        LPK_HIP(hipGetLastError());
+        if ((rc = b->get_slots()) != LP_OK) return rc;
+        const double* q = b->h_slot[0].out;
+        if (!(q[0] > 0.0) || !(q[1] > 0.0)) return fail(LP_EINVAL, "x and s must be positive");
     }
     LPK_HIP(hipStreamSynchronize(p->st));
     if (stt) {

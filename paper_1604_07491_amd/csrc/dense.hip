@@ -93,29 +93,6 @@ void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, do
 }
 
 // ------------------------------------------------------------------------------------
-// u = G p_k (p_k = column ctl->k of P), one wave per row of the dense symmetric G
-__global__ __launch_bounds__(256) void k_gemv_col(int m, const double* __restrict__ G,
-                                                  const double* __restrict__ P, int64_t ldv,
-                                                  double* __restrict__ u,
-                                                  const KrylovCtl* __restrict__ ctl) {
-    if (ctl->done) return;
-    const double* __restrict__ p = P + (int64_t)ctl->k * ldv;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= m) return;
-    const double* __restrict__ gi = G + (int64_t)i * m;
-    double acc = 0.0;
-    for (int j = lane; j < m; j += 64) acc += gi[j] * p[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) u[i] = acc;
-}
-
-void gemv_col(hipStream_t st, int m, const double* G, const double* P, int64_t ldv, double* u,
-              const KrylovCtl* ctl) {
-    hipLaunchKernelGGL(k_gemv_col, dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, G, P, ldv, u, ctl);
-}
-
-// ------------------------------------------------------------------------------------
 // D = alpha (A B) + beta E + F + diag_one * [row + r0 == col], all row-major (FP64
 // MFMA, 64 x 64 tiles, k chunks of 32 staged in LDS).  A: M x K (lda), B: K x N (ldb).
 // E, F may be NULL.  Used for the explicit inner-iteration preconditioner of the dense
@@ -237,34 +214,6 @@ __global__ __launch_bounds__(256) void k_to_f32(int64_t len, const double* __res
 }
 void to_f32(hipStream_t st, int64_t len, const double* a, float* b) {
     if (len > 0) hipLaunchKernelGGL(k_to_f32, dim3(cdiv_u(len, 256)), dim3(256), 0, st, len, a, b);
-}
-
-// p_k = C v_k (C: m x m row-major, precision T), v_k = column ctl->k of V, into P[:,k];
-// one wave per row
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_c(int m, const T* __restrict__ C, const double* __restrict__ V,
-                                                 double* __restrict__ P, int64_t ldv,
-                                                 const KrylovCtl* __restrict__ ctl) {
-    if (ctl->done) return;
-    const int64_t k = ctl->k;
-    const double* __restrict__ v = V + k * ldv;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= m) return;
-    const T* __restrict__ ci = C + (int64_t)i * m;
-    T acc = 0;
-    for (int j = lane; j < m; j += 64) acc += ci[j] * (T)v[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) P[k * ldv + i] = (double)acc;
-}
-
-void apply_c_f64(hipStream_t st, int m, const double* C, const double* V, double* P, int64_t ldv,
-                 const KrylovCtl* ctl) {
-    hipLaunchKernelGGL((k_apply_c<double>), dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, C, V, P, ldv, ctl);
-}
-void apply_c_f32(hipStream_t st, int m, const float* C, const double* V, double* P, int64_t ldv,
-                 const KrylovCtl* ctl) {
-    hipLaunchKernelGGL((k_apply_c<float>), dim3(cdiv_u(m, 4)), dim3(256), 0, st, m, C, V, P, ldv, ctl);
 }
 
 }  // namespace lpk

@@ -1,0 +1,1081 @@
+// The batched engine: interior-point iterations (Sec. 2.1) of many LPs in lockstep, each
+// phase one launch for the whole batch, with the search-direction solves by AB-GMRES
+// preconditioned by inner iterations (Sec. 3.2) on the row-scaled problem (Sec. 3.5).
+//
+// Differences from the paper's single-LP CPU layout, all exact in exact arithmetic:
+//  * flexible final step: the multiplier vectors p_k of every preconditioner application
+//    are kept (P = [p_1 .. p_k]) and the solution is dw = A_hat^T (P y); z_k = A_hat^T p_k
+//    is recomputed in FP64, so the Arnoldi relation and dw in R(A_hat^T) hold to FP64 even
+//    when the sweeps run in FP32.  The multipliers also give dy = diag(rho)^-1 P y with no
+//    extra matrix-vector product.
+//  * classical Gram-Schmidt applied twice in place of modified Gram-Schmidt (Sec. 3.2 uses
+//    MGS); both orthogonalise to working precision, CGS2 in two reductions per pass.
+//  * the Hessenberg least-squares problem is kept in QR form by Givens rotations on the
+//    device; the host only polls the convergence flags every few iterations.
+//
+// Every reduction of an instance is partitioned by that instance's own sizes, so a
+// problem's iterates are bitwise the same alone and in any batch.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+
+#include "lpk_impl.h"
+
+namespace lpk {
+
+double now_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int gs_rpl_for(int64_t m) {
+    int rpl = 1;
+    while (rpl < 8 && (int64_t)64 * rpl * 1024 < m) rpl *= 2;
+    return rpl;
+}
+
+bool gs_fusable(int64_t nchunks, int64_t kmax) { return nchunks <= 32 && kmax + 1 <= 2048; }
+
+static inline int cdiv_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+bool batch_compatible(const lp_problem* a, const lp_problem* b) {
+    return a->opt.precision == b->opt.precision && a->opt.inner == b->opt.inner &&
+           a->gsor == b->gsor && a->opt.inner_sweeps == b->opt.inner_sweeps && a->device == b->device;
+}
+
+// ------------------------------------------------------------------------------------
+// Batch
+
+Batch::~Batch() {
+    prof_release(*this);
+    drop_graph();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    if (d_inst) (void)hipFree(d_inst);
+    if (d_slot) (void)hipFree(d_slot);
+    if (d_param) (void)hipFree(d_param);
+    if (d_part) (void)hipFree(d_part);
+    if (h_slot) (void)hipHostFree(h_slot);
+    if (h_param) (void)hipHostFree(h_param);
+    if (own_stream && st) (void)hipStreamDestroy(st);
+}
+
+lp_status Batch::init(int capacity, hipStream_t stream, bool own) {
+    cap = capacity;
+    st = stream;
+    own_stream = own;
+    (void)hipGetDevice(&device);
+    mem.assign((size_t)cap, nullptr);
+    h_inst.assign((size_t)cap, Inst{});
+    LPK_HIP(hipMalloc(&d_inst, sizeof(Inst) * cap));
+    LPK_HIP(hipMalloc(&d_slot, sizeof(Slot) * cap));
+    LPK_HIP(hipMalloc(&d_param, sizeof(Param) * cap));
+    LPK_HIP(hipMalloc(&d_part, sizeof(double) * RED_NQ * RED_MAXBLK * cap));
+    LPK_HIP(hipHostMalloc((void**)&h_slot, sizeof(Slot) * cap, hipHostMallocDefault));
+    LPK_HIP(hipHostMalloc((void**)&h_param, sizeof(Param) * cap, hipHostMallocDefault));
+    memset(h_slot, 0, sizeof(Slot) * cap);
+    memset(h_param, 0, sizeof(Param) * cap);
+    for (int i = 0; i < cap; ++i) h_slot[i].ctl.done = 1;
+    LPK_HIP(hipMemcpyAsync(d_slot, h_slot, sizeof(Slot) * cap, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(d_param, h_param, sizeof(Param) * cap, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    dirty = true;
+    return LP_OK;
+}
+
+int Batch::free_slot() const {
+    for (int i = 0; i < cap; ++i)
+        if (!mem[i]) return i;
+    return -1;
+}
+
+int Batch::members() const {
+    int c = 0;
+    for (lp_problem* p : mem) c += p != nullptr;
+    return c;
+}
+
+void Batch::drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_iters = 0;
+}
+
+static Inst make_inst(Batch& B, int slot) {
+    Inst in;
+    memset(&in, 0, sizeof(in));
+    in.ctl = &B.d_slot[slot].ctl;
+    in.out = B.d_slot[slot].out;
+    in.part = B.d_part + (int64_t)slot * RED_NQ * RED_MAXBLK;
+    in.scal = B.d_param[slot].scal;
+    in.mode = &B.d_param[slot].mode;
+    const lp_problem* p = B.mem[slot];
+    if (!p) return in;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    in.m = (int32_t)p->m;
+    in.n = (int32_t)p->n;
+    in.nnz = (int32_t)p->nnz;
+    in.ncol = (p->gsor || p->opt.inner != LP_NESOR) ? 0 : (int32_t)p->colours.size();
+    in.g_csr = p->g_csr;
+    in.g_csc = p->g_csc;
+    in.nchunks = p->nchunks;
+    in.gsor = p->gsor ? 1 : 0;
+    in.rpl = p->rpl;
+    in.nbr = red_blocks(std::max(p->m, p->n));
+    in.nbs = spmv_blocks(p->m, p->g_csr);
+    in.ldv = p->ldv;
+    in.ldh = p->ldh;
+    in.ldp = p->kmax + 1;
+    in.kmax = p->kmax;
+    in.rp = p->rp;
+    in.ci = p->ci;
+    in.cp = p->cp;
+    in.ri = p->ri;
+    in.cstart = p->cstart;
+    in.cg = p->cg;
+    in.a = p->a;
+    in.ac = p->ac;
+    in.ah = p->ah;
+    in.ahc = p->ahc;
+    in.ah32 = mixed ? p->ah32 : nullptr;
+    in.ahc32 = (mixed && p->opt.inner == LP_CIMMINO) ? p->ahc32 : nullptr;
+    for (int v = 0; v < V_COUNT; ++v) in.vec[v] = p->vec[v];
+    in.z32 = p->z32;
+    in.r32 = p->r32;
+    in.V = p->V;
+    in.P = p->P;
+    in.H = p->H;
+    in.cs = p->cs;
+    in.sn = p->sn;
+    in.gam = p->gam;
+    in.ykr = p->ykr;
+    in.h2 = p->h2;
+    in.gpart = p->gpart;
+    in.gpart2 = p->gpart2;
+    in.G = p->G;
+    in.C = p->Capply;
+    in.C32 = p->C32;
+    in.omega = p->opt.omega;
+    return in;
+}
+
+lp_status Batch::refresh() {
+    L = BLaunch{};
+    L.S = cap;
+    L.st = st;
+    L.I = d_inst;
+    L.max_m = L.max_n = L.max_nbr = L.max_nbs = 1;
+    L.max_ldp = 1;
+    for (int i = 0; i < 4; ++i) L.grid_spmv[i] = 1;
+    L.gs_rpl = 1;
+    L.gs_nchunks = 1;
+    L.gs_fused = true;
+    L.max_ncol = 0;
+    L.ell = 1;
+    bool first = true;
+    for (int s = 0; s < cap; ++s) {
+        h_inst[s] = make_inst(*this, s);
+        const lp_problem* p = mem[s];
+        if (!p) continue;
+        const Inst& in = h_inst[s];
+        if (first) {
+            L.mixed = p->opt.precision == LP_MIXED;
+            L.inner = p->gsor ? 3 : p->opt.inner;
+            L.ell = std::max(1, (int)p->opt.inner_sweeps);
+            first = false;
+        }
+        L.max_m = std::max(L.max_m, in.m);
+        L.max_n = std::max(L.max_n, in.n);
+        L.max_nbr = std::max(L.max_nbr, in.nbr);
+        L.max_nbs = std::max(L.max_nbs, in.nbs);
+        L.max_ldp = std::max<int64_t>(L.max_ldp, in.ldp);
+        const int gr = cdiv_i((int64_t)in.m * in.g_csr, BLOCK_THREADS);
+        const int gc = cdiv_i((int64_t)in.n * in.g_csc, BLOCK_THREADS);
+        L.grid_spmv[M_A_CSR] = std::max(L.grid_spmv[M_A_CSR], gr);
+        L.grid_spmv[M_AH_CSR] = std::max(L.grid_spmv[M_AH_CSR], gr);
+        L.grid_spmv[M_A_CSC] = std::max(L.grid_spmv[M_A_CSC], gc);
+        L.grid_spmv[M_AH_CSC] = std::max(L.grid_spmv[M_AH_CSC], gc);
+        L.gs_rpl = std::max(L.gs_rpl, in.rpl);
+        L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
+        L.gs_fused = L.gs_fused && p->gpart2 != nullptr && gs_fusable(p->nchunks, p->kmax);
+        L.max_ncol = std::max(L.max_ncol, in.ncol);
+    }
+    grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
+    for (int s = 0; s < cap; ++s) {
+        const lp_problem* p = mem[s];
+        if (!p || h_inst[s].ncol == 0) continue;
+        for (int c = 0; c < h_inst[s].ncol; ++c) {
+            const Colour& cl = p->colours[c];
+            grid_colour[c] = std::max(grid_colour[c], cdiv_i((int64_t)(cl.r1 - cl.r0) * cl.g, BLOCK_THREADS));
+        }
+    }
+    L.grid_colour = grid_colour.data();
+    LPK_HIP(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * cap, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    drop_graph();
+    dirty = false;
+    return LP_OK;
+}
+
+lp_status Batch::put_params() {
+    LPK_HIP(hipMemcpyAsync(d_param, h_param, sizeof(Param) * cap, hipMemcpyHostToDevice, st));
+    // h_param is written again only after this copy has completed
+    LPK_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+lp_status Batch::get_slots() {
+    LPK_HIP(hipMemcpyAsync(h_slot, d_slot, sizeof(Slot) * cap, hipMemcpyDeviceToHost, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    return LP_OK;
+}
+
+lp_status solo_batch(lp_problem* p, Batch** out) {
+    if (!p->solo) {
+        std::unique_ptr<Batch> b(new Batch());
+        lp_status rc = b->init(1, p->st, false);
+        if (rc != LP_OK) return rc;
+        b->mem[0] = p;
+        p->solo = std::move(b);
+    }
+    Batch* b = p->solo.get();
+    if (b->dirty) {
+        lp_status rc = b->refresh();
+        if (rc != LP_OK) return rc;
+    }
+    *out = b;
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// algorithmic bytes of one launch, summed over the members: every input and output the
+// launch must move, each once
+
+template <typename F>
+static double over_members(const Batch& B, F f) {
+    double s = 0.0;
+    for (const lp_problem* p : B.mem)
+        if (p) s += f(p);
+    return s;
+}
+
+static double sweep_bytes_dense(const Batch& B) {
+    const double sv = B.L.mixed ? 4.0 : 8.0;
+    return over_members(B, [&](const lp_problem* p) { return (double)p->m * p->m * sv + 16.0 * p->m; });
+}
+
+// ------------------------------------------------------------------------------------
+// Krylov iterations
+
+// one application of the inner-iteration preconditioner to column k of V (k and the done
+// flag from each instance's control block), with the start-of-iteration preparation
+static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
+    const BLaunch& L = B.L;
+    const double sv = L.mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
+    const int ell = L.ell;
+    if (with_prep) b_prep(L);
+    if (L.inner == 3) {
+        Prof pr(&B, LP_K_SWEEP, it, sweep_bytes_dense(B));
+        b_apply_c(L);
+    } else if (L.inner == LP_CIMMINO) {
+        for (int sw = 0; sw < ell; ++sw) {
+            const int first = sw == 0;
+            {
+                const double by = over_members(B, [&](const lp_problem* p) {
+                    const double m = p->m, n = p->n, nnz = p->nnz;
+                    (void)n;
+                    return first ? m * (8.0 + sv + 16.0) : nnz * (sv + 4.0) + p->n * sv + m * (4.0 + 8.0 + sv + 16.0);
+                });
+                Prof pr(&B, LP_K_SWEEP, it, by);
+                b_cim_res(L, first);
+            }
+            if (sw + 1 < ell) {
+                const double by = over_members(B, [&](const lp_problem* p) {
+                    const double m = p->m, n = p->n, nnz = p->nnz;
+                    return nnz * (sv + 4.0) + m * sv + n * (4.0 + sv * (first ? 1.0 : 2.0));
+                });
+                Prof pr(&B, LP_K_SWEEP, it, by);
+                b_cim_z(L, first);
+            }
+        }
+    } else {
+        for (int sw = 0; sw < ell; ++sw) {
+            for (int c = 0; c < L.max_ncol; ++c) {
+                const double by = over_members(B, [&](const lp_problem* p) {
+                    const int nc = (int)p->colours.size();
+                    if (c >= nc) return 0.0;
+                    const Colour& cl = p->colours[c];
+                    const int wz = !(sw + 1 == ell && c + 1 == nc);
+                    return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
+                });
+                Prof pr(&B, LP_K_SWEEP, it, by);
+                b_nesor(L, c, sw, ell);
+            }
+        }
+    }
+}
+
+static double csc_bytes(const lp_problem* p) { return p->nnz * 12.0 + p->m * 8.0 + p->n * 8.0 + (p->n + 1) * 4.0; }
+static double csr_bytes(const lp_problem* p) { return p->nnz * 12.0 + p->n * 8.0 + p->m * 8.0 + (p->m + 1) * 4.0; }
+
+static void enqueue_products(Batch& B, int64_t it) {
+    const BLaunch& L = B.L;
+    if (L.inner == 3) {
+        // u = A_hat A_hat^T p_k = G p_k
+        Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, [](const lp_problem* p) { return 8.0 * p->m * p->m + 16.0 * p->m; }));
+        b_gemv_col(L);
+        return;
+    }
+    // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k
+    {
+        Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
+        b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
+    }
+    {
+        Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
+        b_spmv(L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
+    }
+}
+
+// one Krylov iteration (every kernel returns at once for instances whose solve is done)
+static void enqueue_iteration(Batch& B, int64_t it) {
+    const BLaunch& L = B.L;
+    enqueue_precond(B, it, true);
+    enqueue_products(B, it);
+    // CGS2 + Givens; the host iteration index equals the device one while the solve runs
+    const double kk = (double)(it + 1);
+    auto gsb = [&](double per_m, double per_part) {
+        return over_members(B, [&](const lp_problem* p) { return kk * p->m * 8.0 + per_m * p->m + per_part * p->nchunks * kk * 8.0; });
+    };
+    {
+        Prof pr(&B, LP_K_GS_DOTS, it, gsb(8.0, 1.0));
+        b_gs_dots(L);
+    }
+    if (L.gs_fused) {
+        // each update block reduces the previous pass's partials itself (few chunks)
+        {
+            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 2.0));
+            b_gs_update(L, 0);
+        }
+        {
+            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 1.0));
+            b_gs_update(L, 1);
+        }
+    } else {
+        b_gs_reduce(L, 0);
+        {
+            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 1.0));
+            b_gs_update(L, 0);
+        }
+        b_gs_reduce(L, 1);
+        {
+            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 0.0));
+            b_gs_update(L, 1);
+        }
+    }
+    b_gs_finish(L);
+}
+
+// capture `iters` Krylov iterations for the current membership; every kernel argument is
+// fixed (the iteration index, the done flags and the Cimmino steps live in device
+// memory), so the same executable graph serves every iteration of every solve
+static lp_status build_graph(Batch& B, int iters) {
+    if (!B.cap_st) LPK_HIP(hipStreamCreateWithFlags(&B.cap_st, hipStreamNonBlocking));
+    const uint32_t mask = B.prof_mask;
+    B.prof_mask = 0;
+    hipStream_t keep = B.L.st;
+    B.L.st = B.cap_st;
+    hipError_t e = hipStreamBeginCapture(B.cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < iters; ++i) enqueue_iteration(B, -1);
+        e = hipStreamEndCapture(B.cap_st, &B.graph);
+    }
+    B.L.st = keep;
+    B.prof_mask = mask;
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    LPK_HIP(hipGraphInstantiate(&B.gexec, B.graph, nullptr, nullptr, 0));
+    B.graph_iters = iters;
+    return LP_OK;
+}
+
+lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
+    const BLaunch& L = B.L;
+    int64_t kmax_all = 0;
+    int poll_every = 0;
+    bool graphs = true;
+    for (int s = 0; s < B.cap; ++s) {
+        const lp_problem* p = B.mem[s];
+        if (!p || !(B.h_param[s].mode & pmask)) continue;
+        kmax_all = std::max(kmax_all, p->kmax);
+        poll_every = std::max(poll_every, (int)p->opt.poll_every);
+        graphs = graphs && p->opt.use_graphs;
+    }
+    if (info) info->assign((size_t)B.cap, lp_krylov_info{});
+    if (kmax_all == 0) return LP_OK;
+    const int64_t sid = B.solve_id++;
+    if ((int64_t)B.solve_iters.size() <= sid) B.solve_iters.resize(sid + 1, 0);
+    b_init_rhs(L, pmask);
+    b_init_ctl(L, pmask, 0);
+    LPK_HIP(hipGetLastError());
+    const bool use_graph = graphs && B.prof_mask == 0;
+    if (use_graph && !B.gexec) {
+        lp_status grc = build_graph(B, 8);
+        if (grc != LP_OK) return grc;
+    }
+    int64_t enq = 0;
+    int batch = poll_every > 0 ? poll_every : (B.last_iters > 2 ? (int)(B.last_iters - 1) : 4);
+    for (;;) {
+        const int64_t todo = std::max<int64_t>(1, std::min<int64_t>(batch, kmax_all - enq));
+        if (use_graph) {
+            const int64_t launches = (todo + B.graph_iters - 1) / B.graph_iters;
+            for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(B.gexec, B.st));
+            enq += launches * B.graph_iters;
+        } else {
+            for (int64_t i = 0; i < todo; ++i) enqueue_iteration(B, enq + i);
+            enq += todo;
+        }
+        LPK_HIP(hipGetLastError());
+        lp_status rc = B.get_slots();
+        if (rc != LP_OK) return rc;
+        bool all = true;
+        for (int s = 0; s < B.cap; ++s)
+            if (B.mem[s] && (B.h_param[s].mode & pmask) && !B.h_slot[s].ctl.done) all = false;
+        if (all || enq >= kmax_all) break;
+        if (poll_every <= 0) batch = std::max(2, std::min(32, batch < 8 ? 4 : batch / 2));
+    }
+    // dyh = P y with R y = gamma; dw = A_hat^T dyh; true residual ||f_hat - A_hat dw||
+    b_backsolve(L);
+    b_combine(L);
+    b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, -1, false);
+    b_spmv(L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, -1, true);
+    b_true_res(L);
+    LPK_HIP(hipGetLastError());
+    lp_status rc = B.get_slots();
+    if (rc != LP_OK) return rc;
+    int64_t most = 0;
+    for (int s = 0; s < B.cap; ++s) {
+        lp_problem* p = B.mem[s];
+        if (!p || !(B.h_param[s].mode & pmask)) continue;
+        const KrylovCtl& hc = B.h_slot[s].ctl;
+        if (info) {
+            lp_krylov_info& ki = (*info)[s];
+            ki.iters = hc.iters;
+            ki.beta = hc.beta;
+            ki.res_est = hc.res;
+            ki.res_true = hc.res_true;
+            ki.failed = hc.failed;
+            ki.pad0 = 0;
+        }
+        p->krylov_total += hc.iters;
+        p->omega_c = hc.omega_c;
+        most = std::max<int64_t>(most, hc.iters);
+    }
+    B.solve_iters[sid] = most;
+    if (B.prof_recs.size() > 200000) prof_collect(B);
+    B.last_iters = most;
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Scaling
+
+// Dense path, once per scaling: G = A_hat A_hat^T (MFMA), then the inner-iteration
+// preconditioner in the matrix form of Sec. 3.1/3.2, C<l> = sum_{i<l} H^i M^-1 with the SOR
+// splitting M = I/omega + tril(G, -1) (unit diagonal, Sec. 3.5) and H = I - M^-1 G:
+//   X = M^-1 by block forward substitution (64-row blocks: R = I - G[B, <B] X[<B, :] by
+//   GEMM, then the diagonal block's substitution), C_1 = X, C_{i+1} = X + C_i - X (G C_i).
+// l SOR sweeps from zero apply exactly this C to v, so each Krylov iteration needs only
+// p = C v and u = G p.
+lp_status build_dense_preconditioner(Batch& B, lp_problem* p) {
+    hipStream_t st = B.L.st;
+    const int m = (int)p->m;
+    const int64_t mm = (int64_t)m * m;
+    const bool mixed = p->opt.precision == LP_MIXED;
+    const double om = p->opt.omega;
+    const int ell = std::max(1, (int)p->opt.inner_sweeps);
+    const double nbt = (double)((m + 63) / 64);
+    double fl = 2.0 * (double)p->n * 64.0 * 64.0 * nbt * (nbt + 1.0) / 2.0;     // Gram tiles
+    fl += (double)m * m * m / 3.0 * 2.0 + (ell - 1) * 4.0 * (double)m * m * m;   // M^-1 and C
+    Prof pr(&B, LP_K_GRAM, -1, 8.0 * (double)m * p->n + 8.0 * mm * (3.0 + 3.0 * (ell - 1)), fl);
+    gram_f64(st, m, p->n, p->ah, p->n, p->G, nullptr);
+    fill(st, mm, 0.0, p->Xinv);
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const int b = std::min(64, m - r0), ncols = r0 + b;
+        // R = I[B, :] - G[B, 0:r0] X[0:r0, 0:ncols]   (K = 0 for the first block: R = I)
+        gemm_f64(st, b, ncols, r0, -1.0, p->G + (int64_t)r0 * m, m, p->Xinv, m, 0.0, nullptr, nullptr, m,
+                 p->Rblk, m, r0);
+        trsm_diag(st, m, r0, b, p->G, p->Rblk, m, p->Xinv, om, ncols);
+    }
+    const double* Ccur = p->Xinv;
+    double* bufs[2] = {p->Cmat, p->Tmat2};
+    for (int i = 1; i < ell; ++i) {
+        double* Cn = bufs[(i - 1) & 1];
+        gemm_f64(st, m, m, m, 1.0, p->G, m, Ccur, m, 0.0, nullptr, nullptr, m, p->Tmat, m, -1);
+        gemm_f64(st, m, m, m, -1.0, p->Xinv, m, p->Tmat, m, 1.0, p->Xinv, Ccur, m, Cn, m, -1);
+        Ccur = Cn;
+    }
+    if (p->Capply != Ccur) {
+        // the descriptor holds the preconditioner's address
+        p->Capply = Ccur;
+        B.dirty = true;
+    }
+    if (mixed) to_f32(st, mm, Ccur, p->C32);
+    LPK_HIP(hipGetLastError());
+    return LP_OK;
+}
+
+lp_status scale_batch(Batch& B, int pmask) {
+    const BLaunch& L = B.L;
+    b_scale_rows(L, pmask);
+    b_scale_cols(L, pmask);
+    bool pow = false;
+    for (int s = 0; s < B.cap; ++s) {
+        lp_problem* p = B.mem[s];
+        if (!p || !(B.h_param[s].mode & pmask)) continue;
+        if (p->gsor) {
+            lp_status rc = build_dense_preconditioner(B, p);
+            if (rc != LP_OK) return rc;
+        }
+        pow = pow || (B.h_param[s].mode & MD_POW);
+    }
+    if (B.dirty) {
+        lp_status rc = B.refresh();
+        if (rc != LP_OK) return rc;
+    }
+    if (pow) {
+        // 20 power iterations on A_hat A_hat^T from e / sqrt(m): lambda = ||A_hat A_hat^T v||
+        for (int step = 0; step < 20; ++step) b_power_step(B.L, MD_POW, step);
+        b_set_omc(B.L, MD_POW);
+    }
+    LPK_HIP(hipGetLastError());
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Lockstep interior-point driver
+
+void Engine::attach(Batch* b) {
+    B = b;
+    mem.assign((size_t)b->cap, Member{});
+    for (int s = 0; s < b->cap; ++s) {
+        mem[s].p = b->mem[s];
+        mem[s].state = EMPTY;
+    }
+}
+
+int Engine::join(lp_problem* p, bool from_point, int32_t limit_k) {
+    int s = -1;
+    for (int i = 0; i < B->cap; ++i)
+        if (B->mem[i] == p || (!B->mem[i] && s < 0)) {
+            s = i;
+            if (B->mem[i] == p) break;
+        }
+    if (s < 0) return -1;
+    if (B->mem[s] != p) {
+        B->mem[s] = p;
+        B->dirty = true;
+    }
+    if (!from_point) {
+        // x, y, s are overwritten by the starting point
+        p->have_point = false;
+        p->ist.k = 0;
+    }
+    Member mb;
+    mb.p = p;
+    mb.state = from_point ? RUN : INIT;
+    mb.limit_k = limit_k;
+    mb.t_join = now_seconds();
+    mb.k0 = p->krylov_total;
+    mem[s] = mb;
+    return s;
+}
+
+void Engine::leave(int s) {
+    if (B->mem[s]) {
+        B->mem[s] = nullptr;
+        B->dirty = true;
+    }
+    mem[s] = Member{};
+}
+
+bool Engine::any_live() const {
+    for (const Member& mb : mem)
+        if (mb.state == INIT || mb.state == RUN) return true;
+    return false;
+}
+
+static double step_from(double minratio, double eta) {
+    const double a = eta * minratio;
+    return a < 1.0 ? a : 1.0;
+}
+
+static void finish(Engine::Member& mb, lp_status st) {
+    mb.state = Engine::DONE;
+    mb.status = st;
+    mb.iters = mb.p->ist.k;
+    mb.t_done = now_seconds();
+}
+
+void fill_result(const Engine::Member& mb, lp_result* r) {
+    memset(r, 0, sizeof(*r));
+    r->status = mb.status;
+    r->iters = mb.iters;
+    r->gamma = mb.last.gamma;
+    r->gamma_rel = mb.last.gamma_rel;
+    r->pobj = mb.last.pobj;
+    r->dobj = mb.last.dobj;
+    r->rp_rel = mb.last.rp_rel;
+    r->rd_rel = mb.last.rd_rel;
+    r->gap_rel = mb.last.gap_rel;
+    r->krylov_iters = mb.p->krylov_total - mb.k0;
+    r->seconds = mb.t_done - mb.t_join;
+}
+
+lp_status Engine::tick() {
+    Batch& b = *B;
+    lp_status rc;
+#define LPK_RC(x)                         \
+    do {                                  \
+        if ((rc = (x)) != LP_OK) {        \
+            error = rc;                   \
+            return rc;                    \
+        }                                 \
+    } while (0)
+    if (b.dirty) LPK_RC(b.refresh());
+    const BLaunch& L = b.L;
+    int nrun = 0, ninit = 0;
+    for (int s = 0; s < b.cap; ++s) {
+        Param& pr = b.h_param[s];
+        pr.mode = 0;
+        Member& mb = mem[s];
+        if (mb.state == RUN) {
+            pr.mode = MD_RUN;
+            mb.L = lp_iter_info{};
+            mb.cc = false;
+            ++nrun;
+        } else if (mb.state == INIT) {
+            pr.mode = MD_INIT;
+            ++ninit;
+        }
+    }
+    if (!nrun && !ninit) return LP_OK;
+
+    // residuals r_p = b - A x, r_d = c - A^T y - s and the scalars of the error measure
+    // (eq. errorMeasureDef) and of the relative stopping test
+    if (nrun) {
+        LPK_RC(b.put_params());
+        b_spmv(L, M_A_CSR, V_X, V_RP, EPI_B_MINUS, V_B, -1, MD_RUN, false);
+        b_spmv(L, M_A_CSC, V_Y, V_RD, EPI_B1_MINUS_B2, V_C, V_S, MD_RUN, false);
+        b_measures(L, MD_RUN);
+        const int ops[5] = {0, 0, 0, 0, 0};
+        b_red_finish(L, 5, ops, MD_RUN, 0);
+        LPK_HIP(hipGetLastError());
+        LPK_RC(b.get_slots());
+        for (int s = 0; s < b.cap; ++s) {
+            Member& mb = mem[s];
+            if (mb.state != RUN) continue;
+            lp_problem* p = mb.p;
+            const lp_options& o = p->opt;
+            const double* q = b.h_slot[s].out;
+            lp_iter_info& Lg = mb.L;
+            const double nb = p->norm_b, nc = p->norm_c;
+            Lg.mu = q[0] / (double)p->n;
+            Lg.rp_rel = std::sqrt(q[4]) / (nb > 1.0 ? nb : 1.0);
+            Lg.rd_rel = std::sqrt(q[2]) / (nc > 1.0 ? nc : 1.0);
+            Lg.pobj = q[1];
+            Lg.dobj = q[3];
+            Lg.gap_rel = std::fabs(q[1] - q[3]) / (std::fabs(q[1]) > 1.0 ? std::fabs(q[1]) : 1.0);
+            Lg.gamma = std::max(Lg.mu, std::max(Lg.rp_rel, Lg.rd_rel));
+            Lg.gamma_rel = std::max(Lg.gap_rel, std::max(Lg.rp_rel, Lg.rd_rel));
+            bool stop = true;
+            if (!std::isfinite(Lg.gamma_rel)) {
+                set_error("non-finite residuals");
+                p->log.push_back(Lg);
+                mb.last = Lg;
+                finish(mb, LP_DIVERGED);
+            } else if (Lg.gamma_rel <= o.eps_out) {
+                Lg.converged = 1;
+                p->log.push_back(Lg);
+                mb.last = Lg;
+                finish(mb, LP_OK);
+            } else if (p->ist.k >= mb.limit_k) {
+                // the final point is only evaluated
+                p->log.push_back(Lg);
+                mb.last = Lg;
+                finish(mb, LP_NOT_CONVERGED);
+            } else {
+                stop = false;
+            }
+            if (stop) {
+                b.h_param[s].mode = 0;
+                --nrun;
+                continue;
+            }
+            // eps_in schedule of Sec. 4.2 (x0.75 while log10 Gamma in (-3, 1], x0.375 at or
+            // below -3, x1.5 after a failed solve), clamped to [eps_in_min, eps_in_max]
+            if (p->ist.k >= 1) {
+                const double lg = std::log10(Lg.gamma);
+                double fac = 1.0;
+                if (lg <= -3.0) fac = 0.375;
+                else if (lg <= 1.0) fac = 0.75;
+                if (p->ist.fail_prev) fac *= 1.5;
+                p->ist.eps_in *= fac;
+            }
+            p->ist.eps_in = std::min(std::max(p->ist.eps_in, o.eps_in_min), o.eps_in_max);
+            Lg.eps_in = p->ist.eps_in;
+            b.h_param[s].scal[SC_TOL] = p->ist.eps_in;
+        }
+        if (!nrun && !ninit) return LP_OK;
+    }
+
+    // D = diag(sqrt(x/s)) for the step (identity for the starting-point solves); A_hat
+    for (int s = 0; s < b.cap; ++s) {
+        Member& mb = mem[s];
+        if (mb.state != RUN && mb.state != INIT) continue;
+        lp_problem* p = mb.p;
+        if (mb.state == INIT) b.h_param[s].scal[SC_TOL] = p->opt.init_tol;
+        if (p->opt.inner == LP_CIMMINO && !p->gsor) {
+            if (p->opt.omega_c > 0.0) b.h_param[s].scal[SC_OMC] = p->opt.omega_c;
+            else b.h_param[s].mode |= MD_POW;
+        }
+    }
+    LPK_RC(b.put_params());
+    b_scaling(L);
+    LPK_RC(scale_batch(b, MD_RUN | MD_INIT));
+
+    // first solve: predictor f_af = b + A (d^2 o r_d); starting point: f = b (t = 0)
+    b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_B_PLUS, V_B, -1, MD_RUN | MD_INIT, false);
+    std::vector<lp_krylov_info> ki;
+    LPK_RC(krylov_batch(b, MD_RUN | MD_INIT, &ki));
+    b_post1(b.L);
+    {
+        const int ops[2] = {1, 1};
+        b_red_finish(b.L, 2, ops, MD_RUN, 0);
+    }
+    LPK_HIP(hipGetLastError());
+    LPK_RC(b.get_slots());
+    int ncc = 0;
+    for (int s = 0; s < b.cap; ++s) {
+        Member& mb = mem[s];
+        if (mb.state != RUN) continue;
+        lp_iter_info& Lg = mb.L;
+        Lg.k_af = ki[s].iters;
+        Lg.res_af = ki[s].beta > 0.0 ? ki[s].res_true / ki[s].beta : 0.0;
+        Lg.fail_af = ki[s].failed;
+        const double eta = mb.p->opt.eta;
+        mb.ap = step_from(b.h_slot[s].out[0], eta);
+        mb.ad = step_from(b.h_slot[s].out[1], eta);
+        if (mb.ap < 1.0 || mb.ad < 1.0) {
+            mb.cc = true;
+            b.h_param[s].mode |= MD_CC;
+            b.h_param[s].scal[SC_AP] = mb.ap;
+            b.h_param[s].scal[SC_AD] = mb.ad;
+            ++ncc;
+        }
+    }
+    if (ncc) {
+        LPK_RC(b.put_params());
+        b_mu_af(b.L);
+        const int ops[1] = {0};
+        b_red_finish(b.L, 1, ops, MD_CC, 0);
+        LPK_HIP(hipGetLastError());
+        LPK_RC(b.get_slots());
+        for (int s = 0; s < b.cap; ++s) {
+            Member& mb = mem[s];
+            if (mb.state != RUN || !mb.cc) continue;
+            const lp_options& o = mb.p->opt;
+            lp_iter_info& Lg = mb.L;
+            const double mu_af = b.h_slot[s].out[0] / (double)mb.p->n;
+            double sigma;
+            if (Lg.gamma > 1e-3) {
+                const double r = mu_af / Lg.mu;
+                sigma = r * r;
+            } else {
+                sigma = 10.0 * Lg.gamma;
+            }
+            if (sigma > o.sigma_max) sigma = o.sigma_max;
+            Lg.sigma = sigma;
+            b.h_param[s].scal[SC_SMU] = sigma * Lg.mu;
+        }
+    }
+    // second solve: corrector f_cc = A ((dx_af o ds_af - sigma mu) / s); starting point:
+    // f = A c
+    if (ncc || ninit) {
+        LPK_RC(b.put_params());
+        b_rhs2(b.L);
+        b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_PLAIN, -1, -1, MD_CC | MD_INIT, false);
+        LPK_RC(krylov_batch(b, MD_CC | MD_INIT, &ki));
+        b_post2(b.L);
+        const int ops[2] = {1, 1};
+        b_red_finish(b.L, 2, ops, MD_CC | MD_INIT, 0);
+        LPK_HIP(hipGetLastError());
+        LPK_RC(b.get_slots());
+        for (int s = 0; s < b.cap; ++s) {
+            Member& mb = mem[s];
+            const double* q = b.h_slot[s].out;
+            if (mb.state == RUN && mb.cc) {
+                lp_iter_info& Lg = mb.L;
+                Lg.k_cc = ki[s].iters;
+                Lg.res_cc = ki[s].beta > 0.0 ? ki[s].res_true / ki[s].beta : 0.0;
+                Lg.fail_cc = ki[s].failed;
+                mb.ap = step_from(q[0], mb.p->opt.eta);
+                mb.ad = step_from(q[1], mb.p->opt.eta);
+            } else if (mb.state == INIT) {
+                // shift x~, s~ to positive (Mehrotra's heuristic)
+                b.h_param[s].scal[SC_HX] = -1.5 * q[0] > 0.0 ? -1.5 * q[0] : 0.0;
+                b.h_param[s].scal[SC_HS] = -1.5 * q[1] > 0.0 ? -1.5 * q[1] : 0.0;
+            }
+        }
+    }
+
+    // back-tracking until min_i x_i s_i >= phi x^T s / n at the new point (Sec. 2.1); the
+    // starting points' two shift phases run in the same launches
+    for (int s = 0; s < b.cap; ++s) {
+        Member& mb = mem[s];
+        if (mb.state != RUN) continue;
+        mb.bt = 0;
+        mb.bt_live = true;
+        b.h_param[s].mode |= MD_BT;
+        b.h_param[s].scal[SC_AP] = mb.ap;
+        b.h_param[s].scal[SC_AD] = mb.ad;
+    }
+    int stage = ninit ? 1 : 0;
+    for (;;) {
+        bool bt_any = false;
+        for (int s = 0; s < b.cap; ++s) bt_any = bt_any || (mem[s].state == RUN && mem[s].bt_live);
+        if (!stage && !bt_any) break;
+        LPK_RC(b.put_params());
+        if (stage == 1) b_shift(b.L, MD_INIT);
+        if (stage == 2) {
+            b_shift(b.L, MD_INIT);
+            b_min2(b.L, MD_INIT);
+        }
+        if (bt_any) b_backtrack(b.L);
+        const int ops1[5] = {0, 0, 0, 1, 0};
+        const int ops2[5] = {1, 1, 0, 1, 0};
+        b_red_finish(b.L, 5, stage == 2 ? ops2 : ops1, MD_INIT | MD_BT, 0);
+        LPK_HIP(hipGetLastError());
+        LPK_RC(b.get_slots());
+        for (int s = 0; s < b.cap; ++s) {
+            Member& mb = mem[s];
+            const double* q = b.h_slot[s].out;
+            if (mb.state == INIT && stage == 1) {
+                // balance: x += 1/2 x^T s / sum(s), s += 1/2 x^T s / sum(x)
+                b.h_param[s].scal[SC_HX] = 0.5 * q[0] / q[2];
+                b.h_param[s].scal[SC_HS] = 0.5 * q[0] / q[1];
+            } else if (mb.state == INIT && stage == 2) {
+                lp_problem* p = mb.p;
+                b.h_param[s].mode = 0;
+                if (!(q[0] > 0.0) || !(q[1] > 0.0)) {
+                    set_error("starting point is not strictly positive");
+                    finish(mb, LP_DIVERGED);
+                } else {
+                    p->have_point = true;
+                    p->ist.eps_in = p->opt.eps_in0;
+                    p->ist.k = 0;
+                    p->ist.fail_prev = 0;
+                    mb.state = RUN;   // its first step is the next tick's
+                }
+            } else if (mb.state == RUN && mb.bt_live) {
+                const lp_options& o = mb.p->opt;
+                if (q[3] >= o.phi * q[4] / (double)mb.p->n || mb.bt >= o.max_backtrack) {
+                    mb.bt_live = false;
+                    b.h_param[s].mode &= ~MD_BT;
+                } else {
+                    mb.ap *= o.backtrack;
+                    mb.ad *= o.backtrack;
+                    mb.bt += 1;
+                    b.h_param[s].scal[SC_AP] = mb.ap;
+                    b.h_param[s].scal[SC_AD] = mb.ad;
+                }
+            }
+        }
+        stage = stage == 1 ? 2 : 0;
+    }
+
+    // the step
+    if (nrun) {
+        LPK_RC(b.put_params());
+        b_update(b.L, 0);
+        const int ops[1] = {0};
+        b_red_finish(b.L, 1, ops, MD_RUN, 0);
+        LPK_HIP(hipGetLastError());
+        LPK_RC(b.get_slots());
+        for (int s = 0; s < b.cap; ++s) {
+            Member& mb = mem[s];
+            if (mb.state != RUN || !(b.h_param[s].mode & MD_RUN)) continue;
+            lp_problem* p = mb.p;
+            lp_iter_info& Lg = mb.L;
+            Lg.alpha_p = mb.ap;
+            Lg.alpha_d = mb.ad;
+            Lg.backtracks = mb.bt;
+            p->ist.fail_prev = (Lg.fail_af || Lg.fail_cc) ? 1 : 0;
+            p->ist.k += 1;
+            p->log.push_back(Lg);
+            mb.last = Lg;
+            if (b.h_slot[s].out[0] > 0.0) {
+                set_error("iterate left the positive orthant or became non-finite");
+                finish(mb, LP_DIVERGED);
+            }
+        }
+    }
+#undef LPK_RC
+    return LP_OK;
+}
+
+}  // namespace lpk
+
+using namespace lpk;
+
+lp_problem::~lp_problem() {
+    solo.reset();
+    arena.release();
+}
+
+// ------------------------------------------------------------------------------------
+// Timing replay: the launches of one kernel class for every member of a batch, captured
+// once with control blocks at k = 0 and replayed back-to-back between two events on the
+// batch's stream.
+static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per_launch,
+                             double* bytes_per_launch, double* flops_per_launch, int32_t* launches_per_group) {
+    if (reps < 1 || !us_per_launch) return LP_EINVAL;
+    if (cls != LP_K_SWEEP && cls != LP_K_SPMV_CSR && cls != LP_K_SPMV_CSC && cls != LP_K_GRAM) {
+        set_error("timing replay covers the sweep, the two sparse products and the Gram build");
+        return LP_EINVAL;
+    }
+    for (int s = 0; s < B.cap; ++s) {
+        lp_problem* p = B.mem[s];
+        if (!p) continue;
+        if (!p->have_point && p->krylov_total == 0) {
+            set_error("no scaling yet: run ipm_step, lp_solve or direction_solve first");
+            return LP_EINVAL;
+        }
+        if (cls == LP_K_GRAM && !p->gsor) {
+            set_error("no dense Gram path for this problem");
+            return LP_EINVAL;
+        }
+    }
+    if (B.dirty) {
+        lp_status rc = B.refresh();
+        if (rc != LP_OK) return rc;
+    }
+    for (int s = 0; s < B.cap; ++s) {
+        KrylovCtl t{};
+        t.done = 1;
+        if (B.mem[s]) {
+            t.done = 0;
+            t.active = 1;
+            t.kmax = 1;
+            t.omega_c = B.mem[s]->omega_c;
+        }
+        B.h_slot[s].ctl = t;
+    }
+    hipStream_t st = B.st;
+    LPK_HIP(hipMemcpyAsync(B.d_slot, B.h_slot, sizeof(Slot) * B.cap, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    if (!B.cap_st) LPK_HIP(hipStreamCreateWithFlags(&B.cap_st, hipStreamNonBlocking));
+    const uint32_t mask = B.prof_mask;
+    B.prof_mask = 0;
+    double bytes = 0.0, flops = 0.0;
+    int64_t launches = 0;
+    B.count_bytes = &bytes;
+    B.count_flops = &flops;
+    B.count_launch = &launches;
+    B.count_cls = cls;
+    B.L.st = B.cap_st;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(B.cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (cls == LP_K_SWEEP) {
+            enqueue_precond(B, -1, false);
+        } else if (cls == LP_K_SPMV_CSC) {
+            if (B.L.inner != 3) {
+                Prof pr(&B, LP_K_SPMV_CSC, -1, over_members(B, csc_bytes));
+                b_spmv(B.L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
+            }
+        } else if (cls == LP_K_SPMV_CSR) {
+            if (B.L.inner == 3) {
+                enqueue_products(B, -1);   // the dense path's only product, u = G p_k
+            } else {
+                Prof pr(&B, LP_K_SPMV_CSR, -1, over_members(B, csr_bytes));
+                b_spmv(B.L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
+            }
+        } else {
+            for (int s = 0; s < B.cap; ++s)
+                if (B.mem[s]) (void)build_dense_preconditioner(B, B.mem[s]);
+        }
+        e = hipStreamEndCapture(B.cap_st, &g);
+    }
+    B.L.st = st;
+    B.prof_mask = mask;
+    B.count_bytes = nullptr;
+    B.count_flops = nullptr;
+    B.count_launch = nullptr;
+    B.count_cls = -1;
+    if (e != hipSuccess) return hip_fail(e, "timing capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "timing graph instantiate");
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    LPK_HIP(hipEventCreate(&a));
+    LPK_HIP(hipEventCreate(&b));
+    LPK_HIP(hipGraphLaunch(ex, st));   // warm
+    LPK_HIP(hipEventRecord(a, st));
+    for (int32_t r = 0; r < reps; ++r) LPK_HIP(hipGraphLaunch(ex, st));
+    LPK_HIP(hipEventRecord(b, st));
+    LPK_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    LPK_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    const double per = launches > 0 ? (double)launches : 1.0;
+    *us_per_launch = (double)ms * 1e3 / ((double)reps * per);
+    if (bytes_per_launch) *bytes_per_launch = bytes / per;
+    if (flops_per_launch) *flops_per_launch = flops / per;
+    if (launches_per_group) *launches_per_group = (int32_t)launches;
+    return LP_OK;
+}
+
+extern "C" lp_status lp_time_kernel(lp_problem* p, int32_t cls, int32_t reps, double* us_per_launch,
+                                    double* bytes_per_launch, double* flops_per_launch,
+                                    int32_t* launches_per_group) {
+    if (!p) return LP_EINVAL;
+    Batch* b = nullptr;
+    lp_status rc = solo_batch(p, &b);
+    if (rc != LP_OK) return rc;
+    return time_kernel(*b, cls, reps, us_per_launch, bytes_per_launch, flops_per_launch, launches_per_group);
+}
+
+extern "C" lp_status lp_time_batch_kernel(lp_problem** problems, int32_t count, int32_t cls, int32_t reps,
+                                          double* us_per_launch, double* bytes_per_launch,
+                                          double* flops_per_launch, int32_t* launches_per_group) {
+    if (!problems || count < 1) {
+        set_error("NULL problems or count < 1");
+        return LP_EINVAL;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (!problems[i]) {
+            set_error("NULL problem");
+            return LP_EINVAL;
+        }
+        if (!batch_compatible(problems[0], problems[i])) {
+            set_error("problems of one timed batch must share precision, inner iterations and layout");
+            return LP_EINVAL;
+        }
+    }
+    for (int32_t i = 0; i < count; ++i) LPK_HIP(hipStreamSynchronize(problems[i]->st));
+    Batch B;
+    lp_status rc = B.init(count, problems[0]->st, false);
+    if (rc != LP_OK) return rc;
+    for (int32_t i = 0; i < count; ++i) B.mem[i] = problems[i];
+    rc = time_kernel(B, cls, reps, us_per_launch, bytes_per_launch, flops_per_launch, launches_per_group);
+    (void)hipStreamSynchronize(B.st);
+    return rc;
+}

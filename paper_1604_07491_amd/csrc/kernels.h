@@ -1,4 +1,10 @@
-// Internal launch wrappers of the HIP kernels (gfx950).  Not part of the C ABI.
+// Device-side data of the batched engine and the launch interface of its kernels (gfx950).
+// Not part of the C ABI.
+//
+// Every kernel works on a batch of LP instances: the launch grid is (x, S) and
+// blockIdx.y selects the instance descriptor Inst[blockIdx.y], which holds that instance's
+// sizes and device pointers.  grid.x covers the largest instance; blocks beyond an
+// instance's own range return at once.  A single LP is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,16 +12,16 @@
 
 namespace lpk {
 
-// Device-resident control block of one Krylov solve.  Every kernel of the Krylov loop
-// reads the current iteration index k and the done flag from here, so one iteration is
-// the same launch sequence for every k (it can be captured once and replayed).
+// Per-instance control block of one Krylov solve.  The loop kernels read the iteration
+// index k and the done flag from here, so one iteration is the same launch sequence for
+// every k and every instance (it is captured once and replayed).
 struct KrylovCtl {
-    int32_t k;          // number of basis vectors already completed (iteration index)
-    int32_t done;       // 1: converged, broken down or at kmax; later kernels return early
-    int32_t iters;      // iterations accepted into the least-squares solution
+    int32_t k;          // basis vectors completed (iteration index)
+    int32_t done;       // 1: converged, broken down, at kmax, or not taking part
+    int32_t iters;      // iterations in the least-squares solution
     int32_t failed;     // 1: tolerance not met
     int32_t kmax;
-    int32_t pad;
+    int32_t active;     // 1: this instance takes part in the current solve
     double beta;        // ||f_hat||
     double thresh;      // tol * beta
     double res;         // |gamma_{k+1}|
@@ -24,169 +30,144 @@ struct KrylovCtl {
     double omega_c;     // Cimmino step of the current scaling
 };
 
-enum Epilogue : int {
-    EPI_PLAIN = 0,      // out = sum
-    EPI_B_MINUS = 1,    // out = b1 - sum
-    EPI_B1_MINUS_B2 = 2,// out = b1 - sum - b2
-    EPI_B_PLUS = 3,     // out = b1 + sum
+// vectors of an instance, addressed by selector
+enum VecSel : int {
+    V_X = 0, V_Y, V_S, V_D, V_RHO, V_RP, V_RD, V_TN, V_DXA, V_DSA, V_DYA, V_DYC, V_F, V_DW, V_DYH,
+    V_TMPM, V_TMPN, V_B, V_C, V_FH, V_U, V_Z64, V_R64, V_COUNT
+};
+constexpr int V_PCOL = -1;   // column ctl->k of the multiplier vectors P
+
+// matrices of an instance for the row-dot products
+enum MatSel : int { M_A_CSR = 0, M_A_CSC = 1, M_AH_CSR = 2, M_AH_CSC = 3 };
+
+// per-instance role in the current phase (bit mask in *Inst::mode)
+enum Mode : int {
+    MD_RUN = 1,     // takes an interior-point step this tick
+    MD_INIT = 2,    // computes its starting point this tick
+    MD_CC = 4,      // solves the corrector this tick
+    MD_BT = 8,      // still back-tracking
+    MD_API = 16,    // direction_solve request
+    MD_POW = 32,    // estimates its Cimmino step this tick
 };
 
-// row-dot sparse products: out[r] = epi(sum_k val[k] * x[idx[k]]), r in [0, nrows).
-// Used for CSR (A x) and for CSC stored as CSR of A^T (A^T y).  g = lanes per row.
-void spmv_f64(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
-              const double* val, const double* x, double* out, int epi, const double* b1,
-              const double* b2, const int32_t* skip);
-void spmv_f32(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
-              const float* val, const float* x, float* out, int epi, const double* b1,
-              const int32_t* skip);
-// out = A x with x = column ctl->k of the column-major X (leading dimension ldx); skipped
-// once ctl->done is set
-void spmv_f64_col(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
-                  const double* val, const double* X, int64_t ldx, double* out,
-                  const KrylovCtl* ctl);
-// same with the sum of squares of out accumulated into per-block partials part[nblk]
-int spmv_f64_nrm(hipStream_t st, int g, int nrows, const int32_t* ptr, const int32_t* idx,
-                 const double* val, const double* x, double* out, int epi, const double* b1,
-                 double* part);
+// per-instance scalars of the current phase (Inst::scal)
+enum Scal : int { SC_TOL = 0, SC_AP, SC_AD, SC_SMU, SC_HX, SC_HS, SC_OMC, SC_COUNT = 16 };
 
-// one colour of a NE-SOR sweep over rows [r0, r1) of the colour-permuted row-scaled CSR
-void nesor_colour_f64(hipStream_t st, int g, int r0, int r1, const int32_t* ptr,
-                      const int32_t* idx, const double* val, double* z, const double* V,
-                      double* P, int64_t ldv, double omega, const KrylovCtl* ctl, int write_z);
-void nesor_colour_f32(hipStream_t st, int g, int r0, int r1, const int32_t* ptr,
-                      const int32_t* idx, const float* val, float* z, const double* V,
-                      double* P, int64_t ldv, double omega, const KrylovCtl* ctl, int write_z);
+constexpr int RED_MAXBLK = 1024;
+constexpr int RED_NQ = 8;
 
-// Cimmino pieces: p_k += w * r, with r = v_k - A z (first sweep: r = v_k)
-void cimmino_residual_f64(hipStream_t st, int g, int m, const int32_t* ptr, const int32_t* idx,
-                          const double* val, const double* z, const double* V, double* P,
-                          int64_t ldv, double omega_c, double* r, int first, const KrylovCtl* ctl);
-void cimmino_residual_f32(hipStream_t st, int g, int m, const int32_t* ptr, const int32_t* idx,
-                          const float* val, const float* z, const double* V, double* P,
-                          int64_t ldv, double omega_c, float* r, int first, const KrylovCtl* ctl);
-void cimmino_zupdate_f64(hipStream_t st, int g, int n, const int32_t* cptr, const int32_t* ridx,
-                         const double* cval, const double* r, double* z, double omega_c, int first,
-                         const KrylovCtl* ctl);
-void cimmino_zupdate_f32(hipStream_t st, int g, int n, const int32_t* cptr, const int32_t* ridx,
-                         const float* cval, const float* r, float* z, double omega_c, int first,
-                         const KrylovCtl* ctl);
-
-// start of Krylov iteration k: V[:,k] = U * inv_h (k >= 1), z = 0, P[:,k] = 0
-void krylov_prep(hipStream_t st, int64_t m, int64_t n, double* V, const double* U, double* P,
-                 int64_t ldv, double* z64, float* z32, const KrylovCtl* ctl);
-// column k of P (FP64) -> the n-vector z64 = A_hat^T p  is done by spmv_f64 on the CSC;
-// P column pointer for the current k
-void copy_pcol(hipStream_t st, int64_t m, const double* P, int64_t ldv, double* out,
-               const KrylovCtl* ctl);
-
-// CGS2 on the basis V (column-major, leading dimension ldv, columns 0..k):
-//   dots:  part[c * ldp + j] = sum_{i in chunk c} V[i, j] u[i],  j <= k
-//   reduce: h[j] = sum_c part[c * ldp + j]   (accumulate = 1: h[j] += ...; also h2 out)
-//   update: u[i] -= sum_j V[i, j] h[j];  then part2 dots (next pass) or norm partials
-struct GsPlan {
-    int rpl;            // rows per lane (chunk = 64 * rpl rows)
-    int nchunks;
-    int waves;          // waves per block
+struct Inst {
+    int32_t m, n, nnz, ncol;
+    int32_t g_csr, g_csc, nchunks, gsor;
+    int32_t rpl;                          // Gram-Schmidt rows per lane (chunk = 64 rpl rows)
+    int32_t nbr;                          // blocks of the vector reductions (own sizes only)
+    int32_t nbs;                          // blocks of the reduction over a CSR product
+    int32_t pad0;
+    int64_t ldv, ldh, ldp, kmax;
+    const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
+    const int32_t *cstart, *cg;           // colour row ranges (ncol+1), lanes per row by colour
+    const double *a, *ac;                 // A values (CSR, CSC)
+    double *ah, *ahc;                     // A_hat values (CSR, CSC)
+    float *ah32, *ahc32;                  // FP32 copies (mixed precision)
+    double* vec[V_COUNT];
+    float *z32, *r32;
+    double *V, *P, *H, *cs, *sn, *gam, *ykr, *h2, *gpart, *gpart2;
+    const double *G, *C;                  // dense path: Gram matrix and preconditioner matrix
+    const float* C32;
+    KrylovCtl* ctl;
+    double* part;                         // reduction partials [RED_NQ][RED_MAXBLK]
+    double* out;                          // reduction results [RED_NQ]
+    double* scal;                         // phase scalars [SC_COUNT]
+    int32_t* mode;                        // phase role (Mode bits)
+    double omega;
 };
-GsPlan gs_plan(int64_t m);
-void gs_dots(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
-             const double* u, double* part, int64_t ldp, const KrylovCtl* ctl);
-void gs_reduce(hipStream_t st, const GsPlan& pl, const double* part, int64_t ldp, double* H,
-               int64_t ldh, double* h2, int accumulate, const KrylovCtl* ctl);
-// mode 0: update then dots of the updated u into part; mode 1: update then ||u||^2 partials
-void gs_update(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
-               double* u, const double* h, double* part, int64_t ldp, int mode,
-               const KrylovCtl* ctl);
-// update with the reduction of the previous pass's partials pin fused in (each block sums
-// them; block 0 writes column k of H): usable while gs_fusable
-bool gs_fusable(const GsPlan& pl, int64_t kmax);
-void gs_update_fused(hipStream_t st, const GsPlan& pl, int64_t m, const double* V, int64_t ldv,
-                     double* u, const double* pin, double* part, int64_t ldp, int mode,
-                     double* H, int64_t ldh, const KrylovCtl* ctl);
-// norm finish + Givens + convergence; single block
-void gs_finish(hipStream_t st, const GsPlan& pl, const double* part, double* H, int64_t ldh,
-               double* cs, double* sn, double* gam, KrylovCtl* ctl);
 
-// solve setup: f_hat = f / rho, partial norms; then V[:,0] = f_hat / beta and ctl init
-void krylov_init_rhs(hipStream_t st, int64_t m, const double* f, const double* rho, double* fh,
-                     double* U, double* part, int* nblk_out);
-void krylov_init_ctl(hipStream_t st, int64_t m, const double* part, int nblk, const double* fh,
-                     double* V, double tol, int kmax, KrylovCtl* ctl, double* gam, double omega_c);
-// back substitution R y = gamma(1:iters) (single block)
-void krylov_backsolve(hipStream_t st, const double* H, int64_t ldh, const double* gam,
-                      double* y, KrylovCtl* ctl);
-// dyh = P[:, 0:iters] y
-void krylov_combine(hipStream_t st, int64_t m, const double* P, int64_t ldv, const double* y,
-                    double* dyh, const KrylovCtl* ctl);
-void krylov_true_res(hipStream_t st, const double* part, int nblk, KrylovCtl* ctl);
-
-// dense path: G = A A^T by FP64 MFMA (A dense row-major), u = G p_k
-void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32);
-void gemv_col(hipStream_t st, int m, const double* G, const double* P, int64_t ldv, double* u,
-              const KrylovCtl* ctl);
-
-// dense GEMM D = alpha A B + beta E + F (+1 on the diagonal shifted by diag_r0 >= 0)
-void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
-              const double* B, int64_t ldb, double beta, const double* E, const double* F,
-              int64_t lde, double* D, int64_t ldd, int diag_r0);
-// X[r0:r0+b, 0:ncols] = forward substitution with I/omega + tril(G[r0:r0+b, r0:r0+b], -1)
-void trsm_diag(hipStream_t st, int m, int r0, int b, const double* G, const double* R, int64_t ldr,
-               double* X, double omega, int ncols);
-void to_f32(hipStream_t st, int64_t len, const double* a, float* b);
-// P[:,k] = C V[:,k]
-void apply_c_f64(hipStream_t st, int m, const double* C, const double* V, double* P, int64_t ldv,
-                 const KrylovCtl* ctl);
-void apply_c_f32(hipStream_t st, int m, const float* C, const double* V, double* P, int64_t ldv,
-                 const KrylovCtl* ctl);
-
-// generic reductions: partial results per block, then a fixed-order finish
-struct Red {
-    double* part;       // [nq * maxblk]
-    int maxblk;
-    double* out;        // [nq] device
+// host-side launch description of a batch (maxima over its instances)
+struct BLaunch {
+    const Inst* I;          // device array of S descriptors
+    int S;
+    hipStream_t st;
+    int max_m, max_n;
+    int max_nbr, max_nbs;   // largest per-instance reduction block counts
+    int64_t max_ldp;        // largest kmax + 1
+    int grid_spmv[4];       // blocks of the row-dot products over each matrix
+    int gs_rpl, gs_nchunks; // largest rows per lane (template bound) and chunk count
+    bool gs_fused;
+    int mixed;              // FP32 inner iterations
+    int inner;              // lp_inner of every instance (NE-SOR, Cimmino) or 3: dense SOR
+    int ell;                // inner sweeps per preconditioner application
+    int max_ncol;
+    const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
 };
-int red_blocks(int64_t len);
-void red_finish(hipStream_t st, const Red& r, int nq, int nblk, const int* ops /*host, 0 sum 1 min*/);
 
-// interior-point elementwise kernels (n-space unless noted)
-void ipm_measures(hipStream_t st, const Red& r, int64_t m, int64_t n, const double* x,
-                  const double* s, const double* c, const double* rd, const double* b,
-                  const double* y, const double* rpv);
-void ipm_scaling(hipStream_t st, int64_t n, const double* x, const double* s, const double* rd,
-                 double* d, double* t);
-void scale_rows(hipStream_t st, int g, int m, const int32_t* ptr, const int32_t* idx,
-                const double* a, const double* d, double* rho, double* ah, float* ah32);
-void scale_cols(hipStream_t st, int n, const int32_t* cptr, const int32_t* ridx, const double* ac,
-                const double* d, const double* rho, double* ahc, float* ahc32);
-void ipm_recover_af(hipStream_t st, const Red& r, int64_t n, const double* rd, const double* dw,
-                    const double* d, const double* x, const double* s, double* ds, double* dx);
-void ipm_mu_af(hipStream_t st, const Red& r, int64_t n, const double* x, const double* s,
-               const double* dx, const double* ds, double ap, double ad);
-void ipm_cc_rhs(hipStream_t st, int64_t n, const double* dxa, const double* dsa, const double* s,
-                double smu, double* t);
-void ipm_recover_cc(hipStream_t st, const Red& r, int64_t n, const double* dw, const double* d,
-                    const double* x, const double* s, double smu, double* dxa, double* dsa);
-void ipm_ratio(hipStream_t st, const Red& r, int64_t n, const double* x, const double* s,
-               const double* dx, const double* ds);
-void ipm_backtrack(hipStream_t st, const Red& r, int64_t n, const double* x, const double* s,
-                   const double* dx, const double* ds, double ap, double ad);
-void ipm_update(hipStream_t st, const Red& r, int64_t m, int64_t n, double* x, double* s,
-                double* y, const double* dx, const double* ds, const double* dy, double ap,
-                double ad);
-// y += a * x (m-space), out = a / rho (dy from dyhat)
-void axpy(hipStream_t st, int64_t len, double a, const double* x, double* y);
-void div_by(hipStream_t st, int64_t len, const double* a, const double* rho, double* out);
+// ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------
+enum Epilogue : int { EPI_PLAIN = 0, EPI_B_MINUS = 1, EPI_B1_MINUS_B2 = 2, EPI_B_PLUS = 3 };
+// out = epi(sum) over the rows of matrix `mat` for every instance whose mode has a bit of
+// pmask (pmask 0: instances whose Krylov solve is still running).  x = vec[xsel]
+// (V_PCOL: column k of P); nrm: per-block partials of sum(out^2) into part (quantity 0,
+// Inst::nbs blocks; only for the CSR matrices).
+void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel, int b2sel,
+            int pmask, bool nrm);
+
+// ---- Krylov loop ------------------------------------------------------------------------
+void b_prep(const BLaunch& L);
+void b_nesor(const BLaunch& L, int colour, int sweep, int ell);
+void b_cim_res(const BLaunch& L, int first);
+void b_cim_z(const BLaunch& L, int first);
+void b_gs_dots(const BLaunch& L);
+void b_gs_reduce(const BLaunch& L, int accumulate);
+void b_gs_update(const BLaunch& L, int mode);
+void b_gs_finish(const BLaunch& L);
+void b_apply_c(const BLaunch& L);       // dense: P[:,k] = C v_k
+void b_gemv_col(const BLaunch& L);      // dense: u = G p_k
+// solve set-up (instances with a bit of pmask take part; the others are marked done)
+void b_init_rhs(const BLaunch& L, int pmask);
+void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap);
+void b_backsolve(const BLaunch& L);
+void b_combine(const BLaunch& L);
+void b_true_res(const BLaunch& L);
+
+// ---- scaling (Sec. 2.2, 3.5) ------------------------------------------------------------
+// MD_RUN: d = sqrt(x/s), t = d^2 r_d; MD_INIT: d = 1, t = 0; MD_API: d as given
+void b_scaling(const BLaunch& L);
+void b_scale_rows(const BLaunch& L, int pmask);
+void b_scale_cols(const BLaunch& L, int pmask);
+// one step of the power iteration for the Cimmino step (step 0 starts from e / sqrt(m));
+// b_set_omc then stores 1 / lambda in scal[SC_OMC]
+void b_power_step(const BLaunch& L, int pmask, int step);
+void b_set_omc(const BLaunch& L, int pmask);
+
+// ---- interior-point phases --------------------------------------------------------------
+// out[q] = sum (ops[q] 0) or min (1) of part[q, 0:nb], nb = Inst::nbr (which 0) or nbs (1)
+void b_red_finish(const BLaunch& L, int nq, const int* ops, int pmask, int which);
+// every reduction below uses Inst::nbr blocks per instance
+void b_measures(const BLaunch& L, int pmask);   // q0 x.s, q1 c.x, q2 ||r_d||^2, q3 b.y, q4 ||r_p||^2
+void b_post1(const BLaunch& L);           // after the first solve: q0, q1 ratio minima
+void b_mu_af(const BLaunch& L);           // MD_CC: q0 sum (x + ap dx)(s + ad ds)
+void b_rhs2(const BLaunch& L);            // t for the second solve
+void b_post2(const BLaunch& L);           // after the second solve: q0, q1 minima
+void b_shift(const BLaunch& L, int pmask);     // q0 x.s, q1 sum x, q2 sum s
+void b_min2(const BLaunch& L, int pmask);      // q0 min x, q1 min s
+void b_backtrack(const BLaunch& L);       // MD_BT: q3 min x_i s_i, q4 x.s at the trial point
+void b_update(const BLaunch& L, int q);   // MD_RUN: q = count of entries not finite positive
+void b_div_rho(const BLaunch& L, int dst, int src, int pmask);
+
+// ---- single-instance helpers (argument marshalling of the C ABI) -------------------------
 void gather(hipStream_t st, int64_t len, const double* src, const int32_t* perm, double* dst);
 void scatter(hipStream_t st, int64_t len, const double* src, const int32_t* perm, double* dst);
 void fill(hipStream_t st, int64_t len, double v, double* dst);
-// lambda of A_hat A_hat^T by power iteration (Cimmino step); w = A v / ||A v|| helpers
-void vec_scale_by_norm(hipStream_t st, const Red& r, int64_t len, double* v, int nblk_from);
-void sumsq(hipStream_t st, const Red& r, int64_t len, const double* v);
-void lincomb(hipStream_t st, int64_t len, double a, const double* x, double b, const double* y,
-             double* out);
-// starting point: min x, min s into out[0..1]; shift x += ax, s += as with x.s, sum x,
-// sum s into out[0..2]
-void min2(hipStream_t st, const Red& r, int64_t n, const double* x, const double* s);
-void shift2(hipStream_t st, const Red& r, int64_t n, double* x, double* s, double ax, double as);
+
+// ---- dense path (per instance, once per scaling) -----------------------------------------
+void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32);
+void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, const double* E, const double* F,
+              int64_t lde, double* D, int64_t ldd, int diag_r0);
+void trsm_diag(hipStream_t st, int m, int r0, int b, const double* G, const double* R, int64_t ldr,
+               double* X, double omega, int ncols);
+void to_f32(hipStream_t st, int64_t len, const double* a, float* b);
+
+int red_blocks(int64_t len);
+int spmv_blocks(int64_t rows, int g);   // blocks of a row-dot launch over `rows` rows
+constexpr int BLOCK_THREADS = 256;
 
 }  // namespace lpk

@@ -1,9 +1,10 @@
-// Internal state of an lp_problem.  Not part of the C ABI.
+// Internal state of an lp_problem and of the batched engine.  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,10 @@ lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, 
 
 // lanes per row for a row-dot over rows of mean length len
 int lanes_for(double len);
+// Gram-Schmidt rows per lane for m rows (chunks of 64 rpl rows, at most 1024 chunks)
+int gs_rpl_for(int64_t m);
+// the fused Gram-Schmidt passes need few chunks and the coefficients in LDS
+bool gs_fusable(int64_t nchunks, int64_t kmax);
 
 // owned device allocations of one problem
 struct DevArena {
@@ -67,7 +72,7 @@ struct Colour {
     int64_t nnz;        // nonzeros of the colour
 };
 
-// one timed launch: events a (before) and b (after) on the problem's stream
+// one timed launch: events a (before) and b (after) on the batch's stream
 struct ProfRec {
     int cls;
     int64_t solve;      // which Krylov solve it belongs to
@@ -76,6 +81,19 @@ struct ProfRec {
     double flops;
     hipEvent_t a, b;
 };
+
+// the per-instance control words the host reads back, and the phase parameters it writes
+struct Slot {
+    KrylovCtl ctl;
+    double out[RED_NQ];
+};
+struct Param {
+    double scal[SC_COUNT];
+    int32_t mode;
+    int32_t pad[3];
+};
+
+struct Batch;
 
 }  // namespace lpk
 
@@ -94,87 +112,148 @@ struct lp_problem {
     // host-side structure
     std::vector<int32_t> perm;        // permuted row t is original row perm[t]
     std::vector<lpk::Colour> colours;
+    std::vector<int32_t> h_cstart, h_cg;
     int g_csr = 64, g_csc = 1;
+    int rpl = 1, nchunks = 1;
 
     lpk::DevArena arena;
     // structure and data (permuted rows)
     int32_t *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr, *perm_d = nullptr;
+    int32_t *cstart = nullptr, *cg = nullptr;
     double *a = nullptr, *ac = nullptr;            // A values, CSR and CSC
     double *ah = nullptr, *ahc = nullptr;          // A_hat values, CSR and CSC
     float *ah32 = nullptr, *ahc32 = nullptr;       // FP32 copies (mixed precision)
-    double *b = nullptr, *c = nullptr;             // b permuted, c
-    // iterate and interior-point vectors
-    double *x = nullptr, *y = nullptr, *s = nullptr;
-    double *d = nullptr, *rho = nullptr, *rpv = nullptr, *rdv = nullptr, *tn = nullptr;
-    double *dxa = nullptr, *dsa = nullptr, *dya = nullptr, *dyc = nullptr;
-    double *f = nullptr, *dw = nullptr, *dyh = nullptr, *dtmp_n = nullptr, *dtmp_m = nullptr;
+    double* vec[lpk::V_COUNT] = {nullptr};         // vectors by selector
+    float *z32 = nullptr, *r32 = nullptr;
     // Krylov workspace
     int64_t kmax = 0, ldv = 0, ldh = 0;
     double *V = nullptr, *P = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gam = nullptr;
-    double *ykr = nullptr, *fhU = nullptr, *u = nullptr, *z64 = nullptr, *pcol = nullptr, *h2 = nullptr;
-    float *z32 = nullptr, *r32 = nullptr;
-    double *r64 = nullptr;
+    double *ykr = nullptr, *h2 = nullptr;
     double* gpart = nullptr;                        // (nchunks) x (kmax+1) CGS partials
     double* gpart2 = nullptr;                       // second buffer for the fused passes
-    bool gs_fused = false;
-    // captured Krylov iterations (replayed with hipGraphLaunch)
-    hipStream_t cap_st = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_iters = 0;
-    double* spart = nullptr;                        // per-block partials of a CSR product
-    double* dapi = nullptr;                         // D given to direction_solve
     double norm_b = 0.0, norm_c = 0.0;
-    lpk::KrylovCtl* ctl = nullptr;
-    lpk::GsPlan gs{};
-    double omega_c = 0.0;                           // Cimmino step of the current scaling
-    // reductions
-    lpk::Red red{};
-    double* host_out = nullptr;                     // pinned, 8 doubles
-    lpk::KrylovCtl* host_ctl = nullptr;             // pinned
     // interior-point state
     bool have_point = false;
-    bool scaled_for_d = false;                      // A_hat matches the current iterate
     lp_ipm_state ist{};
     std::vector<lp_iter_info> log;
     int64_t krylov_total = 0;
-    int64_t last_iters = 0;                         // hint for the polling period
-    // profiler
-    uint32_t prof_mask = 0;
-    lpk::KrylovCtl* tctl = nullptr;                 // control block of timing replays
-    double* count_bytes = nullptr;                  // host-side accounting of one capture
-    double* count_flops = nullptr;
-    int64_t* count_launch = nullptr;
-    int count_cls = -1;
-    int64_t solve_id = 0;
-    std::vector<lpk::ProfRec> prof_recs;
-    std::vector<hipEvent_t> prof_pool;
-    std::vector<int64_t> solve_iters;               // iterations of each profiled solve
-    int64_t prof_launch[LP_K_COUNT] = {0};
-    double prof_ms[LP_K_COUNT] = {0}, prof_bytes[LP_K_COUNT] = {0}, prof_flops[LP_K_COUNT] = {0};
+    double omega_c = 0.0;                           // Cimmino step of the current scaling
+    // the batch of one that serves the single-problem entry points
+    std::unique_ptr<lpk::Batch> solo;
+    ~lp_problem();
 };
 
 namespace lpk {
 
-// scale A_hat for the given device vector d (NULL: identity) -- rho, A_hat CSR/CSC
-lp_status build_scaling(lp_problem* p, const double* d_dev);
-// the Krylov solve of the row-scaled min-norm problem for the current A_hat:
-// f (device, permuted rows) -> dw (n) and dyh (m, multipliers with dw = A_hat^T dyh)
-lp_status krylov_solve(lp_problem* p, const double* f_dev, double tol, double* dw,
-                       double* dyh, lp_krylov_info* ki);
-lp_status ipm_init_point(lp_problem* p);
-lp_status ipm_iterate(lp_problem* p, lp_iter_info* info);
-lp_status ipm_evaluate(lp_problem* p, lp_iter_info* info);
-lp_status sync_read(lp_problem* p, const double* dev, double* host, int count);
+// A batch: up to `cap` problems whose phases run in lockstep, one launch per phase for all
+// of them.  Descriptors live in device memory; the graph of Krylov iterations is captured
+// for the current membership and replayed.
+struct Batch {
+    int cap = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::vector<lp_problem*> mem;     // per slot; nullptr when empty
+    Inst* d_inst = nullptr;
+    std::vector<Inst> h_inst;
+    Slot* d_slot = nullptr;
+    Slot* h_slot = nullptr;           // pinned
+    Param* d_param = nullptr;
+    Param* h_param = nullptr;         // pinned
+    double* d_part = nullptr;         // cap x RED_NQ x RED_MAXBLK
+    BLaunch L{};
+    std::vector<int> grid_colour;
+    bool dirty = true;                // membership changed since the descriptors were uploaded
+    // captured Krylov iterations
+    hipStream_t cap_st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_iters = 0;
+    int64_t last_iters = 0;           // polling hint
+    // profiler (events on st) and launch accounting for timing captures
+    uint32_t prof_mask = 0;
+    double* count_bytes = nullptr;
+    double* count_flops = nullptr;
+    int64_t* count_launch = nullptr;
+    int count_cls = -1;
+    int64_t solve_id = 0;
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<int64_t> solve_iters;
+    int64_t prof_launch[LP_K_COUNT] = {0};
+    double prof_ms[LP_K_COUNT] = {0}, prof_bytes[LP_K_COUNT] = {0}, prof_flops[LP_K_COUNT] = {0};
+
+    ~Batch();
+    lp_status init(int capacity, hipStream_t stream, bool own);
+    int free_slot() const;
+    int members() const;
+    // make the device descriptors, launch maxima and graph match the membership
+    lp_status refresh();
+    void drop_graph();
+    // upload the phase parameters of every slot (scal, mode)
+    lp_status put_params();
+    // read the control words and reduction results of every slot (synchronises the stream)
+    lp_status get_slots();
+};
+
+// homogeneity key: problems of one batch share these
+bool batch_compatible(const lp_problem* a, const lp_problem* b);
+
+// the batched Krylov solve (AB-GMRES with inner-iteration preconditioning, Sec. 3.2) for
+// every slot whose mode has a bit of pmask: f = vec[V_F] (permuted rows) -> dw (V_DW) and
+// the multipliers dyh (V_DYH, dw = A_hat^T dyh).  Tolerances from scal[SC_TOL].
+lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info);
+// rho and A_hat for every slot with a bit of pmask (d = vec[V_D]); dense: G and C<l>;
+// Cimmino: the step from the power iteration for slots marked MD_POW
+lp_status scale_batch(Batch& B, int pmask);
+lp_status build_dense_preconditioner(Batch& B, lp_problem* p);
+
+// Lockstep interior-point driver over a batch
+struct Engine {
+    enum State { EMPTY = 0, INIT, RUN, DONE };
+    struct Member {
+        lp_problem* p = nullptr;
+        State state = EMPTY;
+        int32_t limit_k = 0;          // evaluate only once ist.k reaches it
+        lp_status status = LP_OK;
+        int32_t iters = 0;
+        lp_iter_info L{};             // the current tick's log entry
+        lp_iter_info last{};          // the final measures
+        bool cc = false;
+        double ap = 0.0, ad = 0.0;
+        int32_t bt = 0;
+        bool bt_live = false;
+        double t_join = 0.0, t_done = 0.0;
+        int64_t k0 = 0;               // krylov_total at join
+    };
+    Batch* B = nullptr;
+    std::vector<Member> mem;
+    lp_status error = LP_OK;          // a device error stops the whole batch
+
+    void attach(Batch* b);
+    // join a free slot: start INIT (starting point first) or RUN (from the point it holds)
+    int join(lp_problem* p, bool from_point, int32_t limit_k);
+    // one tick: every INIT member computes its starting point, every RUN member takes one
+    // interior-point step or finishes
+    lp_status tick();
+    bool any_live() const;
+    void leave(int slot);             // empty a slot (state DONE or EMPTY)
+};
+
+double now_seconds();
+void fill_result(const Engine::Member& mb, lp_result* r);
 
 // profiler: bracket a launch of class cls with events when cls is enabled
 struct Prof {
-    lp_problem* p;
+    Batch* B;
     int idx = -1;
-    Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops = 0.0);
+    Prof(Batch* b, int cls, int64_t iter, double bytes, double flops = 0.0);
     ~Prof();
 };
-lp_status prof_collect(lp_problem* p);
-void prof_release(lp_problem* p);
+lp_status prof_collect(Batch& B);
+void prof_release(Batch& B);
+
+// the solo batch of a problem (created on first use, on the problem's stream)
+lp_status solo_batch(lp_problem* p, Batch** out);
 
 }  // namespace lpk

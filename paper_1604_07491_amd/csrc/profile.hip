@@ -1,4 +1,4 @@
-// Per-launch kernel timing with HIP events on the problem's stream.  A launch of an
+// Per-launch kernel timing with HIP events on a batch's stream.  A launch of an
 // enabled class is bracketed by two events; statistics are folded in when they are read
 // (or when the record list grows long), keeping only launches that did work: loop
 // kernels enqueued after a solve had converged return at once and are discarded by
@@ -11,7 +11,7 @@ namespace lpk {
 
 static const char* kClassName[LP_K_COUNT] = {"sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update", "gram"};
 
-static hipEvent_t take_event(lp_problem* p) {
+static hipEvent_t take_event(Batch* p) {
     if (!p->prof_pool.empty()) {
         hipEvent_t e = p->prof_pool.back();
         p->prof_pool.pop_back();
@@ -22,7 +22,8 @@ static hipEvent_t take_event(lp_problem* p) {
     return e;
 }
 
-Prof::Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops) : p(pp) {
+Prof::Prof(Batch* pp, int cls, int64_t iter, double bytes, double flops) : B(pp) {
+    Batch* p = B;
     if (p->count_launch && cls == p->count_cls) {
         *p->count_launch += 1;
         *p->count_bytes += bytes;
@@ -38,16 +39,17 @@ Prof::Prof(lp_problem* pp, int cls, int64_t iter, double bytes, double flops) : 
     r.a = take_event(p);
     r.b = take_event(p);
     if (!r.a || !r.b) return;
-    (void)hipEventRecord(r.a, p->st);
+    (void)hipEventRecord(r.a, p->L.st);
     idx = (int)p->prof_recs.size();
     p->prof_recs.push_back(r);
 }
 
 Prof::~Prof() {
-    if (idx >= 0) (void)hipEventRecord(p->prof_recs[idx].b, p->st);
+    if (idx >= 0) (void)hipEventRecord(B->prof_recs[idx].b, B->L.st);
 }
 
-lp_status prof_collect(lp_problem* p) {
+lp_status prof_collect(Batch& B) {
+    Batch* p = &B;
     if (p->prof_recs.empty()) return LP_OK;
     LPK_HIP(hipStreamSynchronize(p->st));
     for (ProfRec& r : p->prof_recs) {
@@ -72,7 +74,8 @@ lp_status prof_collect(lp_problem* p) {
     return LP_OK;
 }
 
-void prof_release(lp_problem* p) {
+void prof_release(Batch& B) {
+    Batch* p = &B;
     if (p->st) (void)hipStreamSynchronize(p->st);
     for (ProfRec& r : p->prof_recs) {
         p->prof_pool.push_back(r.a);
@@ -90,9 +93,12 @@ using namespace lpk;
 
 extern "C" {
 
-lp_status lp_profile(lp_problem* p, uint32_t mask) {
-    if (!p) return LP_EINVAL;
-    lp_status rc = prof_collect(p);
+lp_status lp_profile(lp_problem* pr, uint32_t mask) {
+    if (!pr) return LP_EINVAL;
+    Batch* p = nullptr;
+    lp_status rc = solo_batch(pr, &p);
+    if (rc != LP_OK) return rc;
+    rc = prof_collect(*p);
     if (rc != LP_OK) return rc;
     p->prof_mask = mask;
     for (int c = 0; c < LP_K_COUNT; ++c) {
@@ -104,9 +110,12 @@ lp_status lp_profile(lp_problem* p, uint32_t mask) {
     return LP_OK;
 }
 
-lp_status lp_profile_read(lp_problem* p, lp_kernel_stat* st, int32_t cap, int32_t* n_out) {
-    if (!p || !n_out) return LP_EINVAL;
-    lp_status rc = prof_collect(p);
+lp_status lp_profile_read(lp_problem* pr, lp_kernel_stat* st, int32_t cap, int32_t* n_out) {
+    if (!pr || !n_out) return LP_EINVAL;
+    Batch* p = nullptr;
+    lp_status rc = solo_batch(pr, &p);
+    if (rc != LP_OK) return rc;
+    rc = prof_collect(*p);
     if (rc != LP_OK) return rc;
     *n_out = LP_K_COUNT;
     for (int c = 0; c < LP_K_COUNT && st && c < cap; ++c) {

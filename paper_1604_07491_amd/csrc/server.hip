@@ -1,5 +1,8 @@
-// Concurrent solves: lp_solve_batch over created problems, and the request-driven server
-// (HBM-footprint admission, FIFO with bounded skip, continuous admission as slots free).
+// Many LPs on one MI355X: lp_solve_batch over created problems, and the request-driven
+// server.  Both run the batched engine: up to `width` LPs in lockstep, every phase of an
+// interior-point iteration one launch for all of them.  A finished LP leaves the batch at
+// the end of a tick and a waiting one joins (its starting point is computed during the
+// next tick), so the batch stays full while work remains.
 #include <string.h>
 
 #include <atomic>
@@ -17,46 +20,91 @@
 
 using namespace lpk;
 
-extern "C" lp_status lp_solve_batch(lp_problem** problems, int32_t count, int32_t workers,
-                                    lp_result* results) {
-    if (!problems || !results || count < 0 || workers < 1) return LP_EINVAL;
-    if (count == 0) return LP_OK;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return LP_EDEVICE;
-    std::atomic<int32_t> next{0};
-    std::atomic<int> first_err{LP_OK};
-    const int32_t nw = workers < count ? workers : count;
-    std::vector<std::thread> th;
-    for (int32_t w = 0; w < nw; ++w) {
-        th.emplace_back([&, dev]() {
-            if (hipSetDevice(dev) != hipSuccess) {
-                first_err.store(LP_EDEVICE);
-                return;
-            }
-            hipStream_t st = nullptr;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-                first_err.store(LP_EDEVICE);
-                return;
-            }
-            for (;;) {
-                const int32_t i = next.fetch_add(1);
-                if (i >= count) break;
-                lp_problem* p = problems[i];
-                hipStream_t keep = p->st;
-                p->st = st;
-                const lp_status rc = lp_solve(p, &results[i]);
-                p->st = keep;
-                if (rc != LP_OK && rc != LP_NOT_CONVERGED && rc != LP_DIVERGED) {
-                    int expect = LP_OK;
-                    first_err.compare_exchange_strong(expect, (int)rc);
-                }
-            }
-            (void)hipStreamSynchronize(st);
+// one group of compatible problems through one batch of width `width`
+static lp_status solve_group(lp_problem** problems, const std::vector<int32_t>& idx, int32_t width,
+                             lp_result* results) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LP_EDEVICE;
+    for (int32_t i : idx)
+        if (hipStreamSynchronize(problems[i]->st) != hipSuccess) {
             (void)hipStreamDestroy(st);
-        });
+            return LP_EDEVICE;
+        }
+    Batch B;
+    lp_status rc = B.init(std::min<int32_t>(width, (int32_t)idx.size()), st, true);
+    if (rc != LP_OK) return rc;
+    Engine E;
+    E.attach(&B);
+    std::vector<int32_t> who((size_t)B.cap, -1);
+    size_t next = 0;
+    auto refill = [&]() {
+        while (next < idx.size()) {
+            const int slot = B.free_slot();
+            if (slot < 0) break;
+            const int32_t i = idx[next++];
+            lp_problem* p = problems[i];
+            bool from_point = false;
+            if (p->opt.start != 0) {
+                if (!p->have_point) {
+                    memset(&results[i], 0, sizeof(lp_result));
+                    results[i].status = LP_EINVAL;
+                    continue;
+                }
+                p->ist.eps_in = p->opt.eps_in0;
+                p->ist.k = 0;
+                p->ist.fail_prev = 0;
+                from_point = true;
+            }
+            p->log.clear();
+            p->krylov_total = 0;
+            who[E.join(p, from_point, p->opt.ipm_max_iter)] = i;
+        }
+    };
+    refill();
+    while (E.any_live()) {
+        rc = E.tick();
+        if (rc != LP_OK) break;
+        for (int s = 0; s < B.cap; ++s) {
+            if (E.mem[s].state != Engine::DONE) continue;
+            fill_result(E.mem[s], &results[who[s]]);
+            E.leave(s);
+            who[s] = -1;
+        }
+        refill();
     }
-    for (auto& t : th) t.join();
-    return (lp_status)first_err.load();
+    (void)hipStreamSynchronize(st);
+    return rc;
+}
+
+extern "C" lp_status lp_solve_batch(lp_problem** problems, int32_t count, int32_t width,
+                                    lp_result* results) {
+    if (!problems || !results || count < 0 || width < 1) {
+        set_error("NULL arrays, count < 0 or width < 1");
+        return LP_EINVAL;
+    }
+    for (int32_t i = 0; i < count; ++i)
+        if (!problems[i]) {
+            set_error("NULL problem");
+            return LP_EINVAL;
+        }
+    // groups of problems that can share launches, in order of first appearance
+    std::vector<std::vector<int32_t>> groups;
+    for (int32_t i = 0; i < count; ++i) {
+        bool placed = false;
+        for (auto& g : groups)
+            if (batch_compatible(problems[g[0]], problems[i])) {
+                g.push_back(i);
+                placed = true;
+                break;
+            }
+        if (!placed) groups.push_back({i});
+    }
+    lp_status first = LP_OK;
+    for (auto& g : groups) {
+        const lp_status rc = solve_group(problems, g, width, results);
+        if (rc != LP_OK && first == LP_OK) first = rc;
+    }
+    return first;
 }
 
 namespace {
@@ -76,6 +124,12 @@ struct Solution {
     std::vector<double> x, y, s;
 };
 
+// a created problem waiting to join the batch
+struct Ready {
+    std::unique_ptr<Request> req;
+    lp_problem* p = nullptr;
+};
+
 }  // namespace
 
 struct lp_server {
@@ -83,8 +137,10 @@ struct lp_server {
     int device = 0;
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<std::unique_ptr<Request>> queue;
+    std::condition_variable cv_work, cv_ready, cv_done;
+    std::deque<std::unique_ptr<Request>> queue;   // submitted, not admitted
+    std::deque<Ready> ready;                      // admitted and created, not joined
+    int32_t preparing = 0;
     std::deque<lp_completion> done;
     std::map<uint64_t, Solution> solutions;
     uint64_t next_ticket = 1;
@@ -92,7 +148,7 @@ struct lp_server {
     int32_t running = 0;
     int64_t outstanding = 0;   // submitted and not completed
     bool stop = false;
-    std::vector<std::thread> workers;
+    std::thread prep, engine;
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -122,7 +178,22 @@ static std::unique_ptr<Request> take_admissible(lp_server* s) {
     return nullptr;
 }
 
-static void worker_main(lp_server* s) {
+static void complete(lp_server* s, lp_completion cpl, uint64_t fp, Solution sol, bool was_running) {
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->in_use -= fp;
+        if (was_running) s->running -= 1;
+        s->outstanding -= 1;
+        s->solutions[cpl.ticket] = std::move(sol);
+        s->done.push_back(cpl);
+    }
+    s->cv_work.notify_all();
+    s->cv_ready.notify_all();
+    s->cv_done.notify_all();
+}
+
+// admission and host-side set-up (validation was done at submit; colouring, CSC, copies)
+static void prep_main(lp_server* s) {
     if (hipSetDevice(s->device) != hipSuccess) return;
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
@@ -136,50 +207,119 @@ static void worker_main(lp_server* s) {
             });
             if (!r) break;   // stopping and nothing queued
             s->in_use += r->footprint;
-            s->running += 1;
+            s->preparing += 1;
         }
-        lp_completion cpl;
-        memset(&cpl, 0, sizeof(cpl));
-        cpl.ticket = r->ticket;
-        cpl.t_submit = r->t_submit;
-        cpl.t_start = s->now();
-        cpl.footprint = r->footprint;
         lp_options o = s->opt.solver;
         o.device_io = 0;
         o.stream = st;
         lp_problem* p = nullptr;
-        Solution sol;
-        lp_status rc = lp_create(r->m, r->n, r->nnz, r->rp.data(), r->ci.data(), r->val.data(),
-                                 r->b.data(), r->c.data(), &o, &p);
-        if (rc == LP_OK) {
-            lp_result res;
-            rc = lp_solve(p, &res);
-            cpl.iters = res.iters;
-            cpl.pobj = res.pobj;
-            cpl.dobj = res.dobj;
-            cpl.gamma_rel = res.gamma_rel;
-            cpl.krylov_iters = res.krylov_iters;
-            sol.x.resize((size_t)r->n);
-            sol.y.resize((size_t)r->m);
-            sol.s.resize((size_t)r->n);
-            lp_status rc2 = lp_get_state(p, sol.x.data(), sol.y.data(), sol.s.data(), nullptr);
-            if (rc2 != LP_OK && (rc == LP_OK || rc == LP_NOT_CONVERGED)) rc = rc2;
-            lp_destroy(p);
+        const lp_status rc = lp_create(r->m, r->n, r->nnz, r->rp.data(), r->ci.data(), r->val.data(),
+                                       r->b.data(), r->c.data(), &o, &p);
+        if (rc != LP_OK) {
+            lp_completion cpl;
+            memset(&cpl, 0, sizeof(cpl));
+            cpl.ticket = r->ticket;
+            cpl.status = rc;
+            cpl.t_submit = r->t_submit;
+            cpl.t_start = cpl.t_done = s->now();
+            cpl.footprint = r->footprint;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->preparing -= 1;
+            }
+            complete(s, cpl, r->footprint, Solution(), false);
+            continue;
         }
-        cpl.status = rc;
-        cpl.t_done = s->now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->in_use -= r->footprint;
-            s->running -= 1;
-            s->outstanding -= 1;
-            s->solutions[r->ticket] = std::move(sol);
-            s->done.push_back(cpl);
+            s->preparing -= 1;
+            Ready rd;
+            rd.req = std::move(r);
+            rd.p = p;
+            s->ready.push_back(std::move(rd));
         }
-        s->cv_work.notify_all();
-        s->cv_done.notify_all();
+        s->cv_ready.notify_all();
     }
+    (void)hipStreamSynchronize(st);
+    // problems created here now run on the engine's stream
     (void)hipStreamDestroy(st);
+}
+
+// the lockstep batch: join ready problems into free slots at tick boundaries, tick, and
+// complete the members that finished
+static void engine_main(lp_server* s) {
+    if (hipSetDevice(s->device) != hipSuccess) return;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    Batch B;
+    if (B.init(s->opt.slots, st, true) != LP_OK) return;
+    Engine E;
+    E.attach(&B);
+    std::vector<Ready> held((size_t)B.cap);
+    std::vector<double> t_start((size_t)B.cap, 0.0);
+    for (;;) {
+        std::vector<Ready> joining;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_ready.wait(lk, [&] {
+                if (E.any_live()) return true;
+                if (!s->ready.empty()) return true;
+                return s->stop && s->queue.empty() && s->ready.empty() && s->preparing == 0;
+            });
+            int free = 0;
+            for (int i = 0; i < B.cap; ++i) free += B.mem[i] == nullptr;
+            while (free > 0 && !s->ready.empty()) {
+                joining.push_back(std::move(s->ready.front()));
+                s->ready.pop_front();
+                --free;
+                s->running += 1;
+            }
+            if (joining.empty() && !E.any_live()) break;
+        }
+        for (Ready& rd : joining) {
+            // the problem was created (and synchronised) on the preparer's stream
+            rd.p->st = st;
+            const int slot = E.join(rd.p, false, rd.p->opt.ipm_max_iter);
+            t_start[slot] = s->now();
+            held[slot] = std::move(rd);
+        }
+        const lp_status trc = E.tick();
+        for (int slot = 0; slot < B.cap; ++slot) {
+            Engine::Member& mb = E.mem[slot];
+            if (mb.state != Engine::DONE && !(trc != LP_OK && mb.state != Engine::EMPTY)) continue;
+            Ready& rd = held[slot];
+            lp_completion cpl;
+            memset(&cpl, 0, sizeof(cpl));
+            cpl.ticket = rd.req->ticket;
+            cpl.t_submit = rd.req->t_submit;
+            cpl.t_start = t_start[slot];
+            cpl.footprint = rd.req->footprint;
+            Solution sol;
+            if (trc != LP_OK) {
+                cpl.status = trc;
+            } else {
+                lp_result res;
+                fill_result(mb, &res);
+                cpl.status = res.status;
+                cpl.iters = res.iters;
+                cpl.pobj = res.pobj;
+                cpl.dobj = res.dobj;
+                cpl.gamma_rel = res.gamma_rel;
+                cpl.krylov_iters = res.krylov_iters;
+                sol.x.resize((size_t)rd.req->n);
+                sol.y.resize((size_t)rd.req->m);
+                sol.s.resize((size_t)rd.req->n);
+                const lp_status rc2 = lp_get_state(rd.p, sol.x.data(), sol.y.data(), sol.s.data(), nullptr);
+                if (rc2 != LP_OK) cpl.status = rc2;
+            }
+            cpl.t_done = s->now();
+            E.leave(slot);
+            lp_destroy(rd.p);
+            const uint64_t fp = rd.req->footprint;
+            held[slot] = Ready();
+            complete(s, cpl, fp, std::move(sol), true);
+        }
+    }
 }
 
 extern "C" {
@@ -187,7 +327,7 @@ extern "C" {
 lp_status lp_server_options_default(lp_server_options* o) {
     if (!o) return LP_EINVAL;
     memset(o, 0, sizeof(*o));
-    o->slots = 8;
+    o->slots = 32;
     o->max_skip = 8;
     o->hbm_budget = 0;
     return lp_options_default(&o->solver);
@@ -218,7 +358,8 @@ lp_status lp_server_create(const lp_server_options* o, lp_server** out) {
         s->opt.hbm_budget = (uint64_t)(0.8 * (double)fr);
     }
     s->t0 = std::chrono::steady_clock::now();
-    for (int32_t w = 0; w < s->opt.slots; ++w) s->workers.emplace_back(worker_main, s);
+    s->prep = std::thread(prep_main, s);
+    s->engine = std::thread(engine_main, s);
     *out = s;
     return LP_OK;
 }
@@ -316,7 +457,9 @@ lp_status lp_server_destroy(lp_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    for (auto& t : s->workers) t.join();
+    s->prep.join();
+    s->cv_ready.notify_all();
+    s->engine.join();
     delete s;
     return LP_OK;
 }

@@ -1,7 +1,8 @@
-"""Concurrent solves and the request server (GPU).
+"""Lockstep batches and the request server (GPU).
 
-Every solve's arithmetic is independent of what else runs on the device, so a result must
-be bitwise identical alone and in the concurrent mix.  Admission must keep the summed
+Every reduction of an LP is partitioned by that LP's own sizes, so a result must be
+bitwise identical alone (a batch of one) and inside any batch, including when LPs leave
+and others join mid-way.  Admission must keep the summed
 footprint of running requests within the budget, reject requests that can never fit, and
 still complete every accepted request."""
 import numpy as np
@@ -32,7 +33,7 @@ def test_batch_results_identical_alone_and_in_mix(precision):
             r = lpk.lp_solve(p)
             alone.append((r, lpk.lp_get_state(p)[:3]))
     probs = [lpk.from_lp(lp, lpk.options(precision=precision)) for lp in lps]
-    res = lpk.lp_solve_batch(probs, workers=3)
+    res = lpk.lp_solve_batch(probs, width=3)
     for i, p in enumerate(probs):
         x, y, s, _ = lpk.lp_get_state(p)
         r0, (x0, y0, s0) = alone[i]
@@ -44,6 +45,47 @@ def test_batch_results_identical_alone_and_in_mix(precision):
     for lp, (r0, _) in zip(lps[:3], alone[:3]):
         o = oracle.ipm(lp)
         assert abs(r0["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+
+
+def test_batch_mixed_groups_and_dense():
+    """fp64 and mixed problems in one call form two groups; small dense (basis pursuit)
+    problems run the Gram-matrix path in lockstep."""
+    sp = _mix(3, seed0=20)
+    bp = [synth.basis_pursuit_lp(64, 160, 6, seed=s) for s in (3, 4, 5)]
+    mk = [
+        lambda: lpk.from_lp(sp[0]),
+        lambda: lpk.from_lp(sp[1], lpk.options(precision="mixed")),
+        lambda: lpk.from_lp(sp[2]),
+    ] + [(lambda lp=lp: lpk.lp_create_dense(lp.dense, lp.b, lp.c)) for lp in bp]
+    alone = []
+    for f in mk:
+        with f() as q:
+            r = lpk.lp_solve(q)
+            alone.append((r, lpk.lp_get_state(q)[0]))
+    made = [f() for f in mk]
+    res = lpk.lp_solve_batch(made, width=2)
+    for i, p in enumerate(made):
+        assert res[i]["status"] == lpk.LP_OK
+        assert res[i]["iters"] == alone[i][0]["iters"]
+        assert np.array_equal(lpk.lp_get_state(p)[0], alone[i][1])
+        p.close()
+
+
+def test_batch_timing_replay():
+    lps = _mix(4, seed0=30)
+    probs = [lpk.from_lp(lp) for lp in lps]
+    lpk.lp_solve_batch(probs, width=4)
+    one = lpk.lp_time_kernel(probs[0], lpk.LP_K_SWEEP, reps=20)
+    allb = lpk.lp_time_batch_kernel(probs, lpk.LP_K_SWEEP, reps=20)
+    assert allb["us_per_launch"] > 0 and one["us_per_launch"] > 0
+    # bytes are summed over the batch
+    per = []
+    for p in probs:
+        t = lpk.lp_time_kernel(p, lpk.LP_K_SWEEP, reps=2)
+        per.append(t["bytes_per_launch"] * t["launches_per_group"])
+    assert abs(allb["bytes_per_launch"] * allb["launches_per_group"] - sum(per)) <= 1e-9 * sum(per)
+    for p in probs:
+        p.close()
 
 
 def test_server_admission_and_results():
