@@ -50,8 +50,8 @@ def main():
     ap.add_argument("--workload", default="transport_300x300",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
                              "sparse_120000x434580"])
-    ap.add_argument("--batch", type=int, default=32, help="LPs per step")
-    ap.add_argument("--width", type=int, default=32, help="LPs in lockstep")
+    ap.add_argument("--batch", type=int, default=64, help="LPs per step")
+    ap.add_argument("--width", type=int, default=64, help="LPs in lockstep")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "cimmino"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

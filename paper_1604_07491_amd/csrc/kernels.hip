@@ -1,6 +1,6 @@
 // Batched HIP kernels of the interior-point direction path for CDNA4 (gfx950, wave64).
 //
-// Grid (x, S): blockIdx.y is the instance, Inst[blockIdx.y] its descriptor.  Reductions
+// Grid (x, S): one row of blocks per instance (see block_map), Inst[instance] its descriptor.  Reductions
 // are two-stage (per-block partials, then one fixed-order pass per instance), so results
 // are deterministic and do not depend on the other instances of the batch.
 //
@@ -21,7 +21,35 @@ namespace lpk {
 constexpr int BLOCK = 256;
 constexpr int GRID_CAP = 2048;
 
-#define INST const Inst& in = I[blockIdx.y]
+// Workgroups are dispatched to the 8 XCDs round-robin in linear order (x fastest).  When
+// the batch is a multiple of 8, hardware block w is mapped to instance (w mod 8) + 8 q and
+// block index w / 8 - q gx of it (q = (w / 8) / gx), so every block of one instance runs on
+// the same XCD and that instance's vectors (z, V, the row data) stay in one L2.  Otherwise
+// blockIdx is used as it is.  Either way the map is a bijection onto (instance, block).
+struct BlockMap {
+    int inst, bx;
+};
+__device__ __forceinline__ BlockMap block_map() {
+    BlockMap r;
+    const int gx = (int)gridDim.x;
+    if ((gridDim.y & 7) == 0) {
+        const int w = (int)blockIdx.x + (int)blockIdx.y * gx;
+        const int local = w >> 3;
+        const int q = local / gx;
+        r.inst = (w & 7) + 8 * q;
+        r.bx = local - q * gx;
+    } else {
+        r.inst = (int)blockIdx.y;
+        r.bx = (int)blockIdx.x;
+    }
+    return r;
+}
+
+#define INST                               \
+    const BlockMap bm_ = block_map();      \
+    const int bx = bm_.bx;                 \
+    (void)bx;                              \
+    const Inst& in = I[bm_.inst]
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 static inline unsigned capg(int64_t blocks, int64_t cap) {
@@ -83,8 +111,8 @@ __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
     return in.ctl->active != 0;                 // -1: took part in the current solve
 }
 
-__device__ __forceinline__ void write_part(const Inst& in, int q, double v) {
-    if (threadIdx.x == 0) in.part[q * RED_MAXBLK + blockIdx.x] = v;
+__device__ __forceinline__ void write_part(const Inst& in, int bx, int q, double v) {
+    if (threadIdx.x == 0) in.part[q * RED_MAXBLK + bx] = v;
 }
 
 // ------------------------------------------------------------------------------------
@@ -112,9 +140,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     const int64_t total = (int64_t)rows * g;
     // the reduction's partition depends on the instance alone (nbs blocks)
     const int nb = nrm ? in.nbs : (int)gridDim.x;
-    if ((int)blockIdx.x >= nb) return;
+    if (bx >= nb) return;
     double q = 0.0;
-    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK; t0 < total; t0 += (int64_t)nb * BLOCK) {
+    for (int64_t t0 = (int64_t)bx * BLOCK; t0 < total; t0 += (int64_t)nb * BLOCK) {
         const int64_t t = t0 + threadIdx.x;
         const int row = (int)(t / g);
         double sum = 0.0;
@@ -135,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     }
     if (nrm) {
         const double r = block_sum(q, sh);
-        write_part(in, 0, r);
+        write_part(in, bx, 0, r);
     }
 }
 
@@ -156,16 +184,16 @@ __global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int 
     const double ih = in.ctl->inv_h;
     const double* __restrict__ u = in.vec[V_U];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < in.m; i += stride) {
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) {
         in.V[k * in.ldv + i] = u[i] * ih;
         in.P[k * in.ldv + i] = 0.0;
     }
     if (inner == 0 && !in.gsor) {   // NE-SOR
         if (mixed) {
-            for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
+            for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
         } else {
             double* __restrict__ z = in.vec[V_Z64];
-            for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < in.n; j += stride) z[j] = 0.0;
+            for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) z[j] = 0.0;
         }
     }
 }
@@ -188,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     INST;
     if (in.ctl->done || in.gsor || c >= in.ncol) return;
     const int r0 = in.cstart[c], r1 = in.cstart[c + 1], g = in.cg[c];
-    const int tid = blockIdx.x * BLOCK + threadIdx.x;
+    const int tid = bx * BLOCK + threadIdx.x;
     const int row = r0 + tid / g, lane = tid & (g - 1);
     if (row >= r1) return;   // uniform inside the sub-group; no block barrier below
     const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
@@ -268,7 +296,7 @@ __global__ __launch_bounds__(BLOCK) void k_cim_res(const Inst* __restrict__ I, i
     }
     const double w = in.ctl->omega_c;
     const int64_t total = (int64_t)in.m * g;
-    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
+    for (int64_t t0 = (int64_t)bx * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
         const int64_t t = t0 + threadIdx.x;
         const int row = (int)(t / g);
         T sum = 0;
@@ -301,7 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_cim_z(const Inst* __restrict__ I, int
     }
     const T wc = (T)in.ctl->omega_c;
     const int64_t total = (int64_t)in.n * g;
-    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
+    for (int64_t t0 = (int64_t)bx * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
         const int64_t t = t0 + threadIdx.x;
         const int col = (int)(t / g);
         T sum = 0;
@@ -334,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply_c(const Inst* __restrict__ I) {
     if (in.ctl->done || !in.gsor) return;
     const int64_t k = in.ctl->k;
     const int m = in.m;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int i = bx * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= m) return;
     const double* __restrict__ v = in.V + k * in.ldv;
     const T* __restrict__ ci;
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(BLOCK) void k_gemv_col(const Inst* __restrict__ I) 
     if (in.ctl->done || !in.gsor) return;
     const int m = in.m;
     const double* __restrict__ p = in.P + (int64_t)in.ctl->k * in.ldv;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int i = bx * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= m) return;
     const double* __restrict__ gi = in.G + (int64_t)i * m;
     double acc = 0.0;
@@ -379,12 +407,12 @@ constexpr int GS_HLDS = 2048;   // coefficients staged in LDS by the fused reduc
 template <int RPL>
 __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_dots(const Inst* __restrict__ I) {
     INST;
-    if (in.ctl->done || (int)blockIdx.x >= in.nchunks) return;
+    if (in.ctl->done || bx >= in.nchunks) return;
     const int k = in.ctl->k;
     const int rpl = in.rpl;   // <= RPL
     const int64_t m = in.m;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * 64 * rpl;
+    const int64_t base = (int64_t)bx * 64 * rpl;
     const double* __restrict__ u = in.vec[V_U];
     double uu[RPL];
 #pragma unroll
@@ -401,7 +429,7 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_dots(const Inst* __restric
             if (t < rpl && i < m) acc += vj[i] * uu[t];
         }
         acc = wave_sum(acc);
-        if (lane == 0) in.gpart[(int64_t)blockIdx.x * in.ldp + j] = acc;
+        if (lane == 0) in.gpart[(int64_t)bx * in.ldp + j] = acc;
     }
 }
 
@@ -415,12 +443,12 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
     __shared__ double sh[GS_WAVES];
     __shared__ double hl[GS_HLDS];
     INST;
-    if (in.ctl->done || (int)blockIdx.x >= in.nchunks) return;
+    if (in.ctl->done || bx >= in.nchunks) return;
     const int k = in.ctl->k;
     const int rpl = in.rpl;   // <= RPL
     const int64_t m = in.m;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * 64 * rpl;
+    const int64_t base = (int64_t)bx * 64 * rpl;
     double* __restrict__ u = in.vec[V_U];
     const double* h = in.h2;
     double* pout = (fused && mode == 0) ? in.gpart2 : in.gpart;
@@ -430,7 +458,7 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
             double sj = 0.0;
             for (int c = 0; c < in.nchunks; ++c) sj += pin[(int64_t)c * in.ldp + j];
             hl[j] = sj;
-            if (blockIdx.x == 0) {
+            if (bx == 0) {
                 double* hk = in.H + (int64_t)k * in.ldh;
                 if (mode == 0) hk[j] = sj;
                 else hk[j] += sj;
@@ -481,13 +509,13 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
                 if (t < rpl && i < m) a += vj[i] * uu[t];
             }
             a = wave_sum(a);
-            if (lane == 0) pout[(int64_t)blockIdx.x * in.ldp + j] = a;
+            if (lane == 0) pout[(int64_t)bx * in.ldp + j] = a;
         }
     } else {
         double q = 0.0;
         if (threadIdx.x < 64 * rpl) q = unew[threadIdx.x] * unew[threadIdx.x];
         const double r = block_sum(q, sh);
-        if (threadIdx.x == 0) pout[blockIdx.x] = r;
+        if (threadIdx.x == 0) pout[bx] = r;
     }
 }
 
@@ -518,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_gs_reduce(const Inst* __restrict__ I,
     INST;
     if (in.ctl->done) return;
     const int k = in.ctl->k;
-    const int j = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = bx * BLOCK + threadIdx.x;
     if (j > k) return;
     double s = 0.0;
     for (int c = 0; c < in.nchunks; ++c) s += in.gpart[(int64_t)c * in.ldp + j];
@@ -533,29 +561,51 @@ void b_gs_reduce(const BLaunch& L, int accumulate) {
 }
 
 // ||u||^2 from the chunk partials, h_{k+1,k} = ||u||, the earlier Givens rotations on
-// column k of H, the new rotation, gamma, and the test |gamma_{k+1}| <= tol * beta
+// column k of H, the new rotation, gamma, and the test |gamma_{k+1}| <= tol * beta.  The
+// rotations are a serial chain through one carried entry; column k and the rotation
+// coefficients are staged through LDS in chunks by the whole block, so the chain itself
+// runs on LDS loads that do not wait on global memory.
+constexpr int GF_CH = 1024;
+
 __global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
+    __shared__ double hb[GF_CH], cb[GF_CH], sb[GF_CH], ob[GF_CH];
+    __shared__ double carry_s;
     INST;
     KrylovCtl* ctl = in.ctl;
     if (ctl->done) return;
     double q = 0.0;
     for (int c = threadIdx.x; c < in.nchunks; c += BLOCK) q += in.gpart[c];
     const double nrm2 = block_sum(q, sh);
-    if (threadIdx.x != 0) return;
     const int k = ctl->k;
-    const double hn = sqrt(nrm2);
     double* hk = in.H + (int64_t)k * in.ldh;
-    // the rotated entry i+1 is carried in a register so the loads of cs, sn and hk do not
-    // wait on the previous step
-    double carry = hk[0];
+    if (threadIdx.x == 0) carry_s = hk[0];
+    for (int base = 0; base < k; base += GF_CH) {
+        const int len = k - base < GF_CH ? k - base : GF_CH;
+        __syncthreads();
+        for (int t = threadIdx.x; t < len; t += BLOCK) {
+            hb[t] = hk[base + t + 1];
+            cb[t] = in.cs[base + t];
+            sb[t] = in.sn[base + t];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double carry = carry_s;
 #pragma unroll 8
-    for (int i = 0; i < k; ++i) {
-        const double b = hk[i + 1], c = in.cs[i], s = in.sn[i];
-        hk[i] = c * carry + s * b;
-        carry = -s * carry + c * b;
+            for (int i = 0; i < len; ++i) {
+                const double bv = hb[i], c = cb[i], s = sb[i];
+                ob[i] = c * carry + s * bv;
+                carry = -s * carry + c * bv;
+            }
+            carry_s = carry;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < len; t += BLOCK) hk[base + t] = ob[t];
     }
-    const double a = carry, b = hn;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(nrm2);
+    const double a = carry_s, b = hn;
     const double r = hypot(a, b);
     if (r == 0.0) {
         ctl->done = 1;
@@ -591,21 +641,21 @@ void b_gs_finish(const BLaunch& L) {
 __global__ __launch_bounds__(BLOCK) void k_init_rhs(const Inst* __restrict__ I, int pmask) {
     __shared__ double sh[BLOCK / 64];
     INST;
-    if (!takes_part(in, pmask) || (int)blockIdx.x >= in.nbr) return;
+    if (!takes_part(in, pmask) || bx >= in.nbr) return;
     const double* __restrict__ f = in.vec[V_F];
     const double* __restrict__ rho = in.vec[V_RHO];
     double* __restrict__ fh = in.vec[V_FH];
     double* __restrict__ U = in.vec[V_U];
     double q = 0.0;
     const int64_t stride = (int64_t)in.nbr * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < in.m; i += stride) {
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) {
         const double v = f[i] / rho[i];
         fh[i] = v;
         U[i] = v;
         q += v * v;
     }
     const double r = block_sum(q, sh);
-    write_part(in, 0, r);
+    write_part(in, bx, 0, r);
 }
 
 void b_init_rhs(const BLaunch& L, int pmask) {
@@ -675,7 +725,7 @@ __global__ __launch_bounds__(BLOCK) void k_combine(const Inst* __restrict__ I) {
     INST;
     if (!in.ctl->active) return;
     const int it = in.ctl->iters;
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t i = (int64_t)bx * BLOCK + threadIdx.x;
     if (i >= in.m) return;
     double s = 0.0;
     for (int j = 0; j < it; ++j) s += in.P[(int64_t)j * in.ldv + i] * in.ykr[j];
@@ -711,7 +761,7 @@ __global__ __launch_bounds__(BLOCK) void k_scaling(const Inst* __restrict__ I) {
     double* __restrict__ t = in.vec[V_TN];
     const double *__restrict__ x = in.vec[V_X], *__restrict__ s = in.vec[V_S], *__restrict__ rd = in.vec[V_RD];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < in.n; j += stride) {
+    for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) {
         if (md & MD_RUN) {
             const double dj = sqrt(x[j] / s[j]);
             d[j] = dj;
@@ -736,7 +786,7 @@ __global__ __launch_bounds__(BLOCK) void k_scale_rows(const Inst* __restrict__ I
     const double* __restrict__ d = in.vec[V_D];
     double* __restrict__ rho = in.vec[V_RHO];
     const int64_t total = (int64_t)in.m * g;
-    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
+    for (int64_t t0 = (int64_t)bx * BLOCK; t0 < total; t0 += (int64_t)gridDim.x * BLOCK) {
         const int64_t tt = t0 + threadIdx.x;
         const int row = (int)(tt / g);
         double q = 0.0;
@@ -768,7 +818,7 @@ __global__ __launch_bounds__(BLOCK) void k_scale_cols(const Inst* __restrict__ I
     const double* __restrict__ d = in.vec[V_D];
     const double* __restrict__ rho = in.vec[V_RHO];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < in.n; j += stride) {
+    for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) {
         const double dj = d[j];
         for (int k = in.cp[j]; k < in.cp[j + 1]; ++k) {
             const double v = (in.ac[k] * dj) / rho[in.ri[k]];
@@ -793,7 +843,7 @@ __global__ __launch_bounds__(BLOCK) void k_power_scale(const Inst* __restrict__ 
     double* __restrict__ v = in.vec[V_TMPM];
     const double nr = first ? 0.0 : sqrt(in.out[0]);
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < in.m; i += stride) {
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) {
         if (first) v[i] = 1.0 / sqrt((double)in.m);
         else if (nr > 0.0) v[i] = v[i] / nr;
     }
@@ -865,9 +915,9 @@ void b_red_finish(const BLaunch& L, int nq, const int* ops, int pmask, int which
 // not depend on the other instances of the batch.
 #define IPM_PROLOGUE(cond)                                        \
     INST;                                                         \
-    if (!(cond) || (int)blockIdx.x >= in.nbr) return;             \
+    if (!(cond) || bx >= in.nbr) return;             \
     const int64_t stride = (int64_t)in.nbr * BLOCK;               \
-    const int64_t tid0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x
+    const int64_t tid0 = (int64_t)bx * BLOCK + threadIdx.x
 
 // x.s, c.x, ||r_d||^2 over n and b.y, ||r_p||^2 over m
 __global__ __launch_bounds__(BLOCK) void k_measures(const Inst* __restrict__ I, int pmask) {
@@ -886,11 +936,11 @@ __global__ __launch_bounds__(BLOCK) void k_measures(const Inst* __restrict__ I, 
         q4 += rpv[i] * rpv[i];
     }
     double r;
-    r = block_sum(q0, sh); write_part(in, 0, r);
-    r = block_sum(q1, sh); write_part(in, 1, r);
-    r = block_sum(q2, sh); write_part(in, 2, r);
-    r = block_sum(q3, sh); write_part(in, 3, r);
-    r = block_sum(q4, sh); write_part(in, 4, r);
+    r = block_sum(q0, sh); write_part(in, bx, 0, r);
+    r = block_sum(q1, sh); write_part(in, bx, 1, r);
+    r = block_sum(q2, sh); write_part(in, bx, 2, r);
+    r = block_sum(q3, sh); write_part(in, bx, 3, r);
+    r = block_sum(q4, sh); write_part(in, bx, 4, r);
 }
 
 void b_measures(const BLaunch& L, int pmask) {
@@ -927,8 +977,8 @@ __global__ __launch_bounds__(BLOCK) void k_post1(const Inst* __restrict__ I) {
         for (int64_t j = tid0; j < in.n; j += stride) x[j] = dw[j];
     }
     double r;
-    r = block_min(mp, sh); write_part(in, 0, r);
-    r = block_min(mdd, sh); write_part(in, 1, r);
+    r = block_min(mp, sh); write_part(in, bx, 0, r);
+    r = block_min(mdd, sh); write_part(in, bx, 1, r);
 }
 
 void b_post1(const BLaunch& L) {
@@ -944,7 +994,7 @@ __global__ __launch_bounds__(BLOCK) void k_mu_af(const Inst* __restrict__ I) {
     double q = 0.0;
     for (int64_t j = tid0; j < in.n; j += stride) q += (x[j] + ap * dx[j]) * (s[j] + ad * ds[j]);
     const double r = block_sum(q, sh);
-    write_part(in, 0, r);
+    write_part(in, bx, 0, r);
 }
 
 void b_mu_af(const BLaunch& L) {
@@ -1016,8 +1066,8 @@ __global__ __launch_bounds__(BLOCK) void k_post2(const Inst* __restrict__ I) {
         }
     }
     double r;
-    r = block_min(q0, sh); write_part(in, 0, r);
-    r = block_min(q1, sh); write_part(in, 1, r);
+    r = block_min(q0, sh); write_part(in, bx, 0, r);
+    r = block_min(q1, sh); write_part(in, bx, 1, r);
 }
 
 void b_post2(const BLaunch& L) {
@@ -1040,9 +1090,9 @@ __global__ __launch_bounds__(BLOCK) void k_shift(const Inst* __restrict__ I, int
         q2 += sj;
     }
     double r;
-    r = block_sum(q0, sh); write_part(in, 0, r);
-    r = block_sum(q1, sh); write_part(in, 1, r);
-    r = block_sum(q2, sh); write_part(in, 2, r);
+    r = block_sum(q0, sh); write_part(in, bx, 0, r);
+    r = block_sum(q1, sh); write_part(in, bx, 1, r);
+    r = block_sum(q2, sh); write_part(in, bx, 2, r);
 }
 
 void b_shift(const BLaunch& L, int pmask) {
@@ -1061,8 +1111,8 @@ __global__ __launch_bounds__(BLOCK) void k_min2(const Inst* __restrict__ I, int 
         b = fmin(b, isnan(sj) ? -INFINITY : sj);
     }
     double r;
-    r = block_min(a, sh); write_part(in, 0, r);
-    r = block_min(b, sh); write_part(in, 1, r);
+    r = block_min(a, sh); write_part(in, bx, 0, r);
+    r = block_min(b, sh); write_part(in, bx, 1, r);
 }
 
 void b_min2(const BLaunch& L, int pmask) {
@@ -1083,8 +1133,8 @@ __global__ __launch_bounds__(BLOCK) void k_backtrack(const Inst* __restrict__ I)
         sm += p;
     }
     double r;
-    r = block_min(mn, sh); write_part(in, 3, r);
-    r = block_sum(sm, sh); write_part(in, 4, r);
+    r = block_min(mn, sh); write_part(in, bx, 3, r);
+    r = block_sum(sm, sh); write_part(in, bx, 4, r);
 }
 
 void b_backtrack(const BLaunch& L) {
@@ -1108,7 +1158,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(const Inst* __restrict__ I, in
     }
     for (int64_t i = tid0; i < in.m; i += stride) y[i] = y[i] + ad * dy[i];
     const double r = block_sum(bad, sh);
-    write_part(in, q, r);
+    write_part(in, bx, q, r);
 }
 
 void b_update(const BLaunch& L, int q) {
@@ -1121,7 +1171,7 @@ __global__ __launch_bounds__(BLOCK) void k_div_rho(const Inst* __restrict__ I, i
     double* __restrict__ o = in.vec[dst];
     const double *__restrict__ a = in.vec[src], *__restrict__ rho = in.vec[V_RHO];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < in.m; i += stride) o[i] = a[i] / rho[i];
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) o[i] = a[i] / rho[i];
 }
 
 void b_div_rho(const BLaunch& L, int dst, int src, int pmask) {
