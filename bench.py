@@ -49,7 +49,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="transport_300x300",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
-                             "sparse_120000x434580"])
+                             "sparse_120000x434580", "serving_mix", "streaming_1199000x4345800"])
+    ap.add_argument("--ipm-steps", type=int, default=0,
+                    help="time this many interior-point steps of the first LP instead of whole solves")
+    ap.add_argument("--krylov-cap", type=int, default=1500,
+                    help="serving_mix: Krylov basis cap per solve (stated cap of the mix)")
+    ap.add_argument("--m-hi", type=int, default=20000, help="serving_mix: largest m of the mix")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving_mix: offered load as a fraction of the closed-loop mixed throughput")
     ap.add_argument("--batch", type=int, default=64, help="LPs per step")
     ap.add_argument("--width", type=int, default=64, help="LPs in lockstep")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -66,6 +73,12 @@ def main():
     import paper_1604_07491_amd as lpk
 
     torch.cuda.set_device(0)
+    if args.workload == "serving_mix":
+        return serve_main(args)
+    if args.workload == "streaming_1199000x4345800":
+        return streaming_main(args)
+    if args.ipm_steps > 0:
+        return steps_main(args)
     lps = make_lps(args.workload, args.batch)
     dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
     opts = lpk.options(precision=args.precision, inner=args.inner)
@@ -174,6 +187,176 @@ def main():
     print(json.dumps(line), flush=True)
     for p in probs:
         p.close()
+
+
+def kernel_roofline(p, classes, reps=20):
+    """lp_time_kernel for each class: mean launch duration, algorithmic bytes per launch,
+    GB/s and the fraction of the 8 TB/s HBM peak; 'group' is one preconditioner
+    application (all colours and sweeps) for the sweep class."""
+    import paper_1604_07491_amd as lpk
+    out = {}
+    for name, cls in classes.items():
+        t = lpk.lp_time_kernel(p, cls, reps=reps)
+        gbs = t["bytes_per_launch"] / (t["us_per_launch"] * 1e-6) / 1e9
+        out[name] = {"us_per_launch": t["us_per_launch"], "bytes_per_launch": t["bytes_per_launch"],
+                     "launches_per_group": t["launches_per_group"],
+                     "us_per_group": t["us_per_launch"] * t["launches_per_group"],
+                     "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        print(f"  {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
+def streaming_main(args):
+    """Kernel bandwidth on an instance larger than the Infinity Cache: the config-3
+    generator at 10x (m = 1.2M, n = 4.35M, 34.8M nonzeros; A_hat in CSR and CSC is 0.84 GB
+    in FP64).  One direction solve at D = I builds A_hat; then the sweep and the two
+    products of the Krylov loop are timed by replay."""
+    import numpy as np
+    import paper_1604_07491_amd as lpk
+    from paper_1604_07491_amd import synth
+    t0 = time.perf_counter()
+    lp = synth.streaming_lp(10)
+    print(f"generated {lp.m}x{lp.n}, nnz {lp.nnz} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    res = {}
+    for prec in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        p = lpk.from_lp(lp, lpk.options(precision=prec, krylov_max_iter=8))
+        tc = time.perf_counter() - t0
+        ncol = len(p.colouring())
+        print(f"{prec}: created in {tc:.1f} s", file=sys.stderr, flush=True)
+        dw, dy, info = lpk.direction_solve(p, np.ones(lp.n), lp.b, 1e-12)
+        res[prec] = kernel_roofline(p, {"sweep": lpk.LP_K_SWEEP, "spmv_csr": lpk.LP_K_SPMV_CSR,
+                                        "spmv_csc": lpk.LP_K_SPMV_CSC}, reps=args.steps if args.steps > 3 else 10)
+        res[prec]["create_s"] = tc
+        res[prec]["colours"] = ncol
+        p.close()
+    sw = res["mixed"]["sweep"]
+    line = {"metric": "inner-iteration sweep HBM GB/s (instance larger than the Infinity Cache)",
+            "value": sw["achieved_gbs"], "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32 sweeps + f64", "data": "synthetic",
+            "config": {"workload": "streaming_1199000x4345800", "m": lp.m, "n": lp.n, "nnz": lp.nnz},
+            "kernels": res}
+    print(json.dumps(line), flush=True)
+
+
+def steps_main(args):
+    """Time `ipm_steps` interior-point steps of the workload LP (the starting point is the
+    first call's); for LPs whose whole solve takes hours."""
+    import paper_1604_07491_amd as lpk
+    lp = make_lps(args.workload, 1)[0]
+    t0 = time.perf_counter()
+    p = lpk.from_lp(lp, lpk.options(precision=args.precision, inner=args.inner))
+    tc = time.perf_counter() - t0
+    print(f"created {lp.m}x{lp.n} nnz {lp.nnz} in {tc:.1f} s", file=sys.stderr, flush=True)
+    steps = []
+    for k in range(args.ipm_steps):
+        ts = time.perf_counter()
+        info = lpk.ipm_step(p)
+        dt = time.perf_counter() - ts
+        steps.append({"s": dt, "k_af": info["k_af"], "k_cc": info["k_cc"], "gamma_rel": info["gamma_rel"],
+                      "fail_af": info["fail_af"], "fail_cc": info["fail_cc"], "eps_in": info["eps_in"]})
+        print(f"step {k}: {steps[-1]}", file=sys.stderr, flush=True)
+        if info["converged"]:
+            break
+    kr = kernel_roofline(p, {"sweep": lpk.LP_K_SWEEP, "spmv_csr": lpk.LP_K_SPMV_CSR,
+                             "spmv_csc": lpk.LP_K_SPMV_CSC})
+    line = {"metric": "interior-point steps (time per step, Krylov iterations)", "value":
+            len(steps) / sum(s["s"] for s in steps), "unit": "IPM steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64" if args.precision == "fp64" else "f32 sweeps + f64",
+            "data": "synthetic", "config": {"workload": args.workload, "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+                                            "precision": args.precision, "create_s": tc},
+            "steps": steps, "kernels": kr}
+    print(json.dumps(line), flush=True)
+    p.close()
+
+
+def _serve_run(lps, arrivals, precision, width, cap):
+    """Submit every LP at its arrival time (seconds from the first) to a server; return the
+    completions and the wall time from the first arrival to the last completion."""
+    import paper_1604_07491_amd as lpk
+    solver = lpk.options(precision=precision, krylov_max_iter=cap)
+    with lpk.Server(slots=width, solver=solver) as srv:
+        t0 = time.perf_counter()
+        tickets = {}
+        for i, (lp, ta) in enumerate(zip(lps, arrivals)):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[srv.submit(lp)] = i
+            if (i + 1) % 32 == 0:
+                print(f"  submitted {i + 1}", file=sys.stderr, flush=True)
+        done = []
+        while len(done) < len(lps):
+            srv.wait(len(lps) - len(done), 30.0)
+            got = srv.poll()
+            done += got
+            print(f"  completed {len(done)} / {len(lps)}", file=sys.stderr, flush=True)
+        wall = max(c["t_done"] for c in done) - min(c["t_submit"] for c in done)
+    return done, wall
+
+
+def serve_main(args):
+    """Serving mix: LPs of different sizes arrive as a Poisson process; the server keeps
+    up to `width` of them in one lockstep batch and admits new ones by HBM footprint as
+    others finish.  Closed loop (every LP submitted at t = 0) measures the capacity; the
+    open-loop run offers `load` times the mixed-precision capacity with seeded arrivals;
+    both precisions replay the same trace."""
+    import numpy as np
+    import paper_1604_07491_amd as lpk
+    from paper_1604_07491_amd import synth
+    count = args.batch
+    lps, unit = synth.serving_mix(count=count, m_hi=args.m_hi, rate=1.0)
+    print(f"generated {count} LPs (m {min(l.m for l in lps)}..{max(l.m for l in lps)})", file=sys.stderr,
+          flush=True)
+    out = {}
+    closed = {}
+    for prec in ("mixed", "fp64"):
+        done, wall = _serve_run(lps, np.zeros(count), prec, args.width, args.krylov_cap)
+        closed[prec] = {"lps_per_s": count / wall, "wall_s": wall,
+                        "converged": sum(c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8 for c in done)}
+        print(f"closed loop {prec}: {closed[prec]}", file=sys.stderr, flush=True)
+    rate = args.load * closed["mixed"]["lps_per_s"]
+    arrivals = unit / rate          # unit-rate Poisson trace scaled to the offered rate
+    for prec in ("mixed", "fp64"):
+        done, wall = _serve_run(lps, arrivals, prec, args.width, args.krylov_cap)
+        lat = np.array([c["t_done"] - c["t_submit"] for c in done]) * 1e3
+        ok = [c for c in done if c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8]
+        out[prec] = {"lps_per_s": count / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "converged": len(ok),
+                     "max_gamma_rel": max(c["gamma_rel"] for c in done),
+                     "krylov_iters_total": int(sum(c["krylov_iters"] for c in done)),
+                     "ipm_iters_total": int(sum(c["iters"] for c in done))}
+        print(f"open loop {prec}: {out[prec]}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        # LPs of the mix in a seeded random order until about 20 s of CPU work
+        order = np.random.default_rng(7).permutation(count)
+        tc = time.perf_counter()
+        done_cpu = 0
+        for i in order:
+            oracle.ipm(lps[int(i)])
+            done_cpu += 1
+            if time.perf_counter() - tc > 20.0:
+                break
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": done_cpu / tcpu, "unit": "LPs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done_cpu} LPs of the mix in seeded random order, one core, {tcpu:.1f} s"}
+    m = out["mixed"]
+    line = {
+        "metric": "LPs solved/s at rel. gap 1e-8 (p50/p99 latency), serving mix",
+        "value": m["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": m["wall_s"] * 1e3, "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 sweeps + f64", "data": "synthetic",
+        "config": {"workload": "serving_mix", "lps": count, "m_range": [200, args.m_hi],
+                   "arrival": "Poisson, seed 4242", "rate_per_s": rate, "offered_load": args.load,
+                   "lps_in_lockstep": args.width, "krylov_cap": args.krylov_cap},
+        "open_loop": out, "closed_loop": closed,
+        "mixed_over_fp64": out["mixed"]["lps_per_s"] / out["fp64"]["lps_per_s"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -175,6 +175,18 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         p->colours.push_back(C);
         t0 = t1;
     }
+    // does colour 0 touch every column? (then its first sweep sets z without clearing it)
+    {
+        std::vector<char> hit((size_t)n, 0);
+        int64_t cnt = 0;
+        if (!p->colours.empty())
+            for (int64_t k = prp[p->colours[0].r0]; k < prp[p->colours[0].r1]; ++k)
+                if (!hit[pci[k]]) {
+                    hit[pci[k]] = 1;
+                    ++cnt;
+                }
+        p->zcover = cnt == n;
+    }
     // CSC of the permuted matrix (row indices in the permuted numbering, ascending)
     std::vector<int32_t> pcp((size_t)n + 1, 0), pri((size_t)nnz);
     std::vector<double> pac((size_t)nnz);

@@ -125,6 +125,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.rpl = p->rpl;
     in.nbr = red_blocks(std::max(p->m, p->n));
     in.nbs = spmv_blocks(p->m, p->g_csr);
+    in.zcover = p->zcover ? 1 : 0;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
     in.ldp = p->kmax + 1;
@@ -174,6 +175,7 @@ lp_status Batch::refresh() {
     L.gs_fused = true;
     L.max_ncol = 0;
     L.ell = 1;
+    L.need_prep = false;
     bool first = true;
     for (int s = 0; s < cap; ++s) {
         h_inst[s] = make_inst(*this, s);
@@ -201,6 +203,7 @@ lp_status Batch::refresh() {
         L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
         L.gs_fused = L.gs_fused && p->gpart2 != nullptr && gs_fusable(p->nchunks, p->kmax);
         L.max_ncol = std::max(L.max_ncol, in.ncol);
+        L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
     }
     grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
     for (int s = 0; s < cap; ++s) {
@@ -275,7 +278,7 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
     const BLaunch& L = B.L;
     const double sv = L.mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
     const int ell = L.ell;
-    if (with_prep) b_prep(L);
+    if (with_prep && L.need_prep) b_prep(L);
     if (L.inner == 3) {
         Prof pr(&B, LP_K_SWEEP, it, sweep_bytes_dense(B));
         b_apply_c(L);
@@ -968,6 +971,7 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
             t.done = 0;
             t.active = 1;
             t.kmax = 1;
+            t.inv_h = 1.0;
             t.omega_c = B.mem[s]->omega_c;
         }
         B.h_slot[s].ctl = t;

@@ -62,7 +62,7 @@ struct Inst {
     int32_t rpl;                          // Gram-Schmidt rows per lane (chunk = 64 rpl rows)
     int32_t nbr;                          // blocks of the vector reductions (own sizes only)
     int32_t nbs;                          // blocks of the reduction over a CSR product
-    int32_t pad0;
+    int32_t zcover;                       // 1: the rows of colour 0 cover every column
     int64_t ldv, ldh, ldp, kmax;
     const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
     const int32_t *cstart, *cg;           // colour row ranges (ncol+1), lanes per row by colour
@@ -98,6 +98,7 @@ struct BLaunch {
     int ell;                // inner sweeps per preconditioner application
     int max_ncol;
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
+    bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
 };
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------
@@ -110,6 +111,9 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
             int pmask, bool nrm);
 
 // ---- Krylov loop ------------------------------------------------------------------------
+// The first sweep of every preconditioner application also writes V[:,k] = u / h_{k,k-1}
+// for its rows and overwrites (rather than accumulates) p_k; b_prep only clears the NE-SOR
+// z of instances whose colour 0 does not cover every column (colour 0 then overwrites z).
 void b_prep(const BLaunch& L);
 void b_nesor(const BLaunch& L, int colour, int sweep, int ell);
 void b_cim_res(const BLaunch& L, int first);

@@ -175,33 +175,23 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 }
 
 // ------------------------------------------------------------------------------------
-// start of Krylov iteration k: V[:,k] = u / h (u = f_hat for k = 0), P[:,k] = 0, and the
-// sweep's z = 0 (NE-SOR)
-__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int inner, int mixed) {
+// start of Krylov iteration k, NE-SOR instances whose colour 0 leaves some column
+// uncovered: z = 0 (the first sweep sets V[:,k] and p_k itself)
+__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int mixed) {
     INST;
-    if (in.ctl->done) return;
-    const int64_t k = in.ctl->k;
-    const double ih = in.ctl->inv_h;
-    const double* __restrict__ u = in.vec[V_U];
+    if (in.ctl->done || in.gsor || in.zcover || in.ncol == 0) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) {
-        in.V[k * in.ldv + i] = u[i] * ih;
-        in.P[k * in.ldv + i] = 0.0;
-    }
-    if (inner == 0 && !in.gsor) {   // NE-SOR
-        if (mixed) {
-            for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
-        } else {
-            double* __restrict__ z = in.vec[V_Z64];
-            for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) z[j] = 0.0;
-        }
+    if (mixed) {
+        for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
+    } else {
+        double* __restrict__ z = in.vec[V_Z64];
+        for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) z[j] = 0.0;
     }
 }
 
 void b_prep(const BLaunch& L) {
-    const int64_t len = L.max_m > L.max_n ? L.max_m : L.max_n;
-    hipLaunchKernelGGL(k_prep, dim3(capg(cdiv(len, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I,
-                       L.inner, L.mixed);
+    hipLaunchKernelGGL(k_prep, dim3(capg(cdiv(L.max_n, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I,
+                       L.mixed);
 }
 
 // ------------------------------------------------------------------------------------
@@ -220,9 +210,14 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     const int row = r0 + tid / g, lane = tid & (g - 1);
     if (row >= r1) return;   // uniform inside the sub-group; no block barrier below
     const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
+    // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
+    // every column (no clearing pass needed)
+    const int fresh = sw == 0 && c == 0 && in.zcover;
     const int64_t k = in.ctl->k;
-    const double* __restrict__ v = in.V + k * in.ldv;
+    double* __restrict__ vk = in.V + k * in.ldv;
     double* __restrict__ p = in.P + k * in.ldv;
+    // first sweep: v_k = u / h_{k,k-1} is formed here and stored; p_k starts from delta
+    const double vrow = sw == 0 ? in.vec[V_U][row] * in.ctl->inv_h : vk[row];
     const T* __restrict__ val;
     T* __restrict__ z;
     if constexpr (sizeof(T) == 4) {
@@ -247,24 +242,45 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
             if (kk < e) {
                 a[t] = val[kk];
                 j[t] = idx[kk];
-                acc += a[t] * z[j[t]];
+                if (!fresh) acc += a[t] * z[j[t]];
             }
         }
         acc = sg_sum(acc, g);
-        const T delta = (T)in.omega * ((T)v[row] - acc);
+        const T delta = (T)in.omega * ((T)vrow - acc);
         if (write_z) {
 #pragma unroll
             for (int t = 0; t < R; ++t)
-                if (s + lane + t * g < e) z[j[t]] += delta * a[t];
+                if (s + lane + t * g < e) {
+                    if (fresh) z[j[t]] = delta * a[t];
+                    else z[j[t]] += delta * a[t];
+                }
         }
-        if (lane == 0) p[row] += (double)delta;
+        if (lane == 0) {
+            if (sw == 0) {
+                vk[row] = vrow;
+                p[row] = (double)delta;
+            } else {
+                p[row] += (double)delta;
+            }
+        }
     } else {
-        for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
+        if (!fresh)
+            for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
         acc = sg_sum(acc, g);
-        const T delta = (T)in.omega * ((T)v[row] - acc);
+        const T delta = (T)in.omega * ((T)vrow - acc);
         if (write_z)
-            for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
-        if (lane == 0) p[row] += (double)delta;
+            for (int kk = s + lane; kk < e; kk += g) {
+                if (fresh) z[idx[kk]] = delta * val[kk];
+                else z[idx[kk]] += delta * val[kk];
+            }
+        if (lane == 0) {
+            if (sw == 0) {
+                vk[row] = vrow;
+                p[row] = (double)delta;
+            } else {
+                p[row] += (double)delta;
+            }
+        }
     }
 }
 
@@ -306,9 +322,18 @@ __global__ __launch_bounds__(BLOCK) void k_cim_res(const Inst* __restrict__ I, i
         }
         if (!first) sum = sg_sum(sum, g);
         if (row < in.m && lane == 0) {
-            const T rr = (T)in.V[k * in.ldv + row] - sum;
+            double vrow;
+            if (first) {
+                // first sweep: v_k = u / h_{k,k-1} is formed here and stored
+                vrow = in.vec[V_U][row] * in.ctl->inv_h;
+                in.V[k * in.ldv + row] = vrow;
+            } else {
+                vrow = in.V[k * in.ldv + row];
+            }
+            const T rr = (T)vrow - sum;
             r[row] = rr;
-            in.P[k * in.ldv + row] += w * (double)rr;
+            if (first) in.P[k * in.ldv + row] = w * (double)rr;
+            else in.P[k * in.ldv + row] += w * (double)rr;
         }
     }
 }
@@ -364,12 +389,15 @@ __global__ __launch_bounds__(BLOCK) void k_apply_c(const Inst* __restrict__ I) {
     const int m = in.m;
     const int i = bx * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= m) return;
-    const double* __restrict__ v = in.V + k * in.ldv;
+    // v_k = u / h_{k,k-1} formed on the fly; row i stores its entry of V[:,k]
+    const double* __restrict__ u = in.vec[V_U];
+    const double ih = in.ctl->inv_h;
     const T* __restrict__ ci;
     if constexpr (sizeof(T) == 4) ci = (const T*)in.C32 + (int64_t)i * m;
     else ci = (const T*)in.C + (int64_t)i * m;
+    if (lane == 0) in.V[k * in.ldv + i] = u[i] * ih;
     T acc = 0;
-    for (int j = lane; j < m; j += 64) acc += ci[j] * (T)v[j];
+    for (int j = lane; j < m; j += 64) acc += ci[j] * (T)(u[j] * ih);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) in.P[k * in.ldv + i] = (double)acc;

@@ -115,6 +115,7 @@ struct lp_problem {
     std::vector<int32_t> h_cstart, h_cg;
     int g_csr = 64, g_csc = 1;
     int rpl = 1, nchunks = 1;
+    bool zcover = false;                            // colour 0 covers every column
 
     lpk::DevArena arena;
     // structure and data (permuted rows)

@@ -130,11 +130,15 @@ def sparse_lp(m_base: int = 198, n: int = 500, nnz_per_col: int = 6, n_dup: int 
     row_list = [rows]
     col_list = [cols]
     val_list = [vals]
-    for t, r in enumerate(dup):
-        sel = rows == r
-        row_list.append(np.full(int(sel.sum()), m_base + t, dtype=np.int64))
-        col_list.append(cols[sel])
-        val_list.append(vals[sel])
+    if n_dup > 0:
+        # entries of each base row in their original order (stable sort by row)
+        order = np.argsort(rows, kind="stable")
+        start = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=m_base))])
+        for t, r in enumerate(dup):
+            sel = order[start[r]:start[r + 1]]
+            row_list.append(np.full(sel.size, m_base + t, dtype=np.int64))
+            col_list.append(cols[sel])
+            val_list.append(vals[sel])
     m = m_base + n_dup
     row_ptr, col_idx, val = _csr_from_coo(m, n, np.concatenate(row_list),
                                           np.concatenate(col_list), np.concatenate(val_list))
@@ -247,6 +251,14 @@ def config(idx: int) -> LP:
     if idx == 4:
         return serving_mix(1)[0][0]
     raise ValueError(idx)
+
+
+def streaming_lp(scale: int = 10, seed: int = 3) -> LP:
+    """The config-3 generator scaled ``scale`` times in m and n (8 nonzeros per column,
+    columns scaled by 10^U(-3,3), 100 * scale duplicated rows): an instance whose matrix
+    does not fit the 256 MB Infinity Cache, for kernel bandwidth measurements."""
+    return sparse_lp(119_900 * scale, 434_580 * scale, 8, 100 * scale, seed=seed, col_scale_exp=3.0,
+                     name=f"sparse_{120_000 * scale}x{434_580 * scale}")
 
 
 def serving_mix(count: int = 256, m_lo: int = 200, m_hi: int = 20_000, seed0: int = 1000,
