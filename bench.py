@@ -29,6 +29,22 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+def kernels_digest():
+    import hashlib
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()
+
+
+def counter_traffic(args, kernel, width):
+    """HBM bytes per launch of `kernel` from the committed counter runs, if they were taken
+    for this workload and batch width on the kernels as they are now (else None)."""
+    if not args.traffic or not os.path.exists(args.traffic):
+        return None
+    rec = json.load(open(args.traffic)).get(f"{args.workload}/{args.precision}/w{width}/{kernel}")
+    if not rec or rec.get("kernels_sha256") != kernels_digest():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def make_lps(workload, count):
     from paper_1604_07491_amd import synth
     if workload == "transport_300x300":
@@ -49,7 +65,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="transport_300x300",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
-                             "sparse_120000x434580", "serving_mix", "streaming_1199000x4345800"])
+                             "sparse_120000x434580", "serving_mix", "streaming_1199000x4345800",
+                             "copy_probe"])
     ap.add_argument("--ipm-steps", type=int, default=0,
                     help="time this many interior-point steps of the first LP instead of whole solves")
     ap.add_argument("--krylov-cap", type=int, default=1500,
@@ -62,7 +79,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "cimmino"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=None, help="JSON file: counter-derived bytes per launch by kernel class")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
+                    help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -77,6 +95,23 @@ def main():
         return serve_main(args)
     if args.workload == "streaming_1199000x4345800":
         return streaming_main(args)
+    if args.workload == "copy_probe":
+        # a plain device copy of known size: the reference that scales the HBM byte
+        # counters (FETCH_SIZE, WRITE_SIZE) read for the library's kernels
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
+        print(json.dumps({"metric": "device copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                          "copies": 5, "ms_per_copy": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return
     if args.ipm_steps > 0:
         return steps_main(args)
     lps = make_lps(args.workload, args.batch)
@@ -124,11 +159,13 @@ def main():
     tk = lpk.lp_time_batch_kernel(probs[:width], cls_id[dom], reps=200 if dom != "gram" else 5)
     achieved = tk["bytes_per_launch"] / (tk["us_per_launch"] * 1e-6) / 1e9
     t1 = lpk.lp_time_kernel(p0, cls_id[dom], reps=200 if dom != "gram" else 5)
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(args.workload, {}).get(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "us_per_launch": tk["us_per_launch"],
+    if dom == "gram":
+        # the dense path's build is a contraction: FP64 matrix cores
+        achieved = tk["flops_per_launch"] / (tk["us_per_launch"] * 1e-6) / 1e12
+    traffic = counter_traffic(args, dom, width)
+    bound, peak, unit = ("mfma", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s") if dom == "gram" else ("hbm", HBM_PEAK_GBS, "GB/s")
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic, "us_per_launch": tk["us_per_launch"],
                 "bytes_per_launch": tk["bytes_per_launch"], "launches_per_group": tk["launches_per_group"],
                 "lps_per_launch": width,
                 "timing": "lp_time_batch_kernel replay, 200 x group, HIP events on the library stream",

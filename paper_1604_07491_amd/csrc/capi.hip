@@ -465,17 +465,20 @@ lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, co
 
 void lp_destroy(lp_problem* p) { destroy(p); }
 
-// run the problem alone (its batch of one) until it leaves the engine or `ticks` ticks ran
-static lp_status run_solo(lp_problem* p, bool from_point, int32_t limit_k, int ticks, Engine::Member* out) {
+// run the problem alone (its batch of one) until it leaves the engine, or (one_step) until
+// it has taken one interior-point step
+static lp_status run_solo(lp_problem* p, bool from_point, int32_t limit_k, bool one_step, Engine::Member* out) {
     Batch* b = nullptr;
     lp_status rc = solo_batch(p, &b);
     if (rc != LP_OK) return rc;
     Engine E;
     E.attach(b);
+    E.stepwise = one_step;
     const int s = E.join(p, from_point, limit_k);
     if (s < 0) return fail(LP_EINVAL, "no slot");
-    for (int t = 0; (ticks <= 0 || t < ticks) && E.any_live(); ++t) {
-        rc = E.tick();
+    while (E.any_live()) {
+        if (one_step && E.mem[s].steps > 0) break;
+        rc = E.round();
         if (rc != LP_OK) return rc;
     }
     *out = E.mem[s];
@@ -485,16 +488,10 @@ static lp_status run_solo(lp_problem* p, bool from_point, int32_t limit_k, int t
 lp_status ipm_step(lp_problem* p, lp_iter_info* info) {
     g_err.clear();
     if (!p) return fail(LP_EINVAL, "NULL problem");
-    lp_status rc;
+    if (!p->have_point && p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
     Engine::Member mb;
-    if (!p->have_point) {
-        if (p->opt.start != 0) return fail(LP_EINVAL, "start == 1 needs lp_set_state first");
-        // the starting point takes one tick of its own
-        rc = run_solo(p, false, INT32_MAX, 1, &mb);
-        if (rc != LP_OK) return rc;
-        if (mb.state == Engine::DONE) return mb.status;
-    }
-    rc = run_solo(p, true, INT32_MAX, 1, &mb);
+    // without a point, the starting point comes first, then the step
+    lp_status rc = run_solo(p, p->have_point, INT32_MAX, true, &mb);
     if (rc != LP_OK) return rc;
     if (info) *info = mb.L;
     return mb.state == Engine::DONE && mb.status == LP_DIVERGED ? LP_DIVERGED : LP_OK;
@@ -515,7 +512,7 @@ lp_status lp_solve(lp_problem* p, lp_result* r) {
         from_point = true;
     }
     Engine::Member mb;
-    lp_status rc = run_solo(p, from_point, p->opt.ipm_max_iter, 0, &mb);
+    lp_status rc = run_solo(p, from_point, p->opt.ipm_max_iter, false, &mb);
     if (rc != LP_OK) return rc;
     if (r) {
         fill_result(mb, r);
@@ -549,9 +546,10 @@ lp_status direction_solve(lp_problem* p, const double* d, const double* f, doubl
         if ((rc = copy_in(p, d, p->vec[V_D], n)) != LP_OK) return rc;
     } else {
         // D = diag(sqrt(x/s)) of the current iterate
-        pr.mode = MD_RUN;
+        pr.mode = MD_RUN | MD_SCALE;
         if ((rc = b->put_params()) != LP_OK) return rc;
         b_scaling(b->L);
+        LPK_HIP(hipStreamSynchronize(st));   // the parameters are written again below
     }
     pr.mode = MD_API;
     pr.scal[SC_TOL] = tol;

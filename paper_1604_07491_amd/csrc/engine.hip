@@ -126,6 +126,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.nbr = red_blocks(std::max(p->m, p->n));
     in.nbs = spmv_blocks(p->m, p->g_csr);
     in.zcover = p->zcover ? 1 : 0;
+    in.lds = (in.ncol > 0 && p->n * (mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
     in.ldp = p->kmax + 1;
@@ -162,6 +163,19 @@ static Inst make_inst(Batch& B, int slot) {
     return in;
 }
 
+static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<int>& ca,
+                        const std::vector<int>& cb) {
+    if (a.S != b.S || a.max_m != b.max_m || a.max_n != b.max_n || a.max_nbr != b.max_nbr ||
+        a.max_nbs != b.max_nbs || a.max_ldp != b.max_ldp || a.gs_rpl != b.gs_rpl ||
+        a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.mixed != b.mixed ||
+        a.inner != b.inner || a.ell != b.ell || a.max_ncol != b.max_ncol || a.need_prep != b.need_prep ||
+        a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.max_ncol_global != b.max_ncol_global)
+        return false;
+    for (int i = 0; i < 4; ++i)
+        if (a.grid_spmv[i] != b.grid_spmv[i]) return false;
+    return ca == cb;
+}
+
 lp_status Batch::refresh() {
     L = BLaunch{};
     L.S = cap;
@@ -176,6 +190,9 @@ lp_status Batch::refresh() {
     L.max_ncol = 0;
     L.ell = 1;
     L.need_prep = false;
+    L.any_lds = false;
+    L.lds_bytes = 0;
+    L.max_ncol_global = 0;
     bool first = true;
     for (int s = 0; s < cap; ++s) {
         h_inst[s] = make_inst(*this, s);
@@ -203,12 +220,18 @@ lp_status Batch::refresh() {
         L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
         L.gs_fused = L.gs_fused && p->gpart2 != nullptr && gs_fusable(p->nchunks, p->kmax);
         L.max_ncol = std::max(L.max_ncol, in.ncol);
-        L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
+        if (in.lds) {
+            L.any_lds = true;
+            L.lds_bytes = std::max(L.lds_bytes, in.n * (L.mixed ? 4 : 8));
+        } else {
+            L.max_ncol_global = std::max(L.max_ncol_global, in.ncol);
+            L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
+        }
     }
     grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
     for (int s = 0; s < cap; ++s) {
         const lp_problem* p = mem[s];
-        if (!p || h_inst[s].ncol == 0) continue;
+        if (!p || h_inst[s].ncol == 0 || h_inst[s].lds) continue;
         for (int c = 0; c < h_inst[s].ncol; ++c) {
             const Colour& cl = p->colours[c];
             grid_colour[c] = std::max(grid_colour[c], cdiv_i((int64_t)(cl.r1 - cl.r0) * cl.g, BLOCK_THREADS));
@@ -217,21 +240,30 @@ lp_status Batch::refresh() {
     L.grid_colour = grid_colour.data();
     LPK_HIP(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
-    drop_graph();
+    // the captured iterations read every pointer from the descriptors: they stay valid
+    // while the launch shapes are unchanged
+    if (!same_launch(L, graph_L, grid_colour, graph_colour)) {
+        drop_graph();
+        graph_L = L;
+        graph_colour = grid_colour;
+    }
     dirty = false;
     return LP_OK;
 }
 
 lp_status Batch::put_params() {
+    // the host writes h_param again only after the previous copy has completed: either a
+    // get_slots (which synchronises) came in between, or we wait here
+    if (param_inflight) LPK_HIP(hipStreamSynchronize(st));
     LPK_HIP(hipMemcpyAsync(d_param, h_param, sizeof(Param) * cap, hipMemcpyHostToDevice, st));
-    // h_param is written again only after this copy has completed
-    LPK_HIP(hipStreamSynchronize(st));
+    param_inflight = true;
     return LP_OK;
 }
 
 lp_status Batch::get_slots() {
     LPK_HIP(hipMemcpyAsync(h_slot, d_slot, sizeof(Slot) * cap, hipMemcpyDeviceToHost, st));
     LPK_HIP(hipStreamSynchronize(st));
+    param_inflight = false;
     return LP_OK;
 }
 
@@ -304,11 +336,20 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
             }
         }
     } else {
+        if (L.any_lds) {
+            // the instances whose z fits in LDS: every sweep and colour in one launch
+            const double by = over_members(B, [&](const lp_problem* p) {
+                if (p->n * (L.mixed ? 4 : 8) > LDS_Z_MAX) return 0.0;
+                return ell * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0));
+            });
+            Prof pr(&B, LP_K_SWEEP, it, by);
+            b_sweep_lds(L, ell);
+        }
         for (int sw = 0; sw < ell; ++sw) {
-            for (int c = 0; c < L.max_ncol; ++c) {
+            for (int c = 0; c < L.max_ncol_global; ++c) {
                 const double by = over_members(B, [&](const lp_problem* p) {
                     const int nc = (int)p->colours.size();
-                    if (c >= nc) return 0.0;
+                    if (c >= nc || p->n * (L.mixed ? 4 : 8) <= LDS_Z_MAX) return 0.0;
                     const Colour& cl = p->colours[c];
                     const int wz = !(sw + 1 == ell && c + 1 == nc);
                     return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
@@ -403,8 +444,23 @@ static lp_status build_graph(Batch& B, int iters) {
     return LP_OK;
 }
 
-lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
+// dyh = P y with R y = gamma; dw = A_hat^T dyh; true residual ||f_hat - A_hat dw||
+static void enqueue_assembly(Batch& B, int pmask) {
     const BLaunch& L = B.L;
+    b_backsolve(L, pmask);
+    b_combine(L, pmask);
+    b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, pmask, false);
+    b_spmv(L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, pmask, true);
+    b_true_res(L, pmask);
+}
+
+// start a solve for the pmask instances (f in V_F): f_hat, beta, control blocks
+static void enqueue_start(Batch& B, int pmask) {
+    b_init_rhs(B.L, pmask);
+    b_init_ctl(B.L, pmask, 0);
+}
+
+lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
     int64_t kmax_all = 0;
     int poll_every = 0;
     bool graphs = true;
@@ -418,9 +474,9 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
     if (info) info->assign((size_t)B.cap, lp_krylov_info{});
     if (kmax_all == 0) return LP_OK;
     const int64_t sid = B.solve_id++;
+    B.cur_solve = sid;
     if ((int64_t)B.solve_iters.size() <= sid) B.solve_iters.resize(sid + 1, 0);
-    b_init_rhs(L, pmask);
-    b_init_ctl(L, pmask, 0);
+    enqueue_start(B, pmask);
     LPK_HIP(hipGetLastError());
     const bool use_graph = graphs && B.prof_mask == 0;
     if (use_graph && !B.gexec) {
@@ -448,12 +504,7 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
         if (all || enq >= kmax_all) break;
         if (poll_every <= 0) batch = std::max(2, std::min(32, batch < 8 ? 4 : batch / 2));
     }
-    // dyh = P y with R y = gamma; dw = A_hat^T dyh; true residual ||f_hat - A_hat dw||
-    b_backsolve(L);
-    b_combine(L);
-    b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, -1, false);
-    b_spmv(L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, -1, true);
-    b_true_res(L);
+    enqueue_assembly(B, pmask);
     LPK_HIP(hipGetLastError());
     lp_status rc = B.get_slots();
     if (rc != LP_OK) return rc;
@@ -557,15 +608,12 @@ lp_status scale_batch(Batch& B, int pmask) {
 }
 
 // ------------------------------------------------------------------------------------
-// Lockstep interior-point driver
+// Interior-point driver: one state machine per member, one launch per phase per round
 
 void Engine::attach(Batch* b) {
     B = b;
     mem.assign((size_t)b->cap, Member{});
-    for (int s = 0; s < b->cap; ++s) {
-        mem[s].p = b->mem[s];
-        mem[s].state = EMPTY;
-    }
+    for (int s = 0; s < b->cap; ++s) mem[s].p = b->mem[s];
 }
 
 int Engine::join(lp_problem* p, bool from_point, int32_t limit_k) {
@@ -587,7 +635,8 @@ int Engine::join(lp_problem* p, bool from_point, int32_t limit_k) {
     }
     Member mb;
     mb.p = p;
-    mb.state = from_point ? RUN : INIT;
+    mb.init = !from_point;
+    mb.state = from_point ? MEAS : SCALE;
     mb.limit_k = limit_k;
     mb.t_join = now_seconds();
     mb.k0 = p->krylov_total;
@@ -605,7 +654,7 @@ void Engine::leave(int s) {
 
 bool Engine::any_live() const {
     for (const Member& mb : mem)
-        if (mb.state == INIT || mb.state == RUN) return true;
+        if (mb.state != EMPTY && mb.state != DONE) return true;
     return false;
 }
 
@@ -636,7 +685,83 @@ void fill_result(const Engine::Member& mb, lp_result* r) {
     r->seconds = mb.t_done - mb.t_join;
 }
 
-lp_status Engine::tick() {
+// residuals r_p = b - A x, r_d = c - A^T y - s, the error measure (eq. errorMeasureDef) and
+// the relative stopping test; the eps_in schedule of Sec. 4.2 (x0.75 while log10 Gamma in
+// (-3, 1], x0.375 at or below -3, x1.5 after a failed solve, clamped).  Returns true when
+// the member stops.
+static bool evaluate(Engine::Member& mb, const double* q, Param& pr) {
+    lp_problem* p = mb.p;
+    const lp_options& o = p->opt;
+    lp_iter_info& Lg = mb.L;
+    Lg = lp_iter_info{};
+    const double nb = p->norm_b, nc = p->norm_c;
+    Lg.mu = q[0] / (double)p->n;
+    Lg.rp_rel = std::sqrt(q[4]) / (nb > 1.0 ? nb : 1.0);
+    Lg.rd_rel = std::sqrt(q[2]) / (nc > 1.0 ? nc : 1.0);
+    Lg.pobj = q[1];
+    Lg.dobj = q[3];
+    Lg.gap_rel = std::fabs(q[1] - q[3]) / (std::fabs(q[1]) > 1.0 ? std::fabs(q[1]) : 1.0);
+    Lg.gamma = std::max(Lg.mu, std::max(Lg.rp_rel, Lg.rd_rel));
+    Lg.gamma_rel = std::max(Lg.gap_rel, std::max(Lg.rp_rel, Lg.rd_rel));
+    if (!std::isfinite(Lg.gamma_rel)) {
+        set_error("non-finite residuals");
+        p->log.push_back(Lg);
+        mb.last = Lg;
+        finish(mb, LP_DIVERGED);
+        return true;
+    }
+    if (Lg.gamma_rel <= o.eps_out) {
+        Lg.converged = 1;
+        p->log.push_back(Lg);
+        mb.last = Lg;
+        finish(mb, LP_OK);
+        return true;
+    }
+    if (p->ist.k >= mb.limit_k) {
+        // the final point is only evaluated
+        p->log.push_back(Lg);
+        mb.last = Lg;
+        finish(mb, LP_NOT_CONVERGED);
+        return true;
+    }
+    if (p->ist.k >= 1) {
+        const double lg = std::log10(Lg.gamma);
+        double fac = 1.0;
+        if (lg <= -3.0) fac = 0.375;
+        else if (lg <= 1.0) fac = 0.75;
+        if (p->ist.fail_prev) fac *= 1.5;
+        p->ist.eps_in *= fac;
+    }
+    p->ist.eps_in = std::min(std::max(p->ist.eps_in, o.eps_in_min), o.eps_in_max);
+    Lg.eps_in = p->ist.eps_in;
+    pr.scal[SC_TOL] = p->ist.eps_in;
+    return false;
+}
+
+static void take_solve(Batch& b, int s, Engine::Member& mb, lp_krylov_info* ki) {
+    const KrylovCtl& hc = b.h_slot[s].ctl;
+    ki->iters = hc.iters;
+    ki->beta = hc.beta;
+    ki->res_est = hc.res;
+    ki->res_true = hc.res_true;
+    ki->failed = hc.failed;
+    ki->pad0 = 0;
+    mb.p->krylov_total += hc.iters;
+    mb.p->omega_c = hc.omega_c;
+    mb.last_k = hc.iters;
+    b.last_iters = hc.iters;
+    if (mb.solve_id >= 0 && mb.solve_id < (int64_t)b.solve_iters.size()) b.solve_iters[mb.solve_id] = hc.iters;
+}
+
+// back-tracking from the current step lengths (Sec. 2.1)
+static void begin_bt(Engine::Member& mb, Param& pr) {
+    mb.bt = 0;
+    pr.scal[SC_AP] = mb.ap;
+    pr.scal[SC_AD] = mb.ad;
+    mb.state = Engine::BT;
+}
+
+lp_status Engine::round() {
     Batch& b = *B;
     lp_status rc;
 #define LPK_RC(x)                         \
@@ -647,283 +772,315 @@ lp_status Engine::tick() {
         }                                 \
     } while (0)
     if (b.dirty) LPK_RC(b.refresh());
-    const BLaunch& L = b.L;
-    int nrun = 0, ninit = 0;
+    // Scheduling.  Members of one shape (equal m, n, nnz) have similar solve lengths: they
+    // pass their phases together, once none of them is inside a solve (lockstep; a phase
+    // costs one round for all).  Members of different shapes each advance as soon as their
+    // solve ends, so a small LP is not held by a large one.
+    int iterating = 0;
+    bool uniform = true;
+    const lp_problem* ref = nullptr;
     for (int s = 0; s < b.cap; ++s) {
+        const Member& mb = mem[s];
+        if (mb.state == EMPTY || mb.state == DONE) continue;
+        if (mb.state == KRY1 || mb.state == KRY2) ++iterating;
+        if (!ref) ref = mb.p;
+        else if (mb.p->m != ref->m || mb.p->n != ref->n || mb.p->nnz != ref->nnz) uniform = false;
+    }
+    const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
+    bool has[SH2 + 1] = {false};
+    int live = 0, solving = 0, waiting = 0;
+    for (int s = 0; s < b.cap; ++s) {
+        Member& mb = mem[s];
         Param& pr = b.h_param[s];
-        pr.mode = 0;
-        Member& mb = mem[s];
-        if (mb.state == RUN) {
-            pr.mode = MD_RUN;
-            mb.L = lp_iter_info{};
-            mb.cc = false;
-            ++nrun;
-        } else if (mb.state == INIT) {
-            pr.mode = MD_INIT;
-            ++ninit;
+        const int role = mb.init ? MD_INIT : MD_RUN;
+        int md = 0;
+        if (hold && mb.state != EMPTY && mb.state != DONE && mb.state != KRY1 && mb.state != KRY2) {
+            pr.mode = role;
+            ++live;
+            continue;
         }
-    }
-    if (!nrun && !ninit) return LP_OK;
-
-    // residuals r_p = b - A x, r_d = c - A^T y - s and the scalars of the error measure
-    // (eq. errorMeasureDef) and of the relative stopping test
-    if (nrun) {
-        LPK_RC(b.put_params());
-        b_spmv(L, M_A_CSR, V_X, V_RP, EPI_B_MINUS, V_B, -1, MD_RUN, false);
-        b_spmv(L, M_A_CSC, V_Y, V_RD, EPI_B1_MINUS_B2, V_C, V_S, MD_RUN, false);
-        b_measures(L, MD_RUN);
-        const int ops[5] = {0, 0, 0, 0, 0};
-        b_red_finish(L, 5, ops, MD_RUN, 0);
-        LPK_HIP(hipGetLastError());
-        LPK_RC(b.get_slots());
-        for (int s = 0; s < b.cap; ++s) {
-            Member& mb = mem[s];
-            if (mb.state != RUN) continue;
-            lp_problem* p = mb.p;
-            const lp_options& o = p->opt;
-            const double* q = b.h_slot[s].out;
-            lp_iter_info& Lg = mb.L;
-            const double nb = p->norm_b, nc = p->norm_c;
-            Lg.mu = q[0] / (double)p->n;
-            Lg.rp_rel = std::sqrt(q[4]) / (nb > 1.0 ? nb : 1.0);
-            Lg.rd_rel = std::sqrt(q[2]) / (nc > 1.0 ? nc : 1.0);
-            Lg.pobj = q[1];
-            Lg.dobj = q[3];
-            Lg.gap_rel = std::fabs(q[1] - q[3]) / (std::fabs(q[1]) > 1.0 ? std::fabs(q[1]) : 1.0);
-            Lg.gamma = std::max(Lg.mu, std::max(Lg.rp_rel, Lg.rd_rel));
-            Lg.gamma_rel = std::max(Lg.gap_rel, std::max(Lg.rp_rel, Lg.rd_rel));
-            bool stop = true;
-            if (!std::isfinite(Lg.gamma_rel)) {
-                set_error("non-finite residuals");
-                p->log.push_back(Lg);
-                mb.last = Lg;
-                finish(mb, LP_DIVERGED);
-            } else if (Lg.gamma_rel <= o.eps_out) {
-                Lg.converged = 1;
-                p->log.push_back(Lg);
-                mb.last = Lg;
-                finish(mb, LP_OK);
-            } else if (p->ist.k >= mb.limit_k) {
-                // the final point is only evaluated
-                p->log.push_back(Lg);
-                mb.last = Lg;
-                finish(mb, LP_NOT_CONVERGED);
-            } else {
-                stop = false;
+        switch (mb.state) {
+            case MEAS: md = role | MD_MEAS; break;
+            case SCALE: {
+                md = role | MD_SCALE | MD_START;
+                const lp_options& o = mb.p->opt;
+                if (mb.init) pr.scal[SC_TOL] = o.init_tol;
+                if (o.inner == LP_CIMMINO && !mb.p->gsor) {
+                    if (o.omega_c > 0.0) pr.scal[SC_OMC] = o.omega_c;
+                    else md |= MD_POW;
+                }
+                break;
             }
-            if (stop) {
-                b.h_param[s].mode = 0;
-                --nrun;
-                continue;
-            }
-            // eps_in schedule of Sec. 4.2 (x0.75 while log10 Gamma in (-3, 1], x0.375 at or
-            // below -3, x1.5 after a failed solve), clamped to [eps_in_min, eps_in_max]
-            if (p->ist.k >= 1) {
-                const double lg = std::log10(Lg.gamma);
-                double fac = 1.0;
-                if (lg <= -3.0) fac = 0.375;
-                else if (lg <= 1.0) fac = 0.75;
-                if (p->ist.fail_prev) fac *= 1.5;
-                p->ist.eps_in *= fac;
-            }
-            p->ist.eps_in = std::min(std::max(p->ist.eps_in, o.eps_in_min), o.eps_in_max);
-            Lg.eps_in = p->ist.eps_in;
-            b.h_param[s].scal[SC_TOL] = p->ist.eps_in;
+            case KRY1: case KRY2: md = role; break;
+            case FIN1: md = role | MD_FIN | MD_POST1; break;
+            case MUAF: md = role | MD_MUAF; break;
+            case RHS2: md = role | MD_RHS2 | MD_START; break;
+            case FIN2: md = role | MD_FIN | MD_POST2; break;
+            case BT: md = role | MD_BT; break;
+            case UPD: md = role | MD_UPD | (stepwise ? 0 : MD_MEAS); break;
+            case SH1: md = role | MD_SH1; break;
+            case SH2: md = role | MD_SH2; break;
+            default: md = 0;
         }
-        if (!nrun && !ninit) return LP_OK;
+        pr.mode = md;
+        if (mb.state == EMPTY || mb.state == DONE) continue;
+        has[mb.state] = true;
+        ++live;
+        if (mb.state == KRY1 || mb.state == KRY2 || mb.state == SCALE || mb.state == RHS2) ++solving;
+        else ++waiting;
     }
-
-    // D = diag(sqrt(x/s)) for the step (identity for the starting-point solves); A_hat
-    for (int s = 0; s < b.cap; ++s) {
-        Member& mb = mem[s];
-        if (mb.state != RUN && mb.state != INIT) continue;
-        lp_problem* p = mb.p;
-        if (mb.state == INIT) b.h_param[s].scal[SC_TOL] = p->opt.init_tol;
-        if (p->opt.inner == LP_CIMMINO && !p->gsor) {
-            if (p->opt.omega_c > 0.0) b.h_param[s].scal[SC_OMC] = p->opt.omega_c;
-            else b.h_param[s].mode |= MD_POW;
-        }
-    }
+    if (!live) return LP_OK;
     LPK_RC(b.put_params());
-    b_scaling(L);
-    LPK_RC(scale_batch(b, MD_RUN | MD_INIT));
 
-    // first solve: predictor f_af = b + A (d^2 o r_d); starting point: f = b (t = 0)
-    b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_B_PLUS, V_B, -1, MD_RUN | MD_INIT, false);
-    std::vector<lp_krylov_info> ki;
-    LPK_RC(krylov_batch(b, MD_RUN | MD_INIT, &ki));
-    b_post1(b.L);
-    {
+    // the step, then the measures of the new point (one reduction pass for both)
+    const bool meas = has[MEAS] || (has[UPD] && !stepwise);
+    if (has[UPD]) b_update(b.L, 5);
+    if (meas) {
+        b_spmv(b.L, M_A_CSR, V_X, V_RP, EPI_B_MINUS, V_B, -1, MD_MEAS, false);
+        b_spmv(b.L, M_A_CSC, V_Y, V_RD, EPI_B1_MINUS_B2, V_C, V_S, MD_MEAS, false);
+        b_measures(b.L, MD_MEAS);
+    }
+    if (meas || has[UPD]) {
+        const int ops[6] = {0, 0, 0, 0, 0, 0};
+        b_red_finish(b.L, 6, ops, MD_MEAS | MD_UPD, 0);
+    }
+    // solves that finished: assembly, then direction recovery / starting-point pieces
+    if (has[FIN1] || has[FIN2]) enqueue_assembly(b, MD_FIN);
+    if (has[FIN1]) {
+        b_post1(b.L);
         const int ops[2] = {1, 1};
-        b_red_finish(b.L, 2, ops, MD_RUN, 0);
+        b_red_finish(b.L, 2, ops, MD_POST1, 0);
     }
-    LPK_HIP(hipGetLastError());
-    LPK_RC(b.get_slots());
-    int ncc = 0;
-    for (int s = 0; s < b.cap; ++s) {
-        Member& mb = mem[s];
-        if (mb.state != RUN) continue;
-        lp_iter_info& Lg = mb.L;
-        Lg.k_af = ki[s].iters;
-        Lg.res_af = ki[s].beta > 0.0 ? ki[s].res_true / ki[s].beta : 0.0;
-        Lg.fail_af = ki[s].failed;
-        const double eta = mb.p->opt.eta;
-        mb.ap = step_from(b.h_slot[s].out[0], eta);
-        mb.ad = step_from(b.h_slot[s].out[1], eta);
-        if (mb.ap < 1.0 || mb.ad < 1.0) {
-            mb.cc = true;
-            b.h_param[s].mode |= MD_CC;
-            b.h_param[s].scal[SC_AP] = mb.ap;
-            b.h_param[s].scal[SC_AD] = mb.ad;
-            ++ncc;
-        }
-    }
-    if (ncc) {
-        LPK_RC(b.put_params());
-        b_mu_af(b.L);
-        const int ops[1] = {0};
-        b_red_finish(b.L, 1, ops, MD_CC, 0);
-        LPK_HIP(hipGetLastError());
-        LPK_RC(b.get_slots());
-        for (int s = 0; s < b.cap; ++s) {
-            Member& mb = mem[s];
-            if (mb.state != RUN || !mb.cc) continue;
-            const lp_options& o = mb.p->opt;
-            lp_iter_info& Lg = mb.L;
-            const double mu_af = b.h_slot[s].out[0] / (double)mb.p->n;
-            double sigma;
-            if (Lg.gamma > 1e-3) {
-                const double r = mu_af / Lg.mu;
-                sigma = r * r;
-            } else {
-                sigma = 10.0 * Lg.gamma;
-            }
-            if (sigma > o.sigma_max) sigma = o.sigma_max;
-            Lg.sigma = sigma;
-            b.h_param[s].scal[SC_SMU] = sigma * Lg.mu;
-        }
-    }
-    // second solve: corrector f_cc = A ((dx_af o ds_af - sigma mu) / s); starting point:
-    // f = A c
-    if (ncc || ninit) {
-        LPK_RC(b.put_params());
-        b_rhs2(b.L);
-        b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_PLAIN, -1, -1, MD_CC | MD_INIT, false);
-        LPK_RC(krylov_batch(b, MD_CC | MD_INIT, &ki));
+    if (has[FIN2]) {
         b_post2(b.L);
         const int ops[2] = {1, 1};
-        b_red_finish(b.L, 2, ops, MD_CC | MD_INIT, 0);
-        LPK_HIP(hipGetLastError());
-        LPK_RC(b.get_slots());
-        for (int s = 0; s < b.cap; ++s) {
-            Member& mb = mem[s];
-            const double* q = b.h_slot[s].out;
-            if (mb.state == RUN && mb.cc) {
-                lp_iter_info& Lg = mb.L;
-                Lg.k_cc = ki[s].iters;
-                Lg.res_cc = ki[s].beta > 0.0 ? ki[s].res_true / ki[s].beta : 0.0;
-                Lg.fail_cc = ki[s].failed;
-                mb.ap = step_from(q[0], mb.p->opt.eta);
-                mb.ad = step_from(q[1], mb.p->opt.eta);
-            } else if (mb.state == INIT) {
-                // shift x~, s~ to positive (Mehrotra's heuristic)
-                b.h_param[s].scal[SC_HX] = -1.5 * q[0] > 0.0 ? -1.5 * q[0] : 0.0;
-                b.h_param[s].scal[SC_HS] = -1.5 * q[1] > 0.0 ? -1.5 * q[1] : 0.0;
-            }
-        }
+        b_red_finish(b.L, 2, ops, MD_POST2, 0);
     }
+    if (has[MUAF]) {
+        b_mu_af(b.L);
+        const int ops[1] = {0};
+        b_red_finish(b.L, 1, ops, MD_MUAF, 0);
+    }
+    if (has[BT]) {
+        b_backtrack(b.L);
+        const int ops[5] = {0, 0, 0, 1, 0};
+        b_red_finish(b.L, 5, ops, MD_BT, 0);
+    }
+    if (has[SH1] || has[SH2]) b_shift(b.L, MD_SH1 | MD_SH2);
+    if (has[SH2]) b_min2(b.L, MD_SH2);
+    if (has[SH1]) {
+        const int ops[3] = {0, 0, 0};
+        b_red_finish(b.L, 3, ops, MD_SH1, 0);
+    }
+    if (has[SH2]) {
+        const int ops[2] = {1, 1};
+        b_red_finish(b.L, 2, ops, MD_SH2, 0);
+    }
+    // solves that start: D and A_hat, right-hand sides (predictor f = b + A (d^2 o r_d),
+    // starting point f = b; corrector f = A ((dx_af o ds_af - sigma mu) / s), starting
+    // point f = A c), then f_hat and the control blocks
+    if (has[SCALE]) {
+        b_scaling(b.L);
+        LPK_RC(scale_batch(b, MD_SCALE));
+        b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_B_PLUS, V_B, -1, MD_SCALE, false);
+    }
+    if (has[RHS2]) {
+        b_rhs2(b.L);
+        b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_PLAIN, -1, -1, MD_RHS2, false);
+    }
+    if (has[SCALE] || has[RHS2]) {
+        enqueue_start(b, MD_START);
+        for (int s = 0; s < b.cap; ++s)
+            if (mem[s].state == SCALE || mem[s].state == RHS2) {
+                mem[s].solve_id = b.solve_id++;
+                b.cur_solve = mem[s].solve_id;
+                mem[s].enq = 0;
+                if ((int64_t)b.solve_iters.size() <= mem[s].solve_id) b.solve_iters.resize(mem[s].solve_id + 1, 0);
+            }
+    }
+    LPK_HIP(hipGetLastError());
+    // Krylov iterations for every member inside a solve (the others' kernels return at
+    // once): one graph of iterations while some member waits for its next phase, else
+    // enough to reach the earliest expected convergence
+    if (solving) {
+        int64_t todo = 8;
+        if (!waiting) {
+            // expected iterations to the next useful poll: the first member to finish, or
+            // (held phases) the last one; a member's previous solve length is the guess
+            int64_t rem = hold ? 0 : INT64_MAX;
+            for (int s = 0; s < b.cap; ++s) {
+                const Member& mb = mem[s];
+                if (mb.state != KRY1 && mb.state != KRY2 && mb.state != SCALE && mb.state != RHS2) continue;
+                const int64_t k = (mb.state == KRY1 || mb.state == KRY2) ? b.h_slot[s].ctl.k : 0;
+                const int64_t guess = mb.last_k > 0 ? mb.last_k : b.last_iters;
+                const int64_t r = std::max<int64_t>(1, guess - k);
+                rem = hold ? std::max(rem, r) : std::min(rem, r);
+            }
+            todo = std::max<int64_t>(8, std::min<int64_t>(rem, 256));
+        }
+        bool graphs = b.prof_mask == 0;
+        for (int s = 0; s < b.cap; ++s)
+            if (b.mem[s] && !b.mem[s]->opt.use_graphs) graphs = false;
+        if (graphs && !b.gexec) LPK_RC(build_graph(b, 8));
+        if (graphs) {
+            const int64_t launches = (todo + b.graph_iters - 1) / b.graph_iters;
+            for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(b.gexec, b.st));
+            todo = launches * b.graph_iters;
+        } else {
+            // iteration index for the profiler (meaningful for a batch of one)
+            int64_t it0 = b.cap == 1 ? mem[0].enq : -1;
+            for (int64_t i = 0; i < todo; ++i) enqueue_iteration(b, it0 < 0 ? -1 : it0 + i);
+        }
+        for (Member& mb : mem)
+            if (mb.state == KRY1 || mb.state == KRY2 || mb.state == SCALE || mb.state == RHS2) mb.enq += todo;
+        LPK_HIP(hipGetLastError());
+    }
+    LPK_RC(b.get_slots());
 
-    // back-tracking until min_i x_i s_i >= phi x^T s / n at the new point (Sec. 2.1); the
-    // starting points' two shift phases run in the same launches
+    // transitions (held members keep their state)
     for (int s = 0; s < b.cap; ++s) {
         Member& mb = mem[s];
-        if (mb.state != RUN) continue;
-        mb.bt = 0;
-        mb.bt_live = true;
-        b.h_param[s].mode |= MD_BT;
-        b.h_param[s].scal[SC_AP] = mb.ap;
-        b.h_param[s].scal[SC_AD] = mb.ad;
-    }
-    int stage = ninit ? 1 : 0;
-    for (;;) {
-        bool bt_any = false;
-        for (int s = 0; s < b.cap; ++s) bt_any = bt_any || (mem[s].state == RUN && mem[s].bt_live);
-        if (!stage && !bt_any) break;
-        LPK_RC(b.put_params());
-        if (stage == 1) b_shift(b.L, MD_INIT);
-        if (stage == 2) {
-            b_shift(b.L, MD_INIT);
-            b_min2(b.L, MD_INIT);
-        }
-        if (bt_any) b_backtrack(b.L);
-        const int ops1[5] = {0, 0, 0, 1, 0};
-        const int ops2[5] = {1, 1, 0, 1, 0};
-        b_red_finish(b.L, 5, stage == 2 ? ops2 : ops1, MD_INIT | MD_BT, 0);
-        LPK_HIP(hipGetLastError());
-        LPK_RC(b.get_slots());
-        for (int s = 0; s < b.cap; ++s) {
-            Member& mb = mem[s];
-            const double* q = b.h_slot[s].out;
-            if (mb.state == INIT && stage == 1) {
+        if (mb.state == EMPTY || mb.state == DONE) continue;
+        if (hold && mb.state != KRY1 && mb.state != KRY2) continue;
+        lp_problem* p = mb.p;
+        const lp_options& o = p->opt;
+        Param& pr = b.h_param[s];
+        const double* q = b.h_slot[s].out;
+        const bool done = b.h_slot[s].ctl.done != 0;
+        switch (mb.state) {
+            case UPD: {
+                lp_iter_info& Lg = mb.L;
+                Lg.alpha_p = mb.ap;
+                Lg.alpha_d = mb.ad;
+                Lg.backtracks = mb.bt;
+                p->ist.fail_prev = (Lg.fail_af || Lg.fail_cc) ? 1 : 0;
+                p->ist.k += 1;
+                p->log.push_back(Lg);
+                mb.last = Lg;
+                mb.steps += 1;
+                if (q[5] > 0.0) {
+                    set_error("iterate left the positive orthant or became non-finite");
+                    finish(mb, LP_DIVERGED);
+                    break;
+                }
+                if (stepwise) {
+                    mb.state = MEAS;
+                    break;
+                }
+                if (!evaluate(mb, q, pr)) mb.state = SCALE;
+                break;
+            }
+            case MEAS:
+                if (!evaluate(mb, q, pr)) mb.state = SCALE;
+                break;
+            case SCALE:
+                mb.state = done ? FIN1 : KRY1;
+                break;
+            case KRY1:
+                if (done) mb.state = FIN1;
+                break;
+            case FIN1: {
+                lp_krylov_info ki;
+                take_solve(b, s, mb, &ki);
+                if (mb.init) {
+                    mb.state = RHS2;   // x~ = dw; next: f = A c
+                    break;
+                }
+                lp_iter_info& Lg = mb.L;
+                Lg.k_af = ki.iters;
+                Lg.res_af = ki.beta > 0.0 ? ki.res_true / ki.beta : 0.0;
+                Lg.fail_af = ki.failed;
+                mb.ap = step_from(q[0], o.eta);
+                mb.ad = step_from(q[1], o.eta);
+                mb.cc = mb.ap < 1.0 || mb.ad < 1.0;
+                if (mb.cc) {
+                    pr.scal[SC_AP] = mb.ap;
+                    pr.scal[SC_AD] = mb.ad;
+                    mb.state = MUAF;
+                } else {
+                    Lg.sigma = 0.0;
+                    begin_bt(mb, pr);
+                }
+                break;
+            }
+            case MUAF: {
+                lp_iter_info& Lg = mb.L;
+                const double mu_af = q[0] / (double)p->n;
+                double sigma;
+                if (Lg.gamma > 1e-3) {
+                    const double r = mu_af / Lg.mu;
+                    sigma = r * r;
+                } else {
+                    sigma = 10.0 * Lg.gamma;
+                }
+                if (sigma > o.sigma_max) sigma = o.sigma_max;
+                Lg.sigma = sigma;
+                pr.scal[SC_SMU] = sigma * Lg.mu;
+                mb.state = RHS2;
+                break;
+            }
+            case RHS2:
+                mb.state = done ? FIN2 : KRY2;
+                break;
+            case KRY2:
+                if (done) mb.state = FIN2;
+                break;
+            case FIN2: {
+                lp_krylov_info ki;
+                take_solve(b, s, mb, &ki);
+                if (mb.init) {
+                    // shift x~, s~ to positive (Mehrotra's heuristic)
+                    pr.scal[SC_HX] = -1.5 * q[0] > 0.0 ? -1.5 * q[0] : 0.0;
+                    pr.scal[SC_HS] = -1.5 * q[1] > 0.0 ? -1.5 * q[1] : 0.0;
+                    mb.state = SH1;
+                    break;
+                }
+                lp_iter_info& Lg = mb.L;
+                Lg.k_cc = ki.iters;
+                Lg.res_cc = ki.beta > 0.0 ? ki.res_true / ki.beta : 0.0;
+                Lg.fail_cc = ki.failed;
+                mb.ap = step_from(q[0], o.eta);
+                mb.ad = step_from(q[1], o.eta);
+                begin_bt(mb, pr);
+                break;
+            }
+            case BT:
+                if (q[3] >= o.phi * q[4] / (double)p->n || mb.bt >= o.max_backtrack) {
+                    pr.scal[SC_AP] = mb.ap;
+                    pr.scal[SC_AD] = mb.ad;
+                    mb.state = UPD;
+                } else {
+                    mb.ap *= o.backtrack;
+                    mb.ad *= o.backtrack;
+                    mb.bt += 1;
+                    pr.scal[SC_AP] = mb.ap;
+                    pr.scal[SC_AD] = mb.ad;
+                }
+                break;
+            case SH1:
                 // balance: x += 1/2 x^T s / sum(s), s += 1/2 x^T s / sum(x)
-                b.h_param[s].scal[SC_HX] = 0.5 * q[0] / q[2];
-                b.h_param[s].scal[SC_HS] = 0.5 * q[0] / q[1];
-            } else if (mb.state == INIT && stage == 2) {
-                lp_problem* p = mb.p;
-                b.h_param[s].mode = 0;
+                pr.scal[SC_HX] = 0.5 * q[0] / q[2];
+                pr.scal[SC_HS] = 0.5 * q[0] / q[1];
+                mb.state = SH2;
+                break;
+            case SH2:
                 if (!(q[0] > 0.0) || !(q[1] > 0.0)) {
                     set_error("starting point is not strictly positive");
                     finish(mb, LP_DIVERGED);
                 } else {
                     p->have_point = true;
-                    p->ist.eps_in = p->opt.eps_in0;
+                    p->ist.eps_in = o.eps_in0;
                     p->ist.k = 0;
                     p->ist.fail_prev = 0;
-                    mb.state = RUN;   // its first step is the next tick's
+                    mb.init = false;
+                    mb.state = MEAS;
                 }
-            } else if (mb.state == RUN && mb.bt_live) {
-                const lp_options& o = mb.p->opt;
-                if (q[3] >= o.phi * q[4] / (double)mb.p->n || mb.bt >= o.max_backtrack) {
-                    mb.bt_live = false;
-                    b.h_param[s].mode &= ~MD_BT;
-                } else {
-                    mb.ap *= o.backtrack;
-                    mb.ad *= o.backtrack;
-                    mb.bt += 1;
-                    b.h_param[s].scal[SC_AP] = mb.ap;
-                    b.h_param[s].scal[SC_AD] = mb.ad;
-                }
-            }
-        }
-        stage = stage == 1 ? 2 : 0;
-    }
-
-    // the step
-    if (nrun) {
-        LPK_RC(b.put_params());
-        b_update(b.L, 0);
-        const int ops[1] = {0};
-        b_red_finish(b.L, 1, ops, MD_RUN, 0);
-        LPK_HIP(hipGetLastError());
-        LPK_RC(b.get_slots());
-        for (int s = 0; s < b.cap; ++s) {
-            Member& mb = mem[s];
-            if (mb.state != RUN || !(b.h_param[s].mode & MD_RUN)) continue;
-            lp_problem* p = mb.p;
-            lp_iter_info& Lg = mb.L;
-            Lg.alpha_p = mb.ap;
-            Lg.alpha_d = mb.ad;
-            Lg.backtracks = mb.bt;
-            p->ist.fail_prev = (Lg.fail_af || Lg.fail_cc) ? 1 : 0;
-            p->ist.k += 1;
-            p->log.push_back(Lg);
-            mb.last = Lg;
-            if (b.h_slot[s].out[0] > 0.0) {
-                set_error("iterate left the positive orthant or became non-finite");
-                finish(mb, LP_DIVERGED);
-            }
+                break;
+            default:
+                break;
         }
     }
+    if (b.prof_recs.size() > 200000) prof_collect(b);
 #undef LPK_RC
     return LP_OK;
 }

@@ -40,14 +40,25 @@ constexpr int V_PCOL = -1;   // column ctl->k of the multiplier vectors P
 // matrices of an instance for the row-dot products
 enum MatSel : int { M_A_CSR = 0, M_A_CSC = 1, M_AH_CSR = 2, M_AH_CSC = 3 };
 
-// per-instance role in the current phase (bit mask in *Inst::mode)
+// per-instance role and phase (bit mask in *Inst::mode).  Every instance of a batch is in
+// its own phase; one launch serves all instances whose mode has that phase's bit.
 enum Mode : int {
-    MD_RUN = 1,     // takes an interior-point step this tick
-    MD_INIT = 2,    // computes its starting point this tick
-    MD_CC = 4,      // solves the corrector this tick
-    MD_BT = 8,      // still back-tracking
-    MD_API = 16,    // direction_solve request
-    MD_POW = 32,    // estimates its Cimmino step this tick
+    MD_RUN = 1,        // role: takes interior-point steps
+    MD_INIT = 2,       // role: computes its starting point
+    MD_BT = 8,         // phase: centrality test at the trial point (back-tracking)
+    MD_API = 16,       // direction_solve / lp_set_state request
+    MD_POW = 32,       // with MD_SCALE: estimate the Cimmino step
+    MD_MEAS = 64,      // phase: residuals and error measure
+    MD_SCALE = 128,    // phase: D, A_hat, first right-hand side
+    MD_START = 256,    // a Krylov solve starts this round
+    MD_FIN = 512,      // a Krylov solve is assembled this round
+    MD_POST1 = 1024,   // phase: after the first solve
+    MD_MUAF = 2048,    // phase: mu_af
+    MD_RHS2 = 4096,    // phase: second right-hand side
+    MD_POST2 = 8192,   // phase: after the second solve
+    MD_SH1 = 16384,    // phase: starting point, first shift
+    MD_SH2 = 32768,    // phase: starting point, second shift and minima
+    MD_UPD = 65536,    // phase: the step x, y, s += alpha d
 };
 
 // per-instance scalars of the current phase (Inst::scal)
@@ -63,6 +74,8 @@ struct Inst {
     int32_t nbr;                          // blocks of the vector reductions (own sizes only)
     int32_t nbs;                          // blocks of the reduction over a CSR product
     int32_t zcover;                       // 1: the rows of colour 0 cover every column
+    int32_t lds;                          // 1: whole NE-SOR application in one block, z in LDS
+    int32_t pad1;
     int64_t ldv, ldh, ldp, kmax;
     const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
     const int32_t *cstart, *cg;           // colour row ranges (ncol+1), lanes per row by colour
@@ -99,7 +112,13 @@ struct BLaunch {
     int max_ncol;
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
+    bool any_lds;           // some instance sweeps in one block with z in LDS
+    int lds_bytes;          // largest z of those instances
+    int max_ncol_global;    // colours of the instances swept by per-colour launches
 };
+
+// an NE-SOR instance sweeps in one block with z in LDS when z fits in this many bytes
+constexpr int LDS_Z_MAX = 48 * 1024;
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------
 enum Epilogue : int { EPI_PLAIN = 0, EPI_B_MINUS = 1, EPI_B1_MINUS_B2 = 2, EPI_B_PLUS = 3 };
@@ -116,6 +135,7 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 // z of instances whose colour 0 does not cover every column (colour 0 then overwrites z).
 void b_prep(const BLaunch& L);
 void b_nesor(const BLaunch& L, int colour, int sweep, int ell);
+void b_sweep_lds(const BLaunch& L, int ell);   // every colour and sweep, one block per instance
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 void b_gs_dots(const BLaunch& L);
@@ -126,13 +146,13 @@ void b_apply_c(const BLaunch& L);       // dense: P[:,k] = C v_k
 void b_gemv_col(const BLaunch& L);      // dense: u = G p_k
 // solve set-up (instances with a bit of pmask take part; the others are marked done)
 void b_init_rhs(const BLaunch& L, int pmask);
-void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap);
-void b_backsolve(const BLaunch& L);
-void b_combine(const BLaunch& L);
-void b_true_res(const BLaunch& L);
+void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap);   // other instances untouched
+void b_backsolve(const BLaunch& L, int pmask);
+void b_combine(const BLaunch& L, int pmask);
+void b_true_res(const BLaunch& L, int pmask);
 
 // ---- scaling (Sec. 2.2, 3.5) ------------------------------------------------------------
-// MD_RUN: d = sqrt(x/s), t = d^2 r_d; MD_INIT: d = 1, t = 0; MD_API: d as given
+// MD_SCALE instances: d = sqrt(x/s), t = d^2 r_d; with MD_INIT: d = 1, t = 0
 void b_scaling(const BLaunch& L);
 void b_scale_rows(const BLaunch& L, int pmask);
 void b_scale_cols(const BLaunch& L, int pmask);
@@ -146,14 +166,14 @@ void b_set_omc(const BLaunch& L, int pmask);
 void b_red_finish(const BLaunch& L, int nq, const int* ops, int pmask, int which);
 // every reduction below uses Inst::nbr blocks per instance
 void b_measures(const BLaunch& L, int pmask);   // q0 x.s, q1 c.x, q2 ||r_d||^2, q3 b.y, q4 ||r_p||^2
-void b_post1(const BLaunch& L);           // after the first solve: q0, q1 ratio minima
-void b_mu_af(const BLaunch& L);           // MD_CC: q0 sum (x + ap dx)(s + ad ds)
-void b_rhs2(const BLaunch& L);            // t for the second solve
-void b_post2(const BLaunch& L);           // after the second solve: q0, q1 minima
+void b_post1(const BLaunch& L);           // MD_POST1: q0, q1 ratio minima (MD_RUN) / x = dw (MD_INIT)
+void b_mu_af(const BLaunch& L);           // MD_MUAF: q0 sum (x + ap dx)(s + ad ds)
+void b_rhs2(const BLaunch& L);            // MD_RHS2: t for the second solve
+void b_post2(const BLaunch& L);           // MD_POST2: q0, q1 minima
 void b_shift(const BLaunch& L, int pmask);     // q0 x.s, q1 sum x, q2 sum s
 void b_min2(const BLaunch& L, int pmask);      // q0 min x, q1 min s
 void b_backtrack(const BLaunch& L);       // MD_BT: q3 min x_i s_i, q4 x.s at the trial point
-void b_update(const BLaunch& L, int q);   // MD_RUN: q = count of entries not finite positive
+void b_update(const BLaunch& L, int q);   // MD_UPD: q = count of entries not finite positive
 void b_div_rho(const BLaunch& L, int dst, int src, int pmask);
 
 // ---- single-instance helpers (argument marshalling of the C ABI) -------------------------

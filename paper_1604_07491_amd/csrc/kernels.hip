@@ -107,8 +107,7 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 
 __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
     if (pmask > 0) return (*in.mode & pmask) != 0;
-    if (pmask == 0) return in.ctl->done == 0;   // Krylov loop: still iterating
-    return in.ctl->active != 0;                 // -1: took part in the current solve
+    return in.ctl->done == 0;   // 0: Krylov loop, still iterating
 }
 
 __device__ __forceinline__ void write_part(const Inst& in, int bx, int q, double v) {
@@ -179,7 +178,7 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 // uncovered: z = 0 (the first sweep sets V[:,k] and p_k itself)
 __global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int mixed) {
     INST;
-    if (in.ctl->done || in.gsor || in.zcover || in.ncol == 0) return;
+    if (in.ctl->done || in.gsor || in.zcover || in.lds || in.ncol == 0) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     if (mixed) {
         for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
@@ -204,7 +203,7 @@ void b_prep(const BLaunch& L) {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int ell) {
     INST;
-    if (in.ctl->done || in.gsor || c >= in.ncol) return;
+    if (in.ctl->done || in.gsor || in.lds || c >= in.ncol) return;
     const int r0 = in.cstart[c], r1 = in.cstart[c + 1], g = in.cg[c];
     const int tid = bx * BLOCK + threadIdx.x;
     const int row = r0 + tid / g, lane = tid & (g - 1);
@@ -290,6 +289,104 @@ void b_nesor(const BLaunch& L, int colour, int sweep, int ell) {
         hipLaunchKernelGGL((k_nesor<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
     else
         hipLaunchKernelGGL((k_nesor<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+}
+
+// ------------------------------------------------------------------------------------
+// A whole NE-SOR application (ell sweeps over every colour) for instances whose z fits in
+// LDS: one block of 1024 threads per instance, z zeroed and kept in LDS, a block barrier
+// between colours instead of a kernel launch.  Each row is handled exactly as in k_nesor
+// (same lanes per row, same element-to-lane assignment, same sub-group sum), so the
+// result is bitwise the same as the per-colour launches.
+constexpr int LDS_BLOCK = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict__ I, int ell) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* __restrict__ z = reinterpret_cast<T*>(lds_raw);
+    INST;
+    if (in.ctl->done || !in.lds) return;
+    const int n = in.n;
+    for (int j = threadIdx.x; j < n; j += LDS_BLOCK) z[j] = 0;
+    __syncthreads();
+    const int64_t k = in.ctl->k;
+    const double ih = in.ctl->inv_h;
+    const double* __restrict__ u = in.vec[V_U];
+    double* __restrict__ vk = in.V + k * in.ldv;
+    double* __restrict__ p = in.P + k * in.ldv;
+    const T* __restrict__ val;
+    if constexpr (sizeof(T) == 4) val = (const T*)in.ah32;
+    else val = (const T*)in.ah;
+    const int32_t* __restrict__ idx = in.ci;
+    const T om = (T)in.omega;
+    for (int sw = 0; sw < ell; ++sw) {
+        for (int c = 0; c < in.ncol; ++c) {
+            const int r0 = in.cstart[c], r1 = in.cstart[c + 1], g = in.cg[c];
+            const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
+            const int lane = threadIdx.x & (g - 1);
+            const int per = LDS_BLOCK / g;
+            for (int base = r0; base < r1; base += per) {
+                const int row = base + (int)threadIdx.x / g;
+                if (row < r1) {   // uniform inside the sub-group
+                    const double vrow = sw == 0 ? u[row] * ih : vk[row];
+                    const int s = in.rp[row], e = in.rp[row + 1];
+                    constexpr int R = 8;
+                    T acc = 0;
+                    if (e - s <= g * R) {
+                        T a[R];
+                        int jj[R];
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            const int kk = s + lane + t * g;
+                            a[t] = 0;
+                            jj[t] = 0;
+                            if (kk < e) {
+                                a[t] = val[kk];
+                                jj[t] = idx[kk];
+                                acc += a[t] * z[jj[t]];
+                            }
+                        }
+                        acc = sg_sum(acc, g);
+                        const T delta = om * ((T)vrow - acc);
+                        if (write_z) {
+#pragma unroll
+                            for (int t = 0; t < R; ++t)
+                                if (s + lane + t * g < e) z[jj[t]] += delta * a[t];
+                        }
+                        if (lane == 0) {
+                            if (sw == 0) {
+                                vk[row] = vrow;
+                                p[row] = (double)delta;
+                            } else {
+                                p[row] += (double)delta;
+                            }
+                        }
+                    } else {
+                        for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
+                        acc = sg_sum(acc, g);
+                        const T delta = om * ((T)vrow - acc);
+                        if (write_z)
+                            for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
+                        if (lane == 0) {
+                            if (sw == 0) {
+                                vk[row] = vrow;
+                                p[row] = (double)delta;
+                            } else {
+                                p[row] += (double)delta;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+void b_sweep_lds(const BLaunch& L, int ell) {
+    if (L.mixed)
+        hipLaunchKernelGGL((k_sweep_lds<float>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, ell);
+    else
+        hipLaunchKernelGGL((k_sweep_lds<double>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, ell);
 }
 
 // ------------------------------------------------------------------------------------
@@ -694,20 +791,14 @@ __global__ __launch_bounds__(BLOCK) void k_init_ctl(const Inst* __restrict__ I, 
     __shared__ double sh[BLOCK / 64];
     INST;
     KrylovCtl* ctl = in.ctl;
-    const bool part = takes_part(in, pmask);
+    if (!takes_part(in, pmask)) return;   // other instances keep their solves
     double q = 0.0;
-    if (part)
-        for (int c = threadIdx.x; c < in.nbr; c += BLOCK) q += in.part[c];
+    for (int c = threadIdx.x; c < in.nbr; c += BLOCK) q += in.part[c];
     const double s = block_sum(q, sh);
     if (threadIdx.x != 0) return;
     ctl->k = 0;
     ctl->iters = 0;
     ctl->failed = 0;
-    if (!part) {
-        ctl->active = 0;
-        ctl->done = 1;
-        return;
-    }
     const double beta = sqrt(s);
     int64_t km = in.kmax;
     if (kcap > 0 && kcap < km) km = kcap;
@@ -728,9 +819,9 @@ void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap) {
 }
 
 // R y = gamma(1:iters), R the upper triangle of the rotated Hessenberg matrix
-__global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I) {
+__global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I, int pmask) {
     INST;
-    if (!in.ctl->active) return;
+    if (!takes_part(in, pmask)) return;
     const int it = in.ctl->iters;
     double* __restrict__ y = in.ykr;
     for (int i = threadIdx.x; i < it; i += BLOCK) y[i] = in.gam[i];
@@ -744,14 +835,14 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I)
     }
 }
 
-void b_backsolve(const BLaunch& L) {
-    hipLaunchKernelGGL(k_backsolve, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I);
+void b_backsolve(const BLaunch& L, int pmask) {
+    hipLaunchKernelGGL(k_backsolve, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
 // dyh = P[:, 0:iters] y  (flexible final step: dw = A_hat^T dyh)
-__global__ __launch_bounds__(BLOCK) void k_combine(const Inst* __restrict__ I) {
+__global__ __launch_bounds__(BLOCK) void k_combine(const Inst* __restrict__ I, int pmask) {
     INST;
-    if (!in.ctl->active) return;
+    if (!takes_part(in, pmask)) return;
     const int it = in.ctl->iters;
     const int64_t i = (int64_t)bx * BLOCK + threadIdx.x;
     if (i >= in.m) return;
@@ -760,22 +851,22 @@ __global__ __launch_bounds__(BLOCK) void k_combine(const Inst* __restrict__ I) {
     in.vec[V_DYH][i] = s;
 }
 
-void b_combine(const BLaunch& L) {
-    hipLaunchKernelGGL(k_combine, dim3(cdiv(L.max_m, BLOCK), L.S), dim3(BLOCK), 0, L.st, L.I);
+void b_combine(const BLaunch& L, int pmask) {
+    hipLaunchKernelGGL(k_combine, dim3(cdiv(L.max_m, BLOCK), L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_true_res(const Inst* __restrict__ I) {
+__global__ __launch_bounds__(BLOCK) void k_true_res(const Inst* __restrict__ I, int pmask) {
     __shared__ double sh[BLOCK / 64];
     INST;
-    if (!in.ctl->active) return;
+    if (!takes_part(in, pmask)) return;
     double q = 0.0;
     for (int c = threadIdx.x; c < in.nbs; c += BLOCK) q += in.part[c];
     const double s = block_sum(q, sh);
     if (threadIdx.x == 0) in.ctl->res_true = sqrt(s);
 }
 
-void b_true_res(const BLaunch& L) {
-    hipLaunchKernelGGL(k_true_res, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I);
+void b_true_res(const BLaunch& L, int pmask) {
+    hipLaunchKernelGGL(k_true_res, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
 // ------------------------------------------------------------------------------------
@@ -784,13 +875,13 @@ void b_true_res(const BLaunch& L) {
 __global__ __launch_bounds__(BLOCK) void k_scaling(const Inst* __restrict__ I) {
     INST;
     const int md = *in.mode;
-    if (!(md & (MD_RUN | MD_INIT))) return;
+    if (!(md & MD_SCALE)) return;
     double* __restrict__ d = in.vec[V_D];
     double* __restrict__ t = in.vec[V_TN];
     const double *__restrict__ x = in.vec[V_X], *__restrict__ s = in.vec[V_S], *__restrict__ rd = in.vec[V_RD];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) {
-        if (md & MD_RUN) {
+        if (!(md & MD_INIT)) {
             const double dj = sqrt(x[j] / s[j]);
             d[j] = dj;
             t[j] = dj * dj * rd[j];
@@ -981,7 +1072,7 @@ __device__ __forceinline__ double ratio_term(double v, double dv) { return dv < 
 // ds = r_d - dw/d, dx = -d^2 ds - x (Sec. 2.2) with the ratio tests; MD_INIT: x = dw
 __global__ __launch_bounds__(BLOCK) void k_post1(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
-    IPM_PROLOGUE(*in.mode & (MD_RUN | MD_INIT));
+    IPM_PROLOGUE(*in.mode & MD_POST1);
     const int md = *in.mode;
     double mp = INFINITY, mdd = INFINITY;
     const double* __restrict__ dw = in.vec[V_DW];
@@ -1013,10 +1104,10 @@ void b_post1(const BLaunch& L) {
     hipLaunchKernelGGL(k_post1, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
-// mu_af numerator: sum (x + ap dx)(s + ad ds) for MD_CC instances
+// mu_af numerator: sum (x + ap dx)(s + ad ds) for MD_RHS2 instances
 __global__ __launch_bounds__(BLOCK) void k_mu_af(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
-    IPM_PROLOGUE(*in.mode & MD_CC);
+    IPM_PROLOGUE(*in.mode & MD_MUAF);
     const double ap = in.scal[SC_AP], ad = in.scal[SC_AD];
     const double *x = in.vec[V_X], *s = in.vec[V_S], *dx = in.vec[V_DXA], *ds = in.vec[V_DSA];
     double q = 0.0;
@@ -1029,13 +1120,13 @@ void b_mu_af(const BLaunch& L) {
     hipLaunchKernelGGL(k_mu_af, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
-// input of the second solve's right-hand side f = A t: MD_CC: t = (dx_af ds_af - sigma mu)/s
+// input of the second solve's right-hand side f = A t: MD_RHS2: t = (dx_af ds_af - sigma mu)/s
 // (the corrector of Sec. 2.2); MD_INIT: t = c (f = A c, for the projection of c)
 __global__ __launch_bounds__(BLOCK) void k_rhs2(const Inst* __restrict__ I) {
-    IPM_PROLOGUE(*in.mode & (MD_CC | MD_INIT));
+    IPM_PROLOGUE(*in.mode & MD_RHS2);
     const int md = *in.mode;
     double* __restrict__ t = in.vec[V_TN];
-    if (md & MD_CC) {
+    if (!(md & MD_INIT)) {
         const double smu = in.scal[SC_SMU];
         const double *dxa = in.vec[V_DXA], *dsa = in.vec[V_DSA], *s = in.vec[V_S];
         for (int64_t j = tid0; j < in.n; j += stride) t[j] = (dxa[j] * dsa[j] - smu) / s[j];
@@ -1049,13 +1140,13 @@ void b_rhs2(const BLaunch& L) {
     hipLaunchKernelGGL(k_rhs2, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
-// after the second solve: MD_CC: dy_cc = dyh / rho, dy += dy_cc, the corrector's recovery
+// after the second solve: MD_RHS2: dy_cc = dyh / rho, dy += dy_cc, the corrector's recovery
 // added in place (ds_cc = -dw/d, dx_cc = -d^2 ds_cc - dx_af ds_af / s + sigma mu / s) and
 // the ratio tests of the combined direction; MD_INIT: y = dyh / rho, s = c - dw, then
 // min x and min s (NaN counts as -inf)
 __global__ __launch_bounds__(BLOCK) void k_post2(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
-    IPM_PROLOGUE(*in.mode & (MD_CC | MD_INIT));
+    IPM_PROLOGUE(*in.mode & MD_POST2);
     const int md = *in.mode;
     double q0 = INFINITY, q1 = INFINITY;
     const double *dyh = in.vec[V_DYH], *rho = in.vec[V_RHO], *dw = in.vec[V_DW];
@@ -1172,7 +1263,7 @@ void b_backtrack(const BLaunch& L) {
 // x += ap dx, s += ad ds, y += ad dy; count entries of x, s that are not finite positive
 __global__ __launch_bounds__(BLOCK) void k_update(const Inst* __restrict__ I, int q) {
     __shared__ double sh[BLOCK / 64];
-    IPM_PROLOGUE(*in.mode & MD_RUN);
+    IPM_PROLOGUE(*in.mode & MD_UPD);
     const double ap = in.scal[SC_AP], ad = in.scal[SC_AD];
     double *x = in.vec[V_X], *s = in.vec[V_S], *y = in.vec[V_Y];
     const double *dx = in.vec[V_DXA], *ds = in.vec[V_DSA], *dy = in.vec[V_DYA];

@@ -164,7 +164,10 @@ struct Batch {
     double* d_part = nullptr;         // cap x RED_NQ x RED_MAXBLK
     BLaunch L{};
     std::vector<int> grid_colour;
+    BLaunch graph_L{};                // the launch shapes the graph was captured with
+    std::vector<int> graph_colour;
     bool dirty = true;                // membership changed since the descriptors were uploaded
+    bool param_inflight = false;      // a parameter upload may still be in flight
     // captured Krylov iterations
     hipStream_t cap_st = nullptr;
     hipGraph_t graph = nullptr;
@@ -177,7 +180,8 @@ struct Batch {
     double* count_flops = nullptr;
     int64_t* count_launch = nullptr;
     int count_cls = -1;
-    int64_t solve_id = 0;
+    int64_t solve_id = 0;             // solves started on this batch
+    int64_t cur_solve = -1;           // the solve the launches being enqueued belong to
     std::vector<ProfRec> prof_recs;
     std::vector<hipEvent_t> prof_pool;
     std::vector<int64_t> solve_iters;
@@ -209,36 +213,55 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info);
 lp_status scale_batch(Batch& B, int pmask);
 lp_status build_dense_preconditioner(Batch& B, lp_problem* p);
 
-// Lockstep interior-point driver over a batch
+// Interior-point driver over a batch.  Every member runs its own state machine (its own
+// phase of Mehrotra's iteration or of the starting point); a round launches each phase's
+// kernels once for all members in that phase, then Krylov iterations for every member
+// inside a solve, then reads every member's scalars in one copy.  Members join and leave
+// at any round.
 struct Engine {
-    enum State { EMPTY = 0, INIT, RUN, DONE };
+    enum State {
+        EMPTY = 0, DONE,
+        MEAS,       // residuals, error measure, stopping test
+        SCALE,      // D, A_hat, first right-hand side; starts solve 1
+        KRY1,       // inside solve 1
+        FIN1,       // solve 1 assembled; direction recovery and ratio tests
+        MUAF,       // mu_af at the predictor's step
+        RHS2,       // second right-hand side; starts solve 2
+        KRY2,       // inside solve 2
+        FIN2,       // solve 2 assembled; corrector recovery / starting point y, s
+        BT,         // back-tracking test
+        UPD,        // the step (with the next point's measures unless step-wise)
+        SH1, SH2    // starting point: shifts
+    };
     struct Member {
         lp_problem* p = nullptr;
         State state = EMPTY;
+        bool init = false;            // role: computing the starting point
         int32_t limit_k = 0;          // evaluate only once ist.k reaches it
         lp_status status = LP_OK;
         int32_t iters = 0;
-        lp_iter_info L{};             // the current tick's log entry
+        int32_t steps = 0;            // interior-point steps taken in this engine
+        lp_iter_info L{};             // the current iteration's log entry
         lp_iter_info last{};          // the final measures
         bool cc = false;
         double ap = 0.0, ad = 0.0;
         int32_t bt = 0;
-        bool bt_live = false;
         double t_join = 0.0, t_done = 0.0;
         int64_t k0 = 0;               // krylov_total at join
+        int64_t solve_id = -1, enq = 0;   // profiler bookkeeping of the current solve
+        int64_t last_k = 0;           // iterations of the member's previous solve
     };
     Batch* B = nullptr;
     std::vector<Member> mem;
     lp_status error = LP_OK;          // a device error stops the whole batch
+    bool stepwise = false;            // ipm_step: the update round does not evaluate the next point
 
     void attach(Batch* b);
-    // join a free slot: start INIT (starting point first) or RUN (from the point it holds)
+    // join a free slot: start with the starting point, or from the point it holds
     int join(lp_problem* p, bool from_point, int32_t limit_k);
-    // one tick: every INIT member computes its starting point, every RUN member takes one
-    // interior-point step or finishes
-    lp_status tick();
+    lp_status round();
     bool any_live() const;
-    void leave(int slot);             // empty a slot (state DONE or EMPTY)
+    void leave(int slot);             // empty a slot
 };
 
 double now_seconds();

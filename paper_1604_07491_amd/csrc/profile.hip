@@ -32,7 +32,7 @@ Prof::Prof(Batch* pp, int cls, int64_t iter, double bytes, double flops) : B(pp)
     if (!(p->prof_mask & (1u << cls))) return;
     ProfRec r;
     r.cls = cls;
-    r.solve = p->solve_id;
+    r.solve = p->cur_solve;
     r.iter = iter;
     r.bytes = bytes;
     r.flops = flops;

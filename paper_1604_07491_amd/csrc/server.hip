@@ -1,8 +1,7 @@
 // Many LPs on one MI355X: lp_solve_batch over created problems, and the request-driven
-// server.  Both run the batched engine: up to `width` LPs in lockstep, every phase of an
-// interior-point iteration one launch for all of them.  A finished LP leaves the batch at
-// the end of a tick and a waiting one joins (its starting point is computed during the
-// next tick), so the batch stays full while work remains.
+// server.  Both run the batched engine: up to `width` LPs share every launch, each in its
+// own phase of its own interior-point iteration.  A finished LP leaves the batch after any
+// round and a waiting one joins at once, so the batch stays full while work remains.
 #include <string.h>
 
 #include <atomic>
@@ -62,7 +61,7 @@ static lp_status solve_group(lp_problem** problems, const std::vector<int32_t>& 
     };
     refill();
     while (E.any_live()) {
-        rc = E.tick();
+        rc = E.round();
         if (rc != LP_OK) break;
         for (int s = 0; s < B.cap; ++s) {
             if (E.mem[s].state != Engine::DONE) continue;
@@ -283,7 +282,7 @@ static void engine_main(lp_server* s) {
             t_start[slot] = s->now();
             held[slot] = std::move(rd);
         }
-        const lp_status trc = E.tick();
+        const lp_status trc = E.round();
         for (int slot = 0; slot < B.cap; ++slot) {
             Engine::Member& mb = E.mem[slot];
             if (mb.state != Engine::DONE && !(trc != LP_OK && mb.state != Engine::EMPTY)) continue;

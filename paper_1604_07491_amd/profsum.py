@@ -1,0 +1,75 @@
+"""Reduce rocprofv3 CSV output to the short summaries kept under profiles/.
+
+    python -m paper_1604_07491_amd.profsum trace <rocprof output dir> <out.json>
+    python -m paper_1604_07491_amd.profsum pmc   <rocprof output dir> <out.json>
+
+trace: per (kernel, grid) launch counts and mean durations from the kernel trace, and for
+each batch width the mean duration of the NE-SOR sweep launches of the timing replay (the
+sweep launches after the last back-substitution of that width: bench.py replays the
+dominant kernel last).  pmc: per (kernel, grid) mean counter value, and the mean over the
+last 800 sweep dispatches of the largest grid (the replay window).
+"""
+import collections
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _one(d, pattern):
+    fs = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not fs:
+        raise SystemExit(f"no {pattern} under {d}")
+    return fs[0]
+
+
+def trace_summary(d):
+    rows = list(csv.DictReader(open(_one(d, "*kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        key = (r["Kernel_Name"].split("(")[0][:48], int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]))
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    res = {"kernels": [[k[0], k[1], k[2], n, us / 1e3, us / n]
+                       for k, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:40]]}
+    res["replay"] = {}
+    for y in sorted({int(r["Grid_Size_Y"]) for r in rows if "k_nesor" in r["Kernel_Name"]}):
+        bs = [i for i, r in enumerate(rows) if "k_backsolve" in r["Kernel_Name"] and int(r["Grid_Size_Y"]) == y]
+        if not bs:
+            continue
+        rep = [r for r in rows[bs[-1]:] if "k_nesor" in r["Kernel_Name"] and int(r["Grid_Size_Y"]) == y]
+        us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rep]
+        if us:
+            res["replay"][y] = {"n": len(us), "avg_us": sum(us) / len(us)}
+    sf = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if sf:
+        res["stats_head"] = open(sf[0]).read().splitlines()[:25]
+    return res
+
+
+def pmc_summary(d):
+    rows = list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    seq = []
+    for r in rows:
+        key = (r["Kernel_Name"].split("(")[0][:48], r["Grid_Size"], r["Counter_Name"])
+        v = float(r["Counter_Value"])
+        agg[key][0] += 1
+        agg[key][1] += v
+        seq.append((int(r["Dispatch_Id"]), key, v))
+    res = {"n": len(rows), "by_kernel": [[k[0], k[1], k[2], n, s / n]
+                                         for k, (n, s) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:20]]}
+    seq.sort()
+    grids = [k[1] for _, k, _ in seq if "k_nesor" in k[0]]
+    if grids:
+        big = max(grids, key=int)
+        tail = [v for _, k, v in seq if "k_nesor" in k[0] and k[1] == big][-800:]
+        res.update(nesor_batch_grid=big, nesor_batch_tail_n=len(tail), nesor_batch_tail_avg=sum(tail) / len(tail))
+    return res
+
+
+if __name__ == "__main__":
+    kind, d, out = sys.argv[1:4]
+    json.dump(trace_summary(d) if kind == "trace" else pmc_summary(d), open(out, "w"), indent=1)

@@ -125,3 +125,26 @@ def test_server_admission_and_results():
             assert np.array_equal(x, alone[i])
         with pytest.raises(lpk.LpError):
             srv.result(tickets[0])      # released after the first fetch
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_mixes_lds_and_per_colour_sweeps(precision):
+    """Small LPs sweep in one block with z in LDS; a transportation LP with n = 8000
+    (z over the LDS limit in FP64) sweeps colour by colour.  Both kinds in one batch give
+    each LP's result bitwise as alone, and the optimum matches the oracle's."""
+    lps = [synth.transport_lp(100, 80, seed=3)] + _mix(3, seed0=60)
+    opts = lambda: lpk.options(precision=precision)
+    alone = []
+    for lp in lps:
+        with lpk.from_lp(lp, opts()) as p:
+            r = lpk.lp_solve(p)
+            alone.append((r, lpk.lp_get_state(p)[0]))
+    probs = [lpk.from_lp(lp, opts()) for lp in lps]
+    res = lpk.lp_solve_batch(probs, width=4)
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == lpk.LP_OK
+        assert res[i]["krylov_iters"] == alone[i][0]["krylov_iters"]
+        assert np.array_equal(lpk.lp_get_state(p)[0], alone[i][1])
+        p.close()
+    o = oracle.ipm(lps[0])
+    assert abs(alone[0][0]["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
