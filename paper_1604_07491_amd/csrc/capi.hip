@@ -70,6 +70,57 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     return z.bytes;
 }
 
+// Distinct 128-byte lines touched by the wave-wide loads of z, values and indices, summed
+// over the element steps of the first waves of a colour, per element.  il = 0: a row's g
+// lanes are consecutive; il > 0: il rows per wave, lane l on row l mod il.
+static double line_cost(const Colour& C, const int32_t* rp, const int32_t* ci, int g, int il, int zbytes) {
+    const int rows_per_wave = il ? il : 64 / g;
+    const int gl = il ? 64 / il : g;
+    double lines = 0.0, elems = 0.0;
+    std::vector<int64_t> zl, vl, xl;
+    for (int w = 0; w < 8; ++w) {
+        const int64_t base = (int64_t)C.r0 + (int64_t)w * rows_per_wave;
+        if (base >= C.r1) break;
+        for (int t = 0;; ++t) {
+            zl.clear();
+            vl.clear();
+            xl.clear();
+            for (int l = 0; l < 64; ++l) {
+                const int64_t row = il ? base + (l % il) : base + l / g;
+                const int slot = il ? l / il : l % g;
+                if (row >= C.r1) continue;
+                const int64_t kk = rp[row] + slot + (int64_t)t * gl;
+                if (kk >= rp[row + 1]) continue;
+                zl.push_back((int64_t)ci[kk] * zbytes / 128);
+                vl.push_back(kk * zbytes / 128);
+                xl.push_back(kk * 4 / 128);
+                elems += 1.0;
+            }
+            if (zl.empty()) break;
+            for (std::vector<int64_t>* v : {&zl, &vl, &xl}) {
+                std::sort(v->begin(), v->end());
+                lines += (double)(std::unique(v->begin(), v->end()) - v->begin());
+            }
+        }
+    }
+    return elems > 0.0 ? lines / elems : 0.0;
+}
+
+// the fewest rows per wave (the most lanes per row, the shortest serial chain per lane)
+// whose loads touch under 3/4 of the lines of the consecutive layout
+void choose_layout(Colour& C, const int32_t* rp, const int32_t* ci, int zbytes) {
+    C.il = 0;
+    if (C.g < 16) return;
+    const double cont = line_cost(C, rp, ci, C.g, 0, zbytes);
+    for (int il = 2; il <= 8; il *= 2) {
+        if (line_cost(C, rp, ci, 64 / il, il, zbytes) < 0.75 * cont) {
+            C.il = il;
+            C.g = 64 / il;
+            return;
+        }
+    }
+}
+
 static lp_status validate(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
                           const double* val) {
     if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
@@ -171,7 +222,10 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         C.r0 = (int32_t)t0;
         C.r1 = (int32_t)t1;
         C.g = lanes_for((double)(prp[t1] - prp[t0]) / (double)std::max<int64_t>(1, t1 - t0));
+        C.il = 0;
         C.nnz = prp[t1] - prp[t0];
+        // lane layout by cache-line count, for LPs swept colour by colour (z in HBM)
+        if ((int64_t)n * (mixed ? 4 : 8) > LDS_Z_MAX) choose_layout(C, prp.data(), pci.data(), mixed ? 4 : 8);
         p->colours.push_back(C);
         t0 = t1;
     }
@@ -264,7 +318,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->h_cg.resize(p->colours.size());
     for (size_t cl = 0; cl < p->colours.size(); ++cl) {
         p->h_cstart[cl] = p->colours[cl].r0;
-        p->h_cg[cl] = p->colours[cl].g;
+        p->h_cg[cl] = p->colours[cl].il ? -p->colours[cl].g : p->colours[cl].g;
     }
     p->h_cstart[p->colours.size()] = (int32_t)m;
     LPK_HIP(hipMemcpyAsync(p->cstart, p->h_cstart.data(), sizeof(int32_t) * p->h_cstart.size(), hipMemcpyHostToDevice, st));

@@ -176,6 +176,10 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
     return ca == cb;
 }
 
+static bool same_launch(const Batch& B) {
+    return same_launch(B.L, B.graph_L, B.grid_colour, B.graph_colour) && B.colour_il == B.graph_il;
+}
+
 lp_status Batch::refresh() {
     L = BLaunch{};
     L.S = cap;
@@ -229,23 +233,28 @@ lp_status Batch::refresh() {
         }
     }
     grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
+    colour_il.assign((size_t)std::max(1, L.max_ncol), 0);
     for (int s = 0; s < cap; ++s) {
         const lp_problem* p = mem[s];
         if (!p || h_inst[s].ncol == 0 || h_inst[s].lds) continue;
         for (int c = 0; c < h_inst[s].ncol; ++c) {
             const Colour& cl = p->colours[c];
-            grid_colour[c] = std::max(grid_colour[c], cdiv_i((int64_t)(cl.r1 - cl.r0) * cl.g, BLOCK_THREADS));
+            const int64_t threads = cl.il ? (int64_t)cdiv_i(cl.r1 - cl.r0, cl.il) * 64 : (int64_t)(cl.r1 - cl.r0) * cl.g;
+            if (cl.il) colour_il[c] = 1;
+            grid_colour[c] = std::max(grid_colour[c], cdiv_i(threads, BLOCK_THREADS));
         }
     }
     L.grid_colour = grid_colour.data();
+    L.colour_il = colour_il.data();
     LPK_HIP(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
     // the captured iterations read every pointer from the descriptors: they stay valid
     // while the launch shapes are unchanged
-    if (!same_launch(L, graph_L, grid_colour, graph_colour)) {
+    if (!same_launch(*this)) {
         drop_graph();
         graph_L = L;
         graph_colour = grid_colour;
+        graph_il = colour_il;
     }
     dirty = false;
     return LP_OK;

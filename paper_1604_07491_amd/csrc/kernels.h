@@ -111,6 +111,7 @@ struct BLaunch {
     int ell;                // inner sweeps per preconditioner application
     int max_ncol;
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
+    const char* colour_il;  // host array [max_ncol]: some instance interleaves the colour's rows
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
     bool any_lds;           // some instance sweeps in one block with z in LDS
     int lds_bytes;          // largest z of those instances

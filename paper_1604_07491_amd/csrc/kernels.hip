@@ -73,6 +73,13 @@ __device__ __forceinline__ T sg_sum(T v, int g) {
     return v;
 }
 
+// sum over the lanes of a wave that agree in their low log2(il) bits (one interleaved row)
+template <typename T>
+__device__ __forceinline__ T il_sum(T v, int il) {
+    for (int o = 32; o >= il; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -200,14 +207,33 @@ void b_prep(const BLaunch& L) {
 // row segment (values, column indices) is held in registers between the dot product and
 // the update, so each nonzero is read from memory once per sweep.  The last colour of the
 // last sweep skips the z update (z is recomputed in FP64 from p).
-template <typename T>
+//
+// Lanes of a row: cg[c] > 0: g = cg[c] consecutive lanes per row, a row's elements in
+// lane order.  cg[c] < 0: interleaved, g = -cg[c] lanes per row spaced 64/g apart, so a
+// wave holds 64/g consecutive rows and lanes with the same element slot sit next to each
+// other.  The host picks per colour the form whose loads touch fewer cache lines (rows of
+// a colour whose columns are strided, as the sinks of a transportation matrix, share
+// lines across neighbouring rows).
+template <typename T, int R>
 __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int ell) {
     INST;
     if (in.ctl->done || in.gsor || in.lds || c >= in.ncol) return;
-    const int r0 = in.cstart[c], r1 = in.cstart[c + 1], g = in.cg[c];
+    const int r0 = in.cstart[c], r1 = in.cstart[c + 1], gc = in.cg[c];
     const int tid = bx * BLOCK + threadIdx.x;
-    const int row = r0 + tid / g, lane = tid & (g - 1);
-    if (row >= r1) return;   // uniform inside the sub-group; no block barrier below
+    int g, row, lane, il;
+    if (gc > 0) {
+        g = gc;
+        il = 0;
+        row = r0 + tid / g;
+        lane = tid & (g - 1);
+    } else {
+        g = -gc;
+        il = 64 / g;   // rows per wave
+        const int w = tid >> 6, lw = tid & 63;
+        row = r0 + w * il + (lw & (il - 1));
+        lane = lw / il;
+    }
+    if (row >= r1) return;   // the same for every lane of the row; no block barrier below
     const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
     // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
     // every column (no clearing pass needed)
@@ -228,7 +254,6 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     }
     const int32_t* __restrict__ idx = in.ci;
     const int s = in.rp[row], e = in.rp[row + 1];
-    constexpr int R = 8;
     T acc = 0;
     if (e - s <= g * R) {
         T a[R];
@@ -244,7 +269,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
                 if (!fresh) acc += a[t] * z[j[t]];
             }
         }
-        acc = sg_sum(acc, g);
+        acc = il ? il_sum(acc, il) : sg_sum(acc, g);
         const T delta = (T)in.omega * ((T)vrow - acc);
         if (write_z) {
 #pragma unroll
@@ -265,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     } else {
         if (!fresh)
             for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
-        acc = sg_sum(acc, g);
+        acc = il ? il_sum(acc, il) : sg_sum(acc, g);
         const T delta = (T)in.omega * ((T)vrow - acc);
         if (write_z)
             for (int kk = s + lane; kk < e; kk += g) {
@@ -283,12 +308,18 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     }
 }
 
+// rows held in registers up to R elements per lane: 8, or 16 when some instance lays the
+// colour out interleaved (fewer lanes per row)
 void b_nesor(const BLaunch& L, int colour, int sweep, int ell) {
     const unsigned gx = capg(L.grid_colour[colour], 1 << 30);
-    if (L.mixed)
-        hipLaunchKernelGGL((k_nesor<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
-    else
-        hipLaunchKernelGGL((k_nesor<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+    const bool wide = L.colour_il && L.colour_il[colour];
+    if (L.mixed) {
+        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+        else hipLaunchKernelGGL((k_nesor<float, 8>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+        else hipLaunchKernelGGL((k_nesor<double, 8>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -320,7 +351,8 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
     const T om = (T)in.omega;
     for (int sw = 0; sw < ell; ++sw) {
         for (int c = 0; c < in.ncol; ++c) {
-            const int r0 = in.cstart[c], r1 = in.cstart[c + 1], g = in.cg[c];
+            const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
+            const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
             const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
             const int lane = threadIdx.x & (g - 1);
             const int per = LDS_BLOCK / g;

@@ -69,8 +69,12 @@ struct DevArena {
 struct Colour {
     int32_t r0, r1;     // rows [r0, r1) in the permuted order
     int g;              // lanes per row
+    int il;             // 0: a row's lanes are consecutive; else il rows per wave, interleaved
     int64_t nnz;        // nonzeros of the colour
 };
+
+// the lane layout of a colour's rows whose wave-wide loads touch fewer cache lines
+void choose_layout(Colour& C, const int32_t* rp, const int32_t* ci, int zbytes);
 
 // one timed launch: events a (before) and b (after) on the batch's stream
 struct ProfRec {
@@ -164,8 +168,10 @@ struct Batch {
     double* d_part = nullptr;         // cap x RED_NQ x RED_MAXBLK
     BLaunch L{};
     std::vector<int> grid_colour;
+    std::vector<char> colour_il;
     BLaunch graph_L{};                // the launch shapes the graph was captured with
     std::vector<int> graph_colour;
+    std::vector<char> graph_il;
     bool dirty = true;                // membership changed since the descriptors were uploaded
     bool param_inflight = false;      // a parameter upload may still be in flight
     // captured Krylov iterations

@@ -33,6 +33,8 @@ def _case(name):
         return synth.basis_pursuit_lp(40, 300, 3, seed=4)
     if name == "transport":
         return synth.transport_lp(31, 29, seed=8)
+    if name == "transport_wide":   # z over the LDS limit: colour-by-colour sweeps, sinks interleaved
+        return synth.transport_lp(130, 100, seed=8)
     raise ValueError(name)
 
 
@@ -44,7 +46,7 @@ def _dir_problem(lp, seed=0):
     return d, f
 
 
-@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide"])
 @pytest.mark.parametrize("k", [1, 4, 13])
 def test_direction_solve_fixed_iterations(name, k):
     lp = _case(name)
@@ -64,7 +66,7 @@ def test_direction_solve_fixed_iterations(name, k):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["config0", "ragged", "transport"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "transport", "transport_wide"])
 def test_direction_solve_converged_is_min_norm(name, precision):
     lp = _case(name)
     d, f = _dir_problem(lp, 3)
