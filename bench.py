@@ -171,7 +171,14 @@ def main():
                 "timing": "lp_time_batch_kernel replay, 200 x group, HIP events on the library stream",
                 "single_lp": {"us_per_launch": t1["us_per_launch"], "bytes_per_launch": t1["bytes_per_launch"],
                               "achieved": t1["bytes_per_launch"] / (t1["us_per_launch"] * 1e-6) / 1e9}}
-    extra = {}
+    extra = {"batch_kernels": {}}
+    for name in ("sweep", "spmv_csr", "spmv_csc"):
+        if name not in timed:
+            continue
+        tb = lpk.lp_time_batch_kernel(probs[:width], cls_id[name], reps=200)
+        gbs = tb["bytes_per_launch"] / (tb["us_per_launch"] * 1e-6) / 1e9
+        extra["batch_kernels"][name] = {"us_per_launch": tb["us_per_launch"], "gbs": gbs,
+                                        "frac": gbs / HBM_PEAK_GBS, "launches_per_group": tb["launches_per_group"]}
     if "gram" in timed:
         tg = lpk.lp_time_kernel(p0, lpk.LP_K_GRAM, reps=5)
         extra["dense_build"] = {"bound": "mfma", "ms": tg["us_per_launch"] / 1e3,

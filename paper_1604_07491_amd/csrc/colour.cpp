@@ -48,7 +48,10 @@ int32_t greedy_colour(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci
     return ncol;
 }
 
+// lanes per row for rows of mean length len: the next power of two, at most 64; rows of
+// at most two entries take one lane each (the sub-group sum would cost more than the row)
 int lanes_for(double len) {
+    if (len <= 2.0) return 1;
     int g = 1;
     while (g < 64 && g < len) g *= 2;
     return g;
