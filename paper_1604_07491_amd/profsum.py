@@ -7,7 +7,7 @@ trace: per (kernel, grid) launch counts and mean durations from the kernel trace
 each batch width the mean duration of the NE-SOR sweep launches of the timing replay (the
 sweep launches after the last back-substitution of that width: bench.py replays the
 dominant kernel last).  pmc: per (kernel, grid) mean counter value, and the mean over the
-last 800 sweep dispatches of the largest grid (the replay window).
+last 800 batched sweep dispatches (the replay window of bench.py's kernel table).
 """
 import collections
 import csv
@@ -62,11 +62,11 @@ def pmc_summary(d):
     res = {"n": len(rows), "by_kernel": [[k[0], k[1], k[2], n, s / n]
                                          for k, (n, s) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:20]]}
     seq.sort()
-    grids = [k[1] for _, k, _ in seq if "k_nesor" in k[0]]
-    if grids:
-        big = max(grids, key=int)
-        tail = [v for _, k, v in seq if "k_nesor" in k[0] and k[1] == big][-800:]
-        res.update(nesor_batch_grid=big, nesor_batch_tail_n=len(tail), nesor_batch_tail_avg=sum(tail) / len(tail))
+    # the batched sweep launches (grids above 100k threads), last 800: the final replay of
+    # the sweep group in bench.py (every colour kind of the group in its proportion)
+    tail = [v for _, k, v in seq if "k_nesor" in k[0] and int(k[1]) > 100000][-800:]
+    if tail:
+        res.update(nesor_batch_tail_n=len(tail), nesor_batch_tail_avg=sum(tail) / len(tail))
     return res
 
 
