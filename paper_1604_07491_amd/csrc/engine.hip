@@ -781,7 +781,7 @@ lp_status Engine::round() {
         }                                 \
     } while (0)
     if (b.dirty) LPK_RC(b.refresh());
-    // Scheduling.  Members of one shape (equal m, n, nnz) have similar solve lengths: they
+    // Scheduling.  Members of one shape (equal m and n) have similar solve lengths: they
     // pass their phases together, once none of them is inside a solve (lockstep; a phase
     // costs one round for all).  Members of different shapes each advance as soon as their
     // solve ends, so a small LP is not held by a large one.
@@ -793,7 +793,7 @@ lp_status Engine::round() {
         if (mb.state == EMPTY || mb.state == DONE) continue;
         if (mb.state == KRY1 || mb.state == KRY2) ++iterating;
         if (!ref) ref = mb.p;
-        else if (mb.p->m != ref->m || mb.p->n != ref->n || mb.p->nnz != ref->nnz) uniform = false;
+        else if (mb.p->m != ref->m || mb.p->n != ref->n) uniform = false;
     }
     const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
     bool has[SH2 + 1] = {false};
