@@ -39,7 +39,10 @@ def counter_traffic(args, kernel, width):
     for this workload and batch width on the kernels as they are now (else None)."""
     if not args.traffic or not os.path.exists(args.traffic):
         return None
-    rec = json.load(open(args.traffic)).get(f"{args.workload}/{args.precision}/w{width}/{kernel}")
+    key = f"{args.workload}/{args.precision}/w{width}/{kernel}"
+    if args.inner != "nesor" or args.krylov != "abgmres":
+        key += f"/{args.inner}/{args.krylov}"
+    rec = json.load(open(args.traffic)).get(key)
     if not rec or rec.get("kernels_sha256") != kernels_digest():
         return None
     return rec["bytes_per_launch"]
@@ -77,7 +80,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="LPs per step")
     ap.add_argument("--width", type=int, default=64, help="LPs in lockstep")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--inner", default="nesor", choices=["nesor", "cimmino"])
+    ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
+    ap.add_argument("--krylov", default="abgmres", choices=["abgmres", "cgne", "mrne"],
+                    help="outer iteration: AB-GMRES (Sec. 3.2) or CGNE / MRNE (Sec. 3.3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
@@ -116,7 +121,7 @@ def main():
         return steps_main(args)
     lps = make_lps(args.workload, args.batch)
     dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
-    opts = lpk.options(precision=args.precision, inner=args.inner)
+    opts = lpk.options(precision=args.precision, inner=args.inner, krylov=args.krylov)
     probs = []
     for lp in lps:
         if lp.dense is not None:
@@ -190,7 +195,9 @@ def main():
     if not args.no_cpu_baseline and lps[0].dense is None and lps[0].n <= 200000:
         import oracle
         tc = time.perf_counter()
-        o = oracle.ipm(lps[0])
+        so = oracle.solver_opts(krylov={"abgmres": oracle.ABGMRES, "cgne": oracle.CGNE, "mrne": oracle.MRNE}[args.krylov],
+                                inner={"nesor": oracle.NESOR, "nessor": oracle.NESSOR, "cimmino": oracle.CIMMINO}[args.inner])
+        o = oracle.ipm(lps[0], oracle.ipm_opts(solver=so))
         tcpu = time.perf_counter() - tc
         cpu = {"value": 1.0 / tcpu, "unit": "LPs/s", "cores": 1, "kind": "oracle",
                "sample": f"1 full solve of the {args.workload} LP ({o['iters']} IPM iterations, {tcpu:.2f} s)",
@@ -219,7 +226,8 @@ def main():
         "gamma_rel": r0["gamma_rel"],
         "config": {"workload": args.workload, "m": lps[0].m, "n": lps[0].n, "nnz": lps[0].nnz,
                    "lps_per_step": len(probs), "lps_in_lockstep": args.width,
-                   "precision": args.precision, "inner": args.inner, "krylov": "AB-GMRES",
+                   "precision": args.precision, "inner": args.inner,
+                   "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE"}[args.krylov],
                    "inner_sweeps": 2, "omega": 1.0},
         "roofline": roofline,
         "kernel_classes": {k: {"launches": v["launches"], "ms_total": v["ms_total"],

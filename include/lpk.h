@@ -11,7 +11,9 @@
  * (Sec. 2.2, eq. minnrmprob; D = S^-1/2 X^1/2), row-scaled so that every row of
  * A_hat = diag(rho)^-1 A D has unit norm (Sec. 3.5), and solved by AB-GMRES
  * right-preconditioned by inner iterations (Sec. 3.2, 3.4): multicolour NE-SOR sweeps,
- * Cimmino sweeps, or (for dense A) SOR on the explicit Gram matrix A_hat A_hat^T.
+ * NE-SSOR sweeps, Cimmino sweeps, or (for dense A) SOR on the explicit Gram matrix
+ * A_hat A_hat^T; or by CGNE or MRNE preconditioned by the same sparse inner iterations
+ * (Sec. 3.3).
  * The direction is recovered with the w-recurrence (eq. step_predictor /
  * step_corrector), saving one matrix-vector product per stage.
  *
@@ -60,9 +62,13 @@ typedef struct lp_problem lp_problem;
 /* Options.  lp_options_default() fills the values given in brackets. */
 typedef struct {
     int32_t precision;       /* lp_precision [LP_FP64]                                    */
-    int32_t krylov;          /* lp_krylov [LP_ABGMRES]                                    */
+    int32_t krylov;          /* lp_krylov [LP_ABGMRES]; LP_CGNE / LP_MRNE run the sweeps   */
+                             /* of LP_NESOR, LP_NESSOR or LP_CIMMINO on the sparse rows    */
+                             /* (with lp_create_dense: LP_NESSOR or LP_CIMMINO); LP_MRNE   */
+                             /* needs precision LP_FP64                                    */
     int32_t inner;           /* lp_inner [LP_NESOR]; LP_GSOR needs lp_create_dense        */
-    int32_t inner_sweeps;    /* ell, inner sweeps per preconditioner application [2]      */
+    int32_t inner_sweeps;    /* ell, inner iterations per preconditioner application [2]; */
+                             /* an NE-SSOR iteration is a forward and a backward sweep     */
     double omega;            /* NE-SOR relaxation, (0, 2) [1.0]                           */
     double omega_c;          /* Cimmino step; <= 0: 1/lambda, lambda from 20 power steps [0] */
     int64_t krylov_max_iter; /* Krylov iteration limit; <= 0 means m (Sec. 4.2) [0]       */
@@ -185,8 +191,9 @@ lp_status lp_set_state(lp_problem* p, const double* x, const double* y, const do
 lp_status lp_get_log(const lp_problem* p, lp_iter_info* info, int32_t cap, int32_t* n_out);
 
 /* Device bytes lp_create would allocate for an m x n problem with nnz nonzeros and the
- * given options (NULL = defaults), including the Krylov basis of krylov_max_iter + 1
- * vectors.  Errors: LP_EDIM.                                                          */
+ * given options (NULL = defaults), including (AB-GMRES) the Krylov basis of
+ * krylov_max_iter + 1 vectors; CGNE and MRNE keep a fixed number of vectors.
+ * Errors: LP_EDIM.                                                                    */
 lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options* o,
                              uint64_t* bytes);
 
@@ -207,7 +214,8 @@ typedef enum {
     LP_K_GS_DOTS = 3,        /* Gram-Schmidt dot products V^T u                             */
     LP_K_GS_UPDATE = 4,      /* Gram-Schmidt update u -= V h (with the next dots or norm)   */
     LP_K_GRAM = 5,           /* dense path: G = A_hat A_hat^T with FP64 matrix cores        */
-    LP_K_COUNT = 6
+    LP_K_CG_VEC = 6,         /* CGNE / MRNE dot products and vector updates                 */
+    LP_K_COUNT = 7
 } lp_kernel_class;
 
 typedef struct {

@@ -69,7 +69,8 @@ class KernelStat(C.Structure):
                 ("name", C.c_char * 32)]
 
 
-LP_K_SWEEP, LP_K_SPMV_CSR, LP_K_SPMV_CSC, LP_K_GS_DOTS, LP_K_GS_UPDATE, LP_K_GRAM, LP_K_COUNT = 0, 1, 2, 3, 4, 5, 6
+LP_K_SWEEP, LP_K_SPMV_CSR, LP_K_SPMV_CSC, LP_K_GS_DOTS, LP_K_GS_UPDATE, LP_K_GRAM = 0, 1, 2, 3, 4, 5
+LP_K_CG_VEC, LP_K_COUNT = 6, 7
 
 
 class Result(C.Structure):
@@ -176,6 +177,8 @@ def options(**kw) -> Options:
             v = {"fp64": LP_FP64, "mixed": LP_MIXED}[v]
         if k == "inner" and isinstance(v, str):
             v = {"nesor": LP_NESOR, "cimmino": LP_CIMMINO, "nessor": LP_NESSOR, "gsor": LP_GSOR}[v]
+        if k == "krylov" and isinstance(v, str):
+            v = {"abgmres": LP_ABGMRES, "cgne": LP_CGNE, "mrne": LP_MRNE}[v]
         setattr(o, k, v)
     return o
 

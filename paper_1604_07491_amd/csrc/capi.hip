@@ -28,15 +28,21 @@ static lp_status fail(lp_status s, const std::string& msg) {
     return s;
 }
 
-// Krylov basis capacity: m (Sec. 4.2) unless the options cap it, and at most what fits in
-// a 16 GiB budget for the basis and multiplier vectors
+// Krylov iteration limit: m (Sec. 4.2) unless the options cap it; AB-GMRES keeps a basis
+// and multiplier vector per iteration, so its limit is also at most what fits in a 16 GiB
+// budget for them
 static int64_t plan_kmax(int64_t m, const lp_options& o) {
     int64_t k = m;
     if (o.krylov_max_iter > 0) k = std::min<int64_t>(k, o.krylov_max_iter);
+    if (o.krylov != LP_ABGMRES) return std::max<int64_t>(1, k);
     const int64_t budget = (int64_t)16 << 30;
     const int64_t cap = std::max<int64_t>(8, budget / (16 * (m + 1)));
     return std::max<int64_t>(1, std::min(k, cap));
 }
+
+// columns of V and P (and the order of H): the basis for AB-GMRES, one column for CGNE
+// and MRNE (the preconditioner's input and multipliers)
+static int64_t basis_cols(int64_t kmax, const lp_options& o) { return o.krylov == LP_ABGMRES ? kmax + 1 : 1; }
 
 struct Sizes {
     uint64_t bytes = 0;
@@ -50,20 +56,22 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
     const bool mixed = o.precision == LP_MIXED;
     const int64_t kmax = plan_kmax(m, o);
+    const int64_t cols = basis_cols(kmax, o);
+    const bool cg = o.krylov != LP_ABGMRES;
     const int64_t nchunks = (m + 64 * gs_rpl_for(m) - 1) / (64 * gs_rpl_for(m));
     z.add(m + 1, 4); z.add(nnz, 4); z.add(nnz, 8); z.add(n + 1, 4); z.add(nnz, 4); z.add(nnz, 8);
     z.add(nnz, 8); z.add(nnz, 8);
     if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
     z.add(m, 4);                                  // permutation
     z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
-    for (int i = 0; i < 12; ++i) z.add(m, 8);    // m-vectors
-    for (int i = 0; i < 11; ++i) z.add(n, 8);    // n-vectors
+    for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
+    for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
     z.add(n, 4); z.add(m, 4);                     // z32, r32
-    z.add(m * (kmax + 1), 8); z.add(m * (kmax + 1), 8);   // V, P
-    z.add((kmax + 1) * (kmax + 1), 8);                      // H
-    for (int i = 0; i < 5; ++i) z.add(kmax + 2, 8);
-    z.add(nchunks * (kmax + 1), 8);
-    if (gs_fusable(nchunks, kmax)) z.add(nchunks * (kmax + 1), 8);
+    z.add(m * cols, 8); z.add(m * cols, 8);       // V, P
+    z.add(cols * cols, 8);                        // H
+    for (int i = 0; i < 5; ++i) z.add(cols + 1, 8);
+    z.add(nchunks * cols, 8);
+    if (!cg && gs_fusable(nchunks, kmax)) z.add(nchunks * cols, 8);
     // the problem's batch of one: descriptor, control words, parameters, partials
     z.add(1, sizeof(Inst)); z.add(1, sizeof(Slot)); z.add(1, sizeof(Param));
     z.add((int64_t)RED_NQ * RED_MAXBLK, 8);
@@ -266,8 +274,10 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     // device memory
     DevArena& A = p->arena;
     p->kmax = plan_kmax(m, p->opt);
+    const int64_t cols = basis_cols(p->kmax, p->opt);
+    const bool cg = p->opt.krylov != LP_ABGMRES;
     p->ldv = m;
-    p->ldh = p->kmax + 1;
+    p->ldh = cols;
     p->rpl = gs_rpl_for(m);
     p->nchunks = (int)((m + 64 * p->rpl - 1) / (64 * p->rpl));
     p->rp = A.alloc<int32_t>(m + 1);
@@ -289,18 +299,22 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     for (int q : mv) p->vec[q] = A.alloc<double>(m);
     const int nv[] = {V_X, V_S, V_D, V_RD, V_TN, V_DXA, V_DSA, V_DW, V_TMPN, V_C, V_Z64};
     for (int q : nv) p->vec[q] = A.alloc<double>(n);
+    if (cg) {
+        for (int q : {V_G, V_QM, V_PM}) p->vec[q] = A.alloc<double>(m);
+        for (int q : {V_Q, V_PV}) p->vec[q] = A.alloc<double>(n);
+    }
     p->z32 = A.alloc<float>(n);
     p->r32 = A.alloc<float>(m);
-    p->V = A.alloc<double>(m * (p->kmax + 1));
-    p->P = A.alloc<double>(m * (p->kmax + 1));
-    p->H = A.alloc<double>((p->kmax + 1) * (p->kmax + 1));
-    p->cs = A.alloc<double>(p->kmax + 2);
-    p->sn = A.alloc<double>(p->kmax + 2);
-    p->gam = A.alloc<double>(p->kmax + 2);
-    p->ykr = A.alloc<double>(p->kmax + 2);
-    p->h2 = A.alloc<double>(p->kmax + 2);
-    p->gpart = A.alloc<double>((int64_t)p->nchunks * (p->kmax + 1));
-    if (gs_fusable(p->nchunks, p->kmax)) p->gpart2 = A.alloc<double>((int64_t)p->nchunks * (p->kmax + 1));
+    p->V = A.alloc<double>(m * cols);
+    p->P = A.alloc<double>(m * cols);
+    p->H = A.alloc<double>(cols * cols);
+    p->cs = A.alloc<double>(cols + 1);
+    p->sn = A.alloc<double>(cols + 1);
+    p->gam = A.alloc<double>(cols + 1);
+    p->ykr = A.alloc<double>(cols + 1);
+    p->h2 = A.alloc<double>(cols + 1);
+    p->gpart = A.alloc<double>((int64_t)p->nchunks * cols);
+    if (!cg && gs_fusable(p->nchunks, p->kmax)) p->gpart2 = A.alloc<double>((int64_t)p->nchunks * cols);
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);
         p->Xinv = A.alloc<double>(m * m);
@@ -333,7 +347,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     LPK_HIP(hipMemcpyAsync(p->perm_d, p->perm.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->vec[V_B], pb.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->vec[V_C], c, sizeof(double) * n, hipMemcpyHostToDevice, st));
-    LPK_HIP(hipMemsetAsync(p->H, 0, sizeof(double) * (p->kmax + 1) * (p->kmax + 1), st));
+    LPK_HIP(hipMemsetAsync(p->H, 0, sizeof(double) * cols * cols, st));
     LPK_HIP(hipStreamSynchronize(st));
     p->ist.eps_in = p->opt.eps_in0;
     return LP_OK;
@@ -341,9 +355,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
 
 static lp_status check_options(const lp_options& o, bool dense) {
     if (o.precision != LP_FP64 && o.precision != LP_MIXED) return fail(LP_EINVAL, "unknown precision");
-    if (o.krylov != LP_ABGMRES) return fail(LP_EINVAL, "only AB-GMRES is available on the device");
-    if (o.inner != LP_NESOR && o.inner != LP_CIMMINO && !(dense && o.inner == LP_GSOR))
-        return fail(LP_EINVAL, "inner iterations must be NE-SOR or Cimmino (or G-SOR for a dense A)");
+    if (o.krylov != LP_ABGMRES && o.krylov != LP_CGNE && o.krylov != LP_MRNE)
+        return fail(LP_EINVAL, "unknown Krylov method");
+    if (o.inner != LP_NESOR && o.inner != LP_NESSOR && o.inner != LP_CIMMINO && !(dense && o.inner == LP_GSOR))
+        return fail(LP_EINVAL, "inner iterations must be NE-SOR, NE-SSOR or Cimmino (or G-SOR for a dense A)");
+    if (o.krylov != LP_ABGMRES && dense && (o.inner == LP_NESOR || o.inner == LP_GSOR))
+        return fail(LP_EINVAL, "CGNE and MRNE need sparse sweeps: with a dense A use NE-SSOR or Cimmino");
+    // MRNE forms q_k = A_hat^T C g_k by recurrence, which holds only while C is one fixed
+    // linear map; FP32 sweeps perturb C at every application and the recurrence drifts
+    // until the iteration diverges (CGNE recomputes its direction from C g_k each step)
+    if (o.krylov == LP_MRNE && o.precision == LP_MIXED)
+        return fail(LP_EINVAL, "MRNE needs FP64 inner iterations (precision LP_FP64)");
     if (o.inner_sweeps < 1 || o.inner_sweeps > 64) return fail(LP_EINVAL, "inner_sweeps must be in [1, 64]");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LP_EINVAL, "omega must be in (0, 2)");
     if (!(o.eta >= 0.9 && o.eta < 1.0)) return fail(LP_EINVAL, "eta must be in [0.9, 1)");

@@ -41,6 +41,7 @@ static inline int cdiv_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); 
 
 bool batch_compatible(const lp_problem* a, const lp_problem* b) {
     return a->opt.precision == b->opt.precision && a->opt.inner == b->opt.inner &&
+           a->opt.krylov == b->opt.krylov &&
            a->gsor == b->gsor && a->opt.inner_sweeps == b->opt.inner_sweeps && a->device == b->device;
 }
 
@@ -117,7 +118,8 @@ static Inst make_inst(Batch& B, int slot) {
     in.m = (int32_t)p->m;
     in.n = (int32_t)p->n;
     in.nnz = (int32_t)p->nnz;
-    in.ncol = (p->gsor || p->opt.inner != LP_NESOR) ? 0 : (int32_t)p->colours.size();
+    const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
+    in.ncol = (p->gsor || !sor) ? 0 : (int32_t)p->colours.size();
     in.g_csr = p->g_csr;
     in.g_csc = p->g_csc;
     in.nchunks = p->nchunks;
@@ -129,7 +131,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.lds = (in.ncol > 0 && p->n * (mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
-    in.ldp = p->kmax + 1;
+    in.ldp = p->ldh;   // kmax + 1 for AB-GMRES
     in.kmax = p->kmax;
     in.rp = p->rp;
     in.ci = p->ci;
@@ -168,7 +170,8 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
     if (a.S != b.S || a.max_m != b.max_m || a.max_n != b.max_n || a.max_nbr != b.max_nbr ||
         a.max_nbs != b.max_nbs || a.max_ldp != b.max_ldp || a.gs_rpl != b.gs_rpl ||
         a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.mixed != b.mixed ||
-        a.inner != b.inner || a.ell != b.ell || a.max_ncol != b.max_ncol || a.need_prep != b.need_prep ||
+        a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
+        a.need_prep != b.need_prep ||
         a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.max_ncol_global != b.max_ncol_global)
         return false;
     for (int i = 0; i < 4; ++i)
@@ -207,6 +210,7 @@ lp_status Batch::refresh() {
             L.mixed = p->opt.precision == LP_MIXED;
             L.inner = p->gsor ? 3 : p->opt.inner;
             L.ell = std::max(1, (int)p->opt.inner_sweeps);
+            L.krylov = p->opt.krylov;
             first = false;
         }
         L.max_m = std::max(L.max_m, in.m);
@@ -345,26 +349,31 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
             }
         }
     } else {
+        // NE-SOR: ell forward passes; NE-SSOR: ell forward-backward pairs
+        const bool ssor = L.inner == LP_NESSOR;
+        const int npass = ssor ? 2 * ell : ell;
         if (L.any_lds) {
-            // the instances whose z fits in LDS: every sweep and colour in one launch
+            // the instances whose z fits in LDS: every pass and colour in one launch
             const double by = over_members(B, [&](const lp_problem* p) {
                 if (p->n * (L.mixed ? 4 : 8) > LDS_Z_MAX) return 0.0;
-                return ell * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0));
+                return npass * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0));
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, ell);
+            b_sweep_lds(L, npass, ssor ? 1 : 0);
         }
-        for (int sw = 0; sw < ell; ++sw) {
-            for (int c = 0; c < L.max_ncol_global; ++c) {
+        for (int sw = 0; sw < npass; ++sw) {
+            const int dir = ssor ? (sw & 1) : 0;
+            for (int cc = 0; cc < L.max_ncol_global; ++cc) {
+                const int c = dir ? L.max_ncol_global - 1 - cc : cc;
                 const double by = over_members(B, [&](const lp_problem* p) {
                     const int nc = (int)p->colours.size();
                     if (c >= nc || p->n * (L.mixed ? 4 : 8) <= LDS_Z_MAX) return 0.0;
                     const Colour& cl = p->colours[c];
-                    const int wz = !(sw + 1 == ell && c + 1 == nc);
+                    const int wz = !(sw + 1 == npass && c == (dir ? 0 : nc - 1));
                     return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
-                b_nesor(L, c, sw, ell);
+                b_nesor(L, c, sw, npass, dir);
             }
         }
     }
@@ -392,9 +401,70 @@ static void enqueue_products(Batch& B, int64_t it) {
     }
 }
 
+// one CGNE or MRNE iteration (Sec. 3.3): a preconditioner application (multipliers into
+// column 0 of P), its product with A_hat^T in FP64, one product with A_hat, and the
+// vector kernels
+static void enqueue_cg_iteration(Batch& B, int64_t it) {
+    const BLaunch& L = B.L;
+    auto vb = [&](double per_m, double per_n) {
+        return over_members(B, [&](const lp_problem* p) { return per_m * p->m + per_n * p->n; });
+    };
+    if (L.krylov == LP_CGNE) {
+        enqueue_precond(B, it, true);   // C g (g in V_U)
+        {
+            Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
+            b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
+        }
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(16.0, 0.0));
+            b_cg_dot(L, V_U, V_PCOL, 0);
+        }
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(24.0, 24.0));
+            b_cgne_dir(L);
+        }
+        {
+            Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
+            b_spmv(L, M_AH_CSR, V_Q, V_TMPM, EPI_PLAIN, -1, -1, 0, false);
+        }
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(48.0, 24.0));
+            b_cgne_step(L);
+        }
+        b_cg_check(L);
+    } else {
+        {
+            Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
+            b_spmv(L, M_AH_CSR, V_PV, V_U, EPI_PLAIN, -1, -1, PM_ITER_DIR, false);   // t = A_hat p
+        }
+        enqueue_precond(B, it, true);   // C t (at the start: C g)
+        {
+            Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
+            b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
+        }
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(0.0, 16.0));
+            b_cg_dot(L, V_Z64, V_PV, 1);
+        }
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(64.0, 40.0));
+            b_mrne_step(L);
+        }
+        b_cg_check(L);
+        {
+            Prof pr(&B, LP_K_CG_VEC, it, vb(24.0, 24.0));
+            b_mrne_dir(L);
+        }
+    }
+}
+
 // one Krylov iteration (every kernel returns at once for instances whose solve is done)
 static void enqueue_iteration(Batch& B, int64_t it) {
     const BLaunch& L = B.L;
+    if (L.krylov != LP_ABGMRES) {
+        enqueue_cg_iteration(B, it);
+        return;
+    }
     enqueue_precond(B, it, true);
     enqueue_products(B, it);
     // CGS2 + Givens; the host iteration index equals the device one while the solve runs
@@ -453,12 +523,15 @@ static lp_status build_graph(Batch& B, int iters) {
     return LP_OK;
 }
 
-// dyh = P y with R y = gamma; dw = A_hat^T dyh; true residual ||f_hat - A_hat dw||
+// AB-GMRES: dyh = P y with R y = gamma, dw = A_hat^T dyh (CGNE and MRNE update dw and dyh
+// in the iteration); the true residual ||f_hat - A_hat dw||
 static void enqueue_assembly(Batch& B, int pmask) {
     const BLaunch& L = B.L;
-    b_backsolve(L, pmask);
-    b_combine(L, pmask);
-    b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, pmask, false);
+    if (L.krylov == LP_ABGMRES) {
+        b_backsolve(L, pmask);
+        b_combine(L, pmask);
+        b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, pmask, false);
+    }
     b_spmv(L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, pmask, true);
     b_true_res(L, pmask);
 }
@@ -467,6 +540,7 @@ static void enqueue_assembly(Batch& B, int pmask) {
 static void enqueue_start(Batch& B, int pmask) {
     b_init_rhs(B.L, pmask);
     b_init_ctl(B.L, pmask, 0);
+    if (B.L.krylov != LP_ABGMRES) b_cg_init(B.L, pmask);
 }
 
 lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
@@ -920,7 +994,7 @@ lp_status Engine::round() {
             for (int s = 0; s < b.cap; ++s) {
                 const Member& mb = mem[s];
                 if (mb.state != KRY1 && mb.state != KRY2 && mb.state != SCALE && mb.state != RHS2) continue;
-                const int64_t k = (mb.state == KRY1 || mb.state == KRY2) ? b.h_slot[s].ctl.k : 0;
+                const int64_t k = (mb.state == KRY1 || mb.state == KRY2) ? b.h_slot[s].ctl.iters : 0;
                 const int64_t guess = mb.last_k > 0 ? mb.last_k : b.last_iters;
                 const int64_t r = std::max<int64_t>(1, guess - k);
                 rem = hold ? std::max(rem, r) : std::min(rem, r);

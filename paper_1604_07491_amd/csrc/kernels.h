@@ -28,14 +28,27 @@ struct KrylovCtl {
     double inv_h;       // 1 / h_{k+1,k} of the last completed iteration
     double res_true;    // ||f_hat - A_hat dw||
     double omega_c;     // Cimmino step of the current scaling
+    // CGNE / MRNE: gamma of the current direction (CGNE g.Cg, MRNE q.q), MRNE's
+    // coefficient of the next direction, and MRNE's start phase (0 until q_0 is formed)
+    double cg_gamma;
+    double cg_beta;
+    int32_t cg_phase;
+    int32_t pad0;
 };
 
 // vectors of an instance, addressed by selector
 enum VecSel : int {
     V_X = 0, V_Y, V_S, V_D, V_RHO, V_RP, V_RD, V_TN, V_DXA, V_DSA, V_DYA, V_DYC, V_F, V_DW, V_DYH,
-    V_TMPM, V_TMPN, V_B, V_C, V_FH, V_U, V_Z64, V_R64, V_COUNT
+    V_TMPM, V_TMPN, V_B, V_C, V_FH, V_U, V_Z64, V_R64,
+    V_G, V_QM, V_PM,    // CGNE / MRNE m-vectors: residual (MRNE), multipliers of q and p
+    V_Q, V_PV,          // CGNE / MRNE n-vectors: q, p
+    V_COUNT
 };
 constexpr int V_PCOL = -1;   // column ctl->k of the multiplier vectors P
+
+// pmask of the launches that take only the instances still iterating that have a search
+// direction (every CGNE instance, MRNE instances past their start)
+constexpr int PM_ITER_DIR = -1;
 
 // matrices of an instance for the row-dot products
 enum MatSel : int { M_A_CSR = 0, M_A_CSC = 1, M_AH_CSR = 2, M_AH_CSC = 3 };
@@ -107,8 +120,9 @@ struct BLaunch {
     int gs_rpl, gs_nchunks; // largest rows per lane (template bound) and chunk count
     bool gs_fused;
     int mixed;              // FP32 inner iterations
-    int inner;              // lp_inner of every instance (NE-SOR, Cimmino) or 3: dense SOR
+    int inner;              // lp_inner of every instance (NE-SOR, Cimmino, NE-SSOR) or 3: dense SOR
     int ell;                // inner sweeps per preconditioner application
+    int krylov;             // lp_krylov of every instance (0 AB-GMRES, 1 CGNE, 2 MRNE)
     int max_ncol;
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
     const char* colour_il;  // host array [max_ncol]: some instance interleaves the colour's rows
@@ -135,8 +149,11 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 // for its rows and overwrites (rather than accumulates) p_k; b_prep only clears the NE-SOR
 // z of instances whose colour 0 does not cover every column (colour 0 then overwrites z).
 void b_prep(const BLaunch& L);
-void b_nesor(const BLaunch& L, int colour, int sweep, int ell);
-void b_sweep_lds(const BLaunch& L, int ell);   // every colour and sweep, one block per instance
+// one colour of pass `pass` of `npass` (dir 0: colours in order, 1: reversed, the
+// backward half of an NE-SSOR iteration); the first pass forms v_k and p_k
+void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir);
+// every colour of every pass, one block per instance (ssor: passes alternate direction)
+void b_sweep_lds(const BLaunch& L, int npass, int ssor);
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 void b_gs_dots(const BLaunch& L);
@@ -144,6 +161,19 @@ void b_gs_reduce(const BLaunch& L, int accumulate);
 void b_gs_update(const BLaunch& L, int mode);
 void b_gs_finish(const BLaunch& L);
 void b_apply_c(const BLaunch& L);       // dense: P[:,k] = C v_k
+
+// ---- CGNE and MRNE preconditioned by inner iterations (Sec. 3.3) ------------------------
+// The inner iterations act on V_U (the residual g for CGNE, A p for MRNE) and leave their
+// multipliers in P[:,0]; the CSC product gives A_hat^T of those in V_Z64.  Scalars live in
+// each instance's control block; every kernel returns at once for finished instances.
+void b_cg_init(const BLaunch& L, int pmask);   // dw = dyh = 0, directions 0, 1/h = 1; MRNE: g = f_hat
+// partials of vec[x] . y (y = vec[ys], or column 0 of P for V_PCOL) over m (nlen 0) or n
+void b_cg_dot(const BLaunch& L, int xs, int ys, int nlen);
+void b_cgne_dir(const BLaunch& L);     // q = A_hat^T Cg + beta q (and multipliers); q.q
+void b_cgne_step(const BLaunch& L);    // alpha; dw, dyh += alpha (q, qm); g -= alpha A_hat q; g.g
+void b_mrne_step(const BLaunch& L);    // start: q_0; else alpha; dw, dyh, g, q, qm updates; g.g, q.q
+void b_cg_check(const BLaunch& L);     // res = ||g||, the stopping test, the next gamma (and beta)
+void b_mrne_dir(const BLaunch& L);     // p = q + beta p, pm = qm + beta pm
 void b_gemv_col(const BLaunch& L);      // dense: u = G p_k
 // solve set-up (instances with a bit of pmask take part; the others are marked done)
 void b_init_rhs(const BLaunch& L, int pmask);

@@ -114,6 +114,7 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 
 __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
     if (pmask > 0) return (*in.mode & pmask) != 0;
+    if (pmask == PM_ITER_DIR) return in.ctl->done == 0 && in.ctl->cg_phase != 0;
     return in.ctl->done == 0;   // 0: Krylov loop, still iterating
 }
 
@@ -206,7 +207,12 @@ void b_prep(const BLaunch& L) {
 // d a_i to z.  Rows of one colour share no column, so the z updates are disjoint.  The
 // row segment (values, column indices) is held in registers between the dot product and
 // the update, so each nonzero is read from memory once per sweep.  The last colour of the
-// last sweep skips the z update (z is recomputed in FP64 from p).
+// last pass skips the z update (z is recomputed in FP64 from p).
+//
+// A pass visits the colours in order (dir 0) or in reverse (dir 1).  NE-SSOR (Sec. 3.3)
+// alternates the two: each of its iterations is a forward and a backward sweep, and
+// reversing the colour order reverses the row order of the colour-major permutation up to
+// the order of rows inside one colour, which do not interact.
 //
 // Lanes of a row: cg[c] > 0: g = cg[c] consecutive lanes per row, a row's elements in
 // lane order.  cg[c] < 0: interleaved, g = -cg[c] lanes per row spaced 64/g apart, so a
@@ -215,7 +221,7 @@ void b_prep(const BLaunch& L) {
 // a colour whose columns are strided, as the sinks of a transportation matrix, share
 // lines across neighbouring rows).
 template <typename T, int R>
-__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int ell) {
+__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir) {
     INST;
     if (in.ctl->done || in.gsor || in.lds || c >= in.ncol) return;
     const int r0 = in.cstart[c], r1 = in.cstart[c + 1], gc = in.cg[c];
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
         lane = lw / il;
     }
     if (row >= r1) return;   // the same for every lane of the row; no block barrier below
-    const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
+    const int write_z = !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
     // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
@@ -310,28 +316,29 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
 
 // rows held in registers up to R elements per lane: 8, or 16 when some instance lays the
 // colour out interleaved (fewer lanes per row)
-void b_nesor(const BLaunch& L, int colour, int sweep, int ell) {
+void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir) {
     const unsigned gx = capg(L.grid_colour[colour], 1 << 30);
     const bool wide = L.colour_il && L.colour_il[colour];
+    const dim3 gr(gx, L.S), bl(BLOCK);
     if (L.mixed) {
-        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
-        else hipLaunchKernelGGL((k_nesor<float, 8>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
+        else hipLaunchKernelGGL((k_nesor<float, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
     } else {
-        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
-        else hipLaunchKernelGGL((k_nesor<double, 8>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, colour, sweep, ell);
+        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
+        else hipLaunchKernelGGL((k_nesor<double, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
     }
 }
 
 // ------------------------------------------------------------------------------------
-// A whole NE-SOR application (ell sweeps over every colour) for instances whose z fits in
-// LDS: one block of 1024 threads per instance, z zeroed and kept in LDS, a block barrier
+// A whole NE-SOR or NE-SSOR application (every pass over every colour) for instances
+// whose z fits in LDS: one block of 1024 threads per instance, z zeroed and kept in LDS, a block barrier
 // between colours instead of a kernel launch.  Each row is handled exactly as in k_nesor
 // (same lanes per row, same element-to-lane assignment, same sub-group sum), so the
 // result is bitwise the same as the per-colour launches.
 constexpr int LDS_BLOCK = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict__ I, int ell) {
+__global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* __restrict__ z = reinterpret_cast<T*>(lds_raw);
     INST;
@@ -349,11 +356,13 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
     else val = (const T*)in.ah;
     const int32_t* __restrict__ idx = in.ci;
     const T om = (T)in.omega;
-    for (int sw = 0; sw < ell; ++sw) {
-        for (int c = 0; c < in.ncol; ++c) {
+    for (int sw = 0; sw < npass; ++sw) {
+        const int dir = ssor ? (sw & 1) : 0;
+        for (int cc = 0; cc < in.ncol; ++cc) {
+            const int c = dir ? in.ncol - 1 - cc : cc;
             const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
             const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
-            const int write_z = !(sw == ell - 1 && c == in.ncol - 1);
+            const int write_z = !(sw == npass - 1 && cc == in.ncol - 1);
             const int lane = threadIdx.x & (g - 1);
             const int per = LDS_BLOCK / g;
             for (int base = r0; base < r1; base += per) {
@@ -414,11 +423,11 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
     }
 }
 
-void b_sweep_lds(const BLaunch& L, int ell) {
+void b_sweep_lds(const BLaunch& L, int npass, int ssor) {
     if (L.mixed)
-        hipLaunchKernelGGL((k_sweep_lds<float>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, ell);
+        hipLaunchKernelGGL((k_sweep_lds<float>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, npass, ssor);
     else
-        hipLaunchKernelGGL((k_sweep_lds<double>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, ell);
+        hipLaunchKernelGGL((k_sweep_lds<double>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, npass, ssor);
 }
 
 // ------------------------------------------------------------------------------------
@@ -899,6 +908,275 @@ __global__ __launch_bounds__(BLOCK) void k_true_res(const Inst* __restrict__ I, 
 
 void b_true_res(const BLaunch& L, int pmask) {
     hipLaunchKernelGGL(k_true_res, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
+}
+
+// ------------------------------------------------------------------------------------
+// CGNE and MRNE preconditioned by inner iterations (Sec. 3.3), on A_hat dw = f_hat with
+// dw_0 = 0.  The preconditioner C is the inner-iteration operator: applied to a vector
+// t it gives the multipliers p = C t (column 0 of P) and A_hat^T p (V_Z64, in FP64).
+// The multipliers of every n-vector the method forms are carried along, so dyh with
+// dw = A_hat^T dyh comes out of the iteration itself.
+//
+// Vectors.  CGNE: g (residual) = V_U, C g = P0, A_hat^T C g = V_Z64, q = V_Q with its
+// multipliers V_QM, A_hat q = V_TMPM.  MRNE: g = V_G, t = A_hat p = V_U, C t = P0,
+// v = A_hat^T C t = V_Z64, q = V_Q (multipliers V_QM), p = V_PV (multipliers V_PM).
+//
+// Partials (Inst::part, nbr blocks each): CG_DOT the step's numerator or denominator
+// dot product, CG_QQ = q.q, CG_GG = g.g.  A multi-block kernel reads scalars only from
+// the control block (written by earlier launches) and from complete partials; only the
+// one-block check kernel writes the control block, so no block reads a scalar that
+// another block of the same launch writes.
+constexpr int CG_DOT = 1, CG_QQ = 2, CG_GG = 3;
+
+// the sum of the nb partials of quantity q in fixed order, on every thread of the block
+__device__ __forceinline__ double part_total(const Inst& in, int q, int nb, double* sh) {
+    double v = 0.0;
+    for (int c = threadIdx.x; c < nb; c += blockDim.x) v += in.part[q * RED_MAXBLK + c];
+    const double r = block_sum(v, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[0] = r;
+    __syncthreads();
+    return sh[0];
+}
+
+// start: dw = 0, dyh = 0, q = qm = p = pm = 0; the sweeps read t unscaled (1/h = 1) into
+// column k = 0; MRNE: g = f_hat (t starts as f_hat, written by the start of the solve)
+__global__ __launch_bounds__(BLOCK) void k_cg_init(const Inst* __restrict__ I, int pmask, int mrne) {
+    INST;
+    if (!takes_part(in, pmask)) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    for (int64_t j = t0; j < in.n; j += stride) {
+        in.vec[V_DW][j] = 0.0;
+        in.vec[V_Q][j] = 0.0;
+        in.vec[V_PV][j] = 0.0;
+    }
+    for (int64_t i = t0; i < in.m; i += stride) {
+        in.vec[V_DYH][i] = 0.0;
+        in.vec[V_QM][i] = 0.0;
+        in.vec[V_PM][i] = 0.0;
+        if (mrne) in.vec[V_G][i] = in.vec[V_FH][i];
+    }
+    if (bx == 0 && threadIdx.x == 0) {
+        KrylovCtl* ctl = in.ctl;
+        ctl->k = 0;
+        ctl->inv_h = 1.0;
+        ctl->cg_gamma = 0.0;
+        ctl->cg_beta = 0.0;
+        ctl->cg_phase = mrne ? 0 : 1;
+    }
+}
+
+void b_cg_init(const BLaunch& L, int pmask) {
+    const unsigned gx = capg(cdiv(L.max_m > L.max_n ? L.max_m : L.max_n, BLOCK), GRID_CAP);
+    hipLaunchKernelGGL(k_cg_init, dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, pmask, L.krylov == 2 ? 1 : 0);
+}
+
+// The loop kernels below run on nbr blocks per instance, each a grid-stride slice of
+// the instance's vectors, and return at once for finished instances.
+__global__ __launch_bounds__(BLOCK) void k_cg_dot(const Inst* __restrict__ I, int xs, int ys, int nlen) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (in.ctl->done || bx >= in.nbr || in.ctl->cg_phase == 0) return;
+    const double* __restrict__ x = in.vec[xs];
+    const double* __restrict__ y = ys == V_PCOL ? in.P : in.vec[ys];
+    const int64_t len = nlen ? in.n : in.m;
+    const int64_t stride = (int64_t)in.nbr * BLOCK;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < len; i += stride) acc += x[i] * y[i];
+    write_part(in, bx, CG_DOT, block_sum(acc, sh));
+}
+
+void b_cg_dot(const BLaunch& L, int xs, int ys, int nlen) {
+    hipLaunchKernelGGL(k_cg_dot, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I, xs, ys, nlen);
+}
+
+// CGNE direction: gamma_new = g . C g (the CG_DOT partials), beta = gamma_new / gamma
+// (0 for the first direction), q = A_hat^T C g + beta q, qm = C g + beta qm; q.q partials
+__global__ __launch_bounds__(BLOCK) void k_cgne_dir(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (in.ctl->done || bx >= in.nbr) return;
+    const double gnew = part_total(in, CG_DOT, in.nbr, sh);
+    const double bk = in.ctl->iters == 0 ? 0.0 : gnew / in.ctl->cg_gamma;
+    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    const double* __restrict__ uu = in.vec[V_Z64];
+    double* __restrict__ q = in.vec[V_Q];
+    double qq = 0.0;
+    for (int64_t j = t0; j < in.n; j += stride) {
+        const double v = uu[j] + bk * q[j];
+        q[j] = v;
+        qq += v * v;
+    }
+    const double* __restrict__ zz = in.P;
+    double* __restrict__ qm = in.vec[V_QM];
+    for (int64_t i = t0; i < in.m; i += stride) qm[i] = zz[i] + bk * qm[i];
+    write_part(in, bx, CG_QQ, block_sum(qq, sh));
+}
+
+void b_cgne_dir(const BLaunch& L) {
+    hipLaunchKernelGGL(k_cgne_dir, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// CGNE step: alpha = gamma_new / q.q; dw += alpha q, dyh += alpha qm, g -= alpha A_hat q
+// (A_hat q in V_TMPM); g.g partials.  q.q = 0 ends the iteration (in the check).
+__global__ __launch_bounds__(BLOCK) void k_cgne_step(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (in.ctl->done || bx >= in.nbr) return;
+    const double qq = part_total(in, CG_QQ, in.nbr, sh);
+    if (qq == 0.0) return;
+    const double alpha = part_total(in, CG_DOT, in.nbr, sh) / qq;
+    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    const double* __restrict__ q = in.vec[V_Q];
+    double* __restrict__ dw = in.vec[V_DW];
+    for (int64_t j = t0; j < in.n; j += stride) dw[j] += alpha * q[j];
+    const double* __restrict__ qm = in.vec[V_QM];
+    const double* __restrict__ aq = in.vec[V_TMPM];
+    double* __restrict__ dyh = in.vec[V_DYH];
+    double* __restrict__ g = in.vec[V_U];
+    double gg = 0.0;
+    for (int64_t i = t0; i < in.m; i += stride) {
+        dyh[i] += alpha * qm[i];
+        const double v = g[i] - alpha * aq[i];
+        g[i] = v;
+        gg += v * v;
+    }
+    write_part(in, bx, CG_GG, block_sum(gg, sh));
+}
+
+void b_cgne_step(const BLaunch& L) {
+    hipLaunchKernelGGL(k_cgne_step, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// MRNE step.  Start (phase 0): q = A_hat^T C g, qm = C g; q.q partials.  Else, with
+// v = A_hat^T C t, t = A_hat p: alpha = gamma / v.p; dw += alpha p, dyh += alpha pm,
+// g -= alpha t, q -= alpha v, qm -= alpha C t; g.g and q.q partials.  v.p = 0 ends the
+// iteration (in the check).
+__global__ __launch_bounds__(BLOCK) void k_mrne_step(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (in.ctl->done || bx >= in.nbr) return;
+    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    const double* __restrict__ v = in.vec[V_Z64];
+    const double* __restrict__ vm = in.P;
+    double* __restrict__ q = in.vec[V_Q];
+    double* __restrict__ qm = in.vec[V_QM];
+    if (in.ctl->cg_phase == 0) {
+        double qq = 0.0;
+        for (int64_t j = t0; j < in.n; j += stride) {
+            q[j] = v[j];
+            qq += v[j] * v[j];
+        }
+        for (int64_t i = t0; i < in.m; i += stride) qm[i] = vm[i];
+        write_part(in, bx, CG_QQ, block_sum(qq, sh));
+        return;
+    }
+    const double vp = part_total(in, CG_DOT, in.nbr, sh);
+    if (vp == 0.0) return;
+    const double alpha = in.ctl->cg_gamma / vp;
+    const double* __restrict__ pv = in.vec[V_PV];
+    double* __restrict__ dw = in.vec[V_DW];
+    double qq = 0.0;
+    for (int64_t j = t0; j < in.n; j += stride) {
+        dw[j] += alpha * pv[j];
+        const double w = q[j] - alpha * v[j];
+        q[j] = w;
+        qq += w * w;
+    }
+    const double* __restrict__ pm = in.vec[V_PM];
+    const double* __restrict__ t = in.vec[V_U];
+    double* __restrict__ dyh = in.vec[V_DYH];
+    double* __restrict__ g = in.vec[V_G];
+    double gg = 0.0;
+    for (int64_t i = t0; i < in.m; i += stride) {
+        dyh[i] += alpha * pm[i];
+        const double w = g[i] - alpha * t[i];
+        g[i] = w;
+        gg += w * w;
+        qm[i] -= alpha * vm[i];
+    }
+    write_part(in, bx, CG_GG, block_sum(gg, sh));
+    write_part(in, bx, CG_QQ, block_sum(qq, sh));
+}
+
+void b_mrne_step(const BLaunch& L) {
+    hipLaunchKernelGGL(k_mrne_step, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// One block per instance: the iteration count, res = ||g|| and the stopping test
+// ||g|| <= tol ||f_hat|| or the limit; a zero denominator stops the iteration where it
+// is.  CGNE: gamma = g . C g of this step (the next direction's reference).  MRNE:
+// start: gamma = q_0 . q_0; after a step: beta = q.q / gamma and gamma = q.q, and
+// gamma = 0 stops the iteration.
+__global__ __launch_bounds__(BLOCK) void k_cg_check(const Inst* __restrict__ I, int mrne) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    KrylovCtl* ctl = in.ctl;
+    if (ctl->done) return;
+    const int nb = in.nbr;
+    if (mrne && ctl->cg_phase == 0) {
+        const double gam = part_total(in, CG_QQ, nb, sh);
+        if (threadIdx.x != 0) return;
+        ctl->cg_gamma = gam;
+        ctl->cg_beta = 0.0;
+        ctl->cg_phase = 1;
+        if (!(gam > 0.0)) {
+            ctl->done = 1;
+            ctl->failed = ctl->res > ctl->thresh;
+        }
+        return;
+    }
+    const double den = part_total(in, mrne ? CG_DOT : CG_QQ, nb, sh);
+    const double gg = part_total(in, CG_GG, nb, sh);
+    const double other = part_total(in, mrne ? CG_QQ : CG_DOT, nb, sh);
+    if (threadIdx.x != 0) return;
+    if (den == 0.0) {
+        ctl->done = 1;
+        ctl->failed = ctl->res > ctl->thresh;
+        return;
+    }
+    const double res = sqrt(gg);
+    const int it = ctl->iters + 1;
+    ctl->res = res;
+    ctl->iters = it;
+    if (!mrne) ctl->cg_gamma = other;
+    if (res <= ctl->thresh || it >= ctl->kmax) {
+        ctl->done = 1;
+        ctl->failed = res > ctl->thresh;
+        return;
+    }
+    if (mrne) {
+        ctl->cg_beta = other / ctl->cg_gamma;
+        ctl->cg_gamma = other;
+        if (!(other > 0.0)) {
+            ctl->done = 1;
+            ctl->failed = 1;
+        }
+    }
+}
+
+void b_cg_check(const BLaunch& L) {
+    hipLaunchKernelGGL(k_cg_check, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, L.krylov == 2 ? 1 : 0);
+}
+
+// MRNE direction: p = q + beta p, pm = qm + beta pm (beta = 0 at the start: p and pm are
+// zero then)
+__global__ __launch_bounds__(BLOCK) void k_mrne_dir(const Inst* __restrict__ I) {
+    INST;
+    if (in.ctl->done || bx >= in.nbr) return;
+    const double bk = in.ctl->cg_beta;
+    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    const double* __restrict__ q = in.vec[V_Q];
+    double* __restrict__ pv = in.vec[V_PV];
+    for (int64_t j = t0; j < in.n; j += stride) pv[j] = q[j] + bk * pv[j];
+    const double* __restrict__ qm = in.vec[V_QM];
+    double* __restrict__ pm = in.vec[V_PM];
+    for (int64_t i = t0; i < in.m; i += stride) pm[i] = qm[i] + bk * pm[i];
+}
+
+void b_mrne_dir(const BLaunch& L) {
+    hipLaunchKernelGGL(k_mrne_dir, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
 // ------------------------------------------------------------------------------------

@@ -9,7 +9,8 @@
 
 namespace lpk {
 
-static const char* kClassName[LP_K_COUNT] = {"sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update", "gram"};
+static const char* kClassName[LP_K_COUNT] = {"sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update", "gram",
+                                              "cg_vec"};
 
 static hipEvent_t take_event(Batch* p) {
     if (!p->prof_pool.empty()) {

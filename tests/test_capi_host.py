@@ -42,9 +42,9 @@ def test_status_strings_and_version():
     assert "gfx950" in lpk.lib().lp_version().decode()
 
 
-def _try_create(m, n, rp, ci, val, b, c):
+def _try_create(m, n, rp, ci, val, b, c, **opts):
     h = ctypes.c_void_p(None)
-    o = lpk.options()
+    o = lpk.options(**opts)
     arrs = [np.ascontiguousarray(rp, np.int64), np.ascontiguousarray(ci, np.int32),
             np.ascontiguousarray(val, np.float64), np.ascontiguousarray(b, np.float64),
             np.ascontiguousarray(c, np.float64)]
@@ -102,3 +102,21 @@ def test_footprint_grows_with_krylov_basis():
     assert a > b > 180000 * 24
     with pytest.raises(lpk.LpError):
         lpk.lp_footprint_bytes(10, 5, 20)
+
+
+def test_footprint_of_cg_methods_is_independent_of_the_iteration_limit():
+    """CGNE and MRNE keep a fixed set of vectors (no Krylov basis)."""
+    g = lpk.lp_footprint_bytes(600, 90000, 180000)   # AB-GMRES, basis of m + 1 vectors
+    for kry in ("cgne", "mrne"):
+        a = lpk.lp_footprint_bytes(600, 90000, 180000, lpk.options(krylov=kry))
+        b = lpk.lp_footprint_bytes(600, 90000, 180000, lpk.options(krylov=kry, krylov_max_iter=50))
+        assert a == b < g
+
+
+def test_unknown_krylov_method_is_rejected_on_the_host():
+    lp = synth.config(0)
+    args = (lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c)
+    assert _try_create(*args, krylov=7)[0] == lpk.LP_EINVAL
+    # MRNE's recurrence needs FP64 sweeps
+    assert _try_create(*args, krylov=lpk.LP_MRNE, precision=lpk.LP_MIXED)[0] == lpk.LP_EINVAL
+    assert _try_create(*args, inner=9)[0] == lpk.LP_EINVAL
