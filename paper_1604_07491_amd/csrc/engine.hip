@@ -1,13 +1,15 @@
 // The batched engine: interior-point iterations (Sec. 2.1) of many LPs in lockstep, each
 // phase one launch for the whole batch, with the search-direction solves by AB-GMRES
-// preconditioned by inner iterations (Sec. 3.2) on the row-scaled problem (Sec. 3.5).
+// (Sec. 3.2) or CGNE / MRNE (Sec. 3.3) preconditioned by inner iterations on the
+// row-scaled problem (Sec. 3.5).
 //
 // Differences from the paper's single-LP CPU layout, all exact in exact arithmetic:
 //  * flexible final step: the multiplier vectors p_k of every preconditioner application
-//    are kept (P = [p_1 .. p_k]) and the solution is dw = A_hat^T (P y); z_k = A_hat^T p_k
-//    is recomputed in FP64, so the Arnoldi relation and dw in R(A_hat^T) hold to FP64 even
-//    when the sweeps run in FP32.  The multipliers also give dy = diag(rho)^-1 P y with no
-//    extra matrix-vector product.
+//    are kept (P = [p_1 .. p_k]) and the solution is dw = A_hat^T (P y).  z_k = A_hat^T p_k
+//    is the z the FP64 NE-SOR sweeps maintain (as in the paper's own sweep); FP32 sweeps
+//    and Cimmino leave no such z and it is recomputed in FP64 from p_k, so the Arnoldi
+//    relation and dw in R(A_hat^T) hold to FP64 even when the sweeps run in FP32.  The
+//    multipliers also give dy = diag(rho)^-1 P y with no extra matrix-vector product.
 //  * classical Gram-Schmidt applied twice in place of modified Gram-Schmidt (Sec. 3.2 uses
 //    MGS); both orthogonalise to working precision, CGS2 in two reductions per pass.
 //  * the Hessenberg least-squares problem is kept in QR form by Givens rotations on the
@@ -129,6 +131,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.nbs = spmv_blocks(p->m, p->g_csr);
     in.zcover = p->zcover ? 1 : 0;
     in.lds = (in.ncol > 0 && p->n * (mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
+    if (in.lds && lds_stage_bytes(p->m, p->n, p->nnz, mixed ? 4 : 8) <= LDS_STAGE_MAX) in.lds = 2;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
     in.ldp = p->ldh;   // kmax + 1 for AB-GMRES
@@ -172,7 +175,8 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
         a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.mixed != b.mixed ||
         a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
         a.need_prep != b.need_prep ||
-        a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.max_ncol_global != b.max_ncol_global)
+        a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.any_stage != b.any_stage ||
+        a.stage_bytes != b.stage_bytes || a.keep_z != b.keep_z || a.max_ncol_global != b.max_ncol_global)
         return false;
     for (int i = 0; i < 4; ++i)
         if (a.grid_spmv[i] != b.grid_spmv[i]) return false;
@@ -199,6 +203,8 @@ lp_status Batch::refresh() {
     L.need_prep = false;
     L.any_lds = false;
     L.lds_bytes = 0;
+    L.any_stage = false;
+    L.stage_bytes = 0;
     L.max_ncol_global = 0;
     bool first = true;
     for (int s = 0; s < cap; ++s) {
@@ -211,6 +217,7 @@ lp_status Batch::refresh() {
             L.inner = p->gsor ? 3 : p->opt.inner;
             L.ell = std::max(1, (int)p->opt.inner_sweeps);
             L.krylov = p->opt.krylov;
+            L.keep_z = !L.mixed && (L.inner == LP_NESOR || L.inner == LP_NESSOR);
             first = false;
         }
         L.max_m = std::max(L.max_m, in.m);
@@ -228,7 +235,10 @@ lp_status Batch::refresh() {
         L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
         L.gs_fused = L.gs_fused && p->gpart2 != nullptr && gs_fusable(p->nchunks, p->kmax);
         L.max_ncol = std::max(L.max_ncol, in.ncol);
-        if (in.lds) {
+        if (in.lds == 2) {
+            L.any_stage = true;
+            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, L.mixed ? 4 : 8));
+        } else if (in.lds) {
             L.any_lds = true;
             L.lds_bytes = std::max(L.lds_bytes, in.n * (L.mixed ? 4 : 8));
         } else {
@@ -352,14 +362,27 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
         // NE-SOR: ell forward passes; NE-SSOR: ell forward-backward pairs
         const bool ssor = L.inner == LP_NESSOR;
         const int npass = ssor ? 2 * ell : ell;
-        if (L.any_lds) {
-            // the instances whose z fits in LDS: every pass and colour in one launch
+        // the instances whose z fits in LDS: every pass and colour in one launch
+        auto lds_kind = [&](const lp_problem* p) {
+            if (p->n * (L.mixed ? 4 : 8) > LDS_Z_MAX) return 0;
+            return lds_stage_bytes(p->m, p->n, p->nnz, L.mixed ? 4 : 8) <= LDS_STAGE_MAX ? 2 : 1;
+        };
+        if (L.any_stage) {
+            // row data read once per application
             const double by = over_members(B, [&](const lp_problem* p) {
-                if (p->n * (L.mixed ? 4 : 8) > LDS_Z_MAX) return 0.0;
-                return npass * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0));
+                if (lds_kind(p) != 2) return 0.0;
+                return p->nnz * (sv + 4.0) + (p->m + 1) * 4.0 + (double)p->m * (8.0 + 16.0) + (L.keep_z ? 8.0 * p->n : 0.0);
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, true);
+        }
+        if (L.any_lds) {
+            const double by = over_members(B, [&](const lp_problem* p) {
+                if (lds_kind(p) != 1) return 0.0;
+                return npass * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0)) + (L.keep_z ? 8.0 * p->n : 0.0);
+            });
+            Prof pr(&B, LP_K_SWEEP, it, by);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, false);
         }
         for (int sw = 0; sw < npass; ++sw) {
             const int dir = ssor ? (sw & 1) : 0;
@@ -369,7 +392,7 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
                     const int nc = (int)p->colours.size();
                     if (c >= nc || p->n * (L.mixed ? 4 : 8) <= LDS_Z_MAX) return 0.0;
                     const Colour& cl = p->colours[c];
-                    const int wz = !(sw + 1 == npass && c == (dir ? 0 : nc - 1));
+                    const int wz = L.keep_z || !(sw + 1 == npass && c == (dir ? 0 : nc - 1));
                     return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
@@ -390,8 +413,9 @@ static void enqueue_products(Batch& B, int64_t it) {
         b_gemv_col(L);
         return;
     }
-    // outer operator in FP64: z_k = A_hat^T p_k, u = A_hat z_k
-    {
+    // outer operator in FP64: z_k = A_hat^T p_k (left by the FP64 sweeps, else by a
+    // product with the CSC copy), u = A_hat z_k
+    if (!L.keep_z) {
         Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
         b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
     }
@@ -411,7 +435,7 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
     };
     if (L.krylov == LP_CGNE) {
         enqueue_precond(B, it, true);   // C g (g in V_U)
-        {
+        if (!L.keep_z) {
             Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
             b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
         }
@@ -438,7 +462,7 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
             b_spmv(L, M_AH_CSR, V_PV, V_U, EPI_PLAIN, -1, -1, PM_ITER_DIR, false);   // t = A_hat p
         }
         enqueue_precond(B, it, true);   // C t (at the start: C g)
-        {
+        if (!L.keep_z) {
             Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
             b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
         }
@@ -855,10 +879,13 @@ lp_status Engine::round() {
         }                                 \
     } while (0)
     if (b.dirty) LPK_RC(b.refresh());
-    // Scheduling.  Members of one shape (equal m and n) have similar solve lengths: they
-    // pass their phases together, once none of them is inside a solve (lockstep; a phase
-    // costs one round for all).  Members of different shapes each advance as soon as their
-    // solve ends, so a small LP is not held by a large one.
+    // Scheduling.  Members with one sparsity structure (equal m, n and nnz: the same model
+    // with other data, as the LPs of one transportation network with other costs) have
+    // similar solve lengths: they pass their phases together, once none of them is inside
+    // a solve (lockstep; a phase costs one round for all).  Otherwise each member advances
+    // as soon as its own solve ends, so no LP waits for a slower one.  Measured on 64
+    // transportation LPs (lockstep faster) and on 64 random sparse LPs of one shape whose
+    // solve lengths differ (advancing alone faster).
     int iterating = 0;
     bool uniform = true;
     const lp_problem* ref = nullptr;
@@ -867,7 +894,7 @@ lp_status Engine::round() {
         if (mb.state == EMPTY || mb.state == DONE) continue;
         if (mb.state == KRY1 || mb.state == KRY2) ++iterating;
         if (!ref) ref = mb.p;
-        else if (mb.p->m != ref->m || mb.p->n != ref->n) uniform = false;
+        else if (mb.p->m != ref->m || mb.p->n != ref->n || mb.p->nnz != ref->nnz) uniform = false;
     }
     const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
     bool has[SH2 + 1] = {false};

@@ -87,7 +87,8 @@ struct Inst {
     int32_t nbr;                          // blocks of the vector reductions (own sizes only)
     int32_t nbs;                          // blocks of the reduction over a CSR product
     int32_t zcover;                       // 1: the rows of colour 0 cover every column
-    int32_t lds;                          // 1: whole NE-SOR application in one block, z in LDS
+    int32_t lds;                          // whole NE-SOR application in one block: 1 z in LDS,
+                                          // 2 z, the row data, v_k and p_k in LDS
     int32_t pad1;
     int64_t ldv, ldh, ldp, kmax;
     const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
@@ -127,13 +128,22 @@ struct BLaunch {
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
     const char* colour_il;  // host array [max_ncol]: some instance interleaves the colour's rows
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
-    bool any_lds;           // some instance sweeps in one block with z in LDS
+    bool any_lds;           // some instance sweeps in one block with z in LDS (lds == 1)
     int lds_bytes;          // largest z of those instances
+    bool any_stage;         // some instance sweeps in one block from LDS alone (lds == 2)
+    int stage_bytes;        // largest LDS footprint of those instances
+    bool keep_z;            // FP64 NE-SOR / NE-SSOR: the sweeps leave z_k = A_hat^T p_k in
+                            // V_Z64, and the loop needs no product with A_hat^T
     int max_ncol_global;    // colours of the instances swept by per-colour launches
 };
 
-// an NE-SOR instance sweeps in one block with z in LDS when z fits in this many bytes
+// an NE-SOR instance sweeps in one block with z in LDS when z fits in this many bytes,
+// and with its row data, v_k and p_k in LDS as well when all of them fit in LDS_STAGE_MAX
 constexpr int LDS_Z_MAX = 48 * 1024;
+constexpr int LDS_STAGE_MAX = 64 * 1024;
+inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int tbytes) {
+    return 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1);
+}
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------
 enum Epilogue : int { EPI_PLAIN = 0, EPI_B_MINUS = 1, EPI_B1_MINUS_B2 = 2, EPI_B_PLUS = 3 };
@@ -152,8 +162,9 @@ void b_prep(const BLaunch& L);
 // one colour of pass `pass` of `npass` (dir 0: colours in order, 1: reversed, the
 // backward half of an NE-SSOR iteration); the first pass forms v_k and p_k
 void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir);
-// every colour of every pass, one block per instance (ssor: passes alternate direction)
-void b_sweep_lds(const BLaunch& L, int npass, int ssor);
+// every colour of every pass, one block per instance (ssor: passes alternate direction);
+// staged: the instances with Inst::lds == 2 (row data in LDS), else those with lds == 1
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged);
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 void b_gs_dots(const BLaunch& L);

@@ -206,8 +206,9 @@ void b_prep(const BLaunch& L) {
 // row i of the colour, in parallel, computes d = omega (v_i - a_i . z), adds d to p_i and
 // d a_i to z.  Rows of one colour share no column, so the z updates are disjoint.  The
 // row segment (values, column indices) is held in registers between the dot product and
-// the update, so each nonzero is read from memory once per sweep.  The last colour of the
-// last pass skips the z update (z is recomputed in FP64 from p).
+// the update, so each nonzero is read from memory once per sweep.  In FP64 (keepz) the
+// last colour still updates z, which then holds z_k = A_hat^T p_k for the product that
+// follows; in FP32 it skips the update and z_k is recomputed in FP64 from p.
 //
 // A pass visits the colours in order (dir 0) or in reverse (dir 1).  NE-SSOR (Sec. 3.3)
 // alternates the two: each of its iterations is a forward and a backward sweep, and
@@ -221,7 +222,7 @@ void b_prep(const BLaunch& L) {
 // a colour whose columns are strided, as the sinks of a transportation matrix, share
 // lines across neighbouring rows).
 template <typename T, int R>
-__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir) {
+__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir, int keepz) {
     INST;
     if (in.ctl->done || in.gsor || in.lds || c >= in.ncol) return;
     const int r0 = in.cstart[c], r1 = in.cstart[c + 1], gc = in.cg[c];
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
         lane = lw / il;
     }
     if (row >= r1) return;   // the same for every lane of the row; no block barrier below
-    const int write_z = !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
+    const int write_z = keepz || !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
     // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
@@ -320,41 +321,77 @@ void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir) {
     const unsigned gx = capg(L.grid_colour[colour], 1 << 30);
     const bool wide = L.colour_il && L.colour_il[colour];
     const dim3 gr(gx, L.S), bl(BLOCK);
+    const int kz = L.keep_z ? 1 : 0;
     if (L.mixed) {
-        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
-        else hipLaunchKernelGGL((k_nesor<float, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
+        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, 0);
+        else hipLaunchKernelGGL((k_nesor<float, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, 0);
     } else {
-        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
-        else hipLaunchKernelGGL((k_nesor<double, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir);
+        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
+        else hipLaunchKernelGGL((k_nesor<double, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
     }
 }
 
 // ------------------------------------------------------------------------------------
 // A whole NE-SOR or NE-SSOR application (every pass over every colour) for instances
-// whose z fits in LDS: one block of 1024 threads per instance, z zeroed and kept in LDS, a block barrier
-// between colours instead of a kernel launch.  Each row is handled exactly as in k_nesor
-// (same lanes per row, same element-to-lane assignment, same sub-group sum), so the
-// result is bitwise the same as the per-colour launches.
+// whose z fits in LDS: one block of 1024 threads per instance, z zeroed and kept in LDS,
+// a block barrier between colours instead of a kernel launch.  STAGED (Inst::lds == 2):
+// the instance's whole row data (row pointers, values, column indices), v_k and the
+// multipliers p_k are copied into LDS too, in one coalesced pass, so the colour steps,
+// each a dependent chain of loads, run on LDS alone; v_k and p_k are written back at the
+// end.  Each row is handled exactly as in k_nesor (same lanes per row, same
+// element-to-lane assignment, same sub-group sum), so the result is bitwise the same as
+// the per-colour launches.  keepz: z is copied out to V_Z64 at the end (z_k = A_hat^T p_k).  LDS layout (STAGED): p (m doubles), v (m doubles), values
+// (nnz T), z (n T), row pointers (m + 1 ints), column indices (nnz ints).
 constexpr int LDS_BLOCK = 1024;
 
-template <typename T>
-__global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor) {
+template <typename T, bool STAGED>
+__global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int keepz) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    T* __restrict__ z = reinterpret_cast<T*>(lds_raw);
     INST;
-    if (in.ctl->done || !in.lds) return;
-    const int n = in.n;
-    for (int j = threadIdx.x; j < n; j += LDS_BLOCK) z[j] = 0;
-    __syncthreads();
+    if (in.ctl->done || in.lds != (STAGED ? 2 : 1)) return;
+    const int m = in.m, n = in.n, nnz = in.nnz;
     const int64_t k = in.ctl->k;
     const double ih = in.ctl->inv_h;
     const double* __restrict__ u = in.vec[V_U];
     double* __restrict__ vk = in.V + k * in.ldv;
     double* __restrict__ p = in.P + k * in.ldv;
+    const T* __restrict__ gval;
+    if constexpr (sizeof(T) == 4) gval = (const T*)in.ah32;
+    else gval = (const T*)in.ah;
+    T* __restrict__ z;
     const T* __restrict__ val;
-    if constexpr (sizeof(T) == 4) val = (const T*)in.ah32;
-    else val = (const T*)in.ah;
-    const int32_t* __restrict__ idx = in.ci;
+    const int32_t* __restrict__ idx;
+    const int32_t* __restrict__ rptr;
+    double* __restrict__ pp;   // multipliers being accumulated
+    double* __restrict__ vv;   // v_k as stored after the first pass
+    if constexpr (STAGED) {
+        double* pl = reinterpret_cast<double*>(lds_raw);
+        double* vl = pl + m;
+        T* sv = reinterpret_cast<T*>(vl + m);
+        z = sv + nnz;
+        int32_t* srp = reinterpret_cast<int32_t*>(z + n);
+        int32_t* si = srp + (m + 1);
+        for (int t = threadIdx.x; t < nnz; t += LDS_BLOCK) {
+            sv[t] = gval[t];
+            si[t] = in.ci[t];
+        }
+        for (int t = threadIdx.x; t <= m; t += LDS_BLOCK) srp[t] = in.rp[t];
+        for (int t = threadIdx.x; t < m; t += LDS_BLOCK) vl[t] = u[t] * ih;
+        val = sv;
+        idx = si;
+        rptr = srp;
+        pp = pl;
+        vv = vl;
+    } else {
+        z = reinterpret_cast<T*>(lds_raw);
+        val = gval;
+        idx = in.ci;
+        rptr = in.rp;
+        pp = p;
+        vv = vk;
+    }
+    for (int j = threadIdx.x; j < n; j += LDS_BLOCK) z[j] = 0;
+    __syncthreads();
     const T om = (T)in.omega;
     for (int sw = 0; sw < npass; ++sw) {
         const int dir = ssor ? (sw & 1) : 0;
@@ -362,14 +399,14 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
             const int c = dir ? in.ncol - 1 - cc : cc;
             const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
             const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
-            const int write_z = !(sw == npass - 1 && cc == in.ncol - 1);
+            const int write_z = keepz || !(sw == npass - 1 && cc == in.ncol - 1);
             const int lane = threadIdx.x & (g - 1);
             const int per = LDS_BLOCK / g;
             for (int base = r0; base < r1; base += per) {
                 const int row = base + (int)threadIdx.x / g;
                 if (row < r1) {   // uniform inside the sub-group
-                    const double vrow = sw == 0 ? u[row] * ih : vk[row];
-                    const int s = in.rp[row], e = in.rp[row + 1];
+                    const double vrow = (sw == 0 && !STAGED) ? u[row] * ih : vv[row];
+                    const int s = rptr[row], e = rptr[row + 1];
                     constexpr int R = 8;
                     T acc = 0;
                     if (e - s <= g * R) {
@@ -395,10 +432,10 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
                         }
                         if (lane == 0) {
                             if (sw == 0) {
-                                vk[row] = vrow;
-                                p[row] = (double)delta;
+                                if (!STAGED) vk[row] = vrow;
+                                pp[row] = (double)delta;
                             } else {
-                                p[row] += (double)delta;
+                                pp[row] += (double)delta;
                             }
                         }
                     } else {
@@ -409,10 +446,10 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
                             for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
                         if (lane == 0) {
                             if (sw == 0) {
-                                vk[row] = vrow;
-                                p[row] = (double)delta;
+                                if (!STAGED) vk[row] = vrow;
+                                pp[row] = (double)delta;
                             } else {
-                                p[row] += (double)delta;
+                                pp[row] += (double)delta;
                             }
                         }
                     }
@@ -421,13 +458,29 @@ __global__ __launch_bounds__(LDS_BLOCK) void k_sweep_lds(const Inst* __restrict_
             __syncthreads();
         }
     }
+    if constexpr (STAGED) {
+        for (int t = threadIdx.x; t < m; t += LDS_BLOCK) {
+            p[t] = pp[t];
+            vk[t] = vv[t];
+        }
+    }
+    if (keepz) {
+        double* __restrict__ zo = in.vec[V_Z64];
+        for (int j = threadIdx.x; j < n; j += LDS_BLOCK) zo[j] = (double)z[j];
+    }
 }
 
-void b_sweep_lds(const BLaunch& L, int npass, int ssor) {
-    if (L.mixed)
-        hipLaunchKernelGGL((k_sweep_lds<float>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, npass, ssor);
-    else
-        hipLaunchKernelGGL((k_sweep_lds<double>), dim3(1, L.S), dim3(LDS_BLOCK), L.lds_bytes, L.st, L.I, npass, ssor);
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged) {
+    const dim3 gr(1, L.S), bl(LDS_BLOCK);
+    const int by = staged ? L.stage_bytes : L.lds_bytes;
+    const int kz = L.keep_z ? 1 : 0;
+    if (staged) {
+        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, true>), gr, bl, by, L.st, L.I, npass, ssor, 0);
+        else hipLaunchKernelGGL((k_sweep_lds<double, true>), gr, bl, by, L.st, L.I, npass, ssor, kz);
+    } else {
+        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, false>), gr, bl, by, L.st, L.I, npass, ssor, 0);
+        else hipLaunchKernelGGL((k_sweep_lds<double, false>), gr, bl, by, L.st, L.I, npass, ssor, kz);
+    }
 }
 
 // ------------------------------------------------------------------------------------

@@ -129,10 +129,11 @@ def test_server_admission_and_results():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_mixes_lds_and_per_colour_sweeps(precision):
-    """Small LPs sweep in one block with z in LDS; a transportation LP with n = 8000
-    (z over the LDS limit in FP64) sweeps colour by colour.  Both kinds in one batch give
+    """Small LPs sweep in one block from LDS alone (row data staged); a 302 x 2000 LP
+    keeps z in LDS and reads its rows from memory; a transportation LP with n = 8000 (z
+    over the LDS limit in FP64) sweeps colour by colour.  All three kinds in one batch give
     each LP's result bitwise as alone, and the optimum matches the oracle's."""
-    lps = [synth.transport_lp(100, 80, seed=3)] + _mix(3, seed0=60)
+    lps = [synth.transport_lp(100, 80, seed=3)] + _mix(3, seed0=60) + [synth.sparse_lp(300, 2000, 6, 2, seed=61)]
     opts = lambda: lpk.options(precision=precision)
     alone = []
     for lp in lps:
@@ -140,7 +141,7 @@ def test_batch_mixes_lds_and_per_colour_sweeps(precision):
             r = lpk.lp_solve(p)
             alone.append((r, lpk.lp_get_state(p)[0]))
     probs = [lpk.from_lp(lp, opts()) for lp in lps]
-    res = lpk.lp_solve_batch(probs, width=4)
+    res = lpk.lp_solve_batch(probs, width=len(lps))
     for i, p in enumerate(probs):
         assert res[i]["status"] == lpk.LP_OK
         assert res[i]["krylov_iters"] == alone[i][0]["krylov_iters"]
