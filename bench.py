@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--width", type=int, default=64, help="LPs in lockstep")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
+    ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
+                    help="batch phases: 0 auto, 1 together, 2 each LP alone")
     ap.add_argument("--krylov", default="abgmres", choices=["abgmres", "cgne", "mrne"],
                     help="outer iteration: AB-GMRES (Sec. 3.2) or CGNE / MRNE (Sec. 3.3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -121,7 +123,7 @@ def main():
         return steps_main(args)
     lps = make_lps(args.workload, args.batch)
     dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
-    opts = lpk.options(precision=args.precision, inner=args.inner, krylov=args.krylov)
+    opts = lpk.options(precision=args.precision, inner=args.inner, krylov=args.krylov, schedule=args.schedule)
     probs = []
     for lp in lps:
         if lp.dense is not None:
@@ -156,7 +158,7 @@ def main():
     stats = lpk.lp_profile_read(p0)
     lpk.lp_profile(p0, 0)
     cls_id = {"sweep": lpk.LP_K_SWEEP, "spmv_csr": lpk.LP_K_SPMV_CSR, "spmv_csc": lpk.LP_K_SPMV_CSC,
-              "gram": lpk.LP_K_GRAM}
+              "gs_dots": lpk.LP_K_GS_DOTS, "gs_update": lpk.LP_K_GS_UPDATE, "gram": lpk.LP_K_GRAM}
     timed = {k: v for k, v in stats.items() if k in cls_id and v["launches"] > 0}
     dom = max(timed, key=lambda k: timed[k]["ms_total"])
     # the dominant class for the batch as it runs in the timed steps
@@ -177,7 +179,7 @@ def main():
                 "single_lp": {"us_per_launch": t1["us_per_launch"], "bytes_per_launch": t1["bytes_per_launch"],
                               "achieved": t1["bytes_per_launch"] / (t1["us_per_launch"] * 1e-6) / 1e9}}
     extra = {"batch_kernels": {}}
-    for name in ("sweep", "spmv_csr", "spmv_csc"):
+    for name in ("sweep", "spmv_csr", "spmv_csc", "gs_dots", "gs_update"):
         if name not in timed:
             continue
         tb = lpk.lp_time_batch_kernel(probs[:width], cls_id[name], reps=200)
@@ -228,7 +230,7 @@ def main():
                    "lps_per_step": len(probs), "lps_in_lockstep": args.width,
                    "precision": args.precision, "inner": args.inner,
                    "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE"}[args.krylov],
-                   "inner_sweeps": 2, "omega": 1.0},
+                   "inner_sweeps": 2, "omega": 1.0, "schedule": args.schedule},
         "roofline": roofline,
         "kernel_classes": {k: {"launches": v["launches"], "ms_total": v["ms_total"],
                                "us_per_launch_event_bracketed": v["ms_total"] * 1e3 / max(v["launches"], 1)}

@@ -88,6 +88,11 @@ typedef struct {
     void* stream;            /* hipStream_t [NULL]                                        */
     int32_t poll_every;      /* Krylov iterations enqueued between convergence checks [0=auto] */
     int32_t use_graphs;      /* 1: replay each Krylov iteration as a captured HIP graph [1] */
+    int32_t schedule;        /* batches (lp_solve_batch, lp_server): 0 auto = members of one */
+                             /* structure (equal m, n, nnz) pass each phase together, others */
+                             /* advance alone; 1 always together; 2 always alone [0]; a     */
+                             /* member asking 2 wins over 1, 1 over 0                       */
+    int32_t pad0;
 } lp_options;
 
 /* Per direction solve (Sec. 4.2 stopping rule ||f_hat - A_hat dw|| <= eps_in ||f_hat||). */
@@ -239,12 +244,14 @@ lp_status lp_profile_read(lp_problem* p, lp_kernel_stat* st, int32_t cap, int32_
 
 /* Mean duration of one launch of kernel class cls (LP_K_SWEEP: one application of the
  * inner-iteration preconditioner; LP_K_SPMV_CSR / LP_K_SPMV_CSC: the Krylov loop's two
- * products; LP_K_GRAM: the dense path's Gram and preconditioner build, timed per launch
- * of its kernels), from `reps` back-to-back replays of its launches captured with the
- * current A_hat, between two HIP events on the problem's stream.  Also returns the
- * algorithmic bytes and flops per launch (as in lp_kernel_stat) and the launches in one
- * group (e.g. colours x sweeps).  Needs a scaling: run ipm_step, lp_solve or
- * direction_solve first.  Overwrites column 0 of the Krylov workspace.
+ * products; LP_K_GS_DOTS / LP_K_GS_UPDATE: the AB-GMRES Gram-Schmidt passes at basis
+ * size min(128, krylov limit); LP_K_GRAM: the dense path's Gram and preconditioner
+ * build, timed per launch of its kernels), from `reps` back-to-back replays of its
+ * launches captured with the current A_hat, between two HIP events on the problem's
+ * stream.  Also returns the algorithmic bytes and flops per launch (as in
+ * lp_kernel_stat) and the launches in one group (e.g. colours x sweeps).  Needs a
+ * scaling: run ipm_step, lp_solve or direction_solve first.  Overwrites the Krylov
+ * workspace (column 0, and for the Gram-Schmidt classes one column of H and u).
  * Errors: LP_EINVAL, LP_EDEVICE.                                                        */
 lp_status lp_time_kernel(lp_problem* p, int32_t cls, int32_t reps, double* us_per_launch,
                          double* bytes_per_launch, double* flops_per_launch,

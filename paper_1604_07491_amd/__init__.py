@@ -43,7 +43,8 @@ class Options(C.Structure):
                 ("sigma_max", C.c_double), ("eps_in0", C.c_double), ("eps_in_min", C.c_double),
                 ("eps_in_max", C.c_double), ("init_tol", C.c_double), ("backtrack", C.c_double),
                 ("max_backtrack", C.c_int32), ("device_io", C.c_int32), ("stream", C.c_void_p),
-                ("poll_every", C.c_int32), ("use_graphs", C.c_int32)]
+                ("poll_every", C.c_int32), ("use_graphs", C.c_int32), ("schedule", C.c_int32),
+                ("pad0", C.c_int32)]
 
 
 class KrylovInfo(C.Structure):

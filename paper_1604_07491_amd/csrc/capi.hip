@@ -70,8 +70,12 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     z.add(m * cols, 8); z.add(m * cols, 8);       // V, P
     z.add(cols * cols, 8);                        // H
     for (int i = 0; i < 5; ++i) z.add(cols + 1, 8);
-    z.add(nchunks * cols, 8);
-    if (!cg && gs_fusable(nchunks, kmax)) z.add(nchunks * cols, 8);
+    if (cg) {
+        z.add(nchunks, 8);
+    } else {
+        z.add(std::max<int64_t>(nchunks, (int64_t)gs_segments(m) * cols), 8);
+        z.add((int64_t)gs_segments(m) * cols, 8);
+    }
     // the problem's batch of one: descriptor, control words, parameters, partials
     z.add(1, sizeof(Inst)); z.add(1, sizeof(Slot)); z.add(1, sizeof(Param));
     z.add((int64_t)RED_NQ * RED_MAXBLK, 8);
@@ -313,8 +317,12 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->gam = A.alloc<double>(cols + 1);
     p->ykr = A.alloc<double>(cols + 1);
     p->h2 = A.alloc<double>(cols + 1);
-    p->gpart = A.alloc<double>((int64_t)p->nchunks * cols);
-    if (!cg && gs_fusable(p->nchunks, p->kmax)) p->gpart2 = A.alloc<double>((int64_t)p->nchunks * cols);
+    if (cg) {
+        p->gpart = A.alloc<double>(p->nchunks);
+    } else {
+        p->gpart = A.alloc<double>(std::max<int64_t>(p->nchunks, (int64_t)gs_segments(m) * cols));
+        p->gpart2 = A.alloc<double>((int64_t)gs_segments(m) * cols);
+    }
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);
         p->Xinv = A.alloc<double>(m * m);
@@ -370,6 +378,7 @@ static lp_status check_options(const lp_options& o, bool dense) {
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LP_EINVAL, "omega must be in (0, 2)");
     if (!(o.eta >= 0.9 && o.eta < 1.0)) return fail(LP_EINVAL, "eta must be in [0.9, 1)");
     if (o.ipm_max_iter < 0) return fail(LP_EINVAL, "ipm_max_iter must be >= 0");
+    if (o.schedule < 0 || o.schedule > 2) return fail(LP_EINVAL, "schedule must be 0, 1 or 2");
     if (!(o.eps_in_min > 0.0 && o.eps_in_min <= o.eps_in_max)) return fail(LP_EINVAL, "bad eps_in range");
     return LP_OK;
 }

@@ -37,7 +37,9 @@ int gs_rpl_for(int64_t m) {
     return rpl;
 }
 
-bool gs_fusable(int64_t nchunks, int64_t kmax) { return nchunks <= 32 && kmax + 1 <= 2048; }
+int gs_segments(int64_t m) { return (int)((m + 1023) / 1024); }
+
+bool gs_fusable(int64_t m, int64_t kmax) { return gs_segments(m) <= 4 && kmax + 1 <= 2048; }
 
 static inline int cdiv_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -125,6 +127,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.g_csr = p->g_csr;
     in.g_csc = p->g_csc;
     in.nchunks = p->nchunks;
+    in.nseg = gs_segments(p->m);
     in.gsor = p->gsor ? 1 : 0;
     in.rpl = p->rpl;
     in.nbr = red_blocks(std::max(p->m, p->n));
@@ -172,7 +175,7 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
                         const std::vector<int>& cb) {
     if (a.S != b.S || a.max_m != b.max_m || a.max_n != b.max_n || a.max_nbr != b.max_nbr ||
         a.max_nbs != b.max_nbs || a.max_ldp != b.max_ldp || a.gs_rpl != b.gs_rpl ||
-        a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.mixed != b.mixed ||
+        a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.gs_dots_grid != b.gs_dots_grid || a.mixed != b.mixed ||
         a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
         a.need_prep != b.need_prep ||
         a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.any_stage != b.any_stage ||
@@ -197,6 +200,7 @@ lp_status Batch::refresh() {
     for (int i = 0; i < 4; ++i) L.grid_spmv[i] = 1;
     L.gs_rpl = 1;
     L.gs_nchunks = 1;
+    L.gs_dots_grid = 1;
     L.gs_fused = true;
     L.max_ncol = 0;
     L.ell = 1;
@@ -233,7 +237,9 @@ lp_status Batch::refresh() {
         L.grid_spmv[M_AH_CSC] = std::max(L.grid_spmv[M_AH_CSC], gc);
         L.gs_rpl = std::max(L.gs_rpl, in.rpl);
         L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
-        L.gs_fused = L.gs_fused && p->gpart2 != nullptr && gs_fusable(p->nchunks, p->kmax);
+        L.gs_fused = L.gs_fused && gs_fusable(p->m, p->kmax);
+        // dot tasks: (k + 1) columns x segments, at most 128 blocks of 4 waves per instance
+        L.gs_dots_grid = std::max<int>(L.gs_dots_grid, (int)std::min<int64_t>(128, cdiv_i((int64_t)in.nseg * (p->kmax + 1), 4)));
         L.max_ncol = std::max(L.max_ncol, in.ncol);
         if (in.lds == 2) {
             L.any_stage = true;
@@ -425,6 +431,37 @@ static void enqueue_products(Batch& B, int64_t it) {
     }
 }
 
+// Classical Gram-Schmidt twice and the Givens step, for basis index k = it (the parts
+// selected by `parts`)
+enum { GS_DOTS = 1, GS_UPDATES = 2, GS_FINISH = 4 };
+
+static void enqueue_gs(Batch& B, int64_t it, int parts) {
+    const BLaunch& L = B.L;
+    const double kk = (double)(it + 1);
+    // V once, u once, the partials (segments x (k + 1)) once
+    auto dots_b = [&]() {
+        return over_members(B, [&](const lp_problem* p) { return kk * p->m * 8.0 + p->m * 8.0 + gs_segments(p->m) * kk * 8.0; });
+    };
+    // V once, u read and written, the partials read by every chunk's block (fused)
+    auto upd_b = [&]() {
+        return over_members(B, [&](const lp_problem* p) {
+            return kk * p->m * 8.0 + p->m * 16.0 + (L.gs_fused ? (double)p->nchunks * gs_segments(p->m) * kk * 8.0 : kk * 8.0);
+        });
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        if (parts & GS_DOTS) {
+            Prof pr(&B, LP_K_GS_DOTS, it, dots_b());
+            b_gs_dots(L, pass);
+        }
+        if (parts & GS_UPDATES) {
+            if (!L.gs_fused) b_gs_reduce(L, pass);
+            Prof pr(&B, LP_K_GS_UPDATE, it, upd_b());
+            b_gs_update(L, pass);
+        }
+    }
+    if (parts & GS_FINISH) b_gs_finish(L);
+}
+
 // one CGNE or MRNE iteration (Sec. 3.3): a preconditioner application (multipliers into
 // column 0 of P), its product with A_hat^T in FP64, one product with A_hat, and the
 // vector kernels
@@ -492,37 +529,7 @@ static void enqueue_iteration(Batch& B, int64_t it) {
     enqueue_precond(B, it, true);
     enqueue_products(B, it);
     // CGS2 + Givens; the host iteration index equals the device one while the solve runs
-    const double kk = (double)(it + 1);
-    auto gsb = [&](double per_m, double per_part) {
-        return over_members(B, [&](const lp_problem* p) { return kk * p->m * 8.0 + per_m * p->m + per_part * p->nchunks * kk * 8.0; });
-    };
-    {
-        Prof pr(&B, LP_K_GS_DOTS, it, gsb(8.0, 1.0));
-        b_gs_dots(L);
-    }
-    if (L.gs_fused) {
-        // each update block reduces the previous pass's partials itself (few chunks)
-        {
-            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 2.0));
-            b_gs_update(L, 0);
-        }
-        {
-            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 1.0));
-            b_gs_update(L, 1);
-        }
-    } else {
-        b_gs_reduce(L, 0);
-        {
-            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 1.0));
-            b_gs_update(L, 0);
-        }
-        b_gs_reduce(L, 1);
-        {
-            Prof pr(&B, LP_K_GS_UPDATE, it, gsb(16.0, 0.0));
-            b_gs_update(L, 1);
-        }
-    }
-    b_gs_finish(L);
+    enqueue_gs(B, it, GS_DOTS | GS_UPDATES | GS_FINISH);
 }
 
 // capture `iters` Krylov iterations for the current membership; every kernel argument is
@@ -886,16 +893,20 @@ lp_status Engine::round() {
     // as soon as its own solve ends, so no LP waits for a slower one.  Measured on 64
     // transportation LPs (lockstep faster) and on 64 random sparse LPs of one shape whose
     // solve lengths differ (advancing alone faster).
-    int iterating = 0;
+    // The options' schedule overrides the rule (2 over 1 over 0).
+    int iterating = 0, sched = 0;
     bool uniform = true;
     const lp_problem* ref = nullptr;
     for (int s = 0; s < b.cap; ++s) {
         const Member& mb = mem[s];
         if (mb.state == EMPTY || mb.state == DONE) continue;
         if (mb.state == KRY1 || mb.state == KRY2) ++iterating;
+        sched = std::max(sched, (int)mb.p->opt.schedule);
         if (!ref) ref = mb.p;
         else if (mb.p->m != ref->m || mb.p->n != ref->n || mb.p->nnz != ref->nnz) uniform = false;
     }
+    if (sched == 1) uniform = true;
+    if (sched == 2) uniform = false;
     const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
     bool has[SH2 + 1] = {false};
     int live = 0, solving = 0, waiting = 0;
@@ -1211,10 +1222,13 @@ lp_problem::~lp_problem() {
 static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per_launch,
                              double* bytes_per_launch, double* flops_per_launch, int32_t* launches_per_group) {
     if (reps < 1 || !us_per_launch) return LP_EINVAL;
-    if (cls != LP_K_SWEEP && cls != LP_K_SPMV_CSR && cls != LP_K_SPMV_CSC && cls != LP_K_GRAM) {
-        set_error("timing replay covers the sweep, the two sparse products and the Gram build");
+    if (cls != LP_K_SWEEP && cls != LP_K_SPMV_CSR && cls != LP_K_SPMV_CSC && cls != LP_K_GRAM &&
+        cls != LP_K_GS_DOTS && cls != LP_K_GS_UPDATE) {
+        set_error("timing replay covers the sweep, the sparse products, Gram-Schmidt and the Gram build");
         return LP_EINVAL;
     }
+    const bool gs = cls == LP_K_GS_DOTS || cls == LP_K_GS_UPDATE;
+    int64_t kg = 127;   // Gram-Schmidt classes: basis of kg + 1 vectors
     for (int s = 0; s < B.cap; ++s) {
         lp_problem* p = B.mem[s];
         if (!p) continue;
@@ -1226,7 +1240,13 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
             set_error("no dense Gram path for this problem");
             return LP_EINVAL;
         }
+        if (gs && p->opt.krylov != LP_ABGMRES) {
+            set_error("CGNE and MRNE keep no Krylov basis");
+            return LP_EINVAL;
+        }
+        kg = std::min<int64_t>(kg, p->kmax - 1);
     }
+    kg = std::max<int64_t>(kg, 0);
     if (B.dirty) {
         lp_status rc = B.refresh();
         if (rc != LP_OK) return rc;
@@ -1238,6 +1258,7 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
             t.done = 0;
             t.active = 1;
             t.kmax = 1;
+            t.k = gs ? (int32_t)kg : 0;
             t.inv_h = 1.0;
             t.omega_c = B.mem[s]->omega_c;
         }
@@ -1261,6 +1282,8 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
     if (e == hipSuccess) {
         if (cls == LP_K_SWEEP) {
             enqueue_precond(B, -1, false);
+        } else if (gs) {
+            enqueue_gs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
         } else if (cls == LP_K_SPMV_CSC) {
             if (B.L.inner != 3) {
                 Prof pr(&B, LP_K_SPMV_CSC, -1, over_members(B, csc_bytes));

@@ -89,7 +89,7 @@ struct Inst {
     int32_t zcover;                       // 1: the rows of colour 0 cover every column
     int32_t lds;                          // whole NE-SOR application in one block: 1 z in LDS,
                                           // 2 z, the row data, v_k and p_k in LDS
-    int32_t pad1;
+    int32_t nseg;                         // Gram-Schmidt dot segments of 1024 rows
     int64_t ldv, ldh, ldp, kmax;
     const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
     const int32_t *cstart, *cg;           // colour row ranges (ncol+1), lanes per row by colour
@@ -119,7 +119,8 @@ struct BLaunch {
     int64_t max_ldp;        // largest kmax + 1
     int grid_spmv[4];       // blocks of the row-dot products over each matrix
     int gs_rpl, gs_nchunks; // largest rows per lane (template bound) and chunk count
-    bool gs_fused;
+    int gs_dots_grid;       // blocks per instance of the Gram-Schmidt dot launches
+    bool gs_fused;          // every update block sums the dot partials itself
     int mixed;              // FP32 inner iterations
     int inner;              // lp_inner of every instance (NE-SOR, Cimmino, NE-SSOR) or 3: dense SOR
     int ell;                // inner sweeps per preconditioner application
@@ -167,9 +168,10 @@ void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir);
 void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged);
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
-void b_gs_dots(const BLaunch& L);
-void b_gs_reduce(const BLaunch& L, int accumulate);
-void b_gs_update(const BLaunch& L, int mode);
+// classical Gram-Schmidt, pass 0 and 1: dot partials, (reduce,) update u -= V h
+void b_gs_dots(const BLaunch& L, int pass);
+void b_gs_reduce(const BLaunch& L, int pass);
+void b_gs_update(const BLaunch& L, int pass);
 void b_gs_finish(const BLaunch& L);
 void b_apply_c(const BLaunch& L);       // dense: P[:,k] = C v_k
 

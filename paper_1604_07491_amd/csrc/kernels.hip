@@ -618,47 +618,102 @@ void b_gemv_col(const BLaunch& L) {
 }
 
 // ------------------------------------------------------------------------------------
-// Classical Gram-Schmidt applied twice on V (m x (k+1), column-major).  A block owns a
-// chunk of 64*RPL rows of one instance; its waves split the basis columns.
+// Classical Gram-Schmidt applied twice on V (m x (k+1), column-major), in two kinds of
+// launch per pass:
+//  * dots: the dot products of u with the columns of V.  One wave computes the dot of a
+//    whole segment of GS_SEG rows of one column (16 rows per lane, four independent
+//    accumulators, one wave reduction) and writes it to part[segment][j]; with m <=
+//    GS_SEG a dot is complete in one wave.  The waves of an instance loop over its
+//    (column, segment) tasks.
+//  * update: u -= V h by row chunks of 64 * RPL rows, the waves of a block splitting the
+//    columns and adding their partial sums in LDS.  Fused: every block first sums the
+//    segment partials of h itself (few segments, k + 1 <= GS_HLDS) and block 0 stores
+//    (pass 0) or adds (pass 1) h in column k of H; otherwise k_gs_reduce does that first
+//    and the update reads h from h2.  Pass 1 also writes the chunk's partial of ||u||^2.
+// Buffers: pass 0 dots -> gpart, pass 1 dots -> gpart2, pass 1 norm partials -> gpart.
 constexpr int GS_WAVES = 8;
-constexpr int GS_HLDS = 2048;   // coefficients staged in LDS by the fused reduction
+constexpr int GS_HLDS = 2048;   // coefficients staged in LDS by the fused update
+constexpr int GS_SEG = 1024;    // rows of one dot task
+constexpr int GS_DOT_WAVES = 4; // waves per block of the dot launches (small blocks: the
+                                // blocks beyond an instance's tasks cost less)
 
-template <int RPL>
-__global__ __launch_bounds__(64 * GS_WAVES) void k_gs_dots(const Inst* __restrict__ I) {
+__global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_gs_dots(const Inst* __restrict__ I, int pass) {
     INST;
-    if (in.ctl->done || bx >= in.nchunks) return;
+    if (in.ctl->done) return;
     const int k = in.ctl->k;
-    const int rpl = in.rpl;   // <= RPL
+    const int nseg = in.nseg;
     const int64_t m = in.m;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)bx * 64 * rpl;
+    const int64_t tasks = (int64_t)nseg * (k + 1);
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * GS_DOT_WAVES;
     const double* __restrict__ u = in.vec[V_U];
-    double uu[RPL];
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-        const int64_t i = base + lane + 64 * t;
-        uu[t] = (t < rpl && i < m) ? u[i] : 0.0;
-    }
-    for (int j = w; j <= k; j += GS_WAVES) {
+    double* __restrict__ out = pass ? in.gpart2 : in.gpart;
+    for (int64_t t = (int64_t)bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
+        const int j = (int)(t / nseg);
+        const int sg = (int)(t - (int64_t)j * nseg);
+        const int64_t r0 = (int64_t)sg * GS_SEG;
+        const int64_t r1 = r0 + GS_SEG < m ? r0 + GS_SEG : m;
         const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int64_t i = base + lane + 64 * t;
-            if (t < rpl && i < m) acc += vj[i] * uu[t];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t i = r0 + lane;
+        for (; i + 192 < r1; i += 256) {
+            a0 += vj[i] * u[i];
+            a1 += vj[i + 64] * u[i + 64];
+            a2 += vj[i + 128] * u[i + 128];
+            a3 += vj[i + 192] * u[i + 192];
         }
-        acc = wave_sum(acc);
-        if (lane == 0) in.gpart[(int64_t)bx * in.ldp + j] = acc;
+        for (; i < r1; i += 64) a0 += vj[i] * u[i];
+        const double a = wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0) out[(int64_t)sg * in.ldp + j] = a;
     }
 }
 
-// u -= V h.  fused: every block first sums the previous pass's partials itself (pin, few
-// chunks; block 0 writes column k of H: mode 0 stores, mode 1 adds).  Then mode 0 forms
-// the next pass's dot partials of the updated u, mode 1 the partials of ||u||^2.
+// acc[t] += sum over the wave's columns j (w, w + GS_WAVES, ... <= k, increasing) of
+// V[i_t, j] h[j].  GS_U columns are loaded before any is used, so a wave keeps
+// GS_U * RPL loads in flight; the order of every sum is that of the plain loop.
 template <int RPL>
-__global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restrict__ I, int mode, int fused) {
+constexpr int gs_unroll() { return RPL >= 8 ? 1 : 8 / RPL; }
+
+template <int RPL>
+__device__ __forceinline__ void chunk_axpy(const Inst& in, int k, int w, int lane, int64_t base, int rpl,
+                                           const double* h, double (&acc)[RPL]) {
+    constexpr int U = gs_unroll<RPL>();
+    const int64_t m = in.m;
+    int j = w;
+    for (; j + (U - 1) * GS_WAVES <= k; j += U * GS_WAVES) {
+        double v[U][RPL], hq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            hq[q] = h[j + q * GS_WAVES];
+            const double* __restrict__ vj = in.V + (int64_t)(j + q * GS_WAVES) * in.ldv;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int64_t i = base + lane + 64 * t;
+                v[q][t] = (t < rpl && i < m) ? vj[i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int64_t i = base + lane + 64 * t;
+                if (t < rpl && i < m) acc[t] += v[q][t] * hq[q];
+            }
+    }
+    for (; j <= k; j += GS_WAVES) {
+        const double hj = h[j];
+        const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int64_t i = base + lane + 64 * t;
+            if (t < rpl && i < m) acc[t] += vj[i] * hj;
+        }
+    }
+}
+
+template <int RPL>
+__global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restrict__ I, int pass, int fused) {
     __shared__ double red[GS_WAVES][64 * RPL];
-    __shared__ double unew[64 * RPL];
     __shared__ double sh[GS_WAVES];
     __shared__ double hl[GS_HLDS];
     INST;
@@ -670,16 +725,15 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
     const int64_t base = (int64_t)bx * 64 * rpl;
     double* __restrict__ u = in.vec[V_U];
     const double* h = in.h2;
-    double* pout = (fused && mode == 0) ? in.gpart2 : in.gpart;
     if (fused) {
-        const double* __restrict__ pin = mode == 0 ? in.gpart : in.gpart2;
+        const double* __restrict__ pin = pass == 0 ? in.gpart : in.gpart2;
         for (int j = threadIdx.x; j <= k; j += blockDim.x) {
             double sj = 0.0;
-            for (int c = 0; c < in.nchunks; ++c) sj += pin[(int64_t)c * in.ldp + j];
+            for (int c = 0; c < in.nseg; ++c) sj += pin[(int64_t)c * in.ldp + j];
             hl[j] = sj;
             if (bx == 0) {
                 double* hk = in.H + (int64_t)k * in.ldh;
-                if (mode == 0) hk[j] = sj;
+                if (pass == 0) hk[j] = sj;
                 else hk[j] += sj;
             }
         }
@@ -689,52 +743,26 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
     double acc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) acc[t] = 0.0;
-    for (int j = w; j <= k; j += GS_WAVES) {
-        const double hj = h[j];
-        const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int64_t i = base + lane + 64 * t;
-            if (t < rpl && i < m) acc[t] += vj[i] * hj;
-        }
-    }
+    chunk_axpy<RPL>(in, k, w, lane, base, rpl, h, acc);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = acc[t];
     __syncthreads();
+    double q = 0.0;
     if (threadIdx.x < 64 * rpl) {
         const int r = threadIdx.x;
         const int64_t i = base + r;
         double s = 0.0;
         for (int ww = 0; ww < GS_WAVES; ++ww) s += red[ww][r];
-        double un = 0.0;
         if (i < m) {
-            un = u[i] - s;
+            const double un = u[i] - s;
             u[i] = un;
+            q = un * un;
         }
-        unew[r] = un;
     }
-    if (threadIdx.x >= 64 * rpl && threadIdx.x < 64 * RPL) unew[threadIdx.x] = 0.0;
-    __syncthreads();
-    if (mode == 0) {
-        double uu[RPL];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) uu[t] = unew[lane + 64 * t];
-        for (int j = w; j <= k; j += GS_WAVES) {
-            const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
-            double a = 0.0;
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-                const int64_t i = base + lane + 64 * t;
-                if (t < rpl && i < m) a += vj[i] * uu[t];
-            }
-            a = wave_sum(a);
-            if (lane == 0) pout[(int64_t)bx * in.ldp + j] = a;
-        }
-    } else {
-        double q = 0.0;
-        if (threadIdx.x < 64 * rpl) q = unew[threadIdx.x] * unew[threadIdx.x];
+    if (pass == 1) {
+        // every block reaches this barrier-bearing sum (no early exit above)
         const double r = block_sum(q, sh);
-        if (threadIdx.x == 0) pout[bx] = r;
+        if (threadIdx.x == 0) in.gpart[bx] = r;
     }
 }
 
@@ -746,37 +774,36 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
         default: MACRO(8); break;     \
     }
 
-void b_gs_dots(const BLaunch& L) {
-#define LPK_GD(R) hipLaunchKernelGGL((k_gs_dots<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I)
-    LPK_SWITCH_RPL(LPK_GD)
-#undef LPK_GD
+void b_gs_dots(const BLaunch& L, int pass) {
+    hipLaunchKernelGGL(k_gs_dots, dim3(L.gs_dots_grid, L.S), dim3(64 * GS_DOT_WAVES), 0, L.st, L.I, pass);
 }
 
-void b_gs_update(const BLaunch& L, int mode) {
+void b_gs_update(const BLaunch& L, int pass) {
     const int fused = L.gs_fused ? 1 : 0;
-#define LPK_GU(R) hipLaunchKernelGGL((k_gs_update<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I, mode, fused)
+#define LPK_GU(R) hipLaunchKernelGGL((k_gs_update<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I, pass, fused)
     LPK_SWITCH_RPL(LPK_GU)
 #undef LPK_GU
 }
 
-// h[j] = sum over chunks of part[c, j] (fixed order); pass 1 stores column k of H and h2,
-// pass 2 stores h2 and adds it to column k of H
-__global__ __launch_bounds__(BLOCK) void k_gs_reduce(const Inst* __restrict__ I, int accumulate) {
+// h[j] = sum over the segments of the pass's partials (fixed order) into h2; pass 0
+// stores column k of H, pass 1 adds to it
+__global__ __launch_bounds__(BLOCK) void k_gs_reduce(const Inst* __restrict__ I, int pass) {
     INST;
     if (in.ctl->done) return;
     const int k = in.ctl->k;
     const int j = bx * BLOCK + threadIdx.x;
     if (j > k) return;
+    const double* __restrict__ pin = pass == 0 ? in.gpart : in.gpart2;
     double s = 0.0;
-    for (int c = 0; c < in.nchunks; ++c) s += in.gpart[(int64_t)c * in.ldp + j];
+    for (int c = 0; c < in.nseg; ++c) s += pin[(int64_t)c * in.ldp + j];
     in.h2[j] = s;
     double* hk = in.H + (int64_t)k * in.ldh;
-    if (accumulate) hk[j] += s;
+    if (pass) hk[j] += s;
     else hk[j] = s;
 }
 
-void b_gs_reduce(const BLaunch& L, int accumulate) {
-    hipLaunchKernelGGL(k_gs_reduce, dim3(cdiv(L.max_ldp, BLOCK), L.S), dim3(BLOCK), 0, L.st, L.I, accumulate);
+void b_gs_reduce(const BLaunch& L, int pass) {
+    hipLaunchKernelGGL(k_gs_reduce, dim3(cdiv(L.max_ldp, BLOCK), L.S), dim3(BLOCK), 0, L.st, L.I, pass);
 }
 
 // ||u||^2 from the chunk partials, h_{k+1,k} = ||u||, the earlier Givens rotations on

@@ -37,8 +37,10 @@ lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, 
 int lanes_for(double len);
 // Gram-Schmidt rows per lane for m rows (chunks of 64 rpl rows, at most 1024 chunks)
 int gs_rpl_for(int64_t m);
-// the fused Gram-Schmidt passes need few chunks and the coefficients in LDS
-bool gs_fusable(int64_t nchunks, int64_t kmax);
+// Gram-Schmidt dot segments (1024 rows each) of an m-row basis
+int gs_segments(int64_t m);
+// the fused Gram-Schmidt updates need few dot segments and the coefficients in LDS
+bool gs_fusable(int64_t m, int64_t kmax);
 
 // owned device allocations of one problem
 struct DevArena {
@@ -134,8 +136,8 @@ struct lp_problem {
     int64_t kmax = 0, ldv = 0, ldh = 0;
     double *V = nullptr, *P = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gam = nullptr;
     double *ykr = nullptr, *h2 = nullptr;
-    double* gpart = nullptr;                        // (nchunks) x (kmax+1) CGS partials
-    double* gpart2 = nullptr;                       // second buffer for the fused passes
+    double* gpart = nullptr;                        // CGS pass-0 dot partials (segments x (kmax+1)), norm partials
+    double* gpart2 = nullptr;                       // CGS pass-1 dot partials
     double norm_b = 0.0, norm_c = 0.0;
     // interior-point state
     bool have_point = false;
