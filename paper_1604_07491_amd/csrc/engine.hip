@@ -44,7 +44,7 @@ bool gs_fusable(int64_t m, int64_t kmax) { return gs_segments(m) <= 4 && kmax + 
 static inline int cdiv_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 bool batch_compatible(const lp_problem* a, const lp_problem* b) {
-    return a->opt.precision == b->opt.precision && a->opt.inner == b->opt.inner &&
+    return a->mixed == b->mixed && a->opt.inner == b->opt.inner &&
            a->opt.krylov == b->opt.krylov &&
            a->gsor == b->gsor && a->opt.inner_sweeps == b->opt.inner_sweeps && a->device == b->device;
 }
@@ -118,7 +118,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.mode = &B.d_param[slot].mode;
     const lp_problem* p = B.mem[slot];
     if (!p) return in;
-    const bool mixed = p->opt.precision == LP_MIXED;
+    const bool mixed = p->mixed;
     in.m = (int32_t)p->m;
     in.n = (int32_t)p->n;
     in.nnz = (int32_t)p->nnz;
@@ -217,7 +217,7 @@ lp_status Batch::refresh() {
         if (!p) continue;
         const Inst& in = h_inst[s];
         if (first) {
-            L.mixed = p->opt.precision == LP_MIXED;
+            L.mixed = p->mixed;
             L.inner = p->gsor ? 3 : p->opt.inner;
             L.ell = std::max(1, (int)p->opt.inner_sweeps);
             L.krylov = p->opt.krylov;
@@ -660,7 +660,7 @@ lp_status build_dense_preconditioner(Batch& B, lp_problem* p) {
     hipStream_t st = B.L.st;
     const int m = (int)p->m;
     const int64_t mm = (int64_t)m * m;
-    const bool mixed = p->opt.precision == LP_MIXED;
+    const bool mixed = p->mixed;
     const double om = p->opt.omega;
     const int ell = std::max(1, (int)p->opt.inner_sweeps);
     const double nbt = (double)((m + 63) / 64);

@@ -669,14 +669,15 @@ __global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_gs_dots(const Inst* __res
 }
 
 // acc[t] += sum over the wave's columns j (w, w + GS_WAVES, ... <= k, increasing) of
-// V[i_t, j] h[j].  GS_U columns are loaded before any is used, so a wave keeps
-// GS_U * RPL loads in flight; the order of every sum is that of the plain loop.
+// M[i_t, j] h[j], M column-major with the basis stride (V or P).  GS_U columns are loaded
+// before any is used, so a wave keeps GS_U * RPL loads in flight; the order of every sum
+// is that of the plain loop.
 template <int RPL>
 constexpr int gs_unroll() { return RPL >= 8 ? 1 : 8 / RPL; }
 
 template <int RPL>
-__device__ __forceinline__ void chunk_axpy(const Inst& in, int k, int w, int lane, int64_t base, int rpl,
-                                           const double* h, double (&acc)[RPL]) {
+__device__ __forceinline__ void chunk_axpy(const Inst& in, const double* __restrict__ M, int k, int w, int lane,
+                                           int64_t base, int rpl, const double* h, double (&acc)[RPL]) {
     constexpr int U = gs_unroll<RPL>();
     const int64_t m = in.m;
     int j = w;
@@ -685,7 +686,7 @@ __device__ __forceinline__ void chunk_axpy(const Inst& in, int k, int w, int lan
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             hq[q] = h[j + q * GS_WAVES];
-            const double* __restrict__ vj = in.V + (int64_t)(j + q * GS_WAVES) * in.ldv;
+            const double* __restrict__ vj = M + (int64_t)(j + q * GS_WAVES) * in.ldv;
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
                 const int64_t i = base + lane + 64 * t;
@@ -702,7 +703,7 @@ __device__ __forceinline__ void chunk_axpy(const Inst& in, int k, int w, int lan
     }
     for (; j <= k; j += GS_WAVES) {
         const double hj = h[j];
-        const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
+        const double* __restrict__ vj = M + (int64_t)j * in.ldv;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int64_t i = base + lane + 64 * t;
@@ -743,7 +744,7 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
     double acc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) acc[t] = 0.0;
-    chunk_axpy<RPL>(in, k, w, lane, base, rpl, h, acc);
+    chunk_axpy<RPL>(in, in.V, k, w, lane, base, rpl, h, acc);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = acc[t];
     __syncthreads();
@@ -939,41 +940,113 @@ void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap) {
     hipLaunchKernelGGL(k_init_ctl, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask, kcap);
 }
 
-// R y = gamma(1:iters), R the upper triangle of the rotated Hessenberg matrix
-__global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I, int pmask) {
+// R y = gamma(1:iters), R the upper triangle of the rotated Hessenberg matrix, by
+// columns from the last: y_i = g_i / R_ii, then g_t -= R_ti y_i for t < i.  One wave per
+// instance.  Up to BS_REG iterations, lane l keeps g_t for t = l + 64 r in registers and
+// the next column of R is loaded while the current one is applied, so a step waits on
+// no memory; y_i reaches every lane by a shuffle from its owner.  Longer solves take the
+// same steps with g in memory.  Either way every entry sees the same operations in the
+// same order.
+constexpr int BS_NR = 16;
+constexpr int BS_REG = 64 * BS_NR;
+
+__global__ __launch_bounds__(64) void k_backsolve(const Inst* __restrict__ I, int pmask) {
     INST;
     if (!takes_part(in, pmask)) return;
     const int it = in.ctl->iters;
+    const int lane = threadIdx.x;
     double* __restrict__ y = in.ykr;
-    for (int i = threadIdx.x; i < it; i += BLOCK) y[i] = in.gam[i];
-    __syncthreads();
+    if (it > BS_REG) {
+        for (int i = lane; i < it; i += 64) y[i] = in.gam[i];
+        __syncthreads();
+        for (int i = it - 1; i >= 0; --i) {
+            const double yi = y[i] / in.H[(int64_t)i * in.ldh + i];
+            __syncthreads();
+            if (lane == 0) y[i] = yi;
+            for (int t = lane; t < i; t += 64) y[t] -= in.H[(int64_t)i * in.ldh + t] * yi;
+            __syncthreads();
+        }
+        return;
+    }
+    double g[BS_NR], c[BS_NR], cn[BS_NR];
+#pragma unroll
+    for (int r = 0; r < BS_NR; ++r) {
+        const int t = lane + 64 * r;
+        g[r] = t < it ? in.gam[t] : 0.0;
+    }
+    // column i of R above the diagonal (rows t < i), and its diagonal
+    auto load_col = [&](int i, double (&col)[BS_NR], double& dg) {
+        const double* __restrict__ hc = in.H + (int64_t)i * in.ldh;
+#pragma unroll
+        for (int r = 0; r < BS_NR; ++r) {
+            const int t = lane + 64 * r;
+            col[r] = t < i ? hc[t] : 0.0;
+        }
+        dg = hc[i];
+    };
+    double dg = 1.0, dgn = 1.0;
+    if (it > 0) load_col(it - 1, c, dg);
     for (int i = it - 1; i >= 0; --i) {
-        const double yi = y[i] / in.H[(int64_t)i * in.ldh + i];
-        __syncthreads();
-        if (threadIdx.x == 0) y[i] = yi;
-        for (int t = threadIdx.x; t < i; t += BLOCK) y[t] -= in.H[(int64_t)i * in.ldh + t] * yi;
-        __syncthreads();
+        if (i > 0) load_col(i - 1, cn, dgn);
+        // g_i from its owner lane
+        const int ri = i >> 6;
+        double gi = 0.0;
+#pragma unroll
+        for (int r = 0; r < BS_NR; ++r)
+            if (r == ri) gi = g[r];
+        gi = __shfl(gi, i & 63, 64);
+        const double yi = gi / dg;
+#pragma unroll
+        for (int r = 0; r < BS_NR; ++r) {
+            const int t = lane + 64 * r;
+            if (t == i) g[r] = yi;
+            else if (t < i) g[r] -= c[r] * yi;
+        }
+#pragma unroll
+        for (int r = 0; r < BS_NR; ++r) c[r] = cn[r];
+        dg = dgn;
+    }
+#pragma unroll
+    for (int r = 0; r < BS_NR; ++r) {
+        const int t = lane + 64 * r;
+        if (t < it) y[t] = g[r];
     }
 }
 
 void b_backsolve(const BLaunch& L, int pmask) {
-    hipLaunchKernelGGL(k_backsolve, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
+    hipLaunchKernelGGL(k_backsolve, dim3(1, L.S), dim3(64), 0, L.st, L.I, pmask);
 }
 
-// dyh = P[:, 0:iters] y  (flexible final step: dw = A_hat^T dyh)
-__global__ __launch_bounds__(BLOCK) void k_combine(const Inst* __restrict__ I, int pmask) {
+// dyh = P[:, 0:iters] y  (flexible final step: dw = A_hat^T dyh), by row chunks of
+// 64 * RPL rows with the waves of a block splitting the columns, as the Gram-Schmidt update
+template <int RPL>
+__global__ __launch_bounds__(64 * GS_WAVES) void k_combine(const Inst* __restrict__ I, int pmask) {
+    __shared__ double red[GS_WAVES][64 * RPL];
     INST;
-    if (!takes_part(in, pmask)) return;
+    if (!takes_part(in, pmask) || bx >= in.nchunks) return;
     const int it = in.ctl->iters;
-    const int64_t i = (int64_t)bx * BLOCK + threadIdx.x;
-    if (i >= in.m) return;
-    double s = 0.0;
-    for (int j = 0; j < it; ++j) s += in.P[(int64_t)j * in.ldv + i] * in.ykr[j];
-    in.vec[V_DYH][i] = s;
+    const int rpl = in.rpl;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)bx * 64 * rpl;
+    double acc[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) acc[t] = 0.0;
+    chunk_axpy<RPL>(in, in.P, it - 1, w, lane, base, rpl, in.ykr, acc);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = acc[t];
+    __syncthreads();
+    if (threadIdx.x < 64 * rpl) {
+        const int64_t i = base + threadIdx.x;
+        double s = 0.0;
+        for (int ww = 0; ww < GS_WAVES; ++ww) s += red[ww][threadIdx.x];
+        if (i < in.m) in.vec[V_DYH][i] = s;
+    }
 }
 
 void b_combine(const BLaunch& L, int pmask) {
-    hipLaunchKernelGGL(k_combine, dim3(cdiv(L.max_m, BLOCK), L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
+#define LPK_CB(R) hipLaunchKernelGGL((k_combine<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I, pmask)
+    LPK_SWITCH_RPL(LPK_CB)
+#undef LPK_CB
 }
 
 __global__ __launch_bounds__(BLOCK) void k_true_res(const Inst* __restrict__ I, int pmask) {

@@ -120,3 +120,11 @@ def test_unknown_krylov_method_is_rejected_on_the_host():
     # MRNE's recurrence needs FP64 sweeps
     assert _try_create(*args, krylov=lpk.LP_MRNE, precision=lpk.LP_MIXED)[0] == lpk.LP_EINVAL
     assert _try_create(*args, inner=9)[0] == lpk.LP_EINVAL
+
+
+def test_mixed_precision_allocates_fp32_copies_only_where_sweeps_stream():
+    """FP32 copies of A_hat exist only when z does not fit in LDS (n * 8 > 48 KiB)."""
+    small = (200, 500, 3000)
+    assert lpk.lp_footprint_bytes(*small, lpk.options(precision="mixed")) == lpk.lp_footprint_bytes(*small)
+    big = (600, 90000, 180000)
+    assert lpk.lp_footprint_bytes(*big, lpk.options(precision="mixed")) > lpk.lp_footprint_bytes(*big)

@@ -227,3 +227,16 @@ def test_config2_basis_pursuit_full_size(precision):
     N = lp.meta["N"]
     xr = np.asarray(x)[:N] - np.asarray(x)[N:]
     assert np.abs(xr - lp.meta["x_true"]).max() < 1e-5
+
+
+def test_mixed_small_lp_sweeps_in_fp64():
+    """LP_MIXED keeps the NE-SOR sweeps of an LP whose FP64 z fits in LDS in FP64: such an
+    LP computes exactly as with LP_FP64."""
+    lp = synth.config(0)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        with lpk.from_lp(lp, lpk.options(precision=prec)) as p:
+            r = lpk.lp_solve(p)
+            out[prec] = (r, lpk.lp_get_state(p)[0])
+    assert out["mixed"][0]["krylov_iters"] == out["fp64"][0]["krylov_iters"]
+    assert np.array_equal(out["mixed"][1], out["fp64"][1])
