@@ -30,8 +30,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def kernels_digest():
+    """sha256 of the sweep kernels' source, which the committed counter runs were taken on."""
     import hashlib
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", "sweep.hip"), "rb").read()).hexdigest()
 
 
 def counter_traffic(args, kernel, width):
