@@ -52,17 +52,17 @@ struct Sizes {
     }
 };
 
-bool fp32_sweeps(const lp_options& o, int64_t n, bool gsor) {
+bool fp32_sweeps(const lp_options& o, int64_t n, int64_t ncol, bool gsor) {
     if (o.precision != LP_MIXED) return false;
     // NE-SOR / NE-SSOR sweeps whose FP64 z fits in LDS stream nothing from HBM: FP32
     // would save no bandwidth there, and FP64 sweeps leave z_k = A_hat^T p_k for free
     const bool sor = o.inner == LP_NESOR || o.inner == LP_NESSOR;
-    return gsor || !sor || n * 8 > LDS_Z_MAX;
+    return gsor || !sor || lds_z_bytes(n, ncol, 8) > LDS_Z_MAX;
 }
 
 uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
-    const bool mixed = fp32_sweeps(o, n, false);
+    const bool mixed = fp32_sweeps(o, n, 1, false);
     const int64_t kmax = plan_kmax(m, o);
     const int64_t cols = basis_cols(kmax, o);
     const bool cg = o.krylov != LP_ABGMRES;
@@ -209,7 +209,6 @@ static void destroy(lp_problem* p) {
 static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, const double* val,
                        const double* b, const double* c) {
     const int64_t m = p->m, n = p->n, nnz = p->nnz;
-    const bool mixed = p->mixed = fp32_sweeps(p->opt, n, p->gsor);
     // colouring and the permuted CSR (a dense A is a complete conflict graph: colour =
     // row, the natural order)
     std::vector<int32_t> colour((size_t)m);
@@ -221,6 +220,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     } else {
         ncol = greedy_colour(m, n, rp, ci, colour.data(), p->perm.data());
     }
+    const bool mixed = p->mixed = fp32_sweeps(p->opt, n, ncol, p->gsor);
     std::vector<int32_t> prp((size_t)m + 1), pci((size_t)nnz);
     std::vector<double> pa((size_t)nnz), pb((size_t)m);
     prp[0] = 0;

@@ -133,8 +133,8 @@ static Inst make_inst(Batch& B, int slot) {
     in.nbr = red_blocks(std::max(p->m, p->n));
     in.nbs = spmv_blocks(p->m, p->g_csr);
     in.zcover = p->zcover ? 1 : 0;
-    in.lds = (in.ncol > 0 && p->n * (mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
-    if (in.lds && lds_stage_bytes(p->m, p->n, p->nnz, mixed ? 4 : 8) <= LDS_STAGE_MAX) in.lds = 2;
+    in.lds = (in.ncol > 0 && lds_z_bytes(p->n, in.ncol, mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
+    if (in.lds && lds_stage_bytes(p->m, p->n, p->nnz, in.ncol, mixed ? 4 : 8) <= LDS_STAGE_MAX) in.lds = 2;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
     in.ldp = p->ldh;   // kmax + 1 for AB-GMRES
@@ -243,10 +243,10 @@ lp_status Batch::refresh() {
         L.max_ncol = std::max(L.max_ncol, in.ncol);
         if (in.lds == 2) {
             L.any_stage = true;
-            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, L.mixed ? 4 : 8));
+            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.ncol, L.mixed ? 4 : 8));
         } else if (in.lds) {
             L.any_lds = true;
-            L.lds_bytes = std::max(L.lds_bytes, in.n * (L.mixed ? 4 : 8));
+            L.lds_bytes = std::max<int>(L.lds_bytes, (int)lds_z_bytes(in.n, in.ncol, L.mixed ? 4 : 8));
         } else {
             L.max_ncol_global = std::max(L.max_ncol_global, in.ncol);
             L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
@@ -370,8 +370,9 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
         const int npass = ssor ? 2 * ell : ell;
         // the instances whose z fits in LDS: every pass and colour in one launch
         auto lds_kind = [&](const lp_problem* p) {
-            if (p->n * (L.mixed ? 4 : 8) > LDS_Z_MAX) return 0;
-            return lds_stage_bytes(p->m, p->n, p->nnz, L.mixed ? 4 : 8) <= LDS_STAGE_MAX ? 2 : 1;
+            const int64_t nc = (int64_t)p->colours.size();
+            if (lds_z_bytes(p->n, nc, L.mixed ? 4 : 8) > LDS_Z_MAX) return 0;
+            return lds_stage_bytes(p->m, p->n, p->nnz, nc, L.mixed ? 4 : 8) <= LDS_STAGE_MAX ? 2 : 1;
         };
         if (L.any_stage) {
             // row data read once per application

@@ -142,8 +142,10 @@ struct BLaunch {
 // and with its row data, v_k and p_k in LDS as well when all of them fit in LDS_STAGE_MAX
 constexpr int LDS_Z_MAX = 48 * 1024;
 constexpr int LDS_STAGE_MAX = 64 * 1024;
-inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int tbytes) {
-    return 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1);
+// LDS of the one-block sweep: z with the colour table, and (staged) everything
+inline int64_t lds_z_bytes(int64_t n, int64_t ncol, int tbytes) { return n * tbytes + 4 * (2 * ncol + 1); }
+inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, int tbytes) {
+    return 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1) + 4 * (2 * ncol + 1);
 }
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------

@@ -30,8 +30,8 @@ int32_t greedy_colour(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci
 // device bytes lp_create allocates for these sizes and options
 uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o);
 // the sweeps of a problem with these options run in FP32: LP_MIXED, except NE-SOR and
-// NE-SSOR sweeps whose FP64 z fits in LDS (those run in FP64)
-bool fp32_sweeps(const lp_options& o, int64_t n, bool gsor);
+// NE-SSOR sweeps whose FP64 z (with the colour table of ncol colours) fits in LDS
+bool fp32_sweeps(const lp_options& o, int64_t n, int64_t ncol, bool gsor);
 // host validation of lp_create's inputs (no device call)
 lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
                           const double* val, const double* b, const double* c);
