@@ -187,7 +187,7 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
 }
 
 static bool same_launch(const Batch& B) {
-    return same_launch(B.L, B.graph_L, B.grid_colour, B.graph_colour) && B.colour_il == B.graph_il;
+    return same_launch(B.L, B.graph_L, B.grid_colour, B.graph_colour) && B.colour_r == B.graph_r;
 }
 
 lp_status Batch::refresh() {
@@ -253,19 +253,19 @@ lp_status Batch::refresh() {
         }
     }
     grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
-    colour_il.assign((size_t)std::max(1, L.max_ncol), 0);
+    colour_r.assign((size_t)std::max(1, L.max_ncol), 8);
     for (int s = 0; s < cap; ++s) {
         const lp_problem* p = mem[s];
         if (!p || h_inst[s].ncol == 0 || h_inst[s].lds) continue;
         for (int c = 0; c < h_inst[s].ncol; ++c) {
             const Colour& cl = p->colours[c];
             const int64_t threads = cl.il ? (int64_t)cdiv_i(cl.r1 - cl.r0, cl.il) * 64 : (int64_t)(cl.r1 - cl.r0) * cl.g;
-            if (cl.il) colour_il[c] = 1;
+            colour_r[c] = std::max<char>(colour_r[c], (char)cl.R);
             grid_colour[c] = std::max(grid_colour[c], cdiv_i(threads, BLOCK_THREADS));
         }
     }
     L.grid_colour = grid_colour.data();
-    L.colour_il = colour_il.data();
+    L.colour_r = colour_r.data();
     LPK_HIP(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
     // the captured iterations read every pointer from the descriptors: they stay valid
@@ -274,7 +274,7 @@ lp_status Batch::refresh() {
         drop_graph();
         graph_L = L;
         graph_colour = grid_colour;
-        graph_il = colour_il;
+        graph_r = colour_r;
     }
     dirty = false;
     return LP_OK;

@@ -10,6 +10,38 @@
 
 namespace lpk {
 
+// The descriptors hold generic pointers; loads through them compile to flat accesses that
+// wait on both memory counters.  Kernels view their global arrays through these casts so
+// the loads are global loads and a batch of them can be in flight together.
+#define LPK_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ LPK_GLOBAL T* to_global(T* p) { return (LPK_GLOBAL T*)p; }
+
+// sum over k = s + lane, s + lane + g, ... < e of val[k] x[idx[k]], in increasing k.  The
+// elements go in chunks of U per lane: the chunk's values and indices are loaded together,
+// then its gathers of x, then the products are added (a lane past e adds zero terms).
+template <int U, typename T>
+__device__ __forceinline__ T row_dot(const LPK_GLOBAL T* __restrict__ val, const LPK_GLOBAL int32_t* __restrict__ idx,
+                                     const LPK_GLOBAL T* __restrict__ x, int s, int e, int lane, int g) {
+    T sum = 0;
+    for (int kk = s + lane; kk < e; kk += U * g) {
+        T v[U], xv[U];
+        int j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k2 = kk + u * g;
+            const bool ok = k2 < e;
+            v[u] = ok ? val[k2] : (T)0;
+            j[u] = ok ? idx[k2] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) sum += v[u] * xv[u];
+    }
+    return sum;
+}
+
 constexpr int BLOCK = 256;
 constexpr int GRID_CAP = 2048;
 

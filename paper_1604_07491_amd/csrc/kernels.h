@@ -127,7 +127,7 @@ struct BLaunch {
     int krylov;             // lp_krylov of every instance (0 AB-GMRES, 1 CGNE, 2 MRNE)
     int max_ncol;
     const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
-    const char* colour_il;  // host array [max_ncol]: some instance interleaves the colour's rows
+    const char* colour_r;   // host array [max_ncol]: row elements per lane in registers (8, 16, 32)
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
     bool any_lds;           // some instance sweeps in one block with z in LDS (lds == 1)
     int lds_bytes;          // largest z of those instances

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     } else {
         rows = in.n; g = in.g_csc; ptr = in.cp; idx = in.ri; val = mat == M_A_CSC ? in.ac : in.ahc;
     }
-    const double* __restrict__ x = xsel == V_PCOL ? in.P + (int64_t)in.ctl->k * in.ldv : in.vec[xsel];
+    const LPK_GLOBAL double* __restrict__ x = to_global(xsel == V_PCOL ? in.P + (int64_t)in.ctl->k * in.ldv : in.vec[xsel]);
     double* __restrict__ out = in.vec[outsel];
     const double* __restrict__ b1 = b1sel >= 0 ? in.vec[b1sel] : nullptr;
     const double* __restrict__ b2 = b2sel >= 0 ? in.vec[b2sel] : nullptr;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
         double sum = 0.0;
         if (row < rows) {
             const int s = ptr[row], e = ptr[row + 1];
-            for (int k = s + lane; k < e; k += g) sum += val[k] * x[idx[k]];
+            sum = row_dot<8>(to_global(val), to_global(idx), x, s, e, lane, g);
         }
         sum = sg_sum(sum, g);
         if (row < rows && lane == 0) {
@@ -250,14 +250,14 @@ __global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_gs_dots(const Inst* __res
     const int64_t tasks = (int64_t)nseg * (k + 1);
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * GS_DOT_WAVES;
-    const double* __restrict__ u = in.vec[V_U];
+    const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
     double* __restrict__ out = pass ? in.gpart2 : in.gpart;
     for (int64_t t = (int64_t)bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
         const int j = (int)(t / nseg);
         const int sg = (int)(t - (int64_t)j * nseg);
         const int64_t r0 = (int64_t)sg * GS_SEG;
         const int64_t r1 = r0 + GS_SEG < m ? r0 + GS_SEG : m;
-        const double* __restrict__ vj = in.V + (int64_t)j * in.ldv;
+        const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)j * in.ldv);
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int64_t i = r0 + lane;
         for (; i + 192 < r1; i += 256) {
@@ -290,7 +290,7 @@ __device__ __forceinline__ void chunk_axpy(const Inst& in, const double* __restr
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             hq[q] = h[j + q * GS_WAVES];
-            const double* __restrict__ vj = M + (int64_t)(j + q * GS_WAVES) * in.ldv;
+            const LPK_GLOBAL double* __restrict__ vj = to_global(M + (int64_t)(j + q * GS_WAVES) * in.ldv);
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
                 const int64_t i = base + lane + 64 * t;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void chunk_axpy(const Inst& in, const double* __restr
     }
     for (; j <= k; j += GS_WAVES) {
         const double hj = h[j];
-        const double* __restrict__ vj = M + (int64_t)j * in.ldv;
+        const LPK_GLOBAL double* __restrict__ vj = to_global(M + (int64_t)j * in.ldv);
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int64_t i = base + lane + 64 * t;
@@ -546,7 +546,7 @@ void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap) {
 
 // R y = gamma(1:iters), R the upper triangle of the rotated Hessenberg matrix, by
 // columns from the last: y_i = g_i / R_ii, then g_t -= R_ti y_i for t < i.  Up to BS_REG
-// iterations, the block stages panels of BS_PANEL doubles of R (the columns [c0, c1), rows
+// iterations, the block stages panels of BS_PANEL doubles of H (the columns [c0, c1), rows
 // up to c1) into LDS with all its threads, loads in flight together; then wave 0 applies
 // the panel's columns, lane l holding g_t for t = l + 64 r in registers and y_i reaching
 // every lane by a shuffle from its owner, so a step waits only on LDS.  Longer solves
@@ -587,10 +587,22 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I,
         if (cb > 64) cb = 64;
         const int c0 = c1 - cb > 0 ? c1 - cb : 0;
         __syncthreads();   // the previous panel is consumed
-        // panel[(j - c0) * c1 + t] = R[t, j] for t <= j < c1
-        for (int j = c0; j < c1; ++j) {
-            const double* __restrict__ hc = in.H + (int64_t)j * in.ldh;
-            for (int t = threadIdx.x; t <= j; t += BLOCK) panel[(j - c0) * c1 + t] = hc[t];
+        // panel[(j - c0) * c1 + t] = H[t, j] for t < c1, j in [c0, c1) (the rows below the
+        // diagonal come along unused); eight loads per thread in flight before any store
+        const int tot = (c1 - c0) * c1;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * BLOCK) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = e0 + q * BLOCK;
+                const int j = c0 + e / c1, t = e - (e / c1) * c1;
+                v[q] = e < tot ? in.H[(int64_t)j * in.ldh + t] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = e0 + q * BLOCK;
+                if (e < tot) panel[e] = v[q];
+            }
         }
         __syncthreads();
         if (solver) {
@@ -603,11 +615,19 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I,
                     if (r == ri) gi = g[r];
                 gi = __shfl(gi, i & 63, 64);
                 const double yi = gi / col[i];
+                // branch-free: every lane loads (rows t >= i read the diagonal, unused) and
+                // selects, so the step is one batch of LDS loads and no divergent code
+                double cv[BS_NR];
 #pragma unroll
                 for (int r = 0; r < BS_NR; ++r) {
                     const int t = lane + 64 * r;
-                    if (t == i) g[r] = yi;
-                    else if (t < i) g[r] -= col[t] * yi;
+                    cv[r] = col[t < i ? t : i];
+                }
+#pragma unroll
+                for (int r = 0; r < BS_NR; ++r) {
+                    const int t = lane + 64 * r;
+                    const double upd = g[r] - cv[r] * yi;
+                    g[r] = t == i ? yi : (t < i ? upd : g[r]);
                 }
             }
         }

@@ -75,6 +75,8 @@ struct Colour {
     int32_t r0, r1;     // rows [r0, r1) in the permuted order
     int g;              // lanes per row
     int il;             // 0: a row's lanes are consecutive; else il rows per wave, interleaved
+    int R;              // row elements per lane held in registers (8, 16 or 32)
+    int maxlen;         // longest row
     int64_t nnz;        // nonzeros of the colour
 };
 
@@ -174,10 +176,10 @@ struct Batch {
     double* d_part = nullptr;         // cap x RED_NQ x RED_MAXBLK
     BLaunch L{};
     std::vector<int> grid_colour;
-    std::vector<char> colour_il;
+    std::vector<char> colour_r;       // registers per lane of each colour launch (max over members)
     BLaunch graph_L{};                // the launch shapes the graph was captured with
     std::vector<int> graph_colour;
-    std::vector<char> graph_il;
+    std::vector<char> graph_r;
     bool dirty = true;                // membership changed since the descriptors were uploaded
     bool param_inflight = false;      // a parameter upload may still be in flight
     // captured Krylov iterations

@@ -34,7 +34,10 @@ void b_prep(const BLaunch& L) {
 // row i of the colour, in parallel, computes d = omega (v_i - a_i . z), adds d to p_i and
 // d a_i to z.  Rows of one colour share no column, so the z updates are disjoint.  The
 // row segment (values, column indices) is held in registers between the dot product and
-// the update, so each nonzero is read from memory once per sweep.  In FP64 (keepz) the
+// the update, so each nonzero is read from memory once per sweep.  The loads go in three
+// batches, each in flight together: the row's values and indices, then the gathers of z,
+// then (after the sum) the stores of z; a lane past the row's end loads nothing and adds
+// a zero term.  In FP64 (keepz) the
 // last colour still updates z, which then holds z_k = A_hat^T p_k for the product that
 // follows; in FP32 it skips the update and z_k is recomputed in FP64 from p.
 //
@@ -74,45 +77,43 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
     const int64_t k = in.ctl->k;
-    double* __restrict__ vk = in.V + k * in.ldv;
-    double* __restrict__ p = in.P + k * in.ldv;
+    LPK_GLOBAL double* __restrict__ vk = to_global(in.V + k * in.ldv);
+    LPK_GLOBAL double* __restrict__ p = to_global(in.P + k * in.ldv);
+    const LPK_GLOBAL int32_t* __restrict__ rp = to_global(in.rp);
+    const int s = rp[row], e = rp[row + 1];
     // first sweep: v_k = u / h_{k,k-1} is formed here and stored; p_k starts from delta
-    const double vrow = sw == 0 ? in.vec[V_U][row] * in.ctl->inv_h : vk[row];
-    const T* __restrict__ val;
-    T* __restrict__ z;
+    const double vrow = sw == 0 ? to_global(in.vec[V_U])[row] * in.ctl->inv_h : vk[row];
+    const LPK_GLOBAL T* __restrict__ val;
+    LPK_GLOBAL T* __restrict__ z;
     if constexpr (sizeof(T) == 4) {
-        val = (const T*)in.ah32;
-        z = (T*)in.z32;
+        val = to_global((const T*)in.ah32);
+        z = to_global((T*)in.z32);
     } else {
-        val = (const T*)in.ah;
-        z = (T*)in.vec[V_Z64];
+        val = to_global((const T*)in.ah);
+        z = to_global((T*)in.vec[V_Z64]);
     }
-    const int32_t* __restrict__ idx = in.ci;
-    const int s = in.rp[row], e = in.rp[row + 1];
+    const LPK_GLOBAL int32_t* __restrict__ idx = to_global(in.ci);
     T acc = 0;
     if (e - s <= g * R) {
-        T a[R];
+        T a[R], zv[R];
         int j[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             const int kk = s + lane + t * g;
-            a[t] = 0;
-            j[t] = 0;
-            if (kk < e) {
-                a[t] = val[kk];
-                j[t] = idx[kk];
-                if (!fresh) acc += a[t] * z[j[t]];
-            }
+            const bool ok = kk < e;
+            a[t] = ok ? val[kk] : (T)0;
+            j[t] = ok ? idx[kk] : -1;
         }
+#pragma unroll
+        for (int t = 0; t < R; ++t) zv[t] = (!fresh && j[t] >= 0) ? z[j[t]] : (T)0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc += a[t] * zv[t];
         acc = il ? il_sum(acc, il) : sg_sum(acc, g);
         const T delta = (T)in.omega * ((T)vrow - acc);
         if (write_z) {
 #pragma unroll
             for (int t = 0; t < R; ++t)
-                if (s + lane + t * g < e) {
-                    if (fresh) z[j[t]] = delta * a[t];
-                    else z[j[t]] += delta * a[t];
-                }
+                if (j[t] >= 0) z[j[t]] = fresh ? delta * a[t] : zv[t] + delta * a[t];
         }
         if (lane == 0) {
             if (sw == 0) {
@@ -143,20 +144,23 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     }
 }
 
-// rows held in registers up to R elements per lane: 8, or 16 when some instance lays the
-// colour out interleaved (fewer lanes per row)
+// rows held in registers up to R elements per lane (8, 16 or 32: the most any instance
+// needs for the colour; the arithmetic is the same for every R, only longer rows stream
+// their elements twice)
+template <typename T>
+static void launch_nesor(const BLaunch& L, int R, dim3 gr, int colour, int pass, int npass, int dir, int kz) {
+    const dim3 bl(BLOCK);
+    if (R <= 8) hipLaunchKernelGGL((k_nesor<T, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
+    else if (R <= 16) hipLaunchKernelGGL((k_nesor<T, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
+    else hipLaunchKernelGGL((k_nesor<T, 32>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
+}
+
 void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir) {
     const unsigned gx = capg(L.grid_colour[colour], 1 << 30);
-    const bool wide = L.colour_il && L.colour_il[colour];
-    const dim3 gr(gx, L.S), bl(BLOCK);
-    const int kz = L.keep_z ? 1 : 0;
-    if (L.mixed) {
-        if (wide) hipLaunchKernelGGL((k_nesor<float, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, 0);
-        else hipLaunchKernelGGL((k_nesor<float, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, 0);
-    } else {
-        if (wide) hipLaunchKernelGGL((k_nesor<double, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
-        else hipLaunchKernelGGL((k_nesor<double, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
-    }
+    const int R = L.colour_r ? L.colour_r[colour] : 8;
+    const dim3 gr(gx, L.S);
+    if (L.mixed) launch_nesor<float>(L, R, gr, colour, pass, npass, dir, 0);
+    else launch_nesor<double>(L, R, gr, colour, pass, npass, dir, L.keep_z ? 1 : 0);
 }
 
 }  // namespace lpk
