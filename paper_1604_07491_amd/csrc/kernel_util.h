@@ -128,13 +128,14 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 }
 
 __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
-    if (pmask > 0) return (*in.mode & pmask) != 0;
-    if (pmask == PM_ITER_DIR) return in.ctl->done == 0 && in.ctl->cg_phase != 0;
-    return in.ctl->done == 0;   // 0: Krylov loop, still iterating
+    if (pmask > 0) return (*to_global(in.mode) & pmask) != 0;
+    const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
+    if (pmask == PM_ITER_DIR) return ctl->done == 0 && ctl->cg_phase != 0;
+    return ctl->done == 0;   // 0: Krylov loop, still iterating
 }
 
 __device__ __forceinline__ void write_part(const Inst& in, int bx, int q, double v) {
-    if (threadIdx.x == 0) in.part[q * RED_MAXBLK + bx] = v;
+    if (threadIdx.x == 0) to_global(in.part)[q * RED_MAXBLK + bx] = v;
 }
 
 }  // namespace lpk

@@ -45,11 +45,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     } else {
         rows = in.n; g = in.g_csc; ptr = in.cp; idx = in.ri; val = mat == M_A_CSC ? in.ac : in.ahc;
     }
-    const LPK_GLOBAL double* __restrict__ x = to_global(xsel == V_PCOL ? in.P + (int64_t)in.ctl->k * in.ldv : in.vec[xsel]);
-    double* __restrict__ out = in.vec[outsel];
-    const double* __restrict__ b1 = b1sel >= 0 ? in.vec[b1sel] : nullptr;
-    const double* __restrict__ b2 = b2sel >= 0 ? in.vec[b2sel] : nullptr;
+    const LPK_GLOBAL double* __restrict__ x =
+        to_global(xsel == V_PCOL ? in.P + (int64_t)to_global(in.ctl)->k * in.ldv : in.vec[xsel]);
+    LPK_GLOBAL double* __restrict__ out = to_global(in.vec[outsel]);
+    const LPK_GLOBAL double* __restrict__ b1 = to_global(b1sel >= 0 ? in.vec[b1sel] : nullptr);
+    const LPK_GLOBAL double* __restrict__ b2 = to_global(b2sel >= 0 ? in.vec[b2sel] : nullptr);
+    const LPK_GLOBAL int32_t* __restrict__ gptr = to_global(ptr);
     const int lane = threadIdx.x & (g - 1);
+    const int lg = __ffs(g) - 1;   // g is a power of two
     const int64_t total = (int64_t)rows * g;
     // the reduction's partition depends on the instance alone (nbs blocks)
     const int nb = nrm ? in.nbs : (int)gridDim.x;
@@ -57,10 +60,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     double q = 0.0;
     for (int64_t t0 = (int64_t)bx * BLOCK; t0 < total; t0 += (int64_t)nb * BLOCK) {
         const int64_t t = t0 + threadIdx.x;
-        const int row = (int)(t / g);
+        const int row = (int)(t >> lg);
         double sum = 0.0;
         if (row < rows) {
-            const int s = ptr[row], e = ptr[row + 1];
+            const int s = gptr[row], e = gptr[row + 1];
             sum = row_dot<8>(to_global(val), to_global(idx), x, s, e, lane, g);
         }
         sum = sg_sum(sum, g);
@@ -247,14 +250,14 @@ __global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_gs_dots(const Inst* __res
     const int k = in.ctl->k;
     const int nseg = in.nseg;
     const int64_t m = in.m;
-    const int64_t tasks = (int64_t)nseg * (k + 1);
+    const int tasks = nseg * (k + 1);   // < 2^31: nseg * (kmax + 1) doubles are allocated
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * GS_DOT_WAVES;
+    const int nw = (int)gridDim.x * GS_DOT_WAVES;
     const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
     double* __restrict__ out = pass ? in.gpart2 : in.gpart;
-    for (int64_t t = (int64_t)bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
-        const int j = (int)(t / nseg);
-        const int sg = (int)(t - (int64_t)j * nseg);
+    for (int t = bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
+        const int j = nseg == 1 ? t : t / nseg;
+        const int sg = t - j * nseg;
         const int64_t r0 = (int64_t)sg * GS_SEG;
         const int64_t r1 = r0 + GS_SEG < m ? r0 + GS_SEG : m;
         const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)j * in.ldv);
@@ -328,10 +331,10 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_update(const Inst* __restr
     const int64_t m = in.m;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)bx * 64 * rpl;
-    double* __restrict__ u = in.vec[V_U];
+    LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
     const double* h = in.h2;
     if (fused) {
-        const double* __restrict__ pin = pass == 0 ? in.gpart : in.gpart2;
+        const LPK_GLOBAL double* __restrict__ pin = to_global(pass == 0 ? in.gpart : in.gpart2);
         for (int j = threadIdx.x; j <= k; j += blockDim.x) {
             double sj = 0.0;
             for (int c = 0; c < in.nseg; ++c) sj += pin[(int64_t)c * in.ldp + j];

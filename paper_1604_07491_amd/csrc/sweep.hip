@@ -55,8 +55,10 @@ void b_prep(const BLaunch& L) {
 template <typename T, int R>
 __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir, int keepz) {
     INST;
-    if (in.ctl->done || in.gsor || in.lds || c >= in.ncol) return;
-    const int r0 = in.cstart[c], r1 = in.cstart[c + 1], gc = in.cg[c];
+    const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
+    if (ctl->done || in.gsor || in.lds || c >= in.ncol) return;
+    const LPK_GLOBAL int32_t* cstart = to_global(in.cstart);
+    const int r0 = cstart[c], r1 = cstart[c + 1], gc = to_global(in.cg)[c];
     const int tid = bx * BLOCK + threadIdx.x;
     int g, row, lane, il;
     if (gc > 0) {
@@ -76,13 +78,13 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
-    const int64_t k = in.ctl->k;
+    const int64_t k = ctl->k;
     LPK_GLOBAL double* __restrict__ vk = to_global(in.V + k * in.ldv);
     LPK_GLOBAL double* __restrict__ p = to_global(in.P + k * in.ldv);
     const LPK_GLOBAL int32_t* __restrict__ rp = to_global(in.rp);
     const int s = rp[row], e = rp[row + 1];
     // first sweep: v_k = u / h_{k,k-1} is formed here and stored; p_k starts from delta
-    const double vrow = sw == 0 ? to_global(in.vec[V_U])[row] * in.ctl->inv_h : vk[row];
+    const double vrow = sw == 0 ? to_global(in.vec[V_U])[row] * ctl->inv_h : vk[row];
     const LPK_GLOBAL T* __restrict__ val;
     LPK_GLOBAL T* __restrict__ z;
     if constexpr (sizeof(T) == 4) {
