@@ -55,8 +55,9 @@ typedef enum {
 
 /* LP_MIXED: FP32 inner sweeps (and their products) with the outer Krylov method, the true
  * residual and the interior-point update in FP64.  NE-SOR / NE-SSOR sweeps of an LP whose
- * FP64 z (n doubles) fits in 48 KiB run from LDS and stream nothing from HBM, so they
- * stay in FP64 (the LP then computes as with LP_FP64).                                 */
+ * FP64 z (n doubles) and colour table (2 ncolours + 1 ints) fit in 48 KiB run from LDS
+ * and stream nothing from HBM, so they stay in FP64 (the LP then computes as with
+ * LP_FP64).                                                                            */
 typedef enum { LP_FP64 = 0, LP_MIXED = 1 } lp_precision;
 typedef enum { LP_ABGMRES = 0, LP_CGNE = 1, LP_MRNE = 2 } lp_krylov;
 typedef enum { LP_NESOR = 0, LP_CIMMINO = 1, LP_NESSOR = 2, LP_GSOR = 3 } lp_inner;
