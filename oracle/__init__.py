@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # status codes
 OK, EINVAL, ENOMEM, NOT_CONVERGED, DIVERGED = 0, 1, 4, 7, 8
 NESOR, CIMMINO, NESSOR = 0, 1, 2
-ABGMRES, CGNE, MRNE = 0, 1, 2
+ABGMRES, CGNE, MRNE, BAGMRES = 0, 1, 2, 3
 ORDER_COLOUR, ORDER_NATURAL = 0, 1
 
 

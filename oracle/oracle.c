@@ -23,7 +23,8 @@
  *                         AD (Sec. 3.5, eq. scaleD / scaled_ls)
  *   orc_dirsolve          min-norm problem (eq. minnrmprob) by AB-GMRES (Algorithm
  *                         "AB-GMRES method preconditioned by inner iterations", Sec. 3.2),
- *                         CGNE or MRNE (Algorithms of Sec. 3.1) on the row-scaled system
+ *                         CGNE or MRNE (Algorithms of Sec. 3.1) on the row-scaled system,
+ *                         or BA-GMRES (the corrector-stage remark of Sec. 3.2, eq. ba_ne)
  *   orc_affine_direction  predictor stage via the w-recurrence (eq. step_predictor)
  *   orc_corrector_direction corrector stage via the w-recurrence (eq. step_corrector)
  *   orc_init_point        starting point (Mehrotra's published heuristic; the paper
@@ -44,11 +45,11 @@ enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 4, ORC_NOT_CONVERGED = 7, ORC_DI
 
 /* inner iteration kinds, Krylov kinds, sweep orders */
 enum { ORC_NESOR = 0, ORC_CIMMINO = 1, ORC_NESSOR = 2 };
-enum { ORC_ABGMRES = 0, ORC_CGNE = 1, ORC_MRNE = 2 };
+enum { ORC_ABGMRES = 0, ORC_CGNE = 1, ORC_MRNE = 2, ORC_BAGMRES = 3 };
 enum { ORC_ORDER_COLOUR = 0, ORC_ORDER_NATURAL = 1 };
 
 typedef struct {
-    int32_t krylov;     /* ORC_ABGMRES / ORC_CGNE / ORC_MRNE */
+    int32_t krylov;     /* ORC_ABGMRES / ORC_CGNE / ORC_MRNE / ORC_BAGMRES */
     int32_t inner;      /* ORC_NESOR / ORC_CIMMINO / ORC_NESSOR */
     int32_t ell;        /* inner sweeps per preconditioner application */
     int32_t order;      /* ORC_ORDER_COLOUR or ORC_ORDER_NATURAL */
@@ -503,6 +504,105 @@ static int mrne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
     return ORC_OK;
 }
 
+/* BA-GMRES (Hayami, Yin and Ito; the corrector-stage remark of Sec. 3.2) for the least-   */
+/* squares form min ||A_hat^T dyh - h|| (eq. ba_ne) with the left preconditioner B = C A_hat */
+/* of inner iterations: GMRES on B A_hat^T dyh = B h in m-space.  Here the right-hand side  */
+/* is given as f_hat; when f_hat = A_hat h (the corrector) the Krylov space                 */
+/* K(C A_hat A_hat^T, C f_hat) and the minimised norm ||C (f_hat - A_hat A_hat^T dyh)|| are  */
+/* those of eq. ba_ne, and the same iteration applies to any f_hat in R(A_hat).  dyh_0 = 0; */
+/* Arnoldi by MGS, the least-squares problem by Givens rotations; stop when the             */
+/* preconditioned residual |gamma_{k+1}| <= eps ||C f_hat||, when h_{k+1,k} = 0 or at kmax. */
+/* dw = A_hat^T dyh.                                                                         */
+static int bagmres(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* rp,
+                   const int32_t* ci, const double* ah, const int32_t* perm, double omega_c,
+                   const double* fh, double eps, int64_t kmax, double* dw, double* dyh,
+                   orc_krylov_info* info) {
+    const double beta_f = nrm2(m, fh);
+    info->beta = beta_f;
+    info->iters = 0;
+    info->res_est = 0.0;
+    info->failed = 0;
+    memset(dw, 0, (size_t)n * sizeof(double));
+    memset(dyh, 0, (size_t)m * sizeof(double));
+    if (beta_f == 0.0) return ORC_OK;
+    int64_t ldh = kmax + 1;
+    double* V = (double*)malloc((size_t)m * (size_t)(kmax + 1) * sizeof(double));
+    double* H = (double*)calloc((size_t)ldh * (size_t)kmax, sizeof(double));
+    double* cs = (double*)malloc((size_t)kmax * sizeof(double));
+    double* sn = (double*)malloc((size_t)kmax * sizeof(double));
+    double* gam = (double*)calloc((size_t)kmax + 1, sizeof(double));
+    double* z = (double*)malloc((size_t)n * sizeof(double));
+    double* t = (double*)malloc((size_t)n * sizeof(double));
+    double* s = (double*)malloc((size_t)m * sizeof(double));
+    double* u = (double*)malloc((size_t)m * sizeof(double));
+    double* y = (double*)malloc((size_t)(kmax > 0 ? kmax : 1) * sizeof(double));
+    if (!V || !H || !cs || !sn || !gam || !z || !t || !s || !u || !y) {
+        free(V); free(H); free(cs); free(sn); free(gam); free(z); free(t); free(s); free(u); free(y);
+        return ORC_ENOMEM;
+    }
+    /* r_0 = B h = C f_hat */
+    apply_inner(o, m, n, rp, ci, ah, perm, omega_c, fh, z, u);
+    const double beta = nrm2(m, u);
+    info->res_est = beta;
+    int64_t k = 0;
+    double res = beta;
+    if (beta > 0.0) {
+        for (int64_t i = 0; i < m; ++i) V[i] = u[i] / beta;
+        gam[0] = beta;
+        while (k < kmax) {
+            const double* vk = V + (size_t)k * m;
+            csr_tmv(m, n, rp, ci, ah, vk, t);                        /* A_hat^T v_k */
+            csr_mv(m, rp, ci, ah, t, s);                             /* A_hat A_hat^T v_k */
+            apply_inner(o, m, n, rp, ci, ah, perm, omega_c, s, z, u); /* u = C s */
+            double* hk = H + (size_t)k * ldh;
+            for (int64_t i = 0; i <= k; ++i) {
+                const double* vi = V + (size_t)i * m;
+                hk[i] = dot(m, u, vi);
+                for (int64_t r = 0; r < m; ++r) u[r] -= hk[i] * vi[r];
+            }
+            const double hnext = nrm2(m, u);
+            hk[k + 1] = hnext;
+            if (hnext != 0.0) {
+                double* vn = V + (size_t)(k + 1) * m;
+                for (int64_t r = 0; r < m; ++r) vn[r] = u[r] / hnext;
+            }
+            for (int64_t i = 0; i < k; ++i) {
+                const double a = hk[i], b = hk[i + 1];
+                hk[i] = cs[i] * a + sn[i] * b;
+                hk[i + 1] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = hk[k], b = hk[k + 1];
+            const double r = hypot(a, b);
+            if (r == 0.0) break;
+            cs[k] = a / r;
+            sn[k] = b / r;
+            hk[k] = r;
+            hk[k + 1] = 0.0;
+            gam[k + 1] = -sn[k] * gam[k];
+            gam[k] = cs[k] * gam[k];
+            res = fabs(gam[k + 1]);
+            ++k;
+            if (res <= eps * beta || hnext == 0.0) break;
+        }
+        for (int64_t i = k - 1; i >= 0; --i) {
+            double sum = gam[i];
+            for (int64_t j = i + 1; j < k; ++j) sum -= H[(size_t)j * ldh + i] * y[j];
+            y[i] = sum / H[(size_t)i * ldh + i];
+        }
+        for (int64_t r = 0; r < m; ++r) {
+            double sum = 0.0;
+            for (int64_t j = 0; j < k; ++j) sum += V[(size_t)j * m + r] * y[j];
+            dyh[r] = sum;
+        }
+        csr_tmv(m, n, rp, ci, ah, dyh, dw);
+    }
+    info->iters = k;
+    info->res_est = res;
+    info->failed = res > eps * beta;
+    free(V); free(H); free(cs); free(sn); free(gam); free(z); free(t); free(s); free(u); free(y);
+    return ORC_OK;
+}
+
 /* ----------------------------------------------------------------------------------- */
 /* The search-direction solve: min ||dw|| s.t. (A D) dw = f (eq. minnrmprob), solved on   */
 /* the row-scaled system (eq. scaled_ls).  d may be NULL (D = I).  Outputs dw (n) and   */
@@ -536,6 +636,8 @@ int orc_dirsolve(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, con
             rc = cgne(o, m, n, rp, ci, ah, perm, omega_c, fh, eps, kmax, dw, dyh, info);
         else if (o->krylov == ORC_MRNE)
             rc = mrne(o, m, n, rp, ci, ah, perm, omega_c, fh, eps, kmax, dw, dyh, info);
+        else if (o->krylov == ORC_BAGMRES)
+            rc = bagmres(o, m, n, rp, ci, ah, perm, omega_c, fh, eps, kmax, dw, dyh, info);
         else
             rc = abgmres(o, m, n, rp, ci, ah, perm, omega_c, fh, eps, kmax, dw, dyh, info);
         info->omega_c = omega_c;

@@ -36,6 +36,9 @@ CASES = [
     dict(krylov=oracle.MRNE, inner=oracle.NESSOR, ell=1),
     dict(krylov=oracle.CGNE, inner=oracle.NESSOR, ell=3, omega=1.2),
     dict(krylov=oracle.MRNE, inner=oracle.NESSOR, ell=3, omega=0.9),
+    dict(krylov=oracle.BAGMRES, inner=oracle.NESOR, ell=2),
+    dict(krylov=oracle.BAGMRES, inner=oracle.NESSOR, ell=1),
+    dict(krylov=oracle.BAGMRES, inner=oracle.CIMMINO, ell=2),
 ]
 
 
@@ -44,7 +47,7 @@ CASES = [
 def test_dirsolve_is_min_norm_solution(case, shape):
     m, n, dup = shape
     lp, A, d, AD, f = _problem(m, n, seed=m + n + dup, dup=dup)
-    kmax = 20 * lp.m if case["krylov"] != oracle.ABGMRES else 0
+    kmax = 20 * lp.m if case["krylov"] in (oracle.CGNE, oracle.MRNE) else 0
     opts = oracle.solver_opts(kmax=kmax, **case)
     dw, dy, info = oracle.dirsolve(lp, d, f, 1e-13, opts)
     ref = np.linalg.pinv(AD) @ f
@@ -95,3 +98,57 @@ def test_scaled_equals_unscaled_minimum_norm():
     dw1, _, _ = oracle.dirsolve(lp, d, f, 1e-13)
     dw2, _, _ = oracle.dirsolve(lp2, d, f * sc, 1e-13)
     np.testing.assert_allclose(dw1, dw2, rtol=1e-8, atol=1e-9 * np.abs(dw1).max())
+
+
+@pytest.mark.parametrize("inner,ell", [(oracle.NESOR, 2), (oracle.NESSOR, 1)])
+@pytest.mark.parametrize("seed", [0, 3])
+def test_bagmres_iterate_minimises_the_preconditioned_residual(seed, inner, ell):
+    """BA-GMRES (eq. ba_ne with B = C A_hat) at step k minimises ||C (f_hat - A_hat A_hat^T y)||
+    over y in K_k(C A_hat A_hat^T, C f_hat): checked against an explicit Krylov basis
+    (numpy QR) and a dense least-squares solve, with C applied by the oracle's pinned
+    inner iterations."""
+    lp, A, d, AD, f = _problem(30, 70, seed, dup=2)
+    rho, ah = oracle.scale(lp, d)
+    Ahat = (lp.m, lp.n, lp.row_ptr, lp.col_idx, ah)
+    Ad = np.zeros((lp.m, lp.n))
+    for i in range(lp.m):
+        for kk in range(lp.row_ptr[i], lp.row_ptr[i + 1]):
+            Ad[i, lp.col_idx[kk]] = ah[kk]
+    fh = f / rho
+    _, perm, _ = oracle.colour(lp)
+    ssor = inner == oracle.NESSOR
+
+    def C(g):
+        return oracle.nesor(Ahat, g, 1.0, ell, perm=perm, ssor=ssor)[1]
+
+    q0 = C(fh)
+    for k in (1, 2, 4, 6):
+        dw, dy, info = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(krylov=oracle.BAGMRES, inner=inner, ell=ell, kmax=k))
+        assert info["iters"] == k
+        W = [q0]
+        for _ in range(k - 1):
+            W.append(C(Ad @ (Ad.T @ W[-1])))
+        Q, _ = np.linalg.qr(np.array(W).T)
+        MQ = np.array([C(Ad @ (Ad.T @ Q[:, j])) for j in range(k)]).T
+        c, *_ = np.linalg.lstsq(MQ, q0, rcond=None)
+        yref = Q @ c
+        dyh = dy * rho
+        np.testing.assert_allclose(dyh, yref, rtol=1e-7, atol=1e-9 * np.abs(yref).max())
+        np.testing.assert_allclose(dw, Ad.T @ yref, rtol=1e-7, atol=1e-9 * np.abs(dw).max())
+        # the reported estimate is the preconditioned residual of the iterate
+        pres = np.linalg.norm(q0 - MQ @ c)
+        assert abs(info["res_est"] - pres) <= 1e-9 * np.linalg.norm(q0)
+        # and the true residual is ||f_hat - A_hat dw||
+        assert abs(info["res_true"] - np.linalg.norm(fh - Ad @ dw)) <= 1e-9 * np.linalg.norm(fh)
+
+
+def test_bagmres_solves_the_least_squares_form_of_the_corrector():
+    """With f = (A D) h, the converged BA-GMRES direction is the least-squares solution of
+    min ||(A D)^T dy - h|| (eq. ba_ne): dw = (A D)^T dy = pinv(A D) (A D) h."""
+    lp, A, d, AD, _ = _problem(30, 70, 7, dup=2)
+    h = np.random.default_rng(7).standard_normal(lp.n)
+    f = AD @ h
+    dw, dy, info = oracle.dirsolve(lp, d, f, 1e-13, oracle.solver_opts(krylov=oracle.BAGMRES))
+    dy_ls = np.linalg.lstsq(AD.T, h, rcond=None)[0]
+    np.testing.assert_allclose(dw, AD.T @ dy_ls, rtol=1e-8, atol=1e-10 * np.abs(dw).max())
+    assert not info["failed"]
