@@ -84,14 +84,14 @@ def main():
     ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
                     help="batch phases: 0 auto, 1 together, 2 each LP alone")
-    ap.add_argument("--krylov", default="abgmres", choices=["abgmres", "cgne", "mrne"],
-                    help="outer iteration: AB-GMRES (Sec. 3.2) or CGNE / MRNE (Sec. 3.3)")
+    ap.add_argument("--krylov", default="abgmres", choices=["abgmres", "cgne", "mrne", "bagmres"],
+                    help="outer iteration: AB-GMRES (Sec. 3.2), CGNE / MRNE (Sec. 3.3) or BA-GMRES (eq. ba_ne)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -198,7 +198,8 @@ def main():
     if not args.no_cpu_baseline and lps[0].dense is None and lps[0].n <= 200000:
         import oracle
         tc = time.perf_counter()
-        so = oracle.solver_opts(krylov={"abgmres": oracle.ABGMRES, "cgne": oracle.CGNE, "mrne": oracle.MRNE}[args.krylov],
+        so = oracle.solver_opts(krylov={"abgmres": oracle.ABGMRES, "cgne": oracle.CGNE, "mrne": oracle.MRNE,
+                                          "bagmres": oracle.BAGMRES}[args.krylov],
                                 inner={"nesor": oracle.NESOR, "nessor": oracle.NESSOR, "cimmino": oracle.CIMMINO}[args.inner])
         o = oracle.ipm(lps[0], oracle.ipm_opts(solver=so))
         tcpu = time.perf_counter() - tc
@@ -230,7 +231,7 @@ def main():
         "config": {"workload": args.workload, "m": lps[0].m, "n": lps[0].n, "nnz": lps[0].nnz,
                    "lps_per_step": len(probs), "lps_in_lockstep": args.width,
                    "precision": args.precision, "inner": args.inner,
-                   "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE"}[args.krylov],
+                   "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE", "bagmres": "BA-GMRES"}[args.krylov],
                    "inner_sweeps": 2, "omega": 1.0, "schedule": args.schedule},
         "roofline": roofline,
         "kernel_classes": {k: {"launches": v["launches"], "ms_total": v["ms_total"],

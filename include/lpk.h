@@ -13,7 +13,9 @@
  * right-preconditioned by inner iterations (Sec. 3.2, 3.4): multicolour NE-SOR sweeps,
  * NE-SSOR sweeps, Cimmino sweeps, or (for dense A) SOR on the explicit Gram matrix
  * A_hat A_hat^T; or by CGNE or MRNE preconditioned by the same sparse inner iterations
- * (Sec. 3.3).
+ * (Sec. 3.3); or by BA-GMRES, GMRES on the left-preconditioned normal equations of the
+ * first kind C A_hat A_hat^T dyh = C f_hat in m-space (the corrector-stage remark of
+ * Sec. 3.2, eq. ba_ne), C the NE-SOR or NE-SSOR operator, with dw = A_hat^T dyh.
  * The direction is recovered with the w-recurrence (eq. step_predictor /
  * step_corrector), saving one matrix-vector product per stage.
  *
@@ -59,7 +61,7 @@ typedef enum {
  * and stream nothing from HBM, so they stay in FP64 (the LP then computes as with
  * LP_FP64).                                                                            */
 typedef enum { LP_FP64 = 0, LP_MIXED = 1 } lp_precision;
-typedef enum { LP_ABGMRES = 0, LP_CGNE = 1, LP_MRNE = 2 } lp_krylov;
+typedef enum { LP_ABGMRES = 0, LP_CGNE = 1, LP_MRNE = 2, LP_BAGMRES = 3 } lp_krylov;
 typedef enum { LP_NESOR = 0, LP_CIMMINO = 1, LP_NESSOR = 2, LP_GSOR = 3 } lp_inner;
 
 typedef struct lp_problem lp_problem;
@@ -70,7 +72,10 @@ typedef struct {
     int32_t krylov;          /* lp_krylov [LP_ABGMRES]; LP_CGNE / LP_MRNE run the sweeps   */
                              /* of LP_NESOR, LP_NESSOR or LP_CIMMINO on the sparse rows    */
                              /* (with lp_create_dense: LP_NESSOR or LP_CIMMINO); LP_MRNE   */
-                             /* needs precision LP_FP64                                    */
+                             /* needs precision LP_FP64; LP_BAGMRES needs lp_create,      */
+                             /* LP_NESOR or LP_NESSOR and precision LP_FP64; it stops on  */
+                             /* its own residual |gamma_k| <= tol ||C f_hat||, and         */
+                             /* lp_krylov_info.res_est is that residual                   */
     int32_t inner;           /* lp_inner [LP_NESOR]; LP_GSOR needs lp_create_dense        */
     int32_t inner_sweeps;    /* ell, inner iterations per preconditioner application [2]; */
                              /* an NE-SSOR iteration is a forward and a backward sweep     */
@@ -201,8 +206,9 @@ lp_status lp_set_state(lp_problem* p, const double* x, const double* y, const do
 lp_status lp_get_log(const lp_problem* p, lp_iter_info* info, int32_t cap, int32_t* n_out);
 
 /* Device bytes lp_create would allocate for an m x n problem with nnz nonzeros and the
- * given options (NULL = defaults), including (AB-GMRES) the Krylov basis of
- * krylov_max_iter + 1 vectors; CGNE and MRNE keep a fixed number of vectors.
+ * given options (NULL = defaults), including (AB-GMRES, BA-GMRES) the Krylov basis of
+ * krylov_max_iter + 1 vectors (AB-GMRES also keeps as many multiplier vectors); CGNE
+ * and MRNE keep a fixed number of vectors.
  * Errors: LP_EDIM.                                                                    */
 lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options* o,
                              uint64_t* bytes);
@@ -249,7 +255,7 @@ lp_status lp_profile_read(lp_problem* p, lp_kernel_stat* st, int32_t cap, int32_
 
 /* Mean duration of one launch of kernel class cls (LP_K_SWEEP: one application of the
  * inner-iteration preconditioner; LP_K_SPMV_CSR / LP_K_SPMV_CSC: the Krylov loop's two
- * products; LP_K_GS_DOTS / LP_K_GS_UPDATE: the AB-GMRES Gram-Schmidt passes at basis
+ * products; LP_K_GS_DOTS / LP_K_GS_UPDATE: the AB- or BA-GMRES Gram-Schmidt passes at basis
  * size min(128, krylov limit); LP_K_GRAM: the dense path's Gram and preconditioner
  * build, timed per launch of its kernels), from `reps` back-to-back replays of its
  * launches captured with the current A_hat, between two HIP events on the problem's

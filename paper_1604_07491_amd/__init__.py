@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "liblpk.so")
 LP_OK, LP_EINVAL, LP_EDIM, LP_ENONFINITE, LP_ENOMEM, LP_ETOOBIG, LP_EDEVICE = 0, 1, 2, 3, 4, 5, 6
 LP_NOT_CONVERGED, LP_DIVERGED, LP_KRYLOV_MAXIT = 7, 8, 9
 LP_FP64, LP_MIXED = 0, 1
-LP_ABGMRES, LP_CGNE, LP_MRNE = 0, 1, 2
+LP_ABGMRES, LP_CGNE, LP_MRNE, LP_BAGMRES = 0, 1, 2, 3
 LP_NESOR, LP_CIMMINO, LP_NESSOR, LP_GSOR = 0, 1, 2, 3
 
 
@@ -179,7 +179,7 @@ def options(**kw) -> Options:
         if k == "inner" and isinstance(v, str):
             v = {"nesor": LP_NESOR, "cimmino": LP_CIMMINO, "nessor": LP_NESSOR, "gsor": LP_GSOR}[v]
         if k == "krylov" and isinstance(v, str):
-            v = {"abgmres": LP_ABGMRES, "cgne": LP_CGNE, "mrne": LP_MRNE}[v]
+            v = {"abgmres": LP_ABGMRES, "cgne": LP_CGNE, "mrne": LP_MRNE, "bagmres": LP_BAGMRES}[v]
         setattr(o, k, v)
     return o
 

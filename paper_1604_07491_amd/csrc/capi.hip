@@ -28,21 +28,27 @@ static lp_status fail(lp_status s, const std::string& msg) {
     return s;
 }
 
+static bool is_gmres(const lp_options& o) { return o.krylov == LP_ABGMRES || o.krylov == LP_BAGMRES; }
+
 // Krylov iteration limit: m (Sec. 4.2) unless the options cap it; AB-GMRES keeps a basis
-// and multiplier vector per iteration, so its limit is also at most what fits in a 16 GiB
-// budget for them
+// and multiplier vector per iteration (BA-GMRES a basis vector), so its limit is also at
+// most what fits in a 16 GiB budget for them
 static int64_t plan_kmax(int64_t m, const lp_options& o) {
     int64_t k = m;
     if (o.krylov_max_iter > 0) k = std::min<int64_t>(k, o.krylov_max_iter);
-    if (o.krylov != LP_ABGMRES) return std::max<int64_t>(1, k);
+    if (!is_gmres(o)) return std::max<int64_t>(1, k);
     const int64_t budget = (int64_t)16 << 30;
-    const int64_t cap = std::max<int64_t>(8, budget / (16 * (m + 1)));
+    const int64_t per = o.krylov == LP_ABGMRES ? 16 : 8;
+    const int64_t cap = std::max<int64_t>(8, budget / (per * (m + 1)));
     return std::max<int64_t>(1, std::min(k, cap));
 }
 
-// columns of V and P (and the order of H): the basis for AB-GMRES, one column for CGNE
-// and MRNE (the preconditioner's input and multipliers)
-static int64_t basis_cols(int64_t kmax, const lp_options& o) { return o.krylov == LP_ABGMRES ? kmax + 1 : 1; }
+// columns of V (and the order of H): the basis for AB-GMRES and BA-GMRES, one column for
+// CGNE and MRNE (the preconditioner's input)
+static int64_t basis_cols(int64_t kmax, const lp_options& o) { return is_gmres(o) ? kmax + 1 : 1; }
+// columns of P, the multipliers: one per basis vector for AB-GMRES; BA-GMRES keeps its
+// multipliers in V_U and CGNE / MRNE in one column
+static int64_t mult_cols(int64_t kmax, const lp_options& o) { return o.krylov == LP_ABGMRES ? kmax + 1 : 1; }
 
 struct Sizes {
     uint64_t bytes = 0;
@@ -64,8 +70,8 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
     const bool mixed = fp32_sweeps(o, n, 1, false);
     const int64_t kmax = plan_kmax(m, o);
-    const int64_t cols = basis_cols(kmax, o);
-    const bool cg = o.krylov != LP_ABGMRES;
+    const int64_t cols = basis_cols(kmax, o), pcols = mult_cols(kmax, o);
+    const bool cg = !is_gmres(o);
     const int64_t nchunks = (m + 64 * gs_rpl_for(m) - 1) / (64 * gs_rpl_for(m));
     z.add(m + 1, 4); z.add(nnz, 4); z.add(nnz, 8); z.add(n + 1, 4); z.add(nnz, 4); z.add(nnz, 8);
     z.add(nnz, 8); z.add(nnz, 8);
@@ -75,7 +81,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
     for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
     z.add(n, 4); z.add(m, 4);                     // z32, r32
-    z.add(m * cols, 8); z.add(m * cols, 8);       // V, P
+    z.add(m * cols, 8); z.add(m * pcols, 8);      // V, P
     z.add(cols * cols, 8);                        // H
     for (int i = 0; i < 5; ++i) z.add(cols + 1, 8);
     if (cg) {
@@ -299,8 +305,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     // device memory
     DevArena& A = p->arena;
     p->kmax = plan_kmax(m, p->opt);
-    const int64_t cols = basis_cols(p->kmax, p->opt);
-    const bool cg = p->opt.krylov != LP_ABGMRES;
+    const int64_t cols = basis_cols(p->kmax, p->opt), pcols = mult_cols(p->kmax, p->opt);
+    const bool cg = !is_gmres(p->opt);
     p->ldv = m;
     p->ldh = cols;
     p->rpl = gs_rpl_for(m);
@@ -331,7 +337,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->z32 = A.alloc<float>(n);
     p->r32 = A.alloc<float>(m);
     p->V = A.alloc<double>(m * cols);
-    p->P = A.alloc<double>(m * cols);
+    p->P = A.alloc<double>(m * pcols);
     p->H = A.alloc<double>(cols * cols);
     p->cs = A.alloc<double>(cols + 1);
     p->sn = A.alloc<double>(cols + 1);
@@ -384,11 +390,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
 
 static lp_status check_options(const lp_options& o, bool dense) {
     if (o.precision != LP_FP64 && o.precision != LP_MIXED) return fail(LP_EINVAL, "unknown precision");
-    if (o.krylov != LP_ABGMRES && o.krylov != LP_CGNE && o.krylov != LP_MRNE)
+    if (o.krylov != LP_ABGMRES && o.krylov != LP_CGNE && o.krylov != LP_MRNE && o.krylov != LP_BAGMRES)
         return fail(LP_EINVAL, "unknown Krylov method");
+    // BA-GMRES applies the sweeps to m-vectors in place (input V_U, multipliers V_U);
+    // the Cimmino and dense kernels and the FP32 sweeps keep their AB-GMRES layout
+    if (o.krylov == LP_BAGMRES && (dense || (o.inner != LP_NESOR && o.inner != LP_NESSOR)))
+        return fail(LP_EINVAL, "BA-GMRES needs sparse NE-SOR or NE-SSOR inner iterations");
+    if (o.krylov == LP_BAGMRES && o.precision != LP_FP64)
+        return fail(LP_EINVAL, "BA-GMRES needs FP64 inner iterations (precision LP_FP64)");
     if (o.inner != LP_NESOR && o.inner != LP_NESSOR && o.inner != LP_CIMMINO && !(dense && o.inner == LP_GSOR))
         return fail(LP_EINVAL, "inner iterations must be NE-SOR, NE-SSOR or Cimmino (or G-SOR for a dense A)");
-    if (o.krylov != LP_ABGMRES && dense && (o.inner == LP_NESOR || o.inner == LP_GSOR))
+    if (!is_gmres(o) && dense && (o.inner == LP_NESOR || o.inner == LP_GSOR))
         return fail(LP_EINVAL, "CGNE and MRNE need sparse sweeps: with a dense A use NE-SSOR or Cimmino");
     // MRNE forms q_k = A_hat^T C g_k by recurrence, which holds only while C is one fixed
     // linear map; FP32 sweeps perturb C at every application and the recurrence drifts

@@ -221,7 +221,10 @@ lp_status Batch::refresh() {
             L.inner = p->gsor ? 3 : p->opt.inner;
             L.ell = std::max(1, (int)p->opt.inner_sweeps);
             L.krylov = p->opt.krylov;
-            L.keep_z = !L.mixed && (L.inner == LP_NESOR || L.inner == LP_NESSOR);
+            L.ba = L.krylov == LP_BAGMRES;
+            // FP64 sweeps leave z_k = A_hat^T p_k for the product that follows (BA-GMRES
+            // has no such product: its sweeps end the iteration's operator)
+            L.keep_z = !L.mixed && !L.ba && (L.inner == LP_NESOR || L.inner == LP_NESSOR);
             first = false;
         }
         L.max_m = std::max(L.max_m, in.m);
@@ -334,12 +337,14 @@ static double sweep_bytes_dense(const Batch& B) {
 // Krylov iterations
 
 // one application of the inner-iteration preconditioner to column k of V (k and the done
-// flag from each instance's control block), with the start-of-iteration preparation
-static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
+// flag from each instance's control block), with the start-of-iteration preparation.
+// pmask > 0 (the start of a BA-GMRES solve, NE-SOR / NE-SSOR only): the instances whose
+// mode has a bit of pmask, whatever their control blocks say
+static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0) {
     const BLaunch& L = B.L;
     const double sv = L.mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
     const int ell = L.ell;
-    if (with_prep && L.need_prep) b_prep(L);
+    if (with_prep && L.need_prep) b_prep(L, pmask);
     if (L.inner == 3) {
         Prof pr(&B, LP_K_SWEEP, it, sweep_bytes_dense(B));
         b_apply_c(L);
@@ -381,7 +386,7 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
                 return p->nnz * (sv + 4.0) + (p->m + 1) * 4.0 + (double)p->m * (8.0 + 16.0) + (L.keep_z ? 8.0 * p->n : 0.0);
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0, true);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, true, pmask);
         }
         if (L.any_lds) {
             const double by = over_members(B, [&](const lp_problem* p) {
@@ -389,7 +394,7 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
                 return npass * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0)) + (L.keep_z ? 8.0 * p->n : 0.0);
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0, false);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, false, pmask);
         }
         for (int sw = 0; sw < npass; ++sw) {
             const int dir = ssor ? (sw & 1) : 0;
@@ -403,7 +408,7 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep) {
                     return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
-                b_nesor(L, c, sw, npass, dir);
+                b_nesor(L, c, sw, npass, dir, pmask);
             }
         }
     }
@@ -520,9 +525,30 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
     }
 }
 
+// one BA-GMRES iteration (eq. ba_ne): u = C A_hat A_hat^T v_k (both products in FP64,
+// then the sweeps on u in place), CGS2 and the Givens step, v_{k+1} = u / h_{k+1,k}
+static void enqueue_ba_iteration(Batch& B, int64_t it) {
+    const BLaunch& L = B.L;
+    {
+        Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
+        b_spmv(L, M_AH_CSC, V_VCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
+    }
+    {
+        Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
+        b_spmv(L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
+    }
+    enqueue_precond(B, it, true);
+    enqueue_gs(B, it, GS_DOTS | GS_UPDATES | GS_FINISH);
+    b_ba_vnext(L, 0);
+}
+
 // one Krylov iteration (every kernel returns at once for instances whose solve is done)
 static void enqueue_iteration(Batch& B, int64_t it) {
     const BLaunch& L = B.L;
+    if (L.ba) {
+        enqueue_ba_iteration(B, it);
+        return;
+    }
     if (L.krylov != LP_ABGMRES) {
         enqueue_cg_iteration(B, it);
         return;
@@ -555,11 +581,11 @@ static lp_status build_graph(Batch& B, int iters) {
     return LP_OK;
 }
 
-// AB-GMRES: dyh = P y with R y = gamma, dw = A_hat^T dyh (CGNE and MRNE update dw and dyh
-// in the iteration); the true residual ||f_hat - A_hat dw||
+// AB-GMRES: dyh = P y with R y = gamma, BA-GMRES: dyh = V y; dw = A_hat^T dyh (CGNE and
+// MRNE update dw and dyh in the iteration); the true residual ||f_hat - A_hat dw||
 static void enqueue_assembly(Batch& B, int pmask) {
     const BLaunch& L = B.L;
-    if (L.krylov == LP_ABGMRES) {
+    if (L.krylov == LP_ABGMRES || L.ba) {
         b_backsolve(L, pmask);
         b_combine(L, pmask);
         b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, pmask, false);
@@ -568,11 +594,18 @@ static void enqueue_assembly(Batch& B, int pmask) {
     b_true_res(L, pmask);
 }
 
-// start a solve for the pmask instances (f in V_F): f_hat, beta, control blocks
+// start a solve for the pmask instances (f in V_F): f_hat, beta, control blocks;
+// BA-GMRES: r_0 = C f_hat and v_0 = r_0 / ||r_0||
 static void enqueue_start(Batch& B, int pmask) {
     b_init_rhs(B.L, pmask);
     b_init_ctl(B.L, pmask, 0);
-    if (B.L.krylov != LP_ABGMRES) b_cg_init(B.L, pmask);
+    if (B.L.ba) {
+        enqueue_precond(B, -1, true, pmask);
+        b_ba_start(B.L, pmask);
+        b_ba_vnext(B.L, pmask);
+    } else if (B.L.krylov != LP_ABGMRES) {
+        b_cg_init(B.L, pmask);
+    }
 }
 
 lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
@@ -1241,7 +1274,7 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
             set_error("no dense Gram path for this problem");
             return LP_EINVAL;
         }
-        if (gs && p->opt.krylov != LP_ABGMRES) {
+        if (gs && p->opt.krylov != LP_ABGMRES && p->opt.krylov != LP_BAGMRES) {
             set_error("CGNE and MRNE keep no Krylov basis");
             return LP_EINVAL;
         }

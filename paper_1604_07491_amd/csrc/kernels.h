@@ -45,6 +45,7 @@ enum VecSel : int {
     V_COUNT
 };
 constexpr int V_PCOL = -1;   // column ctl->k of the multiplier vectors P
+constexpr int V_VCOL = -2;   // column ctl->k of the Krylov basis V
 
 // pmask of the launches that take only the instances still iterating that have a search
 // direction (every CGNE instance, MRNE instances past their start)
@@ -133,6 +134,7 @@ struct BLaunch {
     int lds_bytes;          // largest z of those instances
     bool any_stage;         // some instance sweeps in one block from LDS alone (lds == 2)
     int stage_bytes;        // largest LDS footprint of those instances
+    bool ba;                // BA-GMRES: the sweeps map V_U to V_U (input kept in V_R64)
     bool keep_z;            // FP64 NE-SOR / NE-SSOR: the sweeps leave z_k = A_hat^T p_k in
                             // V_Z64, and the loop needs no product with A_hat^T
     int max_ncol_global;    // colours of the instances swept by per-colour launches
@@ -152,7 +154,7 @@ inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, 
 enum Epilogue : int { EPI_PLAIN = 0, EPI_B_MINUS = 1, EPI_B1_MINUS_B2 = 2, EPI_B_PLUS = 3 };
 // out = epi(sum) over the rows of matrix `mat` for every instance whose mode has a bit of
 // pmask (pmask 0: instances whose Krylov solve is still running).  x = vec[xsel]
-// (V_PCOL: column k of P); nrm: per-block partials of sum(out^2) into part (quantity 0,
+// (V_PCOL: column k of P, V_VCOL: column k of V); nrm: per-block partials of sum(out^2) into part (quantity 0,
 // Inst::nbs blocks; only for the CSR matrices).
 void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel, int b2sel,
             int pmask, bool nrm);
@@ -161,13 +163,17 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 // The first sweep of every preconditioner application also writes V[:,k] = u / h_{k,k-1}
 // for its rows and overwrites (rather than accumulates) p_k; b_prep only clears the NE-SOR
 // z of instances whose colour 0 does not cover every column (colour 0 then overwrites z).
-void b_prep(const BLaunch& L);
+void b_prep(const BLaunch& L, int pmask);
 // one colour of pass `pass` of `npass` (dir 0: colours in order, 1: reversed, the
 // backward half of an NE-SSOR iteration); the first pass forms v_k and p_k
-void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir);
+// pmask 0: the instances inside a solve; > 0: those whose mode has a bit of pmask (the
+// start of a BA-GMRES solve applies the preconditioner to f_hat).  L.ba: the input is
+// V_U unscaled, the multipliers go to V_U and the input is kept in V_R64 (V and P are
+// not touched)
+void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir, int pmask);
 // every colour of every pass, one block per instance (ssor: passes alternate direction);
 // staged: the instances with Inst::lds == 2 (row data in LDS), else those with lds == 1
-void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged);
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged, int pmask);
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 // classical Gram-Schmidt, pass 0 and 1: dot partials, (reduce,) update u -= V h
@@ -194,7 +200,16 @@ void b_gemv_col(const BLaunch& L);      // dense: u = G p_k
 void b_init_rhs(const BLaunch& L, int pmask);
 void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap);   // other instances untouched
 void b_backsolve(const BLaunch& L, int pmask);
-void b_combine(const BLaunch& L, int pmask);
+void b_combine(const BLaunch& L, int pmask);   // dyh = P y (BA-GMRES: V y)
+
+// ---- BA-GMRES (the corrector-stage remark of Sec. 3.2, eq. ba_ne): GMRES on
+// C A_hat A_hat^T dyh = C f_hat in m-space, C the inner-iteration operator --------------
+// start, after the preconditioner has mapped V_U = f_hat to C f_hat: beta_C = ||C f_hat||,
+// gamma_0 = beta_C, threshold tol * beta_C, 1/h = 1/beta_C; done if beta_C = 0 (two launches)
+void b_ba_start(const BLaunch& L, int pmask);
+// V[:,k] = V_U / h_{k,k-1} for the instances still iterating: v_0 after the start, and
+// the next basis vector after each Givens step (pmask 0 inside the loop)
+void b_ba_vnext(const BLaunch& L, int pmask);
 void b_true_res(const BLaunch& L, int pmask);
 
 // ---- scaling (Sec. 2.2, 3.5) ------------------------------------------------------------

@@ -45,8 +45,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     } else {
         rows = in.n; g = in.g_csc; ptr = in.cp; idx = in.ri; val = mat == M_A_CSC ? in.ac : in.ahc;
     }
+    const int64_t kcol = xsel < 0 ? (int64_t)to_global(in.ctl)->k * in.ldv : 0;
     const LPK_GLOBAL double* __restrict__ x =
-        to_global(xsel == V_PCOL ? in.P + (int64_t)to_global(in.ctl)->k * in.ldv : in.vec[xsel]);
+        to_global(xsel == V_PCOL ? in.P + kcol : xsel == V_VCOL ? in.V + kcol : in.vec[xsel]);
     LPK_GLOBAL double* __restrict__ out = to_global(in.vec[outsel]);
     const LPK_GLOBAL double* __restrict__ b1 = to_global(b1sel >= 0 ? in.vec[b1sel] : nullptr);
     const LPK_GLOBAL double* __restrict__ b2 = to_global(b2sel >= 0 ? in.vec[b2sel] : nullptr);
@@ -649,10 +650,11 @@ void b_backsolve(const BLaunch& L, int pmask) {
     hipLaunchKernelGGL(k_backsolve, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
-// dyh = P[:, 0:iters] y  (flexible final step: dw = A_hat^T dyh), by row chunks of
-// 64 * RPL rows with the waves of a block splitting the columns, as the Gram-Schmidt update
+// dyh = P[:, 0:iters] y  (flexible final step: dw = A_hat^T dyh; BA-GMRES: dyh = V y),
+// by row chunks of 64 * RPL rows with the waves of a block splitting the columns, as the
+// Gram-Schmidt update
 template <int RPL>
-__global__ __launch_bounds__(64 * GS_WAVES) void k_combine(const Inst* __restrict__ I, int pmask) {
+__global__ __launch_bounds__(64 * GS_WAVES) void k_combine(const Inst* __restrict__ I, int pmask, int ba) {
     __shared__ double red[GS_WAVES][64 * RPL];
     INST;
     if (!takes_part(in, pmask) || bx >= in.nchunks) return;
@@ -663,7 +665,7 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_combine(const Inst* __restric
     double acc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) acc[t] = 0.0;
-    chunk_axpy<RPL>(in, in.P, it - 1, w, lane, base, rpl, in.ykr, acc);
+    chunk_axpy<RPL>(in, ba ? in.V : in.P, it - 1, w, lane, base, rpl, in.ykr, acc);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = acc[t];
     __syncthreads();
@@ -676,9 +678,69 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_combine(const Inst* __restric
 }
 
 void b_combine(const BLaunch& L, int pmask) {
-#define LPK_CB(R) hipLaunchKernelGGL((k_combine<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I, pmask)
+#define LPK_CB(R) \
+    hipLaunchKernelGGL((k_combine<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I, pmask, L.ba ? 1 : 0)
     LPK_SWITCH_RPL(LPK_CB)
 #undef LPK_CB
+}
+
+// ------------------------------------------------------------------------------------
+// BA-GMRES (eq. ba_ne): GMRES on C A_hat A_hat^T dyh = C f_hat, C the inner-iteration
+// operator.  The solve starts once the sweeps have mapped V_U = f_hat to C f_hat:
+// partials of ||C f_hat||^2 (nbr blocks, quantity 0), then one block per instance sets
+// beta_C = ||C f_hat||, gamma_0 = beta_C, the threshold tol * beta_C (the method's own
+// residual, |gamma_k|, is the preconditioned one) and 1 / beta_C, which the next-vector
+// kernel applies to form v_0.  ctl->beta stays ||f_hat||, the scale of the true residual.
+__global__ __launch_bounds__(BLOCK) void k_ba_norm(const Inst* __restrict__ I, int pmask) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (!takes_part(in, pmask) || bx >= in.nbr) return;
+    const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
+    double q = 0.0;
+    const int64_t stride = (int64_t)in.nbr * BLOCK;
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) q += u[i] * u[i];
+    const double r = block_sum(q, sh);
+    write_part(in, bx, 0, r);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ba_ctl(const Inst* __restrict__ I, int pmask) {
+    __shared__ double sh[BLOCK / 64];
+    INST;
+    if (!takes_part(in, pmask)) return;
+    double q = 0.0;
+    for (int c = threadIdx.x; c < in.nbr; c += BLOCK) q += in.part[c];
+    const double s = block_sum(q, sh);
+    if (threadIdx.x != 0) return;
+    KrylovCtl* ctl = in.ctl;
+    const double bc = sqrt(s);
+    in.gam[0] = bc;
+    ctl->res = bc;
+    ctl->thresh = in.scal[SC_TOL] * bc;
+    ctl->inv_h = bc > 0.0 ? 1.0 / bc : 0.0;
+    if (bc == 0.0) ctl->done = 1;
+}
+
+void b_ba_start(const BLaunch& L, int pmask) {
+    hipLaunchKernelGGL(k_ba_norm, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
+    hipLaunchKernelGGL(k_ba_ctl, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
+}
+
+// V[:,k] = u / h_{k,k-1} (u = V_U, 1/h = ctl->inv_h, k = ctl->k) for instances still
+// iterating: after the start (k = 0, 1/h = 1/beta_C) and after each Givens step
+__global__ __launch_bounds__(BLOCK) void k_ba_vnext(const Inst* __restrict__ I, int pmask) {
+    INST;
+    const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
+    if (!takes_part(in, pmask) || ctl->done) return;
+    const double ih = ctl->inv_h;
+    const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
+    LPK_GLOBAL double* __restrict__ v = to_global(in.V + (int64_t)ctl->k * in.ldv);
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)bx * BLOCK + threadIdx.x; i < in.m; i += stride) v[i] = u[i] * ih;
+}
+
+void b_ba_vnext(const BLaunch& L, int pmask) {
+    hipLaunchKernelGGL(k_ba_vnext, dim3(capg(cdiv(L.max_m, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I,
+                       pmask);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_true_res(const Inst* __restrict__ I, int pmask) {

@@ -12,9 +12,9 @@ namespace lpk {
 // ------------------------------------------------------------------------------------
 // start of Krylov iteration k, NE-SOR instances whose colour 0 leaves some column
 // uncovered: z = 0 (the first sweep sets V[:,k] and p_k itself)
-__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int mixed) {
+__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int mixed, int pmask) {
     INST;
-    if (in.ctl->done || in.gsor || in.zcover || in.lds || in.ncol == 0) return;
+    if (!takes_part(in, pmask) || in.gsor || in.zcover || in.lds || in.ncol == 0) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     if (mixed) {
         for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
@@ -24,9 +24,9 @@ __global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int 
     }
 }
 
-void b_prep(const BLaunch& L) {
+void b_prep(const BLaunch& L, int pmask) {
     hipLaunchKernelGGL(k_prep, dim3(capg(cdiv(L.max_n, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I,
-                       L.mixed);
+                       L.mixed, pmask);
 }
 
 // ------------------------------------------------------------------------------------
@@ -53,10 +53,10 @@ void b_prep(const BLaunch& L) {
 // a colour whose columns are strided, as the sinks of a transportation matrix, share
 // lines across neighbouring rows).
 template <typename T, int R>
-__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir, int keepz) {
+__global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir, int keepz, int pmask, int ba) {
     INST;
     const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
-    if (ctl->done || in.gsor || in.lds || c >= in.ncol) return;
+    if (!takes_part(in, pmask) || in.gsor || in.lds || c >= in.ncol) return;
     const LPK_GLOBAL int32_t* cstart = to_global(in.cstart);
     const int r0 = cstart[c], r1 = cstart[c + 1], gc = to_global(in.cg)[c];
     const int tid = bx * BLOCK + threadIdx.x;
@@ -79,12 +79,14 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
     const int64_t k = ctl->k;
-    LPK_GLOBAL double* __restrict__ vk = to_global(in.V + k * in.ldv);
-    LPK_GLOBAL double* __restrict__ p = to_global(in.P + k * in.ldv);
+    // AB-GMRES / CG: input V_U / h into V[:,k], multipliers into P[:,k]; BA-GMRES: input
+    // V_U as it is, kept in V_R64, multipliers into V_U
+    LPK_GLOBAL double* __restrict__ vk = to_global(ba ? in.vec[V_R64] : in.V + k * in.ldv);
+    LPK_GLOBAL double* __restrict__ p = to_global(ba ? in.vec[V_U] : in.P + k * in.ldv);
     const LPK_GLOBAL int32_t* __restrict__ rp = to_global(in.rp);
     const int s = rp[row], e = rp[row + 1];
     // first sweep: v_k = u / h_{k,k-1} is formed here and stored; p_k starts from delta
-    const double vrow = sw == 0 ? to_global(in.vec[V_U])[row] * ctl->inv_h : vk[row];
+    const double vrow = sw == 0 ? to_global(in.vec[V_U])[row] * (ba ? 1.0 : ctl->inv_h) : vk[row];
     const LPK_GLOBAL T* __restrict__ val;
     LPK_GLOBAL T* __restrict__ z;
     if constexpr (sizeof(T) == 4) {
@@ -150,19 +152,21 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
 // needs for the colour; the arithmetic is the same for every R, only longer rows stream
 // their elements twice)
 template <typename T>
-static void launch_nesor(const BLaunch& L, int R, dim3 gr, int colour, int pass, int npass, int dir, int kz) {
+static void launch_nesor(const BLaunch& L, int R, dim3 gr, int colour, int pass, int npass, int dir, int kz,
+                         int pmask) {
     const dim3 bl(BLOCK);
-    if (R <= 8) hipLaunchKernelGGL((k_nesor<T, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
-    else if (R <= 16) hipLaunchKernelGGL((k_nesor<T, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
-    else hipLaunchKernelGGL((k_nesor<T, 32>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz);
+    const int ba = L.ba ? 1 : 0;
+    if (R <= 8) hipLaunchKernelGGL((k_nesor<T, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
+    else if (R <= 16) hipLaunchKernelGGL((k_nesor<T, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
+    else hipLaunchKernelGGL((k_nesor<T, 32>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
 }
 
-void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir) {
+void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir, int pmask) {
     const unsigned gx = capg(L.grid_colour[colour], 1 << 30);
     const int R = L.colour_r ? L.colour_r[colour] : 8;
     const dim3 gr(gx, L.S);
-    if (L.mixed) launch_nesor<float>(L, R, gr, colour, pass, npass, dir, 0);
-    else launch_nesor<double>(L, R, gr, colour, pass, npass, dir, L.keep_z ? 1 : 0);
+    if (L.mixed) launch_nesor<float>(L, R, gr, colour, pass, npass, dir, 0, pmask);
+    else launch_nesor<double>(L, R, gr, colour, pass, npass, dir, L.keep_z ? 1 : 0, pmask);
 }
 
 }  // namespace lpk

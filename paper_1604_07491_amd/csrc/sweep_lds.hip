@@ -17,7 +17,8 @@ namespace lpk {
 // in one coalesced pass, so the colour steps, each a dependent chain of loads, run on LDS
 // alone; v_k and p_k are written back at the end.  Each row is handled exactly as in
 // k_nesor (same lanes per row, same element-to-lane assignment, same sub-group sum).
-// keepz: z is copied out to V_Z64 at the end (z_k = A_hat^T p_k).  A colour step is a
+// keepz: z is copied out to V_Z64 at the end (z_k = A_hat^T p_k).  ba (BA-GMRES): the
+// input is V_U as it is, kept in V_R64, and the multipliers go to V_U.  A colour step is a
 // chain of dependent LDS accesses, sub-group shuffles and a barrier; 1024 threads per block
 // measured as fast as 256 and twice as fast as 64 on the 200 x 500 LPs.
 // LDS layout (STAGED): p (m doubles), v (m doubles), values (nnz T), z (n T), row pointers
@@ -26,16 +27,16 @@ namespace lpk {
 constexpr int NT = 1024;
 
 template <typename T, bool STAGED>
-__global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int keepz) {
+__global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int keepz, int pmask, int ba) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     INST;
-    if (in.ctl->done || in.lds != (STAGED ? 2 : 1)) return;
+    if (!takes_part(in, pmask) || in.lds != (STAGED ? 2 : 1)) return;
     const int m = in.m, n = in.n, nnz = in.nnz, ncol = in.ncol;
     const int64_t k = in.ctl->k;
-    const double ih = in.ctl->inv_h;
+    const double ih = ba ? 1.0 : in.ctl->inv_h;
     const double* __restrict__ u = in.vec[V_U];
-    double* __restrict__ vk = in.V + k * in.ldv;
-    double* __restrict__ p = in.P + k * in.ldv;
+    double* __restrict__ vk = ba ? in.vec[V_R64] : in.V + k * in.ldv;
+    double* __restrict__ p = ba ? in.vec[V_U] : in.P + k * in.ldv;
     const T* __restrict__ gval;
     if constexpr (sizeof(T) == 4) gval = (const T*)in.ah32;
     else gval = (const T*)in.ah;
@@ -160,16 +161,16 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
     }
 }
 
-void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged) {
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged, int pmask) {
     const dim3 gr(1, L.S), bl(NT);
     const int by = staged ? L.stage_bytes : L.lds_bytes;
-    const int kz = L.keep_z ? 1 : 0;
+    const int kz = L.keep_z ? 1 : 0, ba = L.ba ? 1 : 0;
     if (staged) {
-        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, true>), gr, bl, by, L.st, L.I, npass, ssor, 0);
-        else hipLaunchKernelGGL((k_sweep_lds<double, true>), gr, bl, by, L.st, L.I, npass, ssor, kz);
+        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, true>), gr, bl, by, L.st, L.I, npass, ssor, 0, pmask, ba);
+        else hipLaunchKernelGGL((k_sweep_lds<double, true>), gr, bl, by, L.st, L.I, npass, ssor, kz, pmask, ba);
     } else {
-        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, false>), gr, bl, by, L.st, L.I, npass, ssor, 0);
-        else hipLaunchKernelGGL((k_sweep_lds<double, false>), gr, bl, by, L.st, L.I, npass, ssor, kz);
+        if (L.mixed) hipLaunchKernelGGL((k_sweep_lds<float, false>), gr, bl, by, L.st, L.I, npass, ssor, 0, pmask, ba);
+        else hipLaunchKernelGGL((k_sweep_lds<double, false>), gr, bl, by, L.st, L.I, npass, ssor, kz, pmask, ba);
     }
 }
 

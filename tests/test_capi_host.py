@@ -122,6 +122,30 @@ def test_unknown_krylov_method_is_rejected_on_the_host():
     assert _try_create(*args, inner=9)[0] == lpk.LP_EINVAL
 
 
+def test_footprint_of_bagmres_holds_a_basis_but_no_multiplier_vectors():
+    """BA-GMRES keeps a basis of krylov_max_iter + 1 m-vectors like AB-GMRES, but its
+    sweeps leave the multipliers in place, so it holds no per-iteration multiplier vectors."""
+    m, n, nnz, k = 600, 90000, 180000, 50
+    ab = lpk.lp_footprint_bytes(m, n, nnz, lpk.options(krylov_max_iter=k))
+    ba = lpk.lp_footprint_bytes(m, n, nnz, lpk.options(krylov="bagmres", krylov_max_iter=k))
+    ba2 = lpk.lp_footprint_bytes(m, n, nnz, lpk.options(krylov="bagmres", krylov_max_iter=2 * k))
+    # P: k + 1 columns of m doubles against 1 (each allocation rounded up to 256 bytes)
+    assert abs((ab - ba) - 8 * m * k) <= 256
+    assert ba2 - ba >= 8 * m * k
+
+
+def test_bagmres_options_are_checked_on_the_host():
+    lp = synth.config(0)
+    args = (lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c)
+    # BA-GMRES runs the NE-SOR / NE-SSOR sweeps in place, in FP64
+    assert _try_create(*args, krylov=lpk.LP_BAGMRES, inner=lpk.LP_CIMMINO)[0] == lpk.LP_EINVAL
+    assert _try_create(*args, krylov=lpk.LP_BAGMRES, precision=lpk.LP_MIXED)[0] == lpk.LP_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        for inner in (lpk.LP_NESOR, lpk.LP_NESSOR):
+            assert _try_create(*args, krylov=lpk.LP_BAGMRES, inner=inner)[0] == lpk.LP_EDEVICE
+
+
 def test_mixed_precision_allocates_fp32_copies_only_where_sweeps_stream():
     """FP32 copies of A_hat exist only when z does not fit in LDS (n * 8 > 48 KiB)."""
     small = (200, 500, 3000)
