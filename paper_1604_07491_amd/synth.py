@@ -21,6 +21,10 @@ Workload families (sizes are the defaults; every one takes a seed):
 * ``basis_pursuit_lp``: A = [Phi, -Phi] with a dense Gaussian Phi, b = Phi x_true for a
   sparse +-1 signal and c = 1.  Stands in for the dense basis-pursuit problems.
 * ``serving_mix``: a list of sparse LPs of random sizes with Poisson arrival times.
+* ``bounded_lp``: a ``sparse_lp`` matrix with general bounds lo <= x <= hi (lower-bounded,
+  boxed, upper-bounded only, free and fixed variables in stated fractions); the LP is
+  given in that bounded form, not in standard form.  Stands in for the typical LPs with
+  general bounds of the paper's experiments.
 """
 from __future__ import annotations
 
@@ -280,3 +284,63 @@ def serving_mix(count: int = 256, m_lo: int = 200, m_hi: int = 20_000, seed0: in
     gaps = arng.exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps) - gaps[0]
     return lps, arrivals
+
+
+def bounded_lp(m_base: int = 198, n: int = 500, nnz_per_col: int = 6, n_dup: int = 2, seed: int = 0,
+               frac_box: float = 0.3, frac_upper: float = 0.1, frac_free: float = 0.1,
+               frac_fixed: float = 0.02):
+    """``min c^T x  s.t.  A x = b, lo <= x <= hi`` on the matrix of ``sparse_lp``.
+
+    Returns ``(lp, lo, hi)``; ``lp`` carries A, b and c of the bounded problem (its ``b``
+    and ``c`` are those of this LP, not of a standard form).  Variable kinds are drawn in
+    the stated fractions, the rest lower-bounded: lower l ~ U(-2, 2); box l ~ U(-2, 2),
+    u = l + U(1, 3); upper-only u ~ U(-2, 2); free; fixed l = u ~ U(-1, 1).  A strictly
+    interior x0 (fixed variables at their value) gives b = A x0, and a dual point y0 with
+    reduced costs of the right sign (> 0 for lower-bounded, < 0 for upper-only, 0 for
+    free, any for box and fixed) gives c, so a bounded optimum exists.  A row whose
+    variables would all be fixed gets one of them boxed instead.
+    """
+    lp = sparse_lp(m_base, n, nnz_per_col, n_dup, seed=seed, name=f"bounded_{m_base + n_dup}x{n}")
+    rng = np.random.default_rng(seed + 7919)
+    kinds = np.zeros(n, np.int64)   # 0 lower, 1 box, 2 upper, 3 free, 4 fixed
+    order = rng.permutation(n)
+    counts = [int(round(f * n)) for f in (frac_box, frac_upper, frac_free, frac_fixed)]
+    start = 0
+    for k, cnt in zip((1, 2, 3, 4), counts):
+        kinds[order[start:start + cnt]] = k
+        start += cnt
+    for i in range(lp.m):
+        cols = lp.col_idx[lp.row_ptr[i]:lp.row_ptr[i + 1]]
+        if np.all(kinds[cols] == 4):
+            kinds[cols[0]] = 1
+    lo = np.full(n, -np.inf)
+    hi = np.full(n, np.inf)
+    x0 = np.zeros(n)
+    r = np.zeros(n)
+    for j in range(n):
+        k = kinds[j]
+        if k == 0:
+            lo[j] = rng.uniform(-2, 2)
+            x0[j] = lo[j] + rng.uniform(0.5, 1.5)
+            r[j] = rng.uniform(0.5, 1.5)
+        elif k == 1:
+            lo[j] = rng.uniform(-2, 2)
+            hi[j] = lo[j] + rng.uniform(1, 3)
+            x0[j] = lo[j] + (hi[j] - lo[j]) * rng.uniform(0.25, 0.75)
+            r[j] = rng.uniform(-1, 1)
+        elif k == 2:
+            hi[j] = rng.uniform(-2, 2)
+            x0[j] = hi[j] - rng.uniform(0.5, 1.5)
+            r[j] = -rng.uniform(0.5, 1.5)
+        elif k == 3:
+            x0[j] = rng.standard_normal()
+        else:
+            lo[j] = hi[j] = rng.uniform(-1, 1)
+            x0[j] = lo[j]
+            r[j] = rng.standard_normal()
+    y0 = rng.standard_normal(lp.m)
+    lp.b = csr_matvec(lp, x0)
+    lp.c = csr_rmatvec(lp, y0) + r
+    lp.x0, lp.y0, lp.s0 = x0, y0, None
+    lp.meta = dict(lp.meta, family="bounded", kinds=[int(np.sum(kinds == k)) for k in range(5)])
+    return lp, lo, hi
