@@ -59,6 +59,15 @@ def make_lps(workload, count):
         return [synth.basis_pursuit_lp(1024, 8192, 64, seed=2 + i) for i in range(count)]
     if workload == "sparse_120000x434580":
         return [synth.config(3)]
+    if workload == "bounded_200x500":
+        # general bounds (lower, box, upper-only, free, fixed), reduced to the standard form
+        # by the library; lo and hi ride along on the generator's LP
+        out = []
+        for i in range(count):
+            lp, lo, hi = synth.bounded_lp(198, 500, 6, 2, seed=i)
+            lp.lo, lp.hi = lo, hi
+            out.append(lp)
+        return out
     raise ValueError(workload)
 
 
@@ -70,7 +79,7 @@ def main():
     ap.add_argument("--workload", default="transport_300x300",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
                              "sparse_120000x434580", "serving_mix", "streaming_1199000x4345800",
-                             "copy_probe"])
+                             "bounded_200x500", "copy_probe"])
     ap.add_argument("--ipm-steps", type=int, default=0,
                     help="time this many interior-point steps of the first LP instead of whole solves")
     ap.add_argument("--krylov-cap", type=int, default=1500,
@@ -129,6 +138,9 @@ def main():
     for lp in lps:
         if lp.dense is not None:
             probs.append(lpk.lp_create_dense(dev(lp.dense), dev(lp.b), dev(lp.c), opts))
+        elif hasattr(lp, "lo"):
+            probs.append(lpk.lp_create_bounded(lp.m, lp.n, dev(lp.row_ptr), dev(lp.col_idx), dev(lp.val),
+                                               dev(lp.b), dev(lp.c), dev(lp.lo), dev(lp.hi), opts))
         else:
             probs.append(lpk.lp_create(lp.m, lp.n, dev(lp.row_ptr), dev(lp.col_idx), dev(lp.val), dev(lp.b),
                                        dev(lp.c), opts))
@@ -201,7 +213,12 @@ def main():
         so = oracle.solver_opts(krylov={"abgmres": oracle.ABGMRES, "cgne": oracle.CGNE, "mrne": oracle.MRNE,
                                           "bagmres": oracle.BAGMRES}[args.krylov],
                                 inner={"nesor": oracle.NESOR, "nessor": oracle.NESSOR, "cimmino": oracle.CIMMINO}[args.inner])
-        o = oracle.ipm(lps[0], oracle.ipm_opts(solver=so))
+        if hasattr(lps[0], "lo"):
+            from oracle import bounds
+            o = bounds.ipm_bounded(lps[0].to_dense(), lps[0].b, lps[0].c, lps[0].lo, lps[0].hi,
+                                   oracle.ipm_opts(solver=so))
+        else:
+            o = oracle.ipm(lps[0], oracle.ipm_opts(solver=so))
         tcpu = time.perf_counter() - tc
         cpu = {"value": 1.0 / tcpu, "unit": "LPs/s", "cores": 1, "kind": "oracle",
                "sample": f"1 full solve of the {args.workload} LP ({o['iters']} IPM iterations, {tcpu:.2f} s)",
@@ -229,6 +246,7 @@ def main():
         "krylov_iters": r0["krylov_iters"],
         "gamma_rel": r0["gamma_rel"],
         "config": {"workload": args.workload, "m": lps[0].m, "n": lps[0].n, "nnz": lps[0].nnz,
+                   **({"standard_form": {"m": p0.m, "n": p0.n}} if hasattr(lps[0], "lo") else {}),
                    "lps_per_step": len(probs), "lps_in_lockstep": args.width,
                    "precision": args.precision, "inner": args.inner,
                    "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE", "bagmres": "BA-GMRES"}[args.krylov],

@@ -163,6 +163,48 @@ lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
 lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
                           const double* c, const lp_options* o, lp_problem** out);
 
+/* The same problem with general bounds: min c^T x s.t. A x = b, lo <= x <= hi, with
+ * lo[j] = -INFINITY and hi[j] = +INFINITY allowed (n each; host or device per
+ * device_io, like the other inputs).  As for the typical LPs of the experiments
+ * (Sec. 4.3, after LIPSOL), the problem is brought to the standard form of the
+ * introduction on the host and that form is solved:
+ *   lo finite, hi infinite:  x_j = lo_j + x'_j
+ *   both finite, lo < hi:    x_j = lo_j + x'_j plus a row x'_j + w_j = hi_j - lo_j, w_j >= 0
+ *   lo infinite, hi finite:  x_j = hi_j - x'_j
+ *   both infinite (free):    x_j = x+_j - x-_j
+ *   lo == hi (fixed):        x_j = lo_j, the column leaves the problem.
+ * Standard-form columns: the kept variables in order, then the negative parts of the
+ * free variables, then the slacks; rows: the rows of A, then one row per boxed variable
+ * (lp_bounds_standard_form returns exactly this form).  Every other entry point then
+ * works on the standard form (lp_get_state returns its x, y, s; lp_result's objectives
+ * omit the constant sum_j c_j shift_j); lp_bounded_solution maps the iterate back.
+ * m > n is allowed when the standard form has m' <= n'.
+ * Errors: those of lp_create; LP_EINVAL also for NaN bounds, lo_j = +inf, hi_j = -inf,
+ * lo_j > hi_j, or a row whose variables are all fixed; LP_EDIM when m' > n'.            */
+lp_status lp_create_bounded(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* val, const double* b, const double* c,
+                            const double* lo, const double* hi, const lp_options* o, lp_problem** out);
+
+/* For a problem made by lp_create_bounded: the current iterate in the caller's
+ * variables, x[n] (lo <= x <= hi up to the iterate's interiority), the multipliers y[m]
+ * of the rows of A (the first m of the standard form's, caller's row order), and
+ * *obj = c^T x.  x, y host or device per device_io (either may be NULL); obj a host
+ * pointer (may be NULL).  Errors: LP_EINVAL (NULL p, or p not made by lp_create_bounded),
+ * LP_EDEVICE.                                                                          */
+lp_status lp_bounded_solution(const lp_problem* p, double* x, double* y, double* obj);
+
+/* The standard form of lp_create_bounded on the host alone (no device needed; host
+ * arrays).  First call with row_ptr_out == NULL: sizes only (*m_out, *n_out, *nnz_out).
+ * Second call with caller-allocated row_ptr_out[m'+1], col_idx_out[nnz'], val_out[nnz'],
+ * b_out[m'], c_out[n'] and optionally offset (the objective constant).
+ * Errors: LP_EINVAL (malformed CSR, invalid bounds, a row of fixed variables, NULL),
+ * LP_ENONFINITE (b, c or A), LP_EDIM.                                                   */
+lp_status lp_bounds_standard_form(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                  const double* val, const double* b, const double* c, const double* lo,
+                                  const double* hi, int64_t* m_out, int64_t* n_out, int64_t* nnz_out,
+                                  int64_t* row_ptr_out, int32_t* col_idx_out, double* val_out, double* b_out,
+                                  double* c_out, double* offset);
+
 /* Release every device and host resource of p (NULL is a no-op).                        */
 void lp_destroy(lp_problem* p);
 

@@ -101,6 +101,12 @@ SIGNATURES = {
                             C.POINTER(C.c_void_p)]),
     "lp_create_dense": (C.c_int, [C.c_int64, C.c_int64, _P, C.c_int64, _P, _P, C.POINTER(Options),
                                   C.POINTER(C.c_void_p)]),
+    "lp_create_bounded": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P,
+                                    C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "lp_bounded_solution": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
+    "lp_bounds_standard_form": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P,
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                          _P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
     "lp_destroy": (None, [_P]),
     "ipm_step": (C.c_int, [_P, C.POINTER(IterInfo)]),
     "direction_solve": (C.c_int, [_P, _P, _P, C.c_double, _P, _P, C.POINTER(KrylovInfo)]),
@@ -296,6 +302,78 @@ def from_lp(lp, opts: Optional[Options] = None, device=False, **kw) -> Problem:
         t = lambda a: torch.as_tensor(np.asarray(a)).cuda()
         return lp_create(lp.m, lp.n, t(lp.row_ptr), t(lp.col_idx), t(lp.val), t(lp.b), t(lp.c), opts, **kw)
     return lp_create(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c, opts, **kw)
+
+
+def lp_bounds_standard_form(m, n, row_ptr, col_idx, val, b, c, lo, hi) -> dict:
+    """``lp_bounds_standard_form``: the standard form of min c^T x, A x = b, lo <= x <= hi
+    built on the host (host arrays)."""
+    arrs = [np.ascontiguousarray(a, dt) for a, dt in ((row_ptr, np.int64), (col_idx, np.int32),
+                                                     (val, np.float64), (b, np.float64), (c, np.float64),
+                                                     (lo, np.float64), (hi, np.float64))]
+    ms, ns, nz = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    ptrs = [a.ctypes.data for a in arrs]
+    _check(lib().lp_bounds_standard_form(int(m), int(n), *ptrs, C.byref(ms), C.byref(ns), C.byref(nz),
+                                         None, None, None, None, None, None), "lp_bounds_standard_form")
+    rp = np.zeros(ms.value + 1, np.int64)
+    ci = np.zeros(nz.value, np.int32)
+    v = np.zeros(nz.value)
+    bs = np.zeros(ms.value)
+    cs = np.zeros(ns.value)
+    off = C.c_double(0.0)
+    _check(lib().lp_bounds_standard_form(int(m), int(n), *ptrs, C.byref(ms), C.byref(ns), C.byref(nz),
+                                         rp.ctypes.data, ci.ctypes.data, v.ctypes.data, bs.ctypes.data,
+                                         cs.ctypes.data, C.byref(off)), "lp_bounds_standard_form")
+    return dict(m=ms.value, n=ns.value, row_ptr=rp, col_idx=ci, val=v, b=bs, c=cs, offset=off.value)
+
+
+def lp_create_bounded(m, n, row_ptr, col_idx, val, b, c, lo, hi, opts: Optional[Options] = None,
+                      **kw) -> Problem:
+    """``lp_create_bounded`` (general bounds, reduced to the standard form on the host).
+    The returned Problem's m and n are the standard form's; m0 and n0 the caller's."""
+    o = opts if opts is not None else options(**kw)
+    host = [np.asarray(a.cpu() if _is_torch(a) else a) for a in (row_ptr, col_idx, val, b, c, lo, hi)]
+    sf = lp_bounds_standard_form(m, n, *host)   # sizes of the standard form
+    keep = []
+    if not o.stream:
+        import torch
+        if torch.cuda.is_available():
+            o.stream = torch.cuda.current_stream().cuda_stream
+    if _is_torch(val):
+        import torch
+        o.device_io = 1
+        if not o.stream:
+            o.stream = torch.cuda.current_stream().cuda_stream
+    ptrs = []
+    for a, dt in ((row_ptr, np.int64), (col_idx, np.int32), (val, np.float64), (b, np.float64), (c, np.float64),
+                  (lo, np.float64), (hi, np.float64)):
+        p_, k_ = _ptr(a, dt)
+        ptrs.append(p_)
+        keep.append(k_)
+    h = C.c_void_p(None)
+    _check(lib().lp_create_bounded(int(m), int(n), int(host[0][-1]), *ptrs, C.byref(o), C.byref(h)),
+           "lp_create_bounded")
+    p = Problem(h.value, sf["m"], sf["n"], o)
+    p.m0, p.n0 = int(m), int(n)
+    return p
+
+
+def from_bounded_lp(lp, lo, hi, opts: Optional[Options] = None, device=False, **kw) -> Problem:
+    """lp_create_bounded from a bounded generator LP (synth.bounded_lp)."""
+    if device:
+        import torch
+        t = lambda a: torch.as_tensor(np.asarray(a)).cuda()
+        return lp_create_bounded(lp.m, lp.n, t(lp.row_ptr), t(lp.col_idx), t(lp.val), t(lp.b), t(lp.c), t(lo),
+                                 t(hi), opts, **kw)
+    return lp_create_bounded(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c, lo, hi, opts, **kw)
+
+
+def lp_bounded_solution(p: Problem):
+    """(x, y, obj) of a bounded problem in the caller's variables and rows."""
+    x, px = p._out(getattr(p, "n0", p.n))
+    y, py = p._out(getattr(p, "m0", p.m))
+    obj = C.c_double(0.0)
+    _check(lib().lp_bounded_solution(p.h, px, py, C.byref(obj)), "lp_bounded_solution")
+    return x, y, obj.value
 
 
 def ipm_step(p: Problem) -> dict:

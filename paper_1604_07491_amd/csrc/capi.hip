@@ -158,9 +158,9 @@ void choose_layout(Colour& C, const int32_t* rp, const int32_t* ci, int zbytes) 
 }
 
 static lp_status validate(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
-                          const double* val) {
+                          const double* val, bool need_m_le_n = true) {
     if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
-    if (m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
+    if (need_m_le_n && m > n) return fail(LP_EDIM, "m > n: the problem statement assumes m <= n");
     if (nnz < 1 || nnz >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31))
         return fail(LP_EDIM, "nnz and n must be below 2^31");
     if (!rp || !ci || !val) return fail(LP_EINVAL, "NULL CSR array");
@@ -416,6 +416,24 @@ static lp_status check_options(const lp_options& o, bool dense) {
     return LP_OK;
 }
 
+// the bounded-variable reduction of caller arrays already on the host: validation (the
+// original problem may have m > n), then the standard form
+static lp_status bounded_standard(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci,
+                                  const double* val, const double* b, const double* c, const double* lo,
+                                  const double* hi, StdForm& sf, BoundMap& bm) {
+    if (!rp || !ci || !val || !lo || !hi) return fail(LP_EINVAL, "NULL input array");
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    lp_status rc = validate(m, n, rp[m], rp, ci, val, false);
+    if (rc != LP_OK) return rc;
+    if ((rc = check_vec(b, m, "b")) != LP_OK) return rc;
+    if ((rc = check_vec(c, n, "c")) != LP_OK) return rc;
+    std::string err;
+    if (!bounds_to_standard(m, n, rp, ci, val, b, c, lo, hi, sf, bm, err)) return fail(LP_EINVAL, err);
+    if (sf.rp.back() >= ((int64_t)1 << 31) || sf.n >= ((int64_t)1 << 31))
+        return fail(LP_EDIM, "the standard form has 2^31 or more nonzeros or columns");
+    return LP_OK;
+}
+
 static lp_status copy_out(lp_problem* p, const double* dev, double* dst, int64_t len) {
     const hipMemcpyKind k = p->opt.device_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     LPK_HIP(hipMemcpyAsync(dst, dev, sizeof(double) * len, k, p->st));
@@ -463,9 +481,12 @@ lp_status lp_options_default(lp_options* o) {
     return LP_OK;
 }
 
+// host_inputs: the arrays are host arrays whatever opt.device_io says (the bounded-variable
+// entry point passes its standard form); the problem keeps the caller's device_io
 static lp_status create_impl(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
                              const int32_t* col_idx, const double* val, const double* b,
-                             const double* c, const lp_options* o, bool dense, lp_problem** out) {
+                             const double* c, const lp_options* o, bool dense, lp_problem** out,
+                             bool host_inputs = false) {
     g_err.clear();
     if (!out) return fail(LP_EINVAL, "NULL out");
     *out = nullptr;
@@ -480,7 +501,7 @@ static lp_status create_impl(int64_t m, int64_t n, int64_t nnz, const int64_t* r
     std::vector<int64_t> hrp;
     std::vector<int32_t> hci;
     std::vector<double> hval, hb, hc;
-    const bool dev = opt.device_io != 0;
+    const bool dev = opt.device_io != 0 && !host_inputs;
     if (dev) {
         rc = check_device();
         if (rc != LP_OK) return rc;
@@ -533,6 +554,79 @@ lp_status lp_create(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
                     const int32_t* col_idx, const double* val, const double* b, const double* c,
                     const lp_options* o, lp_problem** out) {
     return create_impl(m, n, nnz, row_ptr, col_idx, val, b, c, o, false, out);
+}
+
+lp_status lp_create_bounded(int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* val, const double* b, const double* c,
+                            const double* lo, const double* hi, const lp_options* o, lp_problem** out) {
+    g_err.clear();
+    if (!out) return fail(LP_EINVAL, "NULL out");
+    *out = nullptr;
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    if (!row_ptr || !col_idx || !val || !b || !c || !lo || !hi) return fail(LP_EINVAL, "NULL input array");
+    lp_options opt;
+    if (o) opt = *o;
+    else lp_options_default(&opt);
+    lp_status rc = check_options(opt, false);
+    if (rc != LP_OK) return rc;
+    std::vector<int64_t> hrp;
+    std::vector<int32_t> hci;
+    std::vector<double> hval, hb, hc, hlo, hhi;
+    if (opt.device_io) {
+        if ((rc = check_device()) != LP_OK) return rc;
+        if ((rc = fetch(row_ptr, m + 1, true, hrp)) != LP_OK) return rc;
+        if (hrp[m] < 1 || hrp[m] >= ((int64_t)1 << 31)) return fail(LP_EDIM, "nnz must be in [1, 2^31)");
+        if ((rc = fetch(col_idx, hrp[m], true, hci)) != LP_OK) return rc;
+        if ((rc = fetch(val, hrp[m], true, hval)) != LP_OK) return rc;
+        if ((rc = fetch(b, m, true, hb)) != LP_OK) return rc;
+        if ((rc = fetch(c, n, true, hc)) != LP_OK) return rc;
+        if ((rc = fetch(lo, n, true, hlo)) != LP_OK) return rc;
+        if ((rc = fetch(hi, n, true, hhi)) != LP_OK) return rc;
+        row_ptr = hrp.data();
+        col_idx = hci.data();
+        val = hval.data();
+        b = hb.data();
+        c = hc.data();
+        lo = hlo.data();
+        hi = hhi.data();
+    }
+    if (row_ptr[m] != nnz) return fail(LP_EINVAL, "row_ptr must end at nnz");
+    StdForm sf;
+    auto bm = std::make_unique<BoundMap>();
+    if ((rc = bounded_standard(m, n, row_ptr, col_idx, val, b, c, lo, hi, sf, *bm)) != LP_OK) return rc;
+    rc = create_impl(sf.m, sf.n, sf.rp.back(), sf.rp.data(), sf.ci.data(), sf.val.data(), sf.b.data(),
+                     sf.c.data(), &opt, false, out, true);
+    if (rc != LP_OK) return rc;
+    (*out)->bounds = std::move(bm);
+    return LP_OK;
+}
+
+lp_status lp_bounded_solution(const lp_problem* pc, double* x, double* y, double* obj) {
+    g_err.clear();
+    lp_problem* p = const_cast<lp_problem*>(pc);
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    if (!p->bounds) return fail(LP_EINVAL, "the problem was not created by lp_create_bounded");
+    const BoundMap& bm = *p->bounds;
+    std::vector<double> xs((size_t)p->n), ys((size_t)p->m), xo((size_t)bm.n0);
+    LPK_HIP(hipMemcpyAsync(xs.data(), p->vec[V_X], sizeof(double) * p->n, hipMemcpyDeviceToHost, p->st));
+    scatter(p->st, p->m, p->vec[V_Y], p->perm_d, p->vec[V_TMPM]);
+    LPK_HIP(hipMemcpyAsync(ys.data(), p->vec[V_TMPM], sizeof(double) * p->m, hipMemcpyDeviceToHost, p->st));
+    LPK_HIP(hipStreamSynchronize(p->st));
+    bounds_recover(bm, xs.data(), xo.data());
+    if (obj) {
+        double s = 0.0;
+        for (int64_t j = 0; j < bm.n0; ++j) s += bm.c0[(size_t)j] * xo[(size_t)j];
+        *obj = s;
+    }
+    if (p->opt.device_io) {
+        if (x) LPK_HIP(hipMemcpyAsync(x, xo.data(), sizeof(double) * bm.n0, hipMemcpyHostToDevice, p->st));
+        if (y) LPK_HIP(hipMemcpyAsync(y, ys.data(), sizeof(double) * bm.m0, hipMemcpyHostToDevice, p->st));
+        LPK_HIP(hipStreamSynchronize(p->st));
+    } else {
+        if (x) memcpy(x, xo.data(), sizeof(double) * bm.n0);
+        if (y) memcpy(y, ys.data(), sizeof(double) * bm.m0);
+    }
+    return LP_OK;
 }
 
 lp_status lp_create_dense(int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
@@ -775,6 +869,32 @@ lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, i
     *ncolours = (int32_t)p->colours.size();
     if (sizes)
         for (int32_t c = 0; c < *ncolours && c < cap; ++c) sizes[c] = p->colours[c].r1 - p->colours[c].r0;
+    return LP_OK;
+}
+
+lp_status lp_bounds_standard_form(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                  const double* val, const double* b, const double* c, const double* lo,
+                                  const double* hi, int64_t* m_out, int64_t* n_out, int64_t* nnz_out,
+                                  int64_t* row_ptr_out, int32_t* col_idx_out, double* val_out, double* b_out,
+                                  double* c_out, double* offset) {
+    g_err.clear();
+    if (!m_out || !n_out || !nnz_out) return fail(LP_EINVAL, "NULL size output");
+    if (!row_ptr) return fail(LP_EINVAL, "NULL input array");
+    StdForm sf;
+    BoundMap bm;
+    lp_status rc = bounded_standard(m, n, row_ptr, col_idx, val, b, c, lo, hi, sf, bm);
+    if (rc != LP_OK) return rc;
+    *m_out = sf.m;
+    *n_out = sf.n;
+    *nnz_out = sf.rp.back();
+    if (!row_ptr_out) return LP_OK;   // size query
+    if (!col_idx_out || !val_out || !b_out || !c_out) return fail(LP_EINVAL, "NULL output array");
+    std::copy(sf.rp.begin(), sf.rp.end(), row_ptr_out);
+    std::copy(sf.ci.begin(), sf.ci.end(), col_idx_out);
+    std::copy(sf.val.begin(), sf.val.end(), val_out);
+    std::copy(sf.b.begin(), sf.b.end(), b_out);
+    std::copy(sf.c.begin(), sf.c.end(), c_out);
+    if (offset) *offset = bm.offset;
     return LP_OK;
 }
 

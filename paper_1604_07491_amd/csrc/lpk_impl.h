@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/lpk.h"
+#include "bounds.h"
 #include "kernels.h"
 
 namespace lpk {
@@ -153,6 +154,8 @@ struct lp_problem {
     double omega_c = 0.0;                           // Cimmino step of the current scaling
     // the batch of one that serves the single-problem entry points
     std::unique_ptr<lpk::Batch> solo;
+    // lp_create_bounded: how the caller's variables sit in this standard form
+    std::unique_ptr<lpk::BoundMap> bounds;
     ~lp_problem();
 };
 
