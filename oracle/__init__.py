@@ -257,8 +257,10 @@ def _log_dicts(log, count):
     return [{k: getattr(log[i], k) for k in names} for i in range(count)]
 
 
-def ipm(lp, opts: Optional[IpmOpts] = None, x=None, y=None, s=None):
-    """Whole interior-point solve; returns dict(status, x, y, s, iters, gamma, gamma_rel, log)."""
+def ipm(lp, opts: Optional[IpmOpts] = None, x=None, y=None, s=None, pairs=None):
+    """Whole interior-point solve; returns dict(status, x, y, s, iters, gamma, gamma_rel, log).
+    pairs: (k, 2) column indices of split free variables to recentre after the starting
+    point and every step (the bounded-variable reduction)."""
     m, n, rp, ci, val = _csr(lp)
     o = opts if opts is not None else ipm_opts()
     xx = np.zeros(n) if x is None else np.array(x, np.float64)
@@ -272,10 +274,12 @@ def ipm(lp, opts: Optional[IpmOpts] = None, x=None, y=None, s=None):
     iters = C.c_int32(0)
     g = C.c_double(0)
     gr = C.c_double(0)
-    rc = lib().orc_ipm(C.c_int64(m), C.c_int64(n), _p(rp, np.int64), _p(ci, np.int32),
-                       _p(val, np.float64), _p(b, np.float64), _p(c, np.float64), C.byref(o),
-                       _p(xx, np.float64), _p(yy, np.float64), _p(ss, np.float64), log,
-                       C.byref(iters), C.byref(g), C.byref(gr))
+    pr = np.ascontiguousarray(np.zeros((0, 2)) if pairs is None else pairs, np.int64).reshape(-1, 2)
+    rc = lib().orc_ipm_pairs(C.c_int64(m), C.c_int64(n), _p(rp, np.int64), _p(ci, np.int32),
+                             _p(val, np.float64), _p(b, np.float64), _p(c, np.float64), C.byref(o),
+                             C.c_int64(pr.shape[0]), _p(pr, np.int64) if pr.size else None,
+                             _p(xx, np.float64), _p(yy, np.float64), _p(ss, np.float64), log,
+                             C.byref(iters), C.byref(g), C.byref(gr))
     return dict(status=int(rc), x=xx, y=yy, s=ss, iters=int(iters.value), gamma=g.value,
                 gamma_rel=gr.value, log=_log_dicts(log, int(iters.value) + 1),
                 pobj=float(c @ xx), dobj=float(b @ yy))

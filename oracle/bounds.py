@@ -13,6 +13,11 @@ interior-point method, and maps the solution back.  Per original variable x_j:
 * l = -inf, u = +inf (free):    x_j = x+_j - x-_j (a second column -a_j, cost -c_j).
 * l = u (fixed):                x_j = l_j; the column leaves the problem.
 
+The two parts of a split free variable grow without bound along the central path (their
+dual slacks must both vanish), so the solve recentres each pair after the starting point
+and after every step: a smaller part above (1 + |x+ - x-|) / 2 is lowered by the excess,
+both parts by the same amount (x, A x and c^T x unchanged).
+
 Column order of the standard form: the kept original columns in their order, then the
 negative parts of the free variables, then the slacks; rows: the original rows, then one
 row per box variable.  b' = b - sum_j a_j shift_j over the shifted, reflected and fixed
@@ -162,11 +167,17 @@ def recover(bmap: BoundMap, xs, ys):
     return x, np.asarray(ys, np.float64)[:bmap.m0].copy()
 
 
+def free_pairs(bmap: BoundMap):
+    """(k, 2) standard-form columns (x+_j, x-_j) of the free variables, in variable order."""
+    free = np.flatnonzero(bmap.kind == FREE)
+    return np.stack([bmap.col[free], bmap.col2[free]], axis=1).astype(np.int64)
+
+
 def ipm_bounded(A, b, c, lo, hi, opts=None):
     """Solve min c^T x, A x = b, lo <= x <= hi through the standard form; returns the
     oracle's result dict for the standard form plus x, y and obj in the original space."""
     lp, bmap = standard_form(A, b, c, lo, hi)
-    r = ipm(lp, opts if opts is not None else ipm_opts())
+    r = ipm(lp, opts if opts is not None else ipm_opts(), pairs=free_pairs(bmap))
     x, y = recover(bmap, r["x"], r["y"])
     out = dict(r)
     out.update(x_std=r["x"], y_std=r["y"], x=x, y=y, obj=float(np.asarray(c, np.float64) @ x), lp=lp, bmap=bmap)

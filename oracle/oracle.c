@@ -902,16 +902,39 @@ void orc_ipm_opts_default(orc_ipm_opts* op) {
     op->max_backtrack = 200;
 }
 
+/* Split free variables x_j = x+_j - x-_j (the bounded-variable reduction to standard   */
+/* form): both parts grow without bound along the central path, since the two dual     */
+/* slacks of a pair must both vanish.  After the starting point and after every step,   */
+/* a pair whose smaller part exceeds (1 + |x+ - x-|) / 2 is lowered by the excess, both  */
+/* parts by the same amount, which leaves x_j, A x and c^T x unchanged.  pairs holds    */
+/* the two column indices of each pair.                                                */
+static void recentre_pairs(int64_t npairs, const int64_t* pairs, double* x) {
+    for (int64_t t = 0; t < npairs; ++t) {
+        const int64_t p = pairs[2 * t], q = pairs[2 * t + 1];
+        const double a = x[p], b = x[q];
+        const double lo = a < b ? a : b;
+        const double cap = 0.5 * (1.0 + fabs(a - b));
+        if (lo > cap) {
+            const double d = lo - cap;
+            x[p] = a - d;
+            x[q] = b - d;
+        }
+    }
+}
+
 /* The interior-point loop.  x, y, s are outputs (and inputs when op->start == 1).      */
 /* log may hold max_iter + 1 entries or be NULL.  Returns ORC_OK (stopping test met),   */
 /* ORC_NOT_CONVERGED (iteration limit) or ORC_DIVERGED (non-finite or non-positive).    */
-int orc_ipm(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
-            const double* b, const double* c, const orc_ipm_opts* op, double* x, double* y,
-            double* s, orc_iter_log* log, int32_t* iters, double* gamma_out, double* gamma_rel_out) {
+/* npairs > 0: the split free variables to recentre (recentre_pairs).                  */
+int orc_ipm_pairs(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                  const double* b, const double* c, const orc_ipm_opts* op, int64_t npairs,
+                  const int64_t* pairs, double* x, double* y, double* s, orc_iter_log* log,
+                  int32_t* iters, double* gamma_out, double* gamma_rel_out) {
     int rc;
     if (op->start == 0) {
         rc = orc_init_point(m, n, rp, ci, val, b, c, &op->solver, op->init_tol, x, y, s);
         if (rc != ORC_OK) return rc;
+        recentre_pairs(npairs, pairs, x);
     }
     orc_ipm_state st;
     st.eps_in = op->eps_in0;
@@ -940,6 +963,13 @@ int orc_ipm(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const do
         *gamma_rel_out = L.gamma_rel;
         if (rc != ORC_OK) return rc;
         if (done) return ORC_OK;
+        recentre_pairs(npairs, pairs, x);
     }
     return ORC_NOT_CONVERGED;
+}
+
+int orc_ipm(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+            const double* b, const double* c, const orc_ipm_opts* op, double* x, double* y,
+            double* s, orc_iter_log* log, int32_t* iters, double* gamma_out, double* gamma_rel_out) {
+    return orc_ipm_pairs(m, n, rp, ci, val, b, c, op, 0, NULL, x, y, s, log, iters, gamma_out, gamma_rel_out);
 }

@@ -87,6 +87,23 @@ def test_bounded_optimum_matches_highs(shape):
     assert abs(r["pobj"] + r["bmap"].offset - r["obj"]) <= 1e-8 * max(1.0, abs(r["obj"]))
 
 
+@pytest.mark.parametrize("seed", [6, 8, 43, 56, 60])
+def test_split_free_variables_reach_the_highs_optimum(seed):
+    """LPs of the 200 x 500 bounded family on which the split free variables grew without
+    bound (gamma_rel 1e18 and worse after 99 steps) before the pairs were recentred."""
+    lp0, lo, hi = synth.bounded_lp(198, 500, 6, 2, seed=seed)
+    A = lp0.to_dense()
+    ref = _highs(A, lp0.b, lp0.c, lo, hi)
+    r = bounds.ipm_bounded(A, lp0.b, lp0.c, lo, hi)
+    assert r["status"] == oracle.OK and r["iters"] <= 30
+    assert abs(r["obj"] - ref.fun) <= 1e-7 * max(1.0, abs(ref.fun))
+    # a split pair keeps its smaller part at most (1 + |x|) / 2 (recentred after each step)
+    xs = r["x_std"]
+    pr = bounds.free_pairs(r["bmap"])
+    a, b = xs[pr[:, 0]], xs[pr[:, 1]]
+    assert np.all(np.minimum(a, b) <= 0.5 * (1 + np.abs(a - b)) * (1 + 1e-12))
+
+
 def test_invalid_bounds_are_rejected():
     A = np.array([[1.0, 1.0]])
     with pytest.raises(ValueError):
