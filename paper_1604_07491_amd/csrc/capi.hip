@@ -597,7 +597,30 @@ lp_status lp_create_bounded(int64_t m, int64_t n, int64_t nnz, const int64_t* ro
     rc = create_impl(sf.m, sf.n, sf.rp.back(), sf.rp.data(), sf.ci.data(), sf.val.data(), sf.b.data(),
                      sf.c.data(), &opt, false, out, true);
     if (rc != LP_OK) return rc;
-    (*out)->bounds = std::move(bm);
+    lp_problem* p = *out;
+    // the split free variables' column pairs, recentred by the interior-point steps
+    std::vector<int32_t> pairs;
+    for (int64_t j = 0; j < bm->n0; ++j)
+        if (bm->kind[(size_t)j] == BK_FREE) {
+            pairs.push_back((int32_t)bm->col[(size_t)j]);
+            pairs.push_back((int32_t)bm->col2[(size_t)j]);
+        }
+    if (!pairs.empty()) {
+        p->nfpairs = (int32_t)(pairs.size() / 2);
+        p->fpairs = p->arena.alloc<int32_t>((int64_t)pairs.size());
+        if (!p->fpairs) {
+            destroy(p);
+            *out = nullptr;
+            return fail(LP_ENOMEM, "device allocation failed");
+        }
+        hipError_t e = hipMemcpy(p->fpairs, pairs.data(), sizeof(int32_t) * pairs.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy(p);
+            *out = nullptr;
+            return hip_fail(e, "hipMemcpy");
+        }
+    }
+    p->bounds = std::move(bm);
     return LP_OK;
 }
 

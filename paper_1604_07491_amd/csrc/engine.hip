@@ -168,6 +168,8 @@ static Inst make_inst(Batch& B, int slot) {
     in.C = p->Capply;
     in.C32 = p->C32;
     in.omega = p->opt.omega;
+    in.fpairs = p->fpairs;
+    in.nfpairs = p->nfpairs;
     return in;
 }
 
@@ -244,6 +246,8 @@ lp_status Batch::refresh() {
         // dot tasks: (k + 1) columns x segments, at most 128 blocks of 4 waves per instance
         L.gs_dots_grid = std::max<int>(L.gs_dots_grid, (int)std::min<int64_t>(128, cdiv_i((int64_t)in.nseg * (p->kmax + 1), 4)));
         L.max_ncol = std::max(L.max_ncol, in.ncol);
+        L.any_free = L.any_free || in.nfpairs > 0;
+        L.max_fpairs = std::max(L.max_fpairs, in.nfpairs);
         if (in.lds == 2) {
             L.any_stage = true;
             L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.ncol, L.mixed ? 4 : 8));
@@ -989,7 +993,10 @@ lp_status Engine::round() {
 
     // the step, then the measures of the new point (one reduction pass for both)
     const bool meas = has[MEAS] || (has[UPD] && !stepwise);
-    if (has[UPD]) b_update(b.L, 5);
+    if (has[UPD]) {
+        b_update(b.L, 5);
+        b_free_pairs(b.L, MD_UPD);
+    }
     if (meas) {
         b_spmv(b.L, M_A_CSR, V_X, V_RP, EPI_B_MINUS, V_B, -1, MD_MEAS, false);
         b_spmv(b.L, M_A_CSC, V_Y, V_RD, EPI_B1_MINUS_B2, V_C, V_S, MD_MEAS, false);
@@ -1022,6 +1029,7 @@ lp_status Engine::round() {
         b_red_finish(b.L, 5, ops, MD_BT, 0);
     }
     if (has[SH1] || has[SH2]) b_shift(b.L, MD_SH1 | MD_SH2);
+    if (has[SH2]) b_free_pairs(b.L, MD_SH2);   // the starting point is complete
     if (has[SH2]) b_min2(b.L, MD_SH2);
     if (has[SH1]) {
         const int ops[3] = {0, 0, 0};

@@ -108,6 +108,9 @@ struct Inst {
     double* scal;                         // phase scalars [SC_COUNT]
     int32_t* mode;                        // phase role (Mode bits)
     double omega;
+    const int32_t* fpairs;                // split free variables: (x+ column, x- column) pairs
+    int32_t nfpairs;                      // number of pairs (0 unless made with general bounds)
+    int32_t pad_f;
 };
 
 // host-side launch description of a batch (maxima over its instances)
@@ -135,6 +138,8 @@ struct BLaunch {
     bool any_stage;         // some instance sweeps in one block from LDS alone (lds == 2)
     int stage_bytes;        // largest LDS footprint of those instances
     bool ba;                // BA-GMRES: the sweeps map V_U to V_U (input kept in V_R64)
+    bool any_free;          // some instance has split free variables
+    int max_fpairs;         // most split free variables of an instance
     bool keep_z;            // FP64 NE-SOR / NE-SSOR: the sweeps leave z_k = A_hat^T p_k in
                             // V_Z64, and the loop needs no product with A_hat^T
     int max_ncol_global;    // colours of the instances swept by per-colour launches
@@ -234,7 +239,10 @@ void b_post2(const BLaunch& L);           // MD_POST2: q0, q1 minima
 void b_shift(const BLaunch& L, int pmask);     // q0 x.s, q1 sum x, q2 sum s
 void b_min2(const BLaunch& L, int pmask);      // q0 min x, q1 min s
 void b_backtrack(const BLaunch& L);       // MD_BT: q3 min x_i s_i, q4 x.s at the trial point
-void b_update(const BLaunch& L, int q);   // MD_UPD: q = count of entries not finite positive
+void b_update(const BLaunch& L, int q);
+// split free variables (general bounds): a pair whose smaller part exceeds
+// (1 + |x+ - x-|) / 2 is lowered by the excess, both parts alike (x, A x, c^T x unchanged)
+void b_free_pairs(const BLaunch& L, int pmask);   // MD_UPD: q = count of entries not finite positive
 void b_div_rho(const BLaunch& L, int dst, int src, int pmask);
 
 // ---- single-instance helpers (argument marshalling of the C ABI) -------------------------

@@ -1441,6 +1441,36 @@ void b_update(const BLaunch& L, int q) {
     hipLaunchKernelGGL(k_update, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I, q);
 }
 
+// The two parts of a split free variable x = x+ - x- both grow along the central path
+// (their dual slacks must both vanish).  After the starting point and after each step, a
+// pair whose smaller part exceeds (1 + |x+ - x-|) / 2 is lowered by the excess, both parts
+// by the same amount.  Rounded operations throughout (no contraction), so the new parts
+// are those of the plain formula.
+__global__ __launch_bounds__(BLOCK) void k_free_pairs(const Inst* __restrict__ I, int pmask) {
+    INST;
+    if (!takes_part(in, pmask) || in.nfpairs == 0) return;
+    double* __restrict__ x = in.vec[V_X];
+    const int32_t* __restrict__ pr = in.fpairs;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t t = (int64_t)bx * BLOCK + threadIdx.x; t < in.nfpairs; t += stride) {
+        const int32_t p = pr[2 * t], q = pr[2 * t + 1];
+        const double a = x[p], b = x[q];
+        const double lo = a < b ? a : b;
+        const double cap = __dmul_rn(0.5, __dadd_rn(1.0, fabs(__dsub_rn(a, b))));
+        if (lo > cap) {
+            const double d = __dsub_rn(lo, cap);
+            x[p] = __dsub_rn(a, d);
+            x[q] = __dsub_rn(b, d);
+        }
+    }
+}
+
+void b_free_pairs(const BLaunch& L, int pmask) {
+    if (!L.any_free) return;
+    hipLaunchKernelGGL(k_free_pairs, dim3(capg(cdiv(L.max_fpairs, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st,
+                       L.I, pmask);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_div_rho(const Inst* __restrict__ I, int dst, int src, int pmask) {
     INST;
     if (!takes_part(in, pmask)) return;

@@ -156,6 +156,8 @@ struct lp_problem {
     std::unique_ptr<lpk::Batch> solo;
     // lp_create_bounded: how the caller's variables sit in this standard form
     std::unique_ptr<lpk::BoundMap> bounds;
+    int32_t* fpairs = nullptr;                      // device (x+ column, x- column) per free variable
+    int32_t nfpairs = 0;
     ~lp_problem();
 };
 

@@ -49,6 +49,26 @@ def test_bounded_lp_solve_matches_oracle(shape, krylov):
     assert y.shape == (lp0.m,)
 
 
+@pytest.mark.parametrize("seed", [6, 8, 43, 56, 60])
+def test_split_free_variables_are_recentred(seed):
+    """LPs whose split free variables diverge without the pair recentring (both sides
+    recentre after the starting point and after every step)."""
+    lp0, lo, hi = synth.bounded_lp(198, 500, 6, 2, seed=seed)
+    o = bounds.ipm_bounded(lp0.to_dense(), lp0.b, lp0.c, lo, hi)
+    assert o["status"] == oracle.OK
+    with lpk.from_bounded_lp(lp0, lo, hi) as p:
+        r = lpk.lp_solve(p)
+        x, y, obj = lpk.lp_bounded_solution(p)
+        xs, _, _, _ = lpk.lp_get_state(p)
+    print(f"seed {seed}: gpu iters {r['iters']} oracle {o['iters']} obj {obj!r} oracle {o['obj']!r}", flush=True)
+    assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
+    assert abs(obj - o["obj"]) <= 1e-7 * max(1.0, abs(o["obj"]))
+    _check_point(lp0, lo, hi, x, o["obj"])
+    pr = bounds.free_pairs(o["bmap"])
+    a, b = np.asarray(xs)[pr[:, 0]], np.asarray(xs)[pr[:, 1]]
+    assert np.all(np.minimum(a, b) <= 0.5 * (1 + np.abs(a - b)) * (1 + 1e-12))
+
+
 def test_bounded_device_arrays():
     lp0, lo, hi = synth.bounded_lp(60, 150, 5, 0, seed=1)
     o = bounds.ipm_bounded(lp0.to_dense(), lp0.b, lp0.c, lo, hi)
