@@ -57,7 +57,7 @@ class IpmOpts(C.Structure):
                 ("eps_out", C.c_double), ("eta", C.c_double), ("phi", C.c_double),
                 ("sigma_max", C.c_double), ("eps_in0", C.c_double), ("eps_in_min", C.c_double),
                 ("eps_in_max", C.c_double), ("init_tol", C.c_double), ("backtrack", C.c_double),
-                ("max_backtrack", C.c_int32), ("pad0", C.c_int32)]
+                ("max_backtrack", C.c_int32), ("max_correctors", C.c_int32)]
 
 
 class IterLog(C.Structure):
@@ -65,7 +65,7 @@ class IterLog(C.Structure):
                                           "pobj", "dobj", "alpha_p", "alpha_d", "sigma", "eps_in",
                                           "res_af", "res_cc")] + \
                [("k_af", C.c_int64), ("k_cc", C.c_int64), ("fail_af", C.c_int32),
-                ("fail_cc", C.c_int32), ("backtracks", C.c_int32), ("pad0", C.c_int32)]
+                ("fail_cc", C.c_int32), ("backtracks", C.c_int32), ("correctors", C.c_int32)]
 
 
 class IpmState(C.Structure):
@@ -236,6 +236,33 @@ def corrector_direction(lp, x, s, dx_af, ds_af, sigma_mu, eps, opts=None):
                                        _p(dy, np.float64), _p(ds, np.float64), C.byref(info))
     assert rc == OK, rc
     return dx, dy, ds, info.iters
+
+
+def centrality_target(x, s, dx, ds, tp, td, sigma_mu):
+    """Complementarity target r of a centrality corrector at the trial point (x + tp dx,
+    s + td ds): the products moved into [0.1, 10] sigma mu, decreases capped at 10 sigma mu."""
+    n = len(x)
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (x, s, dx, ds)]
+    r = np.zeros(n)
+    lib().orc_centrality_target(C.c_int64(n), *[_p(a, np.float64) for a in arrs], C.c_double(tp),
+                                C.c_double(td), C.c_double(sigma_mu), _p(r, np.float64))
+    return r
+
+
+def centrality_direction(lp, x, s, r, eps, opts: Optional[SolverOpts] = None):
+    """(dx, dy, ds, info) with A dx = 0, A^T dy + ds = 0, S dx + X ds = r (multiple
+    centrality correctors), by the corrector's min-norm solve."""
+    m, n, rp, ci, val = _csr(lp)
+    o = opts if opts is not None else solver_opts()
+    xx, ss, rr = (np.ascontiguousarray(a, np.float64) for a in (x, s, r))
+    dx, dy, ds = np.zeros(n), np.zeros(m), np.zeros(n)
+    info = KrylovInfo()
+    rc = lib().orc_centrality_direction(C.c_int64(m), C.c_int64(n), _p(rp, np.int64), _p(ci, np.int32),
+                                        _p(val, np.float64), _p(xx, np.float64), _p(ss, np.float64),
+                                        _p(rr, np.float64), C.c_double(eps), C.byref(o), _p(dx, np.float64),
+                                        _p(dy, np.float64), _p(ds, np.float64), C.byref(info))
+    assert rc == OK, rc
+    return dx, dy, ds, {k: getattr(info, k) for k, _ in KrylovInfo._fields_ if k != "pad0"}
 
 
 def init_point(lp, opts=None, tol=1e-10):

@@ -82,14 +82,14 @@ typedef struct {
     double init_tol;    /* tolerance of the two starting-point solves, 1e-10 */
     double backtrack;   /* 0.95 */
     int32_t max_backtrack; /* 200 */
-    int32_t pad0;
+    int32_t max_correctors; /* centrality correctors per step (0: Mehrotra's method alone) */
 } orc_ipm_opts;
 
 typedef struct {
     double mu, gamma, gamma_rel, rp_rel, rd_rel, gap_rel, pobj, dobj;
     double alpha_p, alpha_d, sigma, eps_in, res_af, res_cc;
     int64_t k_af, k_cc;
-    int32_t fail_af, fail_cc, backtracks, pad0;
+    int32_t fail_af, fail_cc, backtracks, correctors;   /* correctors accepted */
 } orc_iter_log;
 
 /* ----------------------------------------------------------------------------------- */
@@ -710,6 +710,58 @@ done:
     return rc;
 }
 
+/* A centrality corrector (multiple centrality correctors of Gondzio, the multi-corrector */
+/* framework the paper names in its comparison with MOSEK): the direction with          */
+/* A dx = 0, A^T dy + ds = 0 and S dx + X ds = r for a complementarity target r, solved  */
+/* like the corrector of Sec. 2.2: f = A t with t = -r/s, min ||dw|| s.t. (A D) dw = f,  */
+/* then ds = -dw/d and dx = -d^2 ds - t.                                                 */
+int orc_centrality_direction(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci,
+                             const double* val, const double* x, const double* s, const double* r,
+                             double eps, const orc_solver_opts* o, double* dx, double* dy, double* ds,
+                             orc_krylov_info* info) {
+    double* d = (double*)malloc((size_t)n * sizeof(double));
+    double* t = (double*)malloc((size_t)n * sizeof(double));
+    double* f = (double*)malloc((size_t)m * sizeof(double));
+    double* dw = (double*)malloc((size_t)n * sizeof(double));
+    int rc = ORC_ENOMEM;
+    if (!d || !t || !f || !dw) goto done;
+    for (int64_t j = 0; j < n; ++j) d[j] = sqrt(x[j] / s[j]);
+    for (int64_t j = 0; j < n; ++j) t[j] = -r[j] / s[j];
+    csr_mv(m, rp, ci, val, t, f);
+    rc = orc_dirsolve(m, n, rp, ci, val, d, f, eps, o, dw, dy, info);
+    if (rc != ORC_OK) goto done;
+    for (int64_t j = 0; j < n; ++j) ds[j] = -dw[j] / d[j];
+    for (int64_t j = 0; j < n; ++j) dx[j] = -d[j] * d[j] * ds[j] - t[j];
+done:
+    free(d); free(t); free(f); free(dw);
+    return rc;
+}
+
+/* Gondzio's corrector parameters: aspiration step increase, acceptance fraction of it,  */
+/* and the box [BMIN, BMAX] sigma mu for the target complementarity products            */
+#define MCC_DELTA 0.1
+#define MCC_GAMMA 0.1
+#define MCC_BMIN 0.1
+#define MCC_BMAX 10.0
+
+/* The complementarity target of a centrality corrector at the trial point of the       */
+/* aspiration step lengths tp, td along (dx, ds): v = (x + tp dx)(s + td ds), each       */
+/* product moved into [BMIN, BMAX] sigma mu, the decrease of large products capped at   */
+/* BMAX sigma mu: r = clip(v) - v, r >= -BMAX sigma mu.                                 */
+void orc_centrality_target(int64_t n, const double* x, const double* s, const double* dx,
+                           const double* ds, double tp, double td, double sigma_mu, double* r) {
+    const double lo = MCC_BMIN * sigma_mu, hi = MCC_BMAX * sigma_mu;
+    for (int64_t j = 0; j < n; ++j) {
+        const double v = (x[j] + tp * dx[j]) * (s[j] + td * ds[j]);
+        double vt = v;
+        if (vt < lo) vt = lo;
+        if (vt > hi) vt = hi;
+        double rj = vt - v;
+        if (rj < -hi) rj = -hi;
+        r[j] = rj;
+    }
+}
+
 /* ----------------------------------------------------------------------------------- */
 /* Starting point: Mehrotra's heuristic, with both least-squares solves done by the     */
 /* same min-norm solver at D = I (so rank-deficient A needs no preprocessing):          */
@@ -851,6 +903,42 @@ int orc_ipm_iterate(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, 
         /* condition min_i x_i s_i >= phi x^T s / n holds at the new point              */
         ap = ratio(n, x, dxa, op->eta);
         ad = ratio(n, s, dsa, op->eta);
+        /* multiple centrality correctors: while a step length is short of 1, aim at     */
+        /* step lengths larger by MCC_DELTA, move the products at that trial point into  */
+        /* the box around sigma mu, and keep the corrected direction when its shorter    */
+        /* step length grows by at least MCC_GAMMA MCC_DELTA; stop at the first miss     */
+        if (op->max_correctors > 0 && sigma > 0.0) {
+            double* r = (double*)malloc((size_t)n * sizeof(double));
+            double* dxk = (double*)malloc((size_t)n * sizeof(double));
+            double* dsk = (double*)malloc((size_t)n * sizeof(double));
+            double* dyk = (double*)malloc((size_t)m * sizeof(double));
+            double* tx = (double*)malloc((size_t)n * sizeof(double));
+            double* ts = (double*)malloc((size_t)n * sizeof(double));
+            rc = ORC_ENOMEM;
+            if (r && dxk && dsk && dyk && tx && ts) {
+                rc = ORC_OK;
+                for (int32_t q = 0; q < op->max_correctors; ++q) {
+                    if (ap >= 1.0 && ad >= 1.0) break;
+                    const double tp = fmin(1.0, ap + MCC_DELTA), td = fmin(1.0, ad + MCC_DELTA);
+                    orc_centrality_target(n, x, s, dxa, dsa, tp, td, sigma * L->mu, r);
+                    orc_krylov_info ik;
+                    rc = orc_centrality_direction(m, n, rp, ci, val, x, s, r, st->eps_in, &op->solver,
+                                                  dxk, dyk, dsk, &ik);
+                    if (rc != ORC_OK) break;
+                    for (int64_t j = 0; j < n; ++j) { tx[j] = dxa[j] + dxk[j]; ts[j] = dsa[j] + dsk[j]; }
+                    const double ap2 = ratio(n, x, tx, op->eta), ad2 = ratio(n, s, ts, op->eta);
+                    if (fmin(ap2, ad2) < fmin(ap, ad) + MCC_GAMMA * MCC_DELTA) break;
+                    memcpy(dxa, tx, (size_t)n * sizeof(double));
+                    memcpy(dsa, ts, (size_t)n * sizeof(double));
+                    for (int64_t i = 0; i < m; ++i) dya[i] += dyk[i];
+                    ap = ap2;
+                    ad = ad2;
+                    L->correctors += 1;
+                }
+            }
+            free(r); free(dxk); free(dsk); free(dyk); free(tx); free(ts);
+            if (rc != ORC_OK) goto done;
+        }
         int32_t t = 0;
         for (;;) {
             double mn = INFINITY, sum = 0.0;
