@@ -95,6 +95,8 @@ def main():
                     help="batch phases: 0 auto, 1 together, 2 each LP alone")
     ap.add_argument("--krylov", default="abgmres", choices=["abgmres", "cgne", "mrne", "bagmres"],
                     help="outer iteration: AB-GMRES (Sec. 3.2), CGNE / MRNE (Sec. 3.3) or BA-GMRES (eq. ba_ne)")
+    ap.add_argument("--correctors", type=int, default=0,
+                    help="multiple centrality correctors per interior-point step (0: Mehrotra's method)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
@@ -133,7 +135,8 @@ def main():
         return steps_main(args)
     lps = make_lps(args.workload, args.batch)
     dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
-    opts = lpk.options(precision=args.precision, inner=args.inner, krylov=args.krylov, schedule=args.schedule)
+    opts = lpk.options(precision=args.precision, inner=args.inner, krylov=args.krylov, schedule=args.schedule,
+                       max_correctors=args.correctors)
     probs = []
     for lp in lps:
         if lp.dense is not None:
@@ -213,12 +216,12 @@ def main():
         so = oracle.solver_opts(krylov={"abgmres": oracle.ABGMRES, "cgne": oracle.CGNE, "mrne": oracle.MRNE,
                                           "bagmres": oracle.BAGMRES}[args.krylov],
                                 inner={"nesor": oracle.NESOR, "nessor": oracle.NESSOR, "cimmino": oracle.CIMMINO}[args.inner])
+        io = oracle.ipm_opts(solver=so, max_correctors=args.correctors)
         if hasattr(lps[0], "lo"):
             from oracle import bounds
-            o = bounds.ipm_bounded(lps[0].to_dense(), lps[0].b, lps[0].c, lps[0].lo, lps[0].hi,
-                                   oracle.ipm_opts(solver=so))
+            o = bounds.ipm_bounded(lps[0].to_dense(), lps[0].b, lps[0].c, lps[0].lo, lps[0].hi, io)
         else:
-            o = oracle.ipm(lps[0], oracle.ipm_opts(solver=so))
+            o = oracle.ipm(lps[0], io)
         tcpu = time.perf_counter() - tc
         cpu = {"value": 1.0 / tcpu, "unit": "LPs/s", "cores": 1, "kind": "oracle",
                "sample": f"1 full solve of the {args.workload} LP ({o['iters']} IPM iterations, {tcpu:.2f} s)",
@@ -250,7 +253,8 @@ def main():
                    "lps_per_step": len(probs), "lps_in_lockstep": args.width,
                    "precision": args.precision, "inner": args.inner,
                    "krylov": {"abgmres": "AB-GMRES", "cgne": "CGNE", "mrne": "MRNE", "bagmres": "BA-GMRES"}[args.krylov],
-                   "inner_sweeps": 2, "omega": 1.0, "schedule": args.schedule},
+                   "inner_sweeps": 2, "omega": 1.0, "schedule": args.schedule,
+                   "max_correctors": args.correctors},
         "roofline": roofline,
         "kernel_classes": {k: {"launches": v["launches"], "ms_total": v["ms_total"],
                                "us_per_launch_event_bracketed": v["ms_total"] * 1e3 / max(v["launches"], 1)}

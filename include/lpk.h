@@ -102,7 +102,16 @@ typedef struct {
                              /* structure (equal m, n, nnz) pass each phase together, others */
                              /* advance alone; 1 always together; 2 always alone [0]; a     */
                              /* member asking 2 wins over 1, 1 over 0                       */
-    int32_t pad0;
+    int32_t max_correctors;  /* multiple centrality correctors per step, in [0, 8] [0]:    */
+                             /* 0 is Mehrotra's predictor-corrector step of Sec. 2.1; K > 0 */
+                             /* adds up to K correctors of Gondzio's multi-corrector method */
+                             /* (the framework the paper names as future work), each one   */
+                             /* more min-norm solve of the corrector's form (eq.            */
+                             /* step_corrector with target products): aim at step lengths  */
+                             /* 0.1 longer, move the products at that trial point into     */
+                             /* [0.1, 10] sigma mu (decreases capped at 10 sigma mu), keep  */
+                             /* the corrected direction if its shorter step length grows by */
+                             /* at least 0.01; stop at the first miss                       */
 } lp_options;
 
 /* Per direction solve (Sec. 4.2 stopping rule ||f_hat - A_hat dw|| <= eps_in ||f_hat||). */
@@ -126,6 +135,9 @@ typedef struct {
     int64_t k_af, k_cc;      /* Krylov iterations of the two solves                       */
     int32_t fail_af, fail_cc, backtracks;
     int32_t converged;       /* 1: the stopping test held at entry; no step was taken     */
+    int32_t correctors;      /* centrality correctors accepted (lp_options.max_correctors) */
+    int32_t pad0;
+    int64_t k_mcc;           /* Krylov iterations of the centrality correctors' solves     */
 } lp_iter_info;
 
 /* Interior-point state beyond (x, y, s): enough to resume at an iteration boundary.     */

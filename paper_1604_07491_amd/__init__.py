@@ -44,7 +44,7 @@ class Options(C.Structure):
                 ("eps_in_max", C.c_double), ("init_tol", C.c_double), ("backtrack", C.c_double),
                 ("max_backtrack", C.c_int32), ("device_io", C.c_int32), ("stream", C.c_void_p),
                 ("poll_every", C.c_int32), ("use_graphs", C.c_int32), ("schedule", C.c_int32),
-                ("pad0", C.c_int32)]
+                ("max_correctors", C.c_int32)]
 
 
 class KrylovInfo(C.Structure):
@@ -57,7 +57,8 @@ class IterInfo(C.Structure):
                                           "pobj", "dobj", "alpha_p", "alpha_d", "sigma", "eps_in",
                                           "res_af", "res_cc")] + \
                [("k_af", C.c_int64), ("k_cc", C.c_int64), ("fail_af", C.c_int32),
-                ("fail_cc", C.c_int32), ("backtracks", C.c_int32), ("converged", C.c_int32)]
+                ("fail_cc", C.c_int32), ("backtracks", C.c_int32), ("converged", C.c_int32),
+                ("correctors", C.c_int32), ("pad0", C.c_int32), ("k_mcc", C.c_int64)]
 
 
 class IpmState(C.Structure):

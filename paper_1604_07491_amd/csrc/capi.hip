@@ -80,6 +80,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
     for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
     for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
+    if (o.max_correctors > 0) { z.add(n, 8); z.add(n, 8); }  // a corrector's dx, ds
     z.add(n, 4); z.add(m, 4);                     // z32, r32
     z.add(m * cols, 8); z.add(m * pcols, 8);      // V, P
     z.add(cols * cols, 8);                        // H
@@ -334,6 +335,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         for (int q : {V_G, V_QM, V_PM}) p->vec[q] = A.alloc<double>(m);
         for (int q : {V_Q, V_PV}) p->vec[q] = A.alloc<double>(n);
     }
+    if (p->opt.max_correctors > 0)
+        for (int q : {V_DXC, V_DSC}) p->vec[q] = A.alloc<double>(n);
     p->z32 = A.alloc<float>(n);
     p->r32 = A.alloc<float>(m);
     p->V = A.alloc<double>(m * cols);
@@ -408,6 +411,7 @@ static lp_status check_options(const lp_options& o, bool dense) {
     if (o.krylov == LP_MRNE && o.precision == LP_MIXED)
         return fail(LP_EINVAL, "MRNE needs FP64 inner iterations (precision LP_FP64)");
     if (o.inner_sweeps < 1 || o.inner_sweeps > 64) return fail(LP_EINVAL, "inner_sweeps must be in [1, 64]");
+    if (o.max_correctors < 0 || o.max_correctors > 8) return fail(LP_EINVAL, "max_correctors must be in [0, 8]");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LP_EINVAL, "omega must be in (0, 2)");
     if (!(o.eta >= 0.9 && o.eta < 1.0)) return fail(LP_EINVAL, "eta must be in [0.9, 1)");
     if (o.ipm_max_iter < 0) return fail(LP_EINVAL, "ipm_max_iter must be >= 0");

@@ -905,12 +905,35 @@ static void take_solve(Batch& b, int s, Engine::Member& mb, lp_krylov_info* ki) 
     if (mb.solve_id >= 0 && mb.solve_id < (int64_t)b.solve_iters.size()) b.solve_iters[mb.solve_id] = hc.iters;
 }
 
+// inside a Krylov solve; inside one or starting one this round
+static bool in_krylov(Engine::State st) { return st == Engine::KRY1 || st == Engine::KRY2 || st == Engine::KRY3; }
+static bool solve_phase(Engine::State st) {
+    return in_krylov(st) || st == Engine::SCALE || st == Engine::RHS2 || st == Engine::RHS3;
+}
+
 // back-tracking from the current step lengths (Sec. 2.1)
 static void begin_bt(Engine::Member& mb, Param& pr) {
     mb.bt = 0;
     pr.scal[SC_AP] = mb.ap;
     pr.scal[SC_AD] = mb.ad;
     mb.state = Engine::BT;
+}
+
+// Multiple centrality correctors (Gondzio): aspiration step lengths MCC_DELTA longer than
+// the current ones; a corrector is kept when the shorter step length grows by at least
+// MCC_GAMMA MCC_DELTA, and the sequence stops at the first miss, after max_correctors, or
+// once both step lengths are 1.
+constexpr double MCC_DELTA = 0.1, MCC_GAMMA = 0.1;
+
+// the next corrector if one is due, else back-tracking
+static void next_corrector(Engine::Member& mb, Param& pr, const lp_options& o) {
+    if (mb.mcc < o.max_correctors && !(mb.ap >= 1.0 && mb.ad >= 1.0)) {
+        pr.scal[SC_AP] = std::min(1.0, mb.ap + MCC_DELTA);
+        pr.scal[SC_AD] = std::min(1.0, mb.ad + MCC_DELTA);
+        mb.state = Engine::RHS3;
+        return;
+    }
+    begin_bt(mb, pr);
 }
 
 lp_status Engine::round() {
@@ -938,7 +961,7 @@ lp_status Engine::round() {
     for (int s = 0; s < b.cap; ++s) {
         const Member& mb = mem[s];
         if (mb.state == EMPTY || mb.state == DONE) continue;
-        if (mb.state == KRY1 || mb.state == KRY2) ++iterating;
+        if (in_krylov(mb.state)) ++iterating;
         sched = std::max(sched, (int)mb.p->opt.schedule);
         if (!ref) ref = mb.p;
         else if (mb.p->m != ref->m || mb.p->n != ref->n || mb.p->nnz != ref->nnz) uniform = false;
@@ -946,14 +969,15 @@ lp_status Engine::round() {
     if (sched == 1) uniform = true;
     if (sched == 2) uniform = false;
     const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
-    bool has[SH2 + 1] = {false};
+    bool has[ST_COUNT] = {false};
+    bool has_add = false;
     int live = 0, solving = 0, waiting = 0;
     for (int s = 0; s < b.cap; ++s) {
         Member& mb = mem[s];
         Param& pr = b.h_param[s];
         const int role = mb.init ? MD_INIT : MD_RUN;
         int md = 0;
-        if (hold && mb.state != EMPTY && mb.state != DONE && mb.state != KRY1 && mb.state != KRY2) {
+        if (hold && mb.state != EMPTY && mb.state != DONE && !in_krylov(mb.state)) {
             pr.mode = role;
             ++live;
             continue;
@@ -970,7 +994,9 @@ lp_status Engine::round() {
                 }
                 break;
             }
-            case KRY1: case KRY2: md = role; break;
+            case KRY1: case KRY2: case KRY3: md = role; break;
+            case RHS3: md = role | MD_RHS3 | MD_START; break;
+            case FIN3: md = role | MD_FIN | MD_POST3; break;
             case FIN1: md = role | MD_FIN | MD_POST1; break;
             case MUAF: md = role | MD_MUAF; break;
             case RHS2: md = role | MD_RHS2 | MD_START; break;
@@ -981,11 +1007,17 @@ lp_status Engine::round() {
             case SH2: md = role | MD_SH2; break;
             default: md = 0;
         }
+        if (mb.mcc_add && mb.state != EMPTY && mb.state != DONE) {
+            // an accepted corrector joins the direction this round, before the phase's kernels
+            md |= MD_MCCADD;
+            has_add = true;
+            mb.mcc_add = false;
+        }
         pr.mode = md;
         if (mb.state == EMPTY || mb.state == DONE) continue;
         has[mb.state] = true;
         ++live;
-        if (mb.state == KRY1 || mb.state == KRY2 || mb.state == SCALE || mb.state == RHS2) ++solving;
+        if (solve_phase(mb.state)) ++solving;
         else ++waiting;
     }
     if (!live) return LP_OK;
@@ -1018,11 +1050,17 @@ lp_status Engine::round() {
         const int ops[2] = {1, 1};
         b_red_finish(b.L, 2, ops, MD_POST2, 0);
     }
+    if (has[FIN3]) {
+        b_post3(b.L);
+        const int ops[2] = {1, 1};
+        b_red_finish(b.L, 2, ops, MD_POST3, 0);
+    }
     if (has[MUAF]) {
         b_mu_af(b.L);
         const int ops[1] = {0};
         b_red_finish(b.L, 1, ops, MD_MUAF, 0);
     }
+    if (has_add) b_mcc_add(b.L);
     if (has[BT]) {
         b_backtrack(b.L);
         const int ops[5] = {0, 0, 0, 1, 0};
@@ -1051,10 +1089,14 @@ lp_status Engine::round() {
         b_rhs2(b.L);
         b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_PLAIN, -1, -1, MD_RHS2, false);
     }
-    if (has[SCALE] || has[RHS2]) {
+    if (has[RHS3]) {   // (after the pending corrector was added above)
+        b_rhs3(b.L);
+        b_spmv(b.L, M_A_CSR, V_TN, V_F, EPI_PLAIN, -1, -1, MD_RHS3, false);
+    }
+    if (has[SCALE] || has[RHS2] || has[RHS3]) {
         enqueue_start(b, MD_START);
         for (int s = 0; s < b.cap; ++s)
-            if (mem[s].state == SCALE || mem[s].state == RHS2) {
+            if (mem[s].state == SCALE || mem[s].state == RHS2 || mem[s].state == RHS3) {
                 mem[s].solve_id = b.solve_id++;
                 b.cur_solve = mem[s].solve_id;
                 mem[s].enq = 0;
@@ -1073,8 +1115,8 @@ lp_status Engine::round() {
             int64_t rem = hold ? 0 : INT64_MAX;
             for (int s = 0; s < b.cap; ++s) {
                 const Member& mb = mem[s];
-                if (mb.state != KRY1 && mb.state != KRY2 && mb.state != SCALE && mb.state != RHS2) continue;
-                const int64_t k = (mb.state == KRY1 || mb.state == KRY2) ? b.h_slot[s].ctl.iters : 0;
+                if (!solve_phase(mb.state)) continue;
+                const int64_t k = in_krylov(mb.state) ? b.h_slot[s].ctl.iters : 0;
                 const int64_t guess = mb.last_k > 0 ? mb.last_k : b.last_iters;
                 const int64_t r = std::max<int64_t>(1, guess - k);
                 rem = hold ? std::max(rem, r) : std::min(rem, r);
@@ -1095,7 +1137,7 @@ lp_status Engine::round() {
             for (int64_t i = 0; i < todo; ++i) enqueue_iteration(b, it0 < 0 ? -1 : it0 + i);
         }
         for (Member& mb : mem)
-            if (mb.state == KRY1 || mb.state == KRY2 || mb.state == SCALE || mb.state == RHS2) mb.enq += todo;
+            if (solve_phase(mb.state)) mb.enq += todo;
         LPK_HIP(hipGetLastError());
     }
     LPK_RC(b.get_slots());
@@ -1104,7 +1146,7 @@ lp_status Engine::round() {
     for (int s = 0; s < b.cap; ++s) {
         Member& mb = mem[s];
         if (mb.state == EMPTY || mb.state == DONE) continue;
-        if (hold && mb.state != KRY1 && mb.state != KRY2) continue;
+        if (hold && !in_krylov(mb.state)) continue;
         lp_problem* p = mb.p;
         const lp_options& o = p->opt;
         Param& pr = b.h_param[s];
@@ -1204,7 +1246,33 @@ lp_status Engine::round() {
                 Lg.fail_cc = ki.failed;
                 mb.ap = step_from(q[0], o.eta);
                 mb.ad = step_from(q[1], o.eta);
-                begin_bt(mb, pr);
+                mb.mcc = 0;
+                if (Lg.sigma > 0.0) next_corrector(mb, pr, o);
+                else begin_bt(mb, pr);
+                break;
+            }
+            case RHS3:
+                mb.state = done ? FIN3 : KRY3;
+                break;
+            case KRY3:
+                if (done) mb.state = FIN3;
+                break;
+            case FIN3: {
+                lp_krylov_info ki;
+                take_solve(b, s, mb, &ki);
+                lp_iter_info& Lg = mb.L;
+                Lg.k_mcc += ki.iters;
+                mb.mcc += 1;
+                const double ap2 = step_from(q[0], o.eta), ad2 = step_from(q[1], o.eta);
+                if (std::min(ap2, ad2) < std::min(mb.ap, mb.ad) + MCC_GAMMA * MCC_DELTA) {
+                    begin_bt(mb, pr);   // rejected: the direction stays as it was
+                    break;
+                }
+                mb.ap = ap2;
+                mb.ad = ad2;
+                mb.mcc_add = true;
+                Lg.correctors += 1;
+                next_corrector(mb, pr, o);
                 break;
             }
             case BT:

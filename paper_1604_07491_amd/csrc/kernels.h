@@ -42,6 +42,7 @@ enum VecSel : int {
     V_TMPM, V_TMPN, V_B, V_C, V_FH, V_U, V_Z64, V_R64,
     V_G, V_QM, V_PM,    // CGNE / MRNE m-vectors: residual (MRNE), multipliers of q and p
     V_Q, V_PV,          // CGNE / MRNE n-vectors: q, p
+    V_DXC, V_DSC,       // a centrality corrector's dx and ds (multiple correctors only)
     V_COUNT
 };
 constexpr int V_PCOL = -1;   // column ctl->k of the multiplier vectors P
@@ -73,6 +74,9 @@ enum Mode : int {
     MD_SH1 = 16384,    // phase: starting point, first shift
     MD_SH2 = 32768,    // phase: starting point, second shift and minima
     MD_UPD = 65536,    // phase: the step x, y, s += alpha d
+    MD_RHS3 = 131072,  // phase: a centrality corrector's right-hand side
+    MD_POST3 = 262144, // phase: after a centrality corrector's solve
+    MD_MCCADD = 524288 // phase: the accepted corrector joins the direction
 };
 
 // per-instance scalars of the current phase (Inst::scal)
@@ -236,6 +240,13 @@ void b_post1(const BLaunch& L);           // MD_POST1: q0, q1 ratio minima (MD_R
 void b_mu_af(const BLaunch& L);           // MD_MUAF: q0 sum (x + ap dx)(s + ad ds)
 void b_rhs2(const BLaunch& L);            // MD_RHS2: t for the second solve
 void b_post2(const BLaunch& L);           // MD_POST2: q0, q1 minima
+// multiple centrality correctors: MD_RHS3 t = -r/s for the target r at the trial point
+// (SC_AP, SC_AD the aspiration step lengths, SC_SMU sigma mu); MD_POST3 the corrector
+// (dxc, dyc, dsc) and the ratio minima of the corrected direction (q0, q1); MD_MCCADD
+// the corrector added to the direction
+void b_rhs3(const BLaunch& L);
+void b_post3(const BLaunch& L);
+void b_mcc_add(const BLaunch& L);
 void b_shift(const BLaunch& L, int pmask);     // q0 x.s, q1 sum x, q2 sum s
 void b_min2(const BLaunch& L, int pmask);      // q0 min x, q1 min s
 void b_backtrack(const BLaunch& L);       // MD_BT: q3 min x_i s_i, q4 x.s at the trial point

@@ -1350,6 +1350,76 @@ void b_post2(const BLaunch& L) {
     hipLaunchKernelGGL(k_post2, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
+// Multiple centrality correctors (Gondzio's multi-corrector method).  The target of a
+// corrector: at the trial point (x + tp dx, s + td ds) of the aspiration step lengths, each
+// product v is moved into [0.1, 10] sigma mu, r = clip(v) - v with r >= -10 sigma mu; the
+// corrector's right-hand side input is t = -r/s (f = A t, a corrector solve as in Sec. 2.2).
+constexpr double MCC_BMIN = 0.1, MCC_BMAX = 10.0;
+
+__global__ __launch_bounds__(BLOCK) void k_rhs3(const Inst* __restrict__ I) {
+    IPM_PROLOGUE(*in.mode & MD_RHS3);
+    const double tp = in.scal[SC_AP], td = in.scal[SC_AD], smu = in.scal[SC_SMU];
+    const double lo = MCC_BMIN * smu, hi = MCC_BMAX * smu;
+    const double *x = in.vec[V_X], *s = in.vec[V_S], *dx = in.vec[V_DXA], *ds = in.vec[V_DSA];
+    double* __restrict__ t = in.vec[V_TN];
+    for (int64_t j = tid0; j < in.n; j += stride) {
+        const double sj = s[j];
+        const double v = (x[j] + tp * dx[j]) * (sj + td * ds[j]);
+        const double vt = fmin(fmax(v, lo), hi);
+        const double r = fmax(vt - v, -hi);
+        t[j] = -r / sj;
+    }
+}
+
+void b_rhs3(const BLaunch& L) {
+    hipLaunchKernelGGL(k_rhs3, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// after a corrector's solve: dyc = dyh / rho, dsc = -dw / d, dxc = -d^2 dsc - t (so that
+// S dxc + X dsc = r), kept apart; the ratio minima of (dx + dxc, ds + dsc)
+__global__ __launch_bounds__(BLOCK) void k_post3(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    IPM_PROLOGUE(*in.mode & MD_POST3);
+    const double *dyh = in.vec[V_DYH], *rho = in.vec[V_RHO], *dw = in.vec[V_DW], *d = in.vec[V_D];
+    const double *x = in.vec[V_X], *s = in.vec[V_S], *dxa = in.vec[V_DXA], *dsa = in.vec[V_DSA];
+    const double* t = in.vec[V_TN];
+    double *dyc = in.vec[V_DYC], *dxc = in.vec[V_DXC], *dsc = in.vec[V_DSC];
+    for (int64_t i = tid0; i < in.m; i += stride) dyc[i] = dyh[i] / rho[i];
+    double q0 = INFINITY, q1 = INFINITY;
+    for (int64_t j = tid0; j < in.n; j += stride) {
+        const double dj = d[j];
+        const double sc = -dw[j] / dj;
+        const double xc = -dj * dj * sc - t[j];
+        dsc[j] = sc;
+        dxc[j] = xc;
+        q0 = fmin(q0, ratio_term(x[j], dxa[j] + xc));
+        q1 = fmin(q1, ratio_term(s[j], dsa[j] + sc));
+    }
+    double r;
+    r = block_min(q0, sh); write_part(in, bx, 0, r);
+    r = block_min(q1, sh); write_part(in, bx, 1, r);
+}
+
+void b_post3(const BLaunch& L) {
+    hipLaunchKernelGGL(k_post3, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// an accepted corrector joins the direction: dx += dxc, ds += dsc, dy += dyc
+__global__ __launch_bounds__(BLOCK) void k_mcc_add(const Inst* __restrict__ I) {
+    IPM_PROLOGUE(*in.mode & MD_MCCADD);
+    double *dxa = in.vec[V_DXA], *dsa = in.vec[V_DSA], *dya = in.vec[V_DYA];
+    const double *dxc = in.vec[V_DXC], *dsc = in.vec[V_DSC], *dyc = in.vec[V_DYC];
+    for (int64_t j = tid0; j < in.n; j += stride) {
+        dxa[j] = dxa[j] + dxc[j];
+        dsa[j] = dsa[j] + dsc[j];
+    }
+    for (int64_t i = tid0; i < in.m; i += stride) dya[i] = dya[i] + dyc[i];
+}
+
+void b_mcc_add(const BLaunch& L) {
+    hipLaunchKernelGGL(k_mcc_add, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
 // starting point: x += hx, s += hs; then x.s, sum x, sum s
 __global__ __launch_bounds__(BLOCK) void k_shift(const Inst* __restrict__ I, int pmask) {
     __shared__ double sh[BLOCK / 64];

@@ -250,7 +250,11 @@ struct Engine {
         FIN2,       // solve 2 assembled; corrector recovery / starting point y, s
         BT,         // back-tracking test
         UPD,        // the step (with the next point's measures unless step-wise)
-        SH1, SH2    // starting point: shifts
+        SH1, SH2,   // starting point: shifts
+        RHS3,       // a centrality corrector's right-hand side; starts its solve
+        KRY3,       // inside a centrality corrector's solve
+        FIN3,       // its solve assembled; corrector recovery and ratio tests
+        ST_COUNT
     };
     struct Member {
         lp_problem* p = nullptr;
@@ -264,6 +268,8 @@ struct Engine {
         lp_iter_info last{};          // the final measures
         bool cc = false;
         double ap = 0.0, ad = 0.0;
+        int32_t mcc = 0;              // centrality correctors tried in this step
+        bool mcc_add = false;         // the last one was accepted: add it in the next round
         int32_t bt = 0;
         double t_join = 0.0, t_done = 0.0;
         int64_t k0 = 0;               // krylov_total at join

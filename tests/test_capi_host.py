@@ -146,6 +146,17 @@ def test_bagmres_options_are_checked_on_the_host():
             assert _try_create(*args, krylov=lpk.LP_BAGMRES, inner=inner)[0] == lpk.LP_EDEVICE
 
 
+def test_centrality_correctors_option():
+    lp = synth.config(0)
+    args = (lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c)
+    for k in (-1, 9):
+        assert _try_create(*args, max_correctors=k)[0] == lpk.LP_EINVAL
+    # a corrector's dx and ds: two more n-vectors
+    a = lpk.lp_footprint_bytes(600, 90000, 180000)
+    b = lpk.lp_footprint_bytes(600, 90000, 180000, lpk.options(max_correctors=2))
+    assert b - a == 2 * 90000 * 8
+
+
 def test_mixed_precision_allocates_fp32_copies_only_where_sweeps_stream():
     """FP32 copies of A_hat exist only when z does not fit in LDS (n * 8 > 48 KiB)."""
     small = (200, 500, 3000)
