@@ -151,10 +151,10 @@ def test_centrality_correctors_option():
     args = (lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b, lp.c)
     for k in (-1, 9):
         assert _try_create(*args, max_correctors=k)[0] == lpk.LP_EINVAL
-    # a corrector's dx and ds: two more n-vectors
+    # a corrector's dx and ds: two more n-vectors (each allocation rounded up to 256 bytes)
     a = lpk.lp_footprint_bytes(600, 90000, 180000)
     b = lpk.lp_footprint_bytes(600, 90000, 180000, lpk.options(max_correctors=2))
-    assert b - a == 2 * 90000 * 8
+    assert 2 * 90000 * 8 <= b - a <= 2 * 90000 * 8 + 512
 
 
 def test_mixed_precision_allocates_fp32_copies_only_where_sweeps_stream():
