@@ -270,6 +270,20 @@ lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options
 /* Number of colours of the row colouring and the colour sizes (sizes may be NULL).      */
 lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, int32_t cap);
 
+/* Presolve of dependent rows (the preprocessing the conclusions name), host only: rows
+ * of A that are scalar multiples of an earlier row, exact duplicates included.  Row k is
+ * such a multiple of row i when both have the same columns and a_kj / a_k0 equals
+ * a_ij / a_i0 to tol (relative; tol = 0 asks for equality), lambda = a_k0 / a_i0.
+ * keep[m] receives 0 for those rows and 1 for the others, *m_keep the rows kept; the
+ * caller builds the reduced LP from the kept rows (the duals of the dropped rows may be
+ * taken as 0).  Linear dependencies among three or more rows are left in place: the
+ * min-norm formulation (Sec. 2.2) solves rank-deficient problems as they are.
+ * Errors: LP_EINVAL (malformed CSR, NULL, tol < 0, or a dropped row whose right-hand
+ * side is not lambda times its partner's to tol: the LP is infeasible),
+ * LP_ENONFINITE, LP_EDIM.                                                              */
+lp_status lp_presolve_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                           const double* val, const double* b, double tol, int32_t* keep, int64_t* m_keep);
+
 /* Greedy row colouring on the host alone (no device needed): colour[m] and the
  * colour-major sweep order perm[m] (rows ascending inside each colour).
  * Errors: LP_EINVAL (malformed CSR).                                                   */

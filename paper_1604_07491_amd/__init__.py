@@ -108,6 +108,7 @@ SIGNATURES = {
     "lp_bounds_standard_form": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P,
                                           C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                           _P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "lp_presolve_rows": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, C.c_double, _P, C.POINTER(C.c_int64)]),
     "lp_destroy": (None, [_P]),
     "ipm_step": (C.c_int, [_P, C.POINTER(IterInfo)]),
     "direction_solve": (C.c_int, [_P, _P, _P, C.c_double, _P, _P, C.POINTER(KrylovInfo)]),
@@ -325,6 +326,18 @@ def lp_bounds_standard_form(m, n, row_ptr, col_idx, val, b, c, lo, hi) -> dict:
                                          rp.ctypes.data, ci.ctypes.data, v.ctypes.data, bs.ctypes.data,
                                          cs.ctypes.data, C.byref(off)), "lp_bounds_standard_form")
     return dict(m=ms.value, n=ns.value, row_ptr=rp, col_idx=ci, val=v, b=bs, c=cs, offset=off.value)
+
+
+def lp_presolve_rows(m, n, row_ptr, col_idx, val, b, tol: float = 1e-12):
+    """``lp_presolve_rows``: a 0/1 mask of the rows to keep (rows that are scalar multiples
+    of an earlier row are dropped)."""
+    arrs = [np.ascontiguousarray(a, dt) for a, dt in ((row_ptr, np.int64), (col_idx, np.int32),
+                                                     (val, np.float64), (b, np.float64))]
+    keep = np.zeros(int(m), np.int32)
+    mk = C.c_int64(0)
+    _check(lib().lp_presolve_rows(int(m), int(n), *[a.ctypes.data for a in arrs], float(tol), keep.ctypes.data,
+                                  C.byref(mk)), "lp_presolve_rows")
+    return keep.astype(bool)
 
 
 def lp_create_bounded(m, n, row_ptr, col_idx, val, b, c, lo, hi, opts: Optional[Options] = None,

@@ -39,4 +39,9 @@ bool bounds_to_standard(int64_t m, int64_t n, const int64_t* rp, const int32_t* 
 // x (n0) from a standard-form point xs.
 void bounds_recover(const BoundMap& map, const double* xs, double* x);
 
+// Presolve: rows that are scalar multiples of an earlier row (keep[i] = 0 for those);
+// false with a message when such a row's right-hand side contradicts (infeasible LP).
+bool presolve_parallel_rows(int64_t m, const int64_t* rp, const int32_t* ci, const double* val,
+                            const double* b, double tol, int32_t* keep, int64_t* m_keep, std::string& err);
+
 }  // namespace lpk

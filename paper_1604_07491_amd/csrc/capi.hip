@@ -925,6 +925,20 @@ lp_status lp_bounds_standard_form(int64_t m, int64_t n, const int64_t* row_ptr, 
     return LP_OK;
 }
 
+lp_status lp_presolve_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                           const double* val, const double* b, double tol, int32_t* keep, int64_t* m_keep) {
+    g_err.clear();
+    if (!row_ptr || !col_idx || !val || !b || !keep || !m_keep) return fail(LP_EINVAL, "NULL argument");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(LP_EINVAL, "tol must be finite and >= 0");
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    lp_status rc = validate(m, n, row_ptr[m], row_ptr, col_idx, val, false);
+    if (rc != LP_OK) return rc;
+    if ((rc = check_vec(b, m, "b")) != LP_OK) return rc;
+    std::string err;
+    if (!presolve_parallel_rows(m, row_ptr, col_idx, val, b, tol, keep, m_keep, err)) return fail(LP_EINVAL, err);
+    return LP_OK;
+}
+
 lp_status lp_colour_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                          int32_t* colour, int32_t* perm, int32_t* ncolours) {
     g_err.clear();
