@@ -1,0 +1,34 @@
+"""Presolve of dependent rows before a GPU solve: the LP with its duplicated rows removed
+(lp_presolve_rows) reaches the optimum of the full LP (the oracle on the full LP).  GPU only."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1604_07491_amd as lpk
+from paper_1604_07491_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _reduced(lp, keep):
+    A = lp.to_dense()[keep]
+    return synth.from_dense(A, lp.b[keep], lp.c)
+
+
+@pytest.mark.parametrize("shape", [(198, 500, 6, 2, 0), (120, 300, 5, 4, 1)])
+def test_presolved_lp_reaches_the_full_optimum(shape):
+    mb, n, k, dup, seed = shape
+    lp = synth.sparse_lp(mb, n, k, dup, seed=seed)
+    keep = lpk.lp_presolve_rows(lp.m, lp.n, lp.row_ptr, lp.col_idx, lp.val, lp.b)
+    assert keep.sum() == mb
+    red = _reduced(lp, keep)
+    o = oracle.ipm(lp)
+    assert o["status"] == oracle.OK
+    with lpk.from_lp(red) as p:
+        r = lpk.lp_solve(p)
+    with lpk.from_lp(lp) as p:
+        rf = lpk.lp_solve(p)
+    print(f"{lp.m}x{lp.n}: reduced iters {r['iters']} krylov {r['krylov_iters']}; "
+          f"full iters {rf['iters']} krylov {rf['krylov_iters']}", flush=True)
+    assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
+    assert abs(r["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
