@@ -15,6 +15,13 @@ Prints one JSON line:
                 achieved = algorithmic bytes per launch (summed over the W LPs) / mean
                 launch duration
   cpu_baseline  the CPU FP64 oracle on the workload LP (one full solve, one core)
+
+Method flags: --krylov (abgmres, cgne, mrne, bagmres), --inner (nesor, nessor, cimmino),
+--precision (fp64, mixed), --correctors K (multiple centrality correctors per step).
+Workloads: the default transportation 300x300 LP, sparse_200x500, bounded_200x500 (general
+bounds, reduced to the standard form by lp_create_bounded), basis_pursuit_1024x16384,
+sparse_120000x434580 (with --ipm-steps), serving_mix, streaming_1199000x4345800 (kernel
+bandwidth), copy_probe (counter calibration).
 """
 import argparse
 import json
