@@ -1039,7 +1039,7 @@ lp_status Engine::round() {
         b_red_finish(b.L, 6, ops, MD_MEAS | MD_UPD, 0);
     }
     // solves that finished: assembly, then direction recovery / starting-point pieces
-    if (has[FIN1] || has[FIN2]) enqueue_assembly(b, MD_FIN);
+    if (has[FIN1] || has[FIN2] || has[FIN3]) enqueue_assembly(b, MD_FIN);
     if (has[FIN1]) {
         b_post1(b.L);
         const int ops[2] = {1, 1};
