@@ -82,6 +82,11 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
     for (int j = threadIdx.x; j < n; j += NT) z[j] = 0;
     __syncthreads();
     const T om = (T)in.omega;
+    // A colour whose rows fit in one wave (rows x lanes <= 64) runs on wave 0 alone, and a
+    // run of such colours needs no block barrier: the LDS accesses of one wave complete in
+    // program order.  A barrier precedes a whole-block colour that follows wave-0 colours
+    // and ends every whole-block colour.
+    bool prev_small = false;
     for (int sw = 0; sw < npass; ++sw) {
         const int dir = ssor ? (sw & 1) : 0;
         for (int cc = 0; cc < ncol; ++cc) {
@@ -90,8 +95,11 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
             const int g = cl[c];
             const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
             const int lane = threadIdx.x & (g - 1);
-            const int per = NT / g;
-            for (int base = r0; base < r1; base += per) {
+            const bool small = (r1 - r0) * g <= 64;
+            if (!small && prev_small) __syncthreads();
+            const int nth = small ? 64 : NT;
+            const int per = nth / g;
+            for (int base = r0; base < r1 && (int)threadIdx.x < nth; base += per) {
                 const int row = base + (int)threadIdx.x / g;
                 if (row < r1) {   // uniform inside the sub-group
                     const double vrow = (sw == 0 && !STAGED) ? u[row] * ih : vv[row];
@@ -100,18 +108,22 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
                     T acc = 0;
                     if (e - s <= g * R) {
                         // (LDS loads return quickly; skipping the empty element slots by
-                        // branch measured faster here than loading in batches)
-                        T a[R];
+                        // branch measured faster here than loading in batches).  The z
+                        // values of the dot are kept for the update: no other row of the
+                        // colour touches these columns, so they are still current.
+                        T a[R], zv[R];
                         int jj[R];
 #pragma unroll
                         for (int t = 0; t < R; ++t) {
                             const int kk = s + lane + t * g;
                             a[t] = 0;
+                            zv[t] = 0;
                             jj[t] = 0;
                             if (kk < e) {
                                 a[t] = val[kk];
                                 jj[t] = idx[kk];
-                                acc += a[t] * z[jj[t]];
+                                zv[t] = z[jj[t]];
+                                acc += a[t] * zv[t];
                             }
                         }
                         acc = sg_sum(acc, g);
@@ -119,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
                         if (write_z) {
 #pragma unroll
                             for (int t = 0; t < R; ++t)
-                                if (s + lane + t * g < e) z[jj[t]] += delta * a[t];
+                                if (s + lane + t * g < e) z[jj[t]] = zv[t] + delta * a[t];
                         }
                         if (lane == 0) {
                             if (sw == 0) {
@@ -146,9 +158,11 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
                     }
                 }
             }
-            __syncthreads();
+            if (!small) __syncthreads();
+            prev_small = small;
         }
     }
+    __syncthreads();   // the last colours may have run on wave 0 alone
     if constexpr (STAGED) {
         for (int t = threadIdx.x; t < m; t += NT) {
             p[t] = pp[t];
