@@ -26,6 +26,33 @@ namespace lpk {
 // Otherwise: z (n T), colour starts, lanes.
 constexpr int NT = 1024;
 
+// one DPP lane move inside each row of 16 lanes (ctrl a quad_perm or row-mirror code)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// sum over the g consecutive lanes of a row (g a power of two, the row's lanes all
+// active).  Inside 16 lanes the partners come from DPP moves: quad_perm [1,0,3,2] and
+// [2,3,0,1] (xor 1, xor 2), then the half-row and row mirrors, whose partners hold the
+// same partial sums as the xor-4 and xor-8 partners; so the result is bitwise that of the
+// xor butterfly, without an LDS round trip per step.  Wider rows finish with shuffles.
+template <typename T>
+__device__ __forceinline__ T sg_sum_lds(T v, int g) {
+    if (g >= 2) v += dpp_move<0xB1>(v);
+    if (g >= 4) v += dpp_move<0x4E>(v);
+    if (g >= 8) v += dpp_move<0x141>(v);
+    if (g >= 16) v += dpp_move<0x140>(v);
+    for (int o = 16; o < g; o <<= 1) v += __shfl_xor(v, o, g);
+    return v;
+}
+
 template <typename T, bool STAGED>
 __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int keepz, int pmask, int ba) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -126,7 +153,7 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
                                 acc += a[t] * zv[t];
                             }
                         }
-                        acc = sg_sum(acc, g);
+                        acc = sg_sum_lds(acc, g);
                         const T delta = om * ((T)vrow - acc);
                         if (write_z) {
 #pragma unroll
@@ -143,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
                         }
                     } else {
                         for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
-                        acc = sg_sum(acc, g);
+                        acc = sg_sum_lds(acc, g);
                         const T delta = om * ((T)vrow - acc);
                         if (write_z)
                             for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
