@@ -109,132 +109,85 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, in
     for (int j = threadIdx.x; j < n; j += NT) z[j] = 0;
     __syncthreads();
     const T om = (T)in.omega;
-    constexpr int R = 8;
     // A colour whose rows fit in one wave (rows x lanes <= 64) runs on wave 0 alone, and a
     // run of such colours needs no block barrier: the LDS accesses of one wave complete in
     // program order.  A barrier precedes a whole-block colour that follows wave-0 colours
     // and ends every whole-block colour.
-    //
-    // Software pipelining: while a colour step runs, the thread loads what the next step
-    // needs and no other row changes: the colour's range and lanes, its row's pointers,
-    // values and column indices, v and the running multiplier.  Only the gather of z waits
-    // for the barrier.  Steps are numbered q = sw * ncol + cc.
-    const int nsteps = npass * ncol;
-    auto colour_at = [&](int q) {
-        const int sw = q / ncol, cc = q - sw * ncol;
-        return (ssor && (sw & 1)) ? ncol - 1 - cc : cc;
-    };
-    // prefetched state of one step for this thread (its row in the colour's first chunk)
-    struct Pre {
-        int r0, r1, g, row, s, e;
-        double vrow, pold;
-        T a[R];
-        int jj[R];
-    };
-    auto prefetch = [&](int q, Pre& P) {
-        const int sw = q / ncol;
-        const int c = colour_at(q);
-        P.r0 = cs[c];
-        P.r1 = cs[c + 1];
-        P.g = cl[c];
-        const int nth = (P.r1 - P.r0) * P.g <= 64 ? 64 : NT;
-        P.row = (int)threadIdx.x < nth ? P.r0 + (int)threadIdx.x / P.g : P.r1;
-        if (P.row >= P.r1) return;
-        P.s = rptr[P.row];
-        P.e = rptr[P.row + 1];
-        P.vrow = (sw == 0 && !STAGED) ? u[P.row] * ih : vv[P.row];
-        P.pold = sw == 0 ? 0.0 : pp[P.row];
-        if (P.e - P.s > P.g * R) return;   // long row: streamed in the step
-        const int lane = threadIdx.x & (P.g - 1);
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const int kk = P.s + lane + t * P.g;
-            P.a[t] = 0;
-            P.jj[t] = -1;
-            if (kk < P.e) {
-                P.a[t] = val[kk];
-                P.jj[t] = idx[kk];
-            }
-        }
-    };
-    // one row of a step: d = omega (v_i - a_i . z), z += d a_i, p_i (+)= d.  Rows of one
-    // colour share no column, so the z values of the dot are still current for the update.
-    auto do_row = [&](int sw, int row, int s, int e, int g, double vrow, double pold, const T* a, const int* jj,
-                      int write_z) {
-        const int lane = threadIdx.x & (g - 1);
-        T acc = 0;
-        if (a) {
-            T zv[R];
-#pragma unroll
-            for (int t = 0; t < R; ++t) zv[t] = jj[t] >= 0 ? z[jj[t]] : (T)0;
-#pragma unroll
-            for (int t = 0; t < R; ++t) acc += a[t] * zv[t];
-            acc = sg_sum_lds(acc, g);
-            const T delta = om * ((T)vrow - acc);
-            if (write_z) {
-#pragma unroll
-                for (int t = 0; t < R; ++t)
-                    if (jj[t] >= 0) z[jj[t]] = zv[t] + delta * a[t];
-            }
-            if (lane == 0) {
-                if (sw == 0 && !STAGED) vk[row] = vrow;
-                pp[row] = pold + (double)delta;
-            }
-        } else {
-            for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
-            acc = sg_sum_lds(acc, g);
-            const T delta = om * ((T)vrow - acc);
-            if (write_z)
-                for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
-            if (lane == 0) {
-                if (sw == 0 && !STAGED) vk[row] = vrow;
-                pp[row] = pold + (double)delta;
-            }
-        }
-    };
-    Pre cur, nxt;
-    if (nsteps > 0) prefetch(0, cur);
     bool prev_small = false;
-    for (int q = 0; q < nsteps; ++q) {
-        const int sw = q / ncol, cc = q - sw * ncol;
-        const int r0 = cur.r0, r1 = cur.r1, g = cur.g;
-        const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
-        const bool small = (r1 - r0) * g <= 64;
-        if (!small && prev_small) __syncthreads();
-        const int nth = small ? 64 : NT;
-        const int per = nth / g;
-        // the colour's first chunk of rows, from the prefetched state
-        if (cur.row < r1) {   // uniform inside the sub-group
-            const bool shortrow = cur.e - cur.s <= g * R;
-            do_row(sw, cur.row, cur.s, cur.e, g, cur.vrow, cur.pold, shortrow ? cur.a : nullptr,
-                   shortrow ? cur.jj : nullptr, write_z);
-        }
-        if (q + 1 < nsteps) prefetch(q + 1, nxt);
-        // further chunks (colours with more rows than the block holds), loaded here
-        for (int base = r0 + per; base < r1 && (int)threadIdx.x < nth; base += per) {
-            const int row = base + (int)threadIdx.x / g;
-            if (row >= r1) continue;
-            const int s = rptr[row], e = rptr[row + 1];
-            const double vrow = (sw == 0 && !STAGED) ? u[row] * ih : vv[row];
-            const double pold = sw == 0 ? 0.0 : pp[row];
-            if (e - s <= g * R) {
-                const int lane = threadIdx.x & (g - 1);
-                T a[R];
-                int jj[R];
+    for (int sw = 0; sw < npass; ++sw) {
+        const int dir = ssor ? (sw & 1) : 0;
+        for (int cc = 0; cc < ncol; ++cc) {
+            const int c = dir ? ncol - 1 - cc : cc;
+            const int r0 = cs[c], r1 = cs[c + 1];
+            const int g = cl[c];
+            const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
+            const int lane = threadIdx.x & (g - 1);
+            const bool small = (r1 - r0) * g <= 64;
+            if (!small && prev_small) __syncthreads();
+            const int nth = small ? 64 : NT;
+            const int per = nth / g;
+            for (int base = r0; base < r1 && (int)threadIdx.x < nth; base += per) {
+                const int row = base + (int)threadIdx.x / g;
+                if (row < r1) {   // uniform inside the sub-group
+                    const double vrow = (sw == 0 && !STAGED) ? u[row] * ih : vv[row];
+                    const int s = rptr[row], e = rptr[row + 1];
+                    constexpr int R = 8;
+                    T acc = 0;
+                    if (e - s <= g * R) {
+                        // (LDS loads return quickly; skipping the empty element slots by
+                        // branch measured faster here than loading in batches).  The z
+                        // values of the dot are kept for the update: no other row of the
+                        // colour touches these columns, so they are still current.
+                        T a[R], zv[R];
+                        int jj[R];
 #pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int kk = s + lane + t * g;
-                    a[t] = kk < e ? val[kk] : (T)0;
-                    jj[t] = kk < e ? idx[kk] : -1;
+                        for (int t = 0; t < R; ++t) {
+                            const int kk = s + lane + t * g;
+                            a[t] = 0;
+                            zv[t] = 0;
+                            jj[t] = 0;
+                            if (kk < e) {
+                                a[t] = val[kk];
+                                jj[t] = idx[kk];
+                                zv[t] = z[jj[t]];
+                                acc += a[t] * zv[t];
+                            }
+                        }
+                        acc = sg_sum_lds(acc, g);
+                        const T delta = om * ((T)vrow - acc);
+                        if (write_z) {
+#pragma unroll
+                            for (int t = 0; t < R; ++t)
+                                if (s + lane + t * g < e) z[jj[t]] = zv[t] + delta * a[t];
+                        }
+                        if (lane == 0) {
+                            if (sw == 0) {
+                                if (!STAGED) vk[row] = vrow;
+                                pp[row] = (double)delta;
+                            } else {
+                                pp[row] += (double)delta;
+                            }
+                        }
+                    } else {
+                        for (int kk = s + lane; kk < e; kk += g) acc += val[kk] * z[idx[kk]];
+                        acc = sg_sum_lds(acc, g);
+                        const T delta = om * ((T)vrow - acc);
+                        if (write_z)
+                            for (int kk = s + lane; kk < e; kk += g) z[idx[kk]] += delta * val[kk];
+                        if (lane == 0) {
+                            if (sw == 0) {
+                                if (!STAGED) vk[row] = vrow;
+                                pp[row] = (double)delta;
+                            } else {
+                                pp[row] += (double)delta;
+                            }
+                        }
+                    }
                 }
-                do_row(sw, row, s, e, g, vrow, pold, a, jj, write_z);
-            } else {
-                do_row(sw, row, s, e, g, vrow, pold, nullptr, nullptr, write_z);
             }
+            if (!small) __syncthreads();
+            prev_small = small;
         }
-        if (!small) __syncthreads();
-        prev_small = small;
-        cur = nxt;
     }
     __syncthreads();   // the last colours may have run on wave 0 alone
     if constexpr (STAGED) {
