@@ -75,3 +75,22 @@ def test_correctors_batch_matches_alone():
     finally:
         for p in probs:
             p.close()
+
+
+@pytest.mark.parametrize("krylov,inner", [("cgne", "nessor"), ("mrne", "nessor"), ("bagmres", "nesor")])
+def test_correctors_with_other_krylov_methods(krylov, inner):
+    """The corrector solves run through whichever Krylov method the LP uses."""
+    lp = _case("transport")
+    kry = {"cgne": oracle.CGNE, "mrne": oracle.MRNE, "bagmres": oracle.BAGMRES}[krylov]
+    inn = {"nessor": oracle.NESSOR, "nesor": oracle.NESOR}[inner]
+    o = oracle.ipm(lp, oracle.ipm_opts(max_correctors=2, solver=oracle.solver_opts(krylov=kry, inner=inn)))
+    assert o["status"] == oracle.OK
+    with lpk.from_lp(lp, lpk.options(max_correctors=2, krylov=krylov, inner=inner)) as p:
+        r = lpk.lp_solve(p)
+        log = lpk.lp_get_log(p)
+    nc = sum(L["correctors"] for L in log)
+    print(f"{krylov}: gpu iters {r['iters']} correctors {nc}; oracle iters {o['iters']} "
+          f"correctors {sum(L['correctors'] for L in o['log'])}", flush=True)
+    assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
+    assert abs(r["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+    assert abs(r["iters"] - o["iters"]) <= 1 and nc > 0
