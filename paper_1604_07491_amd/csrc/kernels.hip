@@ -416,15 +416,21 @@ void b_gs_reduce(const BLaunch& L, int pass) {
 }
 
 // ||u||^2 from the chunk partials, h_{k+1,k} = ||u||, the earlier Givens rotations on
-// column k of H, the new rotation, gamma, and the test |gamma_{k+1}| <= tol * beta.  The
-// rotations are a serial chain through one carried entry; column k and the rotation
-// coefficients are staged through LDS in chunks by the whole block, so the chain itself
-// runs on LDS loads that do not wait on global memory.
+// column k of H, the new rotation, gamma, and the test |gamma_{k+1}| <= tol * beta.
+// Rotation i maps (carry_i, h_{i+1}) to the output entry c_i carry_i + s_i h_{i+1} and the
+// next carry -s_i carry_i + c_i h_{i+1}: the carries follow the first-order linear
+// recurrence carry_{i+1} = a_i carry_i + b_i (a_i = -s_i, b_i = c_i h_{i+1}).  Column k
+// and the coefficients are staged through LDS in chunks; inside a chunk each thread
+// composes the affine maps of its consecutive entries, a block-wide scan composes the
+// threads' maps, and each thread then replays its entries from its starting carry.  The
+// depth is log2(BLOCK) barrier steps instead of a chain of length k (|a_i| <= 1, so the
+// composed maps stay bounded).
 constexpr int GF_CH = 1024;
 
 __global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
     __shared__ double hb[GF_CH], cb[GF_CH], sb[GF_CH], ob[GF_CH];
+    __shared__ double sA[BLOCK], sB[BLOCK];
     __shared__ double carry_s;
     INST;
     KrylovCtl* ctl = in.ctl;
@@ -444,18 +450,48 @@ __global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I)
             sb[t] = in.sn[base + t];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double carry = carry_s;
-#pragma unroll 8
-            for (int i = 0; i < len; ++i) {
-                const double bv = hb[i], c = cb[i], s = sb[i];
-                ob[i] = c * carry + s * bv;
-                carry = -s * carry + c * bv;
-            }
-            carry_s = carry;
+        // this thread's entries [i0, i1) and the composition of their maps, x -> A x + B
+        const int per = (len + BLOCK - 1) / BLOCK;
+        const int t = threadIdx.x;
+        const int i0 = t * per < len ? t * per : len;
+        const int i1 = i0 + per < len ? i0 + per : len;
+        double A = 1.0, B = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const double a = -sb[i], b = cb[i] * hb[i];
+            B = a * B + b;
+            A = a * A;
         }
+        // inclusive scan over the threads: after it, (A, B) composes the maps of threads 0..t
+        sA[t] = A;
+        sB[t] = B;
         __syncthreads();
-        for (int t = threadIdx.x; t < len; t += BLOCK) hk[base + t] = ob[t];
+        for (int d = 1; d < BLOCK; d <<= 1) {
+            double pa = 1.0, pb = 0.0;
+            if (t >= d) {
+                pa = sA[t - d];
+                pb = sB[t - d];
+            }
+            __syncthreads();
+            if (t >= d) {
+                B = A * pb + B;
+                A = A * pa;
+                sA[t] = A;
+                sB[t] = B;
+            }
+            __syncthreads();
+        }
+        // starting carry of this thread's entries: the maps of threads 0..t-1 on carry_s
+        double carry = carry_s;
+        if (t > 0) carry = sA[t - 1] * carry + sB[t - 1];
+        for (int i = i0; i < i1; ++i) {
+            const double bv = hb[i], c = cb[i], s = sb[i];
+            ob[i] = c * carry + s * bv;
+            carry = -s * carry + c * bv;
+        }
+        __syncthreads();   // every thread has read carry_s
+        if (i0 < i1 && i1 == len) carry_s = carry;
+        __syncthreads();
+        for (int q2 = threadIdx.x; q2 < len; q2 += BLOCK) hk[base + q2] = ob[q2];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
