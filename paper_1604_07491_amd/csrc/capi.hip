@@ -355,6 +355,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     }
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);
+        if (gram_work_doubles((int)m) > 0) p->Wgram = A.alloc<double>(gram_work_doubles((int)m));
         p->Xinv = A.alloc<double>(m * m);
         p->Rblk = A.alloc<double>(64 * m);
         if (p->opt.inner_sweeps > 1) {

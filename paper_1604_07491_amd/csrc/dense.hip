@@ -18,19 +18,49 @@ static inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b -
 
 // ------------------------------------------------------------------------------------
 // G = A A^T for a dense row-major A (m x n, leading dimension lda).  A block computes one
-// 64 x 64 tile (tile row bi <= tile column bj; the mirrored tile is written too, so G is
-// exactly symmetric).  Each of the 4 waves owns a 32 x 32 quarter as 2 x 2 tiles of
-// v_mfma_f64_16x16x4: lane l supplies a = A[r0 + l%16][k + l/16] and
+// 64 x 64 tile of the upper triangle (tile row bi <= tile column bj; the mirrored tile is
+// written too, so G is exactly symmetric).  Each of the 4 waves owns a 32 x 32 quarter as
+// 2 x 2 tiles of v_mfma_f64_16x16x4: lane l supplies a = A[r0 + l%16][k + l/16] and
 // b = A[c0 + l%16][k + l/16]; result register r of lane l is D[l/16 + 4r][l%16].
+// K is streamed in chunks of 32 through LDS; the next chunk's global loads are issued into
+// registers before the current chunk's MFMAs, so they run under them.  With few tiles
+// (m up to about 1,800) K is also split over blockIdx.y: each split writes its partial tile
+// to a workspace and a second kernel adds the splits in a fixed order (deterministic).
 constexpr int GT = 64;      // tile edge
 constexpr int GKC = 32;     // k chunk staged in LDS
 constexpr int GKP = GKC + 1;
+constexpr int GLD = (GT * GKC) / 256;   // elements of a chunk each thread loads, per operand
 
-__global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __restrict__ A,
-                                              int64_t lda, double* __restrict__ G,
-                                              float* __restrict__ G32, int nb) {
-    const int bi = blockIdx.x % nb, bj = blockIdx.x / nb;
-    if (bi > bj) return;
+static int gram_tiles(int m) {
+    const int nb = (int)cdiv_u(m, GT);
+    return nb * (nb + 1) / 2;
+}
+
+int gram_splits(int m) {
+    const int t = gram_tiles(m);
+    const int s = 1024 / t;
+    return s < 1 ? 1 : (s > 8 ? 8 : s);
+}
+
+int64_t gram_work_doubles(int m) {
+    const int s = gram_splits(m);
+    return s > 1 ? (int64_t)s * gram_tiles(m) * GT * GT : 0;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __restrict__ A, int64_t lda,
+                                              double* __restrict__ G, float* __restrict__ G32,
+                                              double* __restrict__ W, int nb, int ntile, int64_t kper) {
+    // upper-triangle tile number -> (bi, bj), row by row
+    int tl = blockIdx.x, bi = 0, rowlen = nb;
+    while (tl >= rowlen) {
+        tl -= rowlen;
+        ++bi;
+        rowlen = nb - bi;
+    }
+    const int bj = bi + tl;
+    const int64_t kb = (int64_t)blockIdx.y * kper;
+    const int64_t ke = kb + kper < n ? kb + kper : n;
     __shared__ double As[GT][GKP];
     __shared__ double Bs[GT][GKP];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -41,18 +71,28 @@ __global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = 0; k0 < n; k0 += GKC) {
-        // stage 64 x 32 of the row block and of the column block (zero padded)
+    double ra[GLD], rb[GLD];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < (GT * GKC) / 256; ++q) {
+        for (int q = 0; q < GLD; ++q) {
             const int e = tid + q * 256;
             const int rr = e / GKC, kk = e % GKC;
             const int64_t kg = k0 + kk;
-            const int ra = r0 + rr, rb = c0 + rr;
-            As[rr][kk] = (ra < m && kg < n) ? A[(int64_t)ra * lda + kg] : 0.0;
-            Bs[rr][kk] = (rb < m && kg < n) ? A[(int64_t)rb * lda + kg] : 0.0;
+            const int ia = r0 + rr, ib = c0 + rr;
+            ra[q] = (ia < m && kg < ke) ? A[(int64_t)ia * lda + kg] : 0.0;
+            rb[q] = (ib < m && kg < ke) ? A[(int64_t)ib * lda + kg] : 0.0;
+        }
+    };
+    if (kb < ke) load(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += GKC) {
+#pragma unroll
+        for (int q = 0; q < GLD; ++q) {
+            const int e = tid + q * 256;
+            As[e / GKC][e % GKC] = ra[q];
+            Bs[e / GKC][e % GKC] = rb[q];
         }
         __syncthreads();
+        if (k0 + GKC < ke) load(k0 + GKC);   // in flight during the MFMAs below
 #pragma unroll
         for (int kk = 0; kk < GKC; kk += 4) {
             const int kl = kk + (lane >> 4);
@@ -73,23 +113,62 @@ __global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
-                const int j = c0 + wc + 16 * b + (lane & 15);
-                if (i < m && j < m) {
-                    const double v = acc[a][b][r];
-                    G[(int64_t)i * m + j] = v;
-                    G[(int64_t)j * m + i] = v;
-                    if (G32) {
-                        G32[(int64_t)i * m + j] = (float)v;
-                        G32[(int64_t)j * m + i] = (float)v;
+                const int il = wr + 16 * a + (lane >> 4) + 4 * r;
+                const int jl = wc + 16 * b + (lane & 15);
+                const double v = acc[a][b][r];
+                if constexpr (SPLIT) {
+                    W[((int64_t)blockIdx.y * ntile + blockIdx.x) * (GT * GT) + il * GT + jl] = v;
+                } else {
+                    const int i = r0 + il, j = c0 + jl;
+                    if (i < m && j < m) {
+                        G[(int64_t)i * m + j] = v;
+                        G[(int64_t)j * m + i] = v;
+                        if (G32) {
+                            G32[(int64_t)i * m + j] = (float)v;
+                            G32[(int64_t)j * m + i] = (float)v;
+                        }
                     }
                 }
             }
 }
 
-void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32) {
-    const int nb = (int)cdiv_u(m, GT);
-    hipLaunchKernelGGL(k_gram, dim3(nb * nb), dim3(256), 0, st, m, n, A, lda, G, G32, nb);
+// the splits of each tile added in split order, then written with the mirror
+__global__ __launch_bounds__(256) void k_gram_reduce(int m, const double* __restrict__ W, int nb, int ntile,
+                                                     int splits, double* __restrict__ G, float* __restrict__ G32) {
+    int tl = blockIdx.x, bi = 0, rowlen = nb;
+    while (tl >= rowlen) {
+        tl -= rowlen;
+        ++bi;
+        rowlen = nb - bi;
+    }
+    const int bj = bi + tl;
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        double v = 0.0;
+        for (int sp = 0; sp < splits; ++sp) v += W[((int64_t)sp * ntile + blockIdx.x) * (GT * GT) + e];
+        const int i = bi * GT + e / GT, j = bj * GT + e % GT;
+        if (i < m && j < m) {
+            G[(int64_t)i * m + j] = v;
+            G[(int64_t)j * m + i] = v;
+            if (G32) {
+                G32[(int64_t)i * m + j] = (float)v;
+                G32[(int64_t)j * m + i] = (float)v;
+            }
+        }
+    }
+}
+
+void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32, double* W) {
+    const int nb = (int)cdiv_u(m, GT), ntile = gram_tiles(m);
+    const int splits = W ? gram_splits(m) : 1;
+    const int64_t kper = ((n + splits - 1) / splits + GKC - 1) / GKC * GKC;
+    if (splits > 1) {
+        hipLaunchKernelGGL((k_gram<true>), dim3(ntile, splits), dim3(256), 0, st, m, n, A, lda, G, G32, W, nb,
+                           ntile, kper);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(ntile), dim3(256), 0, st, m, W, nb, ntile, splits, G, G32);
+    } else {
+        hipLaunchKernelGGL((k_gram<false>), dim3(ntile, 1), dim3(256), 0, st, m, n, A, lda, G, G32, W, nb,
+                           ntile, kper);
+    }
 }
 
 // ------------------------------------------------------------------------------------

@@ -705,7 +705,7 @@ lp_status build_dense_preconditioner(Batch& B, lp_problem* p) {
     double fl = 2.0 * (double)p->n * 64.0 * 64.0 * nbt * (nbt + 1.0) / 2.0;     // Gram tiles
     fl += (double)m * m * m / 3.0 * 2.0 + (ell - 1) * 4.0 * (double)m * m * m;   // M^-1 and C
     Prof pr(&B, LP_K_GRAM, -1, 8.0 * (double)m * p->n + 8.0 * mm * (3.0 + 3.0 * (ell - 1)), fl);
-    gram_f64(st, m, p->n, p->ah, p->n, p->G, nullptr);
+    gram_f64(st, m, p->n, p->ah, p->n, p->G, nullptr, p->Wgram);
     fill(st, mm, 0.0, p->Xinv);
     for (int r0 = 0; r0 < m; r0 += 64) {
         const int b = std::min(64, m - r0), ncols = r0 + b;

@@ -262,7 +262,10 @@ void scatter(hipStream_t st, int64_t len, const double* src, const int32_t* perm
 void fill(hipStream_t st, int64_t len, double v, double* dst);
 
 // ---- dense path (per instance, once per scaling) -----------------------------------------
-void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32);
+// W: workspace of gram_work_doubles(m) doubles for the split-K partial tiles (NULL: no split)
+void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32, double* W);
+int gram_splits(int m);
+int64_t gram_work_doubles(int m);
 void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
               const double* B, int64_t ldb, double beta, const double* E, const double* F,
               int64_t lde, double* D, int64_t ldd, int diag_r0);

@@ -118,6 +118,7 @@ struct lp_problem {
     bool mixed = false;                             // FP32 sweeps (LP_MIXED where they stream from HBM)
     bool gsor = false;                              // dense: SOR on the Gram matrix
     double* G = nullptr;                            // m x m Gram matrix A_hat A_hat^T
+    double* Wgram = nullptr;                        // split-K partial tiles of the Gram build
     double *Xinv = nullptr, *Tmat = nullptr, *Tmat2 = nullptr, *Cmat = nullptr, *Rblk = nullptr;
     const double* Capply = nullptr;                 // the preconditioner matrix C<l>
     float* C32 = nullptr;
