@@ -173,41 +173,67 @@ void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, do
 
 // ------------------------------------------------------------------------------------
 // D = alpha (A B) + beta E + F + diag_one * [row + r0 == col], all row-major (FP64
-// MFMA, 64 x 64 tiles, k chunks of 32 staged in LDS).  A: M x K (lda), B: K x N (ldb).
-// E, F may be NULL.  Used for the explicit inner-iteration preconditioner of the dense
-// path.
+// MFMA, 64 x 64 tiles, k chunks of 32 staged in LDS, the next chunk loaded into registers
+// under the current chunk's MFMAs).  A: M x K (lda), B: K x N (ldb).  E, F may be NULL.
+// Used for the explicit inner-iteration preconditioner of the dense path.  With few tiles
+// K is split over blockIdx.y into a workspace, and a second kernel adds the splits in order
+// and applies the epilogue (deterministic).
+__device__ __forceinline__ double gemm_epilogue(double acc, int i, int j, double alpha, double beta,
+                                                const double* __restrict__ E, const double* __restrict__ F,
+                                                int64_t lde, int diag_r0) {
+    double v = alpha * acc;
+    if (E) v += beta * E[(int64_t)i * lde + j];
+    if (F) v += F[(int64_t)i * lde + j];
+    if (diag_r0 >= 0 && i + diag_r0 == j) v += 1.0;
+    return v;
+}
+
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
                                               const double* __restrict__ A, int64_t lda,
                                               const double* __restrict__ B, int64_t ldb,
                                               double beta, const double* __restrict__ E,
                                               const double* __restrict__ F, int64_t lde,
                                               double* __restrict__ D, int64_t ldd, int diag_r0,
-                                              int nbn) {
+                                              int nbn, double* __restrict__ W, int kper) {
     __shared__ double As[GT][GKP];
     __shared__ double Bs[GT][GKP];   // Bs[col][k]
     const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int r0 = bm * GT, c0 = bn * GT;
+    const int kb = (int)blockIdx.y * kper;
+    const int ke = kb + kper < K ? kb + kper : K;
     dbl4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += GKC) {
+    double ra[GLD], rb[GLD];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < (GT * GKC) / 256; ++q) {
+        for (int q = 0; q < GLD; ++q) {
             const int e = tid + q * 256;
             // A tile: row rr, k kk (consecutive threads along k)
             const int rr = e / GKC, kk = e % GKC;
-            const int ra = r0 + rr, ka = k0 + kk;
-            As[rr][kk] = (ra < M && ka < K) ? A[(int64_t)ra * lda + ka] : 0.0;
-            // B tile: k kb, column cc (consecutive threads along the column)
-            const int kb = e / GT, cc = e % GT;
-            const int kg = k0 + kb, cg = c0 + cc;
-            Bs[cc][kb] = (kg < K && cg < N) ? B[(int64_t)kg * ldb + cg] : 0.0;
+            const int ra_ = r0 + rr, ka = k0 + kk;
+            ra[q] = (ra_ < M && ka < ke) ? A[(int64_t)ra_ * lda + ka] : 0.0;
+            // B tile: k kb_, column cc (consecutive threads along the column)
+            const int kb_ = e / GT, cc = e % GT;
+            const int kg = k0 + kb_, cg = c0 + cc;
+            rb[q] = (kg < ke && cg < N) ? B[(int64_t)kg * ldb + cg] : 0.0;
+        }
+    };
+    if (kb < ke) load(kb);
+    for (int k0 = kb; k0 < ke; k0 += GKC) {
+#pragma unroll
+        for (int q = 0; q < GLD; ++q) {
+            const int e = tid + q * 256;
+            As[e / GKC][e % GKC] = ra[q];
+            Bs[e % GT][e / GT] = rb[q];
         }
         __syncthreads();
+        if (k0 + GKC < ke) load(k0 + GKC);   // in flight during the MFMAs below
 #pragma unroll
         for (int kk = 0; kk < GKC; kk += 4) {
             const int kl = kk + (lane >> 4);
@@ -222,31 +248,64 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
         }
         __syncthreads();
     }
+    const int ntile = (int)gridDim.x;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = r0 + wr + 16 * a + (lane >> 4) + 4 * r;
-                const int j = c0 + wc + 16 * b + (lane & 15);
-                if (i < M && j < N) {
-                    double v = alpha * acc[a][b][r];
-                    if (E) v += beta * E[(int64_t)i * lde + j];
-                    if (F) v += F[(int64_t)i * lde + j];
-                    if (diag_r0 >= 0 && i + diag_r0 == j) v += 1.0;
-                    D[(int64_t)i * ldd + j] = v;
+                const int il = wr + 16 * a + (lane >> 4) + 4 * r;
+                const int jl = wc + 16 * b + (lane & 15);
+                if constexpr (SPLIT) {
+                    W[((int64_t)blockIdx.y * ntile + blockIdx.x) * (GT * GT) + il * GT + jl] = acc[a][b][r];
+                } else {
+                    const int i = r0 + il, j = c0 + jl;
+                    if (i < M && j < N)
+                        D[(int64_t)i * ldd + j] = gemm_epilogue(acc[a][b][r], i, j, alpha, beta, E, F, lde, diag_r0);
                 }
             }
 }
 
+__global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, double alpha, double beta,
+                                                     const double* __restrict__ E, const double* __restrict__ F,
+                                                     int64_t lde, double* __restrict__ D, int64_t ldd,
+                                                     int diag_r0, int nbn, const double* __restrict__ W,
+                                                     int splits) {
+    const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
+    const int ntile = (int)gridDim.x;
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        double acc = 0.0;
+        for (int sp = 0; sp < splits; ++sp) acc += W[((int64_t)sp * ntile + blockIdx.x) * (GT * GT) + e];
+        const int i = bm * GT + e / GT, j = bn * GT + e % GT;
+        if (i < M && j < N) D[(int64_t)i * ldd + j] = gemm_epilogue(acc, i, j, alpha, beta, E, F, lde, diag_r0);
+    }
+}
+
 void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
               const double* B, int64_t ldb, double beta, const double* E, const double* F,
-              int64_t lde, double* D, int64_t ldd, int diag_r0) {
+              int64_t lde, double* D, int64_t ldd, int diag_r0, double* W, int64_t wcap) {
     if (M <= 0 || N <= 0) return;
     const int nbm = (int)cdiv_u(M, GT), nbn = (int)cdiv_u(N, GT);
-    hipLaunchKernelGGL(k_gemm, dim3(nbm * nbn), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, E,
-                       F, lde, D, ldd, diag_r0, nbn);
+    const int ntile = nbm * nbn;
+    int splits = 1;
+    if (W && K >= 8 * GKC) {
+        splits = 512 / ntile;
+        if (splits > 8) splits = 8;
+        if (splits > K / (2 * GKC)) splits = K / (2 * GKC);
+        while (splits > 1 && (int64_t)splits * ntile * GT * GT > wcap) --splits;
+        if (splits < 1) splits = 1;
+    }
+    const int kper = ((K + splits - 1) / splits + GKC - 1) / GKC * GKC;
+    if (splits > 1) {
+        hipLaunchKernelGGL((k_gemm<true>), dim3(ntile, splits), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, E, F, lde, D, ldd, diag_r0, nbn, W, kper);
+        hipLaunchKernelGGL(k_gemm_reduce, dim3(ntile), dim3(256), 0, st, M, N, alpha, beta, E, F, lde, D, ldd,
+                           diag_r0, nbn, W, splits);
+    } else {
+        hipLaunchKernelGGL((k_gemm<false>), dim3(ntile, 1), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, E, F, lde, D, ldd, diag_r0, nbn, W, kper);
+    }
 }
 
 // Forward substitution with the diagonal block of M = I/omega + tril(G, -1) (rows

@@ -706,20 +706,21 @@ lp_status build_dense_preconditioner(Batch& B, lp_problem* p) {
     fl += (double)m * m * m / 3.0 * 2.0 + (ell - 1) * 4.0 * (double)m * m * m;   // M^-1 and C
     Prof pr(&B, LP_K_GRAM, -1, 8.0 * (double)m * p->n + 8.0 * mm * (3.0 + 3.0 * (ell - 1)), fl);
     gram_f64(st, m, p->n, p->ah, p->n, p->G, nullptr, p->Wgram);
+    const int64_t wcap = p->Wgram ? gram_work_doubles(m) : 0;
     fill(st, mm, 0.0, p->Xinv);
     for (int r0 = 0; r0 < m; r0 += 64) {
         const int b = std::min(64, m - r0), ncols = r0 + b;
         // R = I[B, :] - G[B, 0:r0] X[0:r0, 0:ncols]   (K = 0 for the first block: R = I)
         gemm_f64(st, b, ncols, r0, -1.0, p->G + (int64_t)r0 * m, m, p->Xinv, m, 0.0, nullptr, nullptr, m,
-                 p->Rblk, m, r0);
+                 p->Rblk, m, r0, p->Wgram, wcap);
         trsm_diag(st, m, r0, b, p->G, p->Rblk, m, p->Xinv, om, ncols);
     }
     const double* Ccur = p->Xinv;
     double* bufs[2] = {p->Cmat, p->Tmat2};
     for (int i = 1; i < ell; ++i) {
         double* Cn = bufs[(i - 1) & 1];
-        gemm_f64(st, m, m, m, 1.0, p->G, m, Ccur, m, 0.0, nullptr, nullptr, m, p->Tmat, m, -1);
-        gemm_f64(st, m, m, m, -1.0, p->Xinv, m, p->Tmat, m, 1.0, p->Xinv, Ccur, m, Cn, m, -1);
+        gemm_f64(st, m, m, m, 1.0, p->G, m, Ccur, m, 0.0, nullptr, nullptr, m, p->Tmat, m, -1, p->Wgram, wcap);
+        gemm_f64(st, m, m, m, -1.0, p->Xinv, m, p->Tmat, m, 1.0, p->Xinv, Ccur, m, Cn, m, -1, p->Wgram, wcap);
         Ccur = Cn;
     }
     if (p->Capply != Ccur) {

@@ -266,9 +266,10 @@ void fill(hipStream_t st, int64_t len, double v, double* dst);
 void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, double* G, float* G32, double* W);
 int gram_splits(int m);
 int64_t gram_work_doubles(int m);
+// W: workspace of wcap doubles for split-K partial tiles (NULL: no split)
 void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A, int64_t lda,
               const double* B, int64_t ldb, double beta, const double* E, const double* F,
-              int64_t lde, double* D, int64_t ldd, int diag_r0);
+              int64_t lde, double* D, int64_t ldd, int diag_r0, double* W, int64_t wcap);
 void trsm_diag(hipStream_t st, int m, int r0, int b, const double* G, const double* R, int64_t ldr,
                double* X, double omega, int ncols);
 void to_f32(hipStream_t st, int64_t len, const double* a, float* b);
