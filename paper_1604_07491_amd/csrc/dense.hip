@@ -323,15 +323,17 @@ __global__ __launch_bounds__(256) void k_trsm_diag(int m, int r0, int b, const d
     __syncthreads();
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= ncols) return;
+    // the sum over t < i runs on four accumulators (t mod 4) so that the FMAs of a row
+    // do not form one dependent chain
     double x[64];
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
         double s = 0.0;
         if (i < b) {
-            s = R[(int64_t)i * ldr + j];
+            double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < i; ++t) s -= gb[i][t] * x[t];
-            s *= omega;
+            for (int t = 0; t < i; ++t) q[t & 3] += gb[i][t] * x[t];
+            s = omega * (R[(int64_t)i * ldr + j] - ((q[0] + q[1]) + (q[2] + q[3])));
         }
         x[i] = s;
     }
