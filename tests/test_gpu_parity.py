@@ -240,3 +240,24 @@ def test_mixed_small_lp_sweeps_in_fp64():
             out[prec] = (r, lpk.lp_get_state(p)[0])
     assert out["mixed"][0]["krylov_iters"] == out["fp64"][0]["krylov_iters"]
     assert np.array_equal(out["mixed"][1], out["fp64"][1])
+
+
+def test_direction_solve_beyond_1024_iterations():
+    """A slowly converging solve (columns scaled by 10^U(-3,3), d spanning 1e-2..1e2) run to a
+    fixed 1,030 AB-GMRES iterations: the Givens step then stages the Hessenberg column in two
+    chunks and the back substitution takes its long-solve path.  The relative residual is
+    still about 1e-10 there, so the iterates agree to rounding amplified by the small
+    Krylov problem: 1e-6 relative, and the true residuals to 1e-9 of ||f_hat||."""
+    lp = synth.sparse_lp(1490, 4000, 8, 10, seed=5, col_scale_exp=3.0)
+    rng = np.random.default_rng(1)
+    d = rng.uniform(0.01, 100.0, lp.n)
+    f = oracle.csr_mv(lp, d * rng.standard_normal(lp.n))
+    k = 1030
+    with lpk.from_lp(lp, lpk.options(krylov_max_iter=k)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
+    odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1))
+    print(f"iters {info['iters']} res_true {info['res_true']:.3e} (oracle {oinfo['res_true']:.3e}) "
+          f"dw err {_rel(dw, odw):.2e}", flush=True)
+    assert info["iters"] == oinfo["iters"] == k
+    assert _rel(dw, odw) <= 1e-6
+    assert abs(info["res_true"] - oinfo["res_true"]) <= 1e-9 * oinfo["beta"]
