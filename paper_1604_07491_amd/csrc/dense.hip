@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_gram(int m, int64_t n, const double* __
             }
 }
 
-// the splits of each tile added in split order, then written with the mirror
+// the splits of each tile added in split order, then written with the mirror; block
+// (tile, y) takes the tile's elements [256 y, 256 y + 256)
 __global__ __launch_bounds__(256) void k_gram_reduce(int m, const double* __restrict__ W, int nb, int ntile,
                                                      int splits, double* __restrict__ G, float* __restrict__ G32) {
     int tl = blockIdx.x, bi = 0, rowlen = nb;
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int m, const double* __rest
         rowlen = nb - bi;
     }
     const int bj = bi + tl;
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    {
+        const int e = (int)blockIdx.y * 256 + threadIdx.x;
         double v = 0.0;
         for (int sp = 0; sp < splits; ++sp) v += W[((int64_t)sp * ntile + blockIdx.x) * (GT * GT) + e];
         const int i = bi * GT + e / GT, j = bj * GT + e % GT;
@@ -164,7 +166,8 @@ void gram_f64(hipStream_t st, int m, int64_t n, const double* A, int64_t lda, do
     if (splits > 1) {
         hipLaunchKernelGGL((k_gram<true>), dim3(ntile, splits), dim3(256), 0, st, m, n, A, lda, G, G32, W, nb,
                            ntile, kper);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(ntile), dim3(256), 0, st, m, W, nb, ntile, splits, G, G32);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(ntile, GT * GT / 256), dim3(256), 0, st, m, W, nb, ntile, splits, G,
+                           G32);
     } else {
         hipLaunchKernelGGL((k_gram<false>), dim3(ntile, 1), dim3(256), 0, st, m, n, A, lda, G, G32, W, nb,
                            ntile, kper);
@@ -274,7 +277,8 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, double alpha,
                                                      int splits) {
     const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
     const int ntile = (int)gridDim.x;
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    {   // block (tile, y) takes the tile's elements [256 y, 256 y + 256)
+        const int e = (int)blockIdx.y * 256 + threadIdx.x;
         double acc = 0.0;
         for (int sp = 0; sp < splits; ++sp) acc += W[((int64_t)sp * ntile + blockIdx.x) * (GT * GT) + e];
         const int i = bm * GT + e / GT, j = bn * GT + e % GT;
@@ -300,8 +304,8 @@ void gemm_f64(hipStream_t st, int M, int N, int K, double alpha, const double* A
     if (splits > 1) {
         hipLaunchKernelGGL((k_gemm<true>), dim3(ntile, splits), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
                            beta, E, F, lde, D, ldd, diag_r0, nbn, W, kper);
-        hipLaunchKernelGGL(k_gemm_reduce, dim3(ntile), dim3(256), 0, st, M, N, alpha, beta, E, F, lde, D, ldd,
-                           diag_r0, nbn, W, splits);
+        hipLaunchKernelGGL(k_gemm_reduce, dim3(ntile, GT * GT / 256), dim3(256), 0, st, M, N, alpha, beta, E, F,
+                           lde, D, ldd, diag_r0, nbn, W, splits);
     } else {
         hipLaunchKernelGGL((k_gemm<false>), dim3(ntile, 1), dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
                            beta, E, F, lde, D, ldd, diag_r0, nbn, W, kper);
@@ -323,9 +327,11 @@ __global__ __launch_bounds__(256) void k_trsm_diag(int m, int r0, int b, const d
     __syncthreads();
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= ncols) return;
-    // the sum over t < i runs on four accumulators (t mod 4) so that the FMAs of a row
-    // do not form one dependent chain
+    // the column of R is loaded first (its loads in flight together); the sum over t < i
+    // runs on four accumulators (t mod 4) so that the FMAs of a row do not form one chain
     double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = i < b ? R[(int64_t)i * ldr + j] : 0.0;
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
         double s = 0.0;
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(256) void k_trsm_diag(int m, int r0, int b, const d
             double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int t = 0; t < i; ++t) q[t & 3] += gb[i][t] * x[t];
-            s = omega * (R[(int64_t)i * ldr + j] - ((q[0] + q[1]) + (q[2] + q[3])));
+            s = omega * (x[i] - ((q[0] + q[1]) + (q[2] + q[3])));
         }
         x[i] = s;
     }
