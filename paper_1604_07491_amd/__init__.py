@@ -2,9 +2,11 @@
 
 Argument marshalling only: every computation runs in the HIP library ``liblpk.so``
 (built by ``paper_1604_07491_amd/build.py``).  The names follow the C ABI of
-``include/lpk.h``: :func:`lp_create`, :func:`lp_create_dense`, :func:`ipm_step`,
-:func:`direction_solve`, :func:`lp_solve`, :func:`lp_get_state`, :func:`lp_set_state`,
-:func:`lp_footprint_bytes`, :func:`lp_colour_rows`.
+``include/lpk.h``: :func:`lp_create`, :func:`lp_create_dense`, :func:`lp_create_bounded`,
+:func:`ipm_step`, :func:`direction_solve`, :func:`lp_solve`, :func:`lp_solve_batch`,
+:func:`lp_get_state`, :func:`lp_set_state`, :func:`lp_bounded_solution`,
+:func:`lp_footprint_bytes`, :func:`lp_colour_rows`, :func:`lp_presolve_rows`,
+:func:`lp_bounds_standard_form`, and the server of ``include/lpk_server.h``.
 
 Arrays may be numpy arrays (host; the library copies them) or torch tensors on the GPU
 (``device_io=1``; their ``data_ptr()`` is passed and torch's current stream is used).
