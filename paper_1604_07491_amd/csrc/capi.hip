@@ -78,6 +78,15 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
     z.add(m, 4);                                  // permutation
     z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
+    if ((o.inner == LP_NESOR || o.inner == LP_NESSOR) && lds_z_bytes(n, m, 4) > LDS_Z_MAX) {
+        // row slices: at most 5/4 of the nonzeros with columns and values (FP32 copy in
+        // mixed precision); slice starts of the colours, slice offsets and lengths, row
+        // positions, slice rows
+        const int64_t np = nnz + nnz / 4 + 1;
+        z.add(np, 4); z.add(np, 8);
+        if (mixed) z.add(np, 4);
+        z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(2 * m, 4);
+    }
     for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
     for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
     if (o.max_correctors > 0) { z.add(n, 8); z.add(n, 8); }  // a corrector's dx, ds
@@ -131,6 +140,79 @@ static double line_cost(const Colour& C, const int32_t* rp, const int32_t* ci, i
         }
     }
     return elems > 0.0 ? lines / elems : 0.0;
+}
+
+// Slices of SL_ROWS rows for colour C, stored slot-major from offset off0 (see Inst): built
+// (true) when the wave-wide loads of the sliced kernel touch under 0.6 of the lines per
+// element that the colour's CSR lane layout touches, padding adds at most a quarter to the
+// colour's elements and every offset stays below 2^31.
+static bool slice_colour(Colour& C, const int32_t* rp, const int32_t* ci, int zbytes, std::vector<int32_t>& soff,
+                         std::vector<int32_t>& slen, std::vector<int32_t>& srows, std::vector<int32_t>& rsl,
+                         std::vector<int32_t>& sidx) {
+    const int64_t rows = C.r1 - C.r0;
+    const int64_t nsl = (rows + SL_ROWS - 1) / SL_ROWS;
+    std::vector<int32_t> ls((size_t)nsl);
+    int64_t padded = 0;
+    for (int64_t q = 0; q < nsl; ++q) {
+        int len = 0;
+        for (int64_t t = C.r0 + q * SL_ROWS; t < std::min<int64_t>(C.r1, C.r0 + (q + 1) * SL_ROWS); ++t)
+            len = std::max<int>(len, rp[t + 1] - rp[t]);
+        ls[q] = (len + SL_GROUPS - 1) / SL_GROUPS * SL_GROUPS;
+        padded += (int64_t)ls[q] * SL_ROWS;
+    }
+    const int64_t off0 = (int64_t)sidx.size();
+    if (padded * 4 > C.nnz * 5 || off0 + padded >= ((int64_t)1 << 31)) return false;
+    // lines per element over the first slices' loads
+    double lines = 0.0, elems = 0.0;
+    std::vector<int64_t> zl, vl, xl;
+    int64_t off = off0;
+    for (int64_t q = 0; q < std::min<int64_t>(nsl, 8); ++q) {
+        for (int wv = 0; wv < SL_THREADS / 64; ++wv)
+            for (int t = 0; t * SL_GROUPS < ls[q]; ++t) {
+                zl.clear();
+                vl.clear();
+                xl.clear();
+                for (int l = 0; l < 64; ++l) {
+                    const int r = l % SL_ROWS, slot = wv * (64 / SL_ROWS) + l / SL_ROWS + t * SL_GROUPS;
+                    const int64_t pos = off + (int64_t)slot * SL_ROWS + r;
+                    vl.push_back(pos * zbytes / 128);
+                    xl.push_back(pos * 4 / 128);
+                    const int64_t row = C.r0 + q * SL_ROWS + r;
+                    if (row < C.r1 && slot < rp[row + 1] - rp[row]) {
+                        zl.push_back((int64_t)ci[rp[row] + slot] * zbytes / 128);
+                        elems += 1.0;
+                    }
+                }
+                for (std::vector<int64_t>* v : {&zl, &vl, &xl}) {
+                    std::sort(v->begin(), v->end());
+                    lines += (double)(std::unique(v->begin(), v->end()) - v->begin());
+                }
+            }
+        off += (int64_t)ls[q] * SL_ROWS;
+    }
+    const double cur = line_cost(C, rp, ci, C.il ? 64 / C.il : C.g, C.il, zbytes);
+    if (elems == 0.0 || lines / elems >= 0.6 * cur) return false;
+    C.slice0 = (int)soff.size();
+    C.nslice = (int)nsl;
+    int steps = 0;
+    sidx.resize((size_t)(off0 + padded), -1);
+    off = off0;
+    for (int64_t q = 0; q < nsl; ++q) {
+        soff.push_back((int32_t)off);
+        slen.push_back(ls[q]);
+        srows.push_back((int32_t)(C.r0 + q * SL_ROWS));
+        srows.push_back((int32_t)std::min<int64_t>(SL_ROWS, C.r1 - C.r0 - q * SL_ROWS));
+        steps = std::max(steps, ls[q] / SL_GROUPS);
+        for (int r = 0; r < SL_ROWS; ++r) {
+            const int64_t row = C.r0 + q * SL_ROWS + r;
+            if (row >= C.r1) break;
+            rsl[row] = (int32_t)(off + r);
+            for (int32_t k = rp[row]; k < rp[row + 1]; ++k) sidx[off + (int64_t)(k - rp[row]) * SL_ROWS + r] = ci[k];
+        }
+        off += (int64_t)ls[q] * SL_ROWS;
+    }
+    C.sR = steps <= 8 ? 8 : steps <= 16 ? 16 : 32;
+    return true;
 }
 
 // registers per lane for a row of len elements over g lanes: 8, 16 or 32 (longer rows
@@ -269,6 +351,25 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         p->colours.push_back(C);
         t0 = t1;
     }
+    // slices for the colours whose neighbouring rows touch neighbouring columns (NE-SOR /
+    // NE-SSOR swept colour by colour)
+    std::vector<int32_t> h_cslice, h_soff, h_slen, h_srows, h_rsl, h_sidx;
+    {
+        const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
+        if (sor && !p->gsor && lds_z_bytes(n, ncol, mixed ? 4 : 8) > LDS_Z_MAX) {
+            h_cslice.assign(p->colours.size(), -1);
+            h_rsl.assign((size_t)m, -1);
+            bool any = false;
+            for (size_t cl = 0; cl < p->colours.size(); ++cl) {
+                Colour& C = p->colours[cl];
+                if (C.g >= 16 && slice_colour(C, prp.data(), pci.data(), mixed ? 4 : 8, h_soff, h_slen, h_srows, h_rsl, h_sidx)) {
+                    h_cslice[cl] = C.slice0;
+                    any = true;
+                }
+            }
+            if (!any) h_cslice.clear();
+        }
+    }
     // does colour 0 touch every column? (then its first sweep sets z without clearing it)
     {
         std::vector<char> hit((size_t)n, 0);
@@ -327,6 +428,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->perm_d = A.alloc<int32_t>(m);
     p->cstart = A.alloc<int32_t>((int64_t)p->colours.size() + 1);
     p->cg = A.alloc<int32_t>((int64_t)p->colours.size());
+    if (!h_cslice.empty()) {
+        p->cslice = A.alloc<int32_t>((int64_t)h_cslice.size());
+        p->soff = A.alloc<int32_t>((int64_t)h_soff.size());
+        p->slen = A.alloc<int32_t>((int64_t)h_slen.size());
+        p->srows = A.alloc<int32_t>((int64_t)h_srows.size());
+        p->nsl = (int32_t)h_soff.size();
+        p->rsl = A.alloc<int32_t>(m);
+        p->sl_idx = A.alloc<int32_t>((int64_t)h_sidx.size());
+        p->sl_val = A.alloc<double>((int64_t)h_sidx.size());
+        if (mixed) p->sl_val32 = A.alloc<float>((int64_t)h_sidx.size());
+    }
     const int mv[] = {V_Y, V_RHO, V_RP, V_DYA, V_DYC, V_F, V_DYH, V_TMPM, V_B, V_FH, V_U, V_R64};
     for (int q : mv) p->vec[q] = A.alloc<double>(m);
     const int nv[] = {V_X, V_S, V_D, V_RD, V_TN, V_DXA, V_DSA, V_DW, V_TMPN, V_C, V_Z64};
@@ -377,6 +489,17 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     LPK_HIP(hipMemcpyAsync(p->cstart, p->h_cstart.data(), sizeof(int32_t) * p->h_cstart.size(), hipMemcpyHostToDevice, st));
     if (!p->h_cg.empty())
         LPK_HIP(hipMemcpyAsync(p->cg, p->h_cg.data(), sizeof(int32_t) * p->h_cg.size(), hipMemcpyHostToDevice, st));
+    if (p->cslice) {
+        LPK_HIP(hipMemcpyAsync(p->cslice, h_cslice.data(), sizeof(int32_t) * h_cslice.size(), hipMemcpyHostToDevice, st));
+        LPK_HIP(hipMemcpyAsync(p->soff, h_soff.data(), sizeof(int32_t) * h_soff.size(), hipMemcpyHostToDevice, st));
+        LPK_HIP(hipMemcpyAsync(p->slen, h_slen.data(), sizeof(int32_t) * h_slen.size(), hipMemcpyHostToDevice, st));
+        LPK_HIP(hipMemcpyAsync(p->srows, h_srows.data(), sizeof(int32_t) * h_srows.size(), hipMemcpyHostToDevice, st));
+        LPK_HIP(hipMemcpyAsync(p->rsl, h_rsl.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+        LPK_HIP(hipMemcpyAsync(p->sl_idx, h_sidx.data(), sizeof(int32_t) * h_sidx.size(), hipMemcpyHostToDevice, st));
+        // padding values stay 0 (the scaling writes only the real elements)
+        LPK_HIP(hipMemsetAsync(p->sl_val, 0, sizeof(double) * h_sidx.size(), st));
+        if (p->sl_val32) LPK_HIP(hipMemsetAsync(p->sl_val32, 0, sizeof(float) * h_sidx.size(), st));
+    }
     LPK_HIP(hipMemcpyAsync(p->rp, prp.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->ci, pci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(p->a, pa.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));

@@ -145,6 +145,16 @@ static Inst make_inst(Batch& B, int slot) {
     in.ri = p->ri;
     in.cstart = p->cstart;
     in.cg = p->cg;
+    in.cslice = p->cslice;
+    in.soff = p->soff;
+    in.slen = p->slen;
+    in.rsl = p->rsl;
+    in.sl_idx = p->sl_idx;
+    in.sl_val = p->sl_val;
+    in.sl_val32 = mixed ? p->sl_val32 : nullptr;
+    in.srows = p->srows;
+    in.nsl = p->cslice ? p->nsl : 0;
+    in.nbc = (int32_t)std::min<int64_t>(RED_MAXBLK, std::max<int64_t>(1, ((int64_t)p->m * p->g_csr + SL_THREADS - 1) / SL_THREADS));
     in.a = p->a;
     in.ac = p->ac;
     in.ah = p->ah;
@@ -181,7 +191,8 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
         a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
         a.need_prep != b.need_prep ||
         a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.any_stage != b.any_stage ||
-        a.stage_bytes != b.stage_bytes || a.keep_z != b.keep_z || a.max_ncol_global != b.max_ncol_global)
+        a.stage_bytes != b.stage_bytes || a.keep_z != b.keep_z || a.max_ncol_global != b.max_ncol_global ||
+        a.grid_ahz != b.grid_ahz)
         return false;
     for (int i = 0; i < 4; ++i)
         if (a.grid_spmv[i] != b.grid_spmv[i]) return false;
@@ -247,6 +258,7 @@ lp_status Batch::refresh() {
         L.gs_dots_grid = std::max<int>(L.gs_dots_grid, (int)std::min<int64_t>(128, cdiv_i((int64_t)in.nseg * (p->kmax + 1), 4)));
         L.max_ncol = std::max(L.max_ncol, in.ncol);
         L.any_free = L.any_free || in.nfpairs > 0;
+        if (in.nsl > 0) L.grid_ahz = std::max(L.grid_ahz, in.nbc + in.nsl);
         L.max_fpairs = std::max(L.max_fpairs, in.nfpairs);
         if (in.lds == 2) {
             L.any_stage = true;
@@ -259,13 +271,21 @@ lp_status Batch::refresh() {
             L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
         }
     }
-    grid_colour.assign((size_t)std::max(1, L.max_ncol), 1);
-    colour_r.assign((size_t)std::max(1, L.max_ncol), 8);
+    // entry c: blocks and registers of colour c's CSR launch; entry max_ncol + c: of its
+    // sliced launch (0 blocks: no instance has colour c in that form)
+    const int nc2 = std::max(1, L.max_ncol);
+    grid_colour.assign(2 * (size_t)nc2, 0);
+    colour_r.assign(2 * (size_t)nc2, 8);
     for (int s = 0; s < cap; ++s) {
         const lp_problem* p = mem[s];
         if (!p || h_inst[s].ncol == 0 || h_inst[s].lds) continue;
         for (int c = 0; c < h_inst[s].ncol; ++c) {
             const Colour& cl = p->colours[c];
+            if (cl.slice0 >= 0) {
+                colour_r[nc2 + c] = std::max<char>(colour_r[nc2 + c], (char)cl.sR);
+                grid_colour[nc2 + c] = std::max(grid_colour[nc2 + c], cl.nslice);
+                continue;
+            }
             const int64_t threads = cl.il ? (int64_t)cdiv_i(cl.r1 - cl.r0, cl.il) * 64 : (int64_t)(cl.r1 - cl.r0) * cl.g;
             colour_r[c] = std::max<char>(colour_r[c], (char)cl.R);
             grid_colour[c] = std::max(grid_colour[c], cdiv_i(threads, BLOCK_THREADS));

@@ -115,7 +115,26 @@ struct Inst {
     const int32_t* fpairs;                // split free variables: (x+ column, x- column) pairs
     int32_t nfpairs;                      // number of pairs (0 unless made with general bounds)
     int32_t pad_f;
+    // row slices of the colours whose neighbouring rows touch neighbouring columns (the
+    // sinks of a transportation matrix): SL_ROWS rows stored slot-major, element (slot s,
+    // row r) of slice q at soff[q] + s * SL_ROWS + r; NULL cslice: no such colour
+    const int32_t* cslice;                // first slice of each colour, -1: CSR rows
+    const int32_t *soff, *slen;           // per slice: offset, slots (a multiple of SL_GROUPS)
+    const int32_t* rsl;                   // per row: position of its slot 0, -1 if not sliced
+    const int32_t* sl_idx;                // column of each sliced element, -1 for padding
+    double* sl_val;                       // A_hat at the sliced elements (0 for padding)
+    float* sl_val32;                      // FP32 copy (mixed precision)
+    const int32_t* srows;                 // per slice: first row, rows (2 entries)
+    int32_t nsl;                          // slices over all colours
+    int32_t nbc;                          // blocks of the CSR rows in the product with slices
 };
+
+#ifndef LPK_SL_GROUPS
+#define LPK_SL_GROUPS 32
+#endif
+constexpr int SL_ROWS = 16;               // rows of a slice
+constexpr int SL_GROUPS = LPK_SL_GROUPS;  // slot groups of a slice's block (4 per wave)
+constexpr int SL_THREADS = SL_ROWS * SL_GROUPS;
 
 // host-side launch description of a batch (maxima over its instances)
 struct BLaunch {
@@ -134,8 +153,10 @@ struct BLaunch {
     int ell;                // inner sweeps per preconditioner application
     int krylov;             // lp_krylov of every instance (0 AB-GMRES, 1 CGNE, 2 MRNE)
     int max_ncol;
-    const int* grid_colour; // host array [max_ncol]: blocks of each colour launch
-    const char* colour_r;   // host array [max_ncol]: row elements per lane in registers (8, 16, 32)
+    const int* grid_colour; // host array [2 max(1, max_ncol)]: blocks of each colour's CSR launch,
+                            // then of its sliced launch (0: none)
+    const char* colour_r;   // host array, same layout: elements (CSR) or slot steps (sliced) per
+                            // lane in registers (8, 16, 32)
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
     bool any_lds;           // some instance sweeps in one block with z in LDS (lds == 1)
     int lds_bytes;          // largest z of those instances
@@ -143,6 +164,7 @@ struct BLaunch {
     int stage_bytes;        // largest LDS footprint of those instances
     bool ba;                // BA-GMRES: the sweeps map V_U to V_U (input kept in V_R64)
     bool any_free;          // some instance has split free variables
+    int grid_ahz;           // blocks of u = A_hat z with slices (0: no instance has slices)
     int max_fpairs;         // most split free variables of an instance
     bool keep_z;            // FP64 NE-SOR / NE-SSOR: the sweeps leave z_k = A_hat^T p_k in
                             // V_Z64, and the loop needs no product with A_hat^T

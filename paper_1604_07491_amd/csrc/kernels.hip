@@ -84,8 +84,85 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
     }
 }
 
+// ------------------------------------------------------------------------------------
+// out = A_hat x for instances with sliced colours: blocks [0, nbc) take the CSR rows
+// (g_csr lanes per row, grid-stride; the rows of slices are skipped), block nbc + q takes
+// slice q as the sliced sweep does (thread: row r = lane mod SL_ROWS, slots
+// 4 w + lane / SL_ROWS + SL_GROUPS t; the four slot groups of a wave by two butterfly
+// steps, then the waves in order).  Instances without slices take the plain row-dot form.
+__global__ __launch_bounds__(SL_THREADS) void k_spmv_ahz(const Inst* __restrict__ I, int xsel, int outsel, int pmask) {
+    __shared__ double red[SL_THREADS / 64][SL_ROWS];
+    INST;
+    if (!takes_part(in, pmask)) return;
+    const int64_t kcol = xsel < 0 ? (int64_t)to_global(in.ctl)->k * in.ldv : 0;
+    const LPK_GLOBAL double* __restrict__ x =
+        to_global(xsel == V_PCOL ? in.P + kcol : xsel == V_VCOL ? in.V + kcol : in.vec[xsel]);
+    LPK_GLOBAL double* __restrict__ out = to_global(in.vec[outsel]);
+    const int nbc = in.nsl > 0 ? in.nbc : (int)gridDim.x;
+    if (bx < nbc) {
+        const int g = in.g_csr;
+        const int lane = threadIdx.x & (g - 1);
+        const int lg = __ffs(g) - 1;
+        const int rows = in.m;
+        const int64_t total = (int64_t)rows * g;
+        const LPK_GLOBAL int32_t* __restrict__ rp = to_global(in.rp);
+        const LPK_GLOBAL int32_t* __restrict__ rsl = to_global(in.nsl > 0 ? in.rsl : nullptr);
+        for (int64_t t0 = (int64_t)bx * SL_THREADS; t0 < total; t0 += (int64_t)nbc * SL_THREADS) {
+            const int row = (int)((t0 + threadIdx.x) >> lg);
+            const bool mine = row < rows && (!rsl || rsl[row] < 0);
+            double sum = 0.0;
+            if (mine) sum = row_dot<8>(to_global((const double*)in.ah), to_global(in.ci), x, rp[row], rp[row + 1], lane, g);
+            sum = sg_sum(sum, g);
+            if (mine && lane == 0) out[row] = sum;
+        }
+        return;
+    }
+    const int q = bx - nbc;
+    if (q >= in.nsl) return;   // the same for the whole block
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int r = ln & (SL_ROWS - 1);
+    const int grp = wv * (64 / SL_ROWS) + ln / SL_ROWS;
+    const int off = to_global(in.soff)[q];
+    const int steps = to_global(in.slen)[q] / SL_GROUPS;
+    const LPK_GLOBAL double* __restrict__ val = to_global((const double*)in.sl_val);
+    const LPK_GLOBAL int32_t* __restrict__ idx = to_global(in.sl_idx);
+    const int base = off + grp * SL_ROWS + r;
+    constexpr int STEP = SL_GROUPS * SL_ROWS;
+    double a0 = 0.0, a1 = 0.0;
+    int t = 0;
+    for (; t + 1 < steps; t += 2) {
+        const int j0 = idx[base + t * STEP], j1 = idx[base + (t + 1) * STEP];
+        const double v0 = val[base + t * STEP], v1 = val[base + (t + 1) * STEP];
+        if (j0 >= 0) a0 += v0 * x[j0];
+        if (j1 >= 0) a1 += v1 * x[j1];
+    }
+    if (t < steps) {
+        const int j0 = idx[base + t * STEP];
+        if (j0 >= 0) a0 += val[base + t * STEP] * x[j0];
+    }
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (ln < SL_ROWS) red[wv][ln] = acc;
+    __syncthreads();
+    if (wv == 0 && ln < SL_ROWS) {
+        const LPK_GLOBAL int32_t* sr = to_global(in.srows) + 2 * q;
+        if (r < sr[1]) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < SL_THREADS / 64; ++w) tot += red[w][r];
+            out[sr[0] + r] = tot;
+        }
+    }
+}
+
 void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel, int b2sel, int pmask,
             bool nrm) {
+    if (mat == M_AH_CSR && epi == EPI_PLAIN && !nrm && L.grid_ahz > 0) {
+        hipLaunchKernelGGL(k_spmv_ahz, dim3(capg(L.grid_ahz, 1 << 30), L.S), dim3(SL_THREADS), 0, L.st, L.I, xsel, outsel,
+                           pmask);
+        return;
+    }
     const unsigned gx = nrm ? (unsigned)L.max_nbs : capg(L.grid_spmv[mat], GRID_CAP);
     hipLaunchKernelGGL(k_spmv, dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, mat, xsel, outsel, epi, b1sel,
                        b2sel, pmask, nrm ? 1 : 0);
@@ -1115,10 +1192,17 @@ __global__ __launch_bounds__(BLOCK) void k_scale_rows(const Inst* __restrict__ I
         if (row < in.m) {
             const double r = sqrt(q);
             if (lane == 0) rho[row] = r;
+            // a sliced row's element k - s sits at slot k - s of its slice
+            const int sl0 = in.rsl ? in.rsl[row] : -1;
             for (int k = s + lane; k < e; k += g) {
                 const double v = (in.a[k] * d[in.ci[k]]) / r;
                 in.ah[k] = v;
                 if (in.ah32) in.ah32[k] = (float)v;
+                if (sl0 >= 0) {
+                    const int q = sl0 + (k - s) * SL_ROWS;
+                    in.sl_val[q] = v;
+                    if (in.sl_val32) in.sl_val32[q] = (float)v;
+                }
             }
         }
     }

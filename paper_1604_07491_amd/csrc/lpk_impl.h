@@ -79,6 +79,9 @@ struct Colour {
     int R;              // row elements per lane held in registers (8, 16 or 32)
     int maxlen;         // longest row
     int64_t nnz;        // nonzeros of the colour
+    int slice0 = -1;    // sliced: first slice (else -1)
+    int nslice = 0;     // sliced: slices of the colour
+    int sR = 8;         // sliced: slot steps per lane held in registers (8, 16 or 32)
 };
 
 // the lane layout of a colour's rows whose wave-wide loads touch fewer cache lines
@@ -135,6 +138,10 @@ struct lp_problem {
     // structure and data (permuted rows)
     int32_t *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr, *perm_d = nullptr;
     int32_t *cstart = nullptr, *cg = nullptr;
+    int32_t *cslice = nullptr, *soff = nullptr, *slen = nullptr, *rsl = nullptr, *sl_idx = nullptr, *srows = nullptr;
+    int32_t nsl = 0;                                // slices over all colours
+    double* sl_val = nullptr;                       // sliced copies of A_hat (see Inst)
+    float* sl_val32 = nullptr;
     double *a = nullptr, *ac = nullptr;            // A values, CSR and CSC
     double *ah = nullptr, *ahc = nullptr;          // A_hat values, CSR and CSC
     float *ah32 = nullptr, *ahc32 = nullptr;       // FP32 copies (mixed precision)

@@ -35,6 +35,10 @@ def _case(name):
         return synth.transport_lp(31, 29, seed=8)
     if name == "transport_wide":   # z over the LDS limit: colour-by-colour sweeps, sinks interleaved
         return synth.transport_lp(130, 100, seed=8)
+    if name == "transport_sliced":   # sinks stored in row slices, the last slice ragged
+        return synth.transport_lp(150, 100, seed=9)
+    if name == "transport_tall":     # sink rows past the register-held slot steps
+        return synth.transport_lp(1100, 32, seed=10)
     if name == "ldsz":             # z in LDS, rows too many to stage there
         return synth.sparse_lp(300, 2000, 6, 2, seed=61)
     raise ValueError(name)
@@ -48,7 +52,8 @@ def _dir_problem(lp, seed=0):
     return d, f
 
 
-@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "ldsz"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
+                                  "transport_tall", "ldsz"])
 @pytest.mark.parametrize("k", [1, 4, 13])
 def test_direction_solve_fixed_iterations(name, k):
     lp = _case(name)
@@ -68,7 +73,7 @@ def test_direction_solve_fixed_iterations(name, k):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["config0", "ragged", "transport", "transport_wide", "ldsz"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "transport", "transport_wide", "transport_sliced", "ldsz"])
 def test_direction_solve_converged_is_min_norm(name, precision):
     lp = _case(name)
     d, f = _dir_problem(lp, 3)
