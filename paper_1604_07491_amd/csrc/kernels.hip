@@ -128,19 +128,22 @@ __global__ __launch_bounds__(SL_THREADS) void k_spmv_ahz(const Inst* __restrict_
     const LPK_GLOBAL int32_t* __restrict__ idx = to_global(in.sl_idx);
     const int base = off + grp * SL_ROWS + r;
     constexpr int STEP = SL_GROUPS * SL_ROWS;
-    double a0 = 0.0, a1 = 0.0;
-    int t = 0;
-    for (; t + 1 < steps; t += 2) {
-        const int j0 = idx[base + t * STEP], j1 = idx[base + (t + 1) * STEP];
-        const double v0 = val[base + t * STEP], v1 = val[base + (t + 1) * STEP];
-        if (j0 >= 0) a0 += v0 * x[j0];
-        if (j1 >= 0) a1 += v1 * x[j1];
+    // up to 16 slot steps per round: all their loads, then all their gathers
+    double acc = 0.0;
+    for (int t0 = 0; t0 < steps; t0 += 16) {
+        double v[16], xv[16];
+        int j[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const bool ok = t0 + u < steps;
+            j[u] = ok ? idx[base + (t0 + u) * STEP] : -1;
+            v[u] = ok ? val[base + (t0 + u) * STEP] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u] * xv[u];
     }
-    if (t < steps) {
-        const int j0 = idx[base + t * STEP];
-        if (j0 >= 0) a0 += val[base + t * STEP] * x[j0];
-    }
-    double acc = a0 + a1;
     acc += __shfl_xor(acc, 16, 64);
     acc += __shfl_xor(acc, 32, 64);
     if (ln < SL_ROWS) red[wv][ln] = acc;
