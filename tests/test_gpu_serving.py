@@ -149,3 +149,29 @@ def test_batch_mixes_lds_and_per_colour_sweeps(precision):
         p.close()
     o = oracle.ipm(lps[0])
     assert abs(alone[0][0]["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_mixes_sliced_and_csr_colours(precision):
+    """A transportation LP whose sink rows are stored in row slices (150 x 100), one whose
+    sinks stay in CSR form (100 x 80: slices would pad by more than a quarter) and a small
+    sparse LP in one batch: colour 1 then runs both the sliced and the CSR sweep launch, each
+    skipping the other kind's LPs.  Every LP's result is bitwise as alone, and the sliced
+    LP's optimum matches the oracle's."""
+    lps = [synth.transport_lp(150, 100, seed=9), synth.transport_lp(100, 80, seed=3)] + _mix(1, seed0=70)
+    opts = lambda: lpk.options(precision=precision)
+    alone = []
+    for lp in lps:
+        with lpk.from_lp(lp, opts()) as p:
+            r = lpk.lp_solve(p)
+            alone.append((r, lpk.lp_get_state(p)[0]))
+    print(f"{precision}: alone iterations", [a[0]["iters"] for a in alone], flush=True)
+    probs = [lpk.from_lp(lp, opts()) for lp in lps]
+    res = lpk.lp_solve_batch(probs, width=len(lps))
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == lpk.LP_OK
+        assert res[i]["krylov_iters"] == alone[i][0]["krylov_iters"]
+        assert np.array_equal(lpk.lp_get_state(p)[0], alone[i][1])
+        p.close()
+    o = oracle.ipm(lps[0])
+    assert abs(alone[0][0]["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
