@@ -262,7 +262,10 @@ lp_status lp_get_log(const lp_problem* p, lp_iter_info* info, int32_t cap, int32
 /* Device bytes lp_create would allocate for an m x n problem with nnz nonzeros and the
  * given options (NULL = defaults), including (AB-GMRES, BA-GMRES) the Krylov basis of
  * krylov_max_iter + 1 vectors (AB-GMRES also keeps as many multiplier vectors); CGNE
- * and MRNE keep a fixed number of vectors.
+ * and MRNE keep a fixed number of vectors.  Where NE-SOR / NE-SSOR sweeps colour by
+ * colour, the count includes the largest possible row slices (a second copy of at most
+ * 5/4 nnz elements that lp_create builds only for colours whose rows touch neighbouring
+ * columns), so it is an upper bound there.
  * Errors: LP_EDIM.                                                                    */
 lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options* o,
                              uint64_t* bytes);
