@@ -128,7 +128,7 @@ __global__ __launch_bounds__(SL_THREADS) void k_spmv_ahz(const Inst* __restrict_
     const LPK_GLOBAL int32_t* __restrict__ idx = to_global(in.sl_idx);
     const int base = off + grp * SL_ROWS + r;
     constexpr int STEP = SL_GROUPS * SL_ROWS;
-    // up to 16 slot steps per round: all their loads, then all their gathers
+    // up to 16 slot steps at a time: all their loads, then all their gathers
     double acc = 0.0;
     for (int t0 = 0; t0 < steps; t0 += 16) {
         double v[16], xv[16];
