@@ -81,11 +81,11 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     if ((o.inner == LP_NESOR || o.inner == LP_NESSOR) && lds_z_bytes(n, m, 4) > LDS_Z_MAX) {
         // row slices: at most 5/4 of the nonzeros with columns and values (FP32 copy in
         // mixed precision); slice starts of the colours, slice offsets and lengths, row
-        // positions, slice rows
+        // positions, slice rows, the other rows
         const int64_t np = nnz + nnz / 4 + 1;
         z.add(np, 4); z.add(np, 8);
         if (mixed) z.add(np, 4);
-        z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(2 * m, 4);
+        z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(2 * m, 4); z.add(m, 4);
     }
     for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
     for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
@@ -353,7 +353,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     }
     // slices for the colours whose neighbouring rows touch neighbouring columns (NE-SOR /
     // NE-SSOR swept colour by colour)
-    std::vector<int32_t> h_cslice, h_soff, h_slen, h_srows, h_rsl, h_sidx;
+    std::vector<int32_t> h_cslice, h_soff, h_slen, h_srows, h_rsl, h_sidx, h_crow;
     {
         const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
         if (sor && !p->gsor && lds_z_bytes(n, ncol, mixed ? 4 : 8) > LDS_Z_MAX) {
@@ -434,6 +434,10 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         p->slen = A.alloc<int32_t>((int64_t)h_slen.size());
         p->srows = A.alloc<int32_t>((int64_t)h_srows.size());
         p->nsl = (int32_t)h_soff.size();
+        for (int64_t t = 0; t < m; ++t)
+            if (h_rsl[t] < 0) h_crow.push_back((int32_t)t);
+        p->ncrow = (int32_t)h_crow.size();
+        p->crow = A.alloc<int32_t>(std::max<int64_t>(1, p->ncrow));
         p->rsl = A.alloc<int32_t>(m);
         p->sl_idx = A.alloc<int32_t>((int64_t)h_sidx.size());
         p->sl_val = A.alloc<double>((int64_t)h_sidx.size());
@@ -494,6 +498,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         LPK_HIP(hipMemcpyAsync(p->soff, h_soff.data(), sizeof(int32_t) * h_soff.size(), hipMemcpyHostToDevice, st));
         LPK_HIP(hipMemcpyAsync(p->slen, h_slen.data(), sizeof(int32_t) * h_slen.size(), hipMemcpyHostToDevice, st));
         LPK_HIP(hipMemcpyAsync(p->srows, h_srows.data(), sizeof(int32_t) * h_srows.size(), hipMemcpyHostToDevice, st));
+        if (p->ncrow > 0)
+            LPK_HIP(hipMemcpyAsync(p->crow, h_crow.data(), sizeof(int32_t) * h_crow.size(), hipMemcpyHostToDevice, st));
         LPK_HIP(hipMemcpyAsync(p->rsl, h_rsl.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
         LPK_HIP(hipMemcpyAsync(p->sl_idx, h_sidx.data(), sizeof(int32_t) * h_sidx.size(), hipMemcpyHostToDevice, st));
         // padding values stay 0 (the scaling writes only the real elements)

@@ -154,7 +154,9 @@ static Inst make_inst(Batch& B, int slot) {
     in.sl_val32 = mixed ? p->sl_val32 : nullptr;
     in.srows = p->srows;
     in.nsl = p->cslice ? p->nsl : 0;
-    in.nbc = (int32_t)std::min<int64_t>(RED_MAXBLK, std::max<int64_t>(1, ((int64_t)p->m * p->g_csr + SL_THREADS - 1) / SL_THREADS));
+    in.crow = p->crow;
+    in.ncrow = p->ncrow;
+    in.nbc = (int32_t)std::min<int64_t>(RED_MAXBLK, std::max<int64_t>(1, ((int64_t)(p->cslice ? p->ncrow : p->m) * p->g_csr + SL_THREADS - 1) / SL_THREADS));
     in.a = p->a;
     in.ac = p->ac;
     in.ah = p->ah;

@@ -127,6 +127,9 @@ struct Inst {
     const int32_t* srows;                 // per slice: first row, rows (2 entries)
     int32_t nsl;                          // slices over all colours
     int32_t nbc;                          // blocks of the CSR rows in the product with slices
+    const int32_t* crow;                  // with slices: the rows kept in CSR form only
+    int32_t ncrow;                        // their number
+    int32_t pad_c;
 };
 
 #ifndef LPK_SL_GROUPS

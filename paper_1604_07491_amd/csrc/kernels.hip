@@ -85,8 +85,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Inst* __restrict__ I, int 
 }
 
 // ------------------------------------------------------------------------------------
-// out = A_hat x for instances with sliced colours: blocks [0, nbc) take the CSR rows
-// (g_csr lanes per row, grid-stride; the rows of slices are skipped), block nbc + q takes
+// out = A_hat x for instances with sliced colours: blocks [0, nbc) take the rows kept in
+// CSR form (g_csr lanes per row, grid-stride over their list), block nbc + q takes
 // slice q as the sliced sweep does (thread: row r = lane mod SL_ROWS, slots
 // 4 w + lane / SL_ROWS + SL_GROUPS t; the four slot groups of a wave by two butterfly
 // steps, then the waves in order).  Instances without slices take the plain row-dot form.
@@ -103,13 +103,15 @@ __global__ __launch_bounds__(SL_THREADS) void k_spmv_ahz(const Inst* __restrict_
         const int g = in.g_csr;
         const int lane = threadIdx.x & (g - 1);
         const int lg = __ffs(g) - 1;
-        const int rows = in.m;
+        // with slices, the listed CSR rows; else every row
+        const LPK_GLOBAL int32_t* __restrict__ crow = to_global(in.nsl > 0 ? in.crow : nullptr);
+        const int rows = crow ? in.ncrow : in.m;
         const int64_t total = (int64_t)rows * g;
         const LPK_GLOBAL int32_t* __restrict__ rp = to_global(in.rp);
-        const LPK_GLOBAL int32_t* __restrict__ rsl = to_global(in.nsl > 0 ? in.rsl : nullptr);
         for (int64_t t0 = (int64_t)bx * SL_THREADS; t0 < total; t0 += (int64_t)nbc * SL_THREADS) {
-            const int row = (int)((t0 + threadIdx.x) >> lg);
-            const bool mine = row < rows && (!rsl || rsl[row] < 0);
+            const int q = (int)((t0 + threadIdx.x) >> lg);
+            const bool mine = q < rows;
+            const int row = mine ? (crow ? crow[q] : q) : 0;
             double sum = 0.0;
             if (mine) sum = row_dot<8>(to_global((const double*)in.ah), to_global(in.ci), x, rp[row], rp[row + 1], lane, g);
             sum = sg_sum(sum, g);

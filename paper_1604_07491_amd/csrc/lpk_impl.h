@@ -140,6 +140,8 @@ struct lp_problem {
     int32_t *cstart = nullptr, *cg = nullptr;
     int32_t *cslice = nullptr, *soff = nullptr, *slen = nullptr, *rsl = nullptr, *sl_idx = nullptr, *srows = nullptr;
     int32_t nsl = 0;                                // slices over all colours
+    int32_t* crow = nullptr;                        // rows not in slices
+    int32_t ncrow = 0;
     double* sl_val = nullptr;                       // sliced copies of A_hat (see Inst)
     float* sl_val32 = nullptr;
     double *a = nullptr, *ac = nullptr;            // A values, CSR and CSC
