@@ -57,6 +57,11 @@ Batch::~Batch() {
     drop_graph();
     if (cap_st) (void)hipStreamDestroy(cap_st);
     if (d_inst) (void)hipFree(d_inst);
+    if (d_inst_c) (void)hipFree(d_inst_c);
+    if (d_pad_slot) (void)hipFree(d_pad_slot);
+    if (d_pad_param) (void)hipFree(d_pad_param);
+    if (d_pad_part) (void)hipFree(d_pad_part);
+    if (h_inst_c) (void)hipHostFree(h_inst_c);
     if (d_slot) (void)hipFree(d_slot);
     if (d_param) (void)hipFree(d_param);
     if (d_part) (void)hipFree(d_part);
@@ -73,6 +78,20 @@ lp_status Batch::init(int capacity, hipStream_t stream, bool own) {
     mem.assign((size_t)cap, nullptr);
     h_inst.assign((size_t)cap, Inst{});
     LPK_HIP(hipMalloc(&d_inst, sizeof(Inst) * cap));
+    LPK_HIP(hipMalloc(&d_inst_c, sizeof(Inst) * cap));
+    LPK_HIP(hipMalloc(&d_pad_slot, sizeof(Slot)));
+    LPK_HIP(hipMalloc(&d_pad_param, sizeof(Param)));
+    LPK_HIP(hipMalloc(&d_pad_part, sizeof(double) * RED_NQ * RED_MAXBLK));
+    LPK_HIP(hipHostMalloc((void**)&h_inst_c, sizeof(Inst) * cap, hipHostMallocDefault));
+    {
+        Slot ps;
+        Param pp;
+        memset(&ps, 0, sizeof(ps));
+        memset(&pp, 0, sizeof(pp));
+        ps.ctl.done = 1;
+        LPK_HIP(hipMemcpy(d_pad_slot, &ps, sizeof(Slot), hipMemcpyHostToDevice));
+        LPK_HIP(hipMemcpy(d_pad_param, &pp, sizeof(Param), hipMemcpyHostToDevice));
+    }
     LPK_HIP(hipMalloc(&d_slot, sizeof(Slot) * cap));
     LPK_HIP(hipMalloc(&d_param, sizeof(Param) * cap));
     LPK_HIP(hipMalloc(&d_part, sizeof(double) * RED_NQ * RED_MAXBLK * cap));
@@ -106,6 +125,14 @@ void Batch::drop_graph() {
     gexec = nullptr;
     graph = nullptr;
     graph_iters = 0;
+    for (int i = 0; i < NARROW; ++i) {
+        if (gexec_c[i]) (void)hipGraphExecDestroy(gexec_c[i]);
+        if (graph_c[i]) (void)hipGraphDestroy(graph_c[i]);
+        gexec_c[i] = nullptr;
+        graph_c[i] = nullptr;
+    }
+    c_slots.clear();
+    c_width = 0;
 }
 
 static Inst make_inst(Batch& B, int slot) {
@@ -300,6 +327,7 @@ lp_status Batch::refresh() {
     L.colour_r = colour_r.data();
     LPK_HIP(hipMemcpyAsync(d_inst, h_inst.data(), sizeof(Inst) * cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
+    c_slots.clear();   // the narrow descriptors are rebuilt from these
     // the captured iterations read every pointer from the descriptors: they stay valid
     // while the launch shapes are unchanged
     if (!same_launch(*this)) {
@@ -607,6 +635,27 @@ static lp_status build_graph(Batch& B, int iters) {
     if (e != hipSuccess) return hip_fail(e, "graph capture");
     LPK_HIP(hipGraphInstantiate(&B.gexec, B.graph, nullptr, nullptr, 0));
     B.graph_iters = iters;
+    return LP_OK;
+}
+
+// capture i of the narrower graphs: the same iterations over d_inst_c, cap >> (i + 1) wide
+static lp_status build_graph_narrow(Batch& B, int i) {
+    if (!B.cap_st) LPK_HIP(hipStreamCreateWithFlags(&B.cap_st, hipStreamNonBlocking));
+    const uint32_t mask = B.prof_mask;
+    B.prof_mask = 0;
+    const BLaunch keep = B.L;
+    B.L.st = B.cap_st;
+    B.L.S = B.cap >> (i + 1);
+    B.L.I = B.d_inst_c;
+    hipError_t e = hipStreamBeginCapture(B.cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int it = 0; it < 8; ++it) enqueue_iteration(B, -1);
+        e = hipStreamEndCapture(B.cap_st, &B.graph_c[i]);
+    }
+    B.L = keep;
+    B.prof_mask = mask;
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    LPK_HIP(hipGraphInstantiate(&B.gexec_c[i], B.graph_c[i], nullptr, nullptr, 0));
     return LP_OK;
 }
 
@@ -1135,27 +1184,75 @@ lp_status Engine::round() {
     // enough to reach the earliest expected convergence
     if (solving) {
         int64_t todo = 8;
+        bool graphs = b.prof_mask == 0;
+        for (int s = 0; s < b.cap; ++s)
+            if (b.mem[s] && !b.mem[s]->opt.use_graphs) graphs = false;
         if (!waiting) {
             // expected iterations to the next useful poll: the first member to finish, or
             // (held phases) the last one; a member's previous solve length is the guess
-            int64_t rem = hold ? 0 : INT64_MAX;
+            std::vector<int64_t> rs;
             for (int s = 0; s < b.cap; ++s) {
                 const Member& mb = mem[s];
                 if (!solve_phase(mb.state)) continue;
                 const int64_t k = in_krylov(mb.state) ? b.h_slot[s].ctl.iters : 0;
                 const int64_t guess = mb.last_k > 0 ? mb.last_k : b.last_iters;
-                const int64_t r = std::max<int64_t>(1, guess - k);
-                rem = hold ? std::max(rem, r) : std::min(rem, r);
+                rs.push_back(std::max<int64_t>(1, guess - k));
+            }
+            std::sort(rs.begin(), rs.end());
+            int64_t rem = rs.empty() ? 8 : rs.front();
+            if (hold && !rs.empty()) {
+                // the last one; with graphs, the one whose end leaves few enough members
+                // iterating for the next narrower capture
+                size_t idx = rs.size() - 1;
+                if (graphs)
+                    for (int i = 0; i < Batch::NARROW; ++i) {
+                        const int w = b.cap >> (i + 1);
+                        if (w >= 8 && w % 8 == 0 && (int)rs.size() > w) {
+                            idx = rs.size() - (size_t)w - 1;
+                            break;
+                        }
+                    }
+                rem = rs[idx];
             }
             todo = std::max<int64_t>(8, std::min<int64_t>(rem, 256));
         }
-        bool graphs = b.prof_mask == 0;
-        for (int s = 0; s < b.cap; ++s)
-            if (b.mem[s] && !b.mem[s]->opt.use_graphs) graphs = false;
         if (graphs && !b.gexec) LPK_RC(build_graph(b, 8));
         if (graphs) {
+            // when the members inside a solve fit a narrower capture, launch that one over
+            // their descriptors: the blocks of the others are never started
+            std::vector<int> act;
+            for (int s = 0; s < b.cap; ++s)
+                if (b.mem[s] && solve_phase(mem[s].state)) act.push_back(s);
+            int wi = -1;
+            for (int i = Batch::NARROW - 1; i >= 0; --i) {
+                const int w = b.cap >> (i + 1);
+                if (w >= 8 && w % 8 == 0 && (int)act.size() <= w) {
+                    wi = i;
+                    break;
+                }
+            }
+            hipGraphExec_t ex = b.gexec;
+            if (wi >= 0) {
+                if (!b.gexec_c[wi]) LPK_RC(build_graph_narrow(b, wi));
+                const int w = b.cap >> (wi + 1);
+                if (act != b.c_slots || w != b.c_width) {
+                    // padding: an empty slot's descriptor over storage of its own
+                    Inst pad;
+                    memset(&pad, 0, sizeof(pad));
+                    pad.ctl = &b.d_pad_slot->ctl;
+                    pad.out = b.d_pad_slot->out;
+                    pad.part = b.d_pad_part;
+                    pad.scal = b.d_pad_param->scal;
+                    pad.mode = &b.d_pad_param->mode;
+                    for (int q = 0; q < w; ++q) b.h_inst_c[q] = q < (int)act.size() ? b.h_inst[act[q]] : pad;
+                    LPK_HIP(hipMemcpyAsync(b.d_inst_c, b.h_inst_c, sizeof(Inst) * w, hipMemcpyHostToDevice, b.st));
+                    b.c_slots = act;
+                    b.c_width = w;
+                }
+                ex = b.gexec_c[wi];
+            }
             const int64_t launches = (todo + b.graph_iters - 1) / b.graph_iters;
-            for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(b.gexec, b.st));
+            for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(ex, b.st));
             todo = launches * b.graph_iters;
         } else {
             // iteration index for the profiler (meaningful for a batch of one)

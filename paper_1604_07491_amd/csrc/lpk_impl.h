@@ -202,6 +202,19 @@ struct Batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 0;
+    // narrower captures of the same iterations for when few members iterate: width
+    // cap >> (i + 1) for capture i, over d_inst_c (the iterating members' descriptors
+    // first, then descriptors whose control block reads done)
+    static constexpr int NARROW = 3;
+    hipGraph_t graph_c[NARROW] = {};
+    hipGraphExec_t gexec_c[NARROW] = {};
+    Inst* d_inst_c = nullptr;
+    Inst* h_inst_c = nullptr;         // pinned
+    Slot* d_pad_slot = nullptr;       // what an empty slot holds, for the padding entries:
+    Param* d_pad_param = nullptr;     // control block with done = 1, parameters, partials
+    double* d_pad_part = nullptr;
+    std::vector<int> c_slots;         // the members d_inst_c holds, in order (empty: none)
+    int c_width = 0;
     int64_t last_iters = 0;           // polling hint
     // profiler (events on st) and launch accounting for timing captures
     uint32_t prof_mask = 0;
