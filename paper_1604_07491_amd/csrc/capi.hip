@@ -211,7 +211,7 @@ static bool slice_colour(Colour& C, const int32_t* rp, const int32_t* ci, int zb
         }
         off += (int64_t)ls[q] * SL_ROWS;
     }
-    C.sR = steps <= 8 ? 8 : steps <= 16 ? 16 : 32;
+    C.sR = steps <= 8 ? 8 : steps <= 12 ? 12 : steps <= 16 ? 16 : 32;
     return true;
 }
 

@@ -159,7 +159,7 @@ struct BLaunch {
     const int* grid_colour; // host array [2 max(1, max_ncol)]: blocks of each colour's CSR launch,
                             // then of its sliced launch (0: none)
     const char* colour_r;   // host array, same layout: elements (CSR) or slot steps (sliced) per
-                            // lane in registers (8, 16, 32)
+                            // lane in registers (8, 16, 32; sliced launches also 12)
     bool need_prep;         // some NE-SOR instance needs z cleared before its first sweep
     bool any_lds;           // some instance sweeps in one block with z in LDS (lds == 1)
     int lds_bytes;          // largest z of those instances

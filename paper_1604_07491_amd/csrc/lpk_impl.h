@@ -81,7 +81,7 @@ struct Colour {
     int64_t nnz;        // nonzeros of the colour
     int slice0 = -1;    // sliced: first slice (else -1)
     int nslice = 0;     // sliced: slices of the colour
-    int sR = 8;         // sliced: slot steps per lane held in registers (8, 16 or 32)
+    int sR = 8;         // sliced: slot steps per lane held in registers (8, 12, 16 or 32)
 };
 
 // the lane layout of a colour's rows whose wave-wide loads touch fewer cache lines

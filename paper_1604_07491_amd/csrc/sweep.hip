@@ -157,7 +157,8 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
 // of a transportation matrix) the z entries of a slot are neighbours too.  A row's sum adds
 // the four slot groups of its wave (two butterfly steps), then the waves' partials in wave
 // order.  Padding elements have column -1 and value 0.  Up to R slot steps per thread stay
-// in registers; longer slices read their elements again for the z update.
+// in registers (8, 12, 16 or 32: the fewest that hold the colour's longest slice, for
+// occupancy); longer slices read their elements again for the z update.
 static_assert(SL_ROWS == 16 && SL_THREADS % 64 == 0, "four slot groups per wave");
 
 template <typename T, int R>
@@ -271,6 +272,7 @@ static void launch_nesor_sl(const BLaunch& L, int R, dim3 gr, int colour, int pa
     const dim3 bl(SL_THREADS);
     const int ba = L.ba ? 1 : 0;
     if (R <= 8) hipLaunchKernelGGL((k_nesor_sl<T, 8>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
+    else if (R <= 12) hipLaunchKernelGGL((k_nesor_sl<T, 12>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
     else if (R <= 16) hipLaunchKernelGGL((k_nesor_sl<T, 16>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
     else hipLaunchKernelGGL((k_nesor_sl<T, 32>), gr, bl, 0, L.st, L.I, colour, pass, npass, dir, kz, pmask, ba);
 }
