@@ -130,21 +130,22 @@ __global__ __launch_bounds__(SL_THREADS) void k_spmv_ahz(const Inst* __restrict_
     const LPK_GLOBAL int32_t* __restrict__ idx = to_global(in.sl_idx);
     const int base = off + grp * SL_ROWS + r;
     constexpr int STEP = SL_GROUPS * SL_ROWS;
-    // up to 16 slot steps at a time: all their loads, then all their gathers
+    // up to 12 slot steps at a time (a transportation sink slice has 10): all their loads,
+    // then all their gathers
     double acc = 0.0;
-    for (int t0 = 0; t0 < steps; t0 += 16) {
-        double v[16], xv[16];
-        int j[16];
+    for (int t0 = 0; t0 < steps; t0 += 12) {
+        double v[12], xv[12];
+        int j[12];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < 12; ++u) {
             const bool ok = t0 + u < steps;
             j[u] = ok ? idx[base + (t0 + u) * STEP] : -1;
             v[u] = ok ? val[base + (t0 + u) * STEP] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : 0.0;
+        for (int u = 0; u < 12; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc += v[u] * xv[u];
+        for (int u = 0; u < 12; ++u) acc += v[u] * xv[u];
     }
     acc += __shfl_xor(acc, 16, 64);
     acc += __shfl_xor(acc, 32, 64);
