@@ -37,9 +37,13 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def kernels_digest():
-    """sha256 of the sweep kernels' source, which the committed counter runs were taken on."""
+    """sha256 of the sweep kernels' source and of the header that sizes their launches, which
+    the committed counter runs were taken on."""
     import hashlib
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", "sweep.hip"), "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def counter_traffic(args, kernel, width):
