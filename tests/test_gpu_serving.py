@@ -175,3 +175,27 @@ def test_batch_mixes_sliced_and_csr_colours(precision):
         p.close()
     o = oracle.ipm(lps[0])
     assert abs(alone[0][0]["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_narrow_graphs_keep_results_bitwise(precision):
+    """Sixteen transportation LPs of one shape wait for each other's solves; while fewer
+    than half of them still iterate, the engine launches narrower captures of the Krylov
+    iterations (widths 8 here) over only those LPs.  Every LP's iterate is bitwise as alone
+    and its Krylov count the same."""
+    lps = [synth.transport_lp(30, 20, seed=100 + i) for i in range(16)]
+    opts = lambda: lpk.options(precision=precision)
+    alone = []
+    for lp in lps:
+        with lpk.from_lp(lp, opts()) as p:
+            r = lpk.lp_solve(p)
+            alone.append((r, lpk.lp_get_state(p)[0]))
+    probs = [lpk.from_lp(lp, opts()) for lp in lps]
+    res = lpk.lp_solve_batch(probs, width=16)
+    ks = sorted(r["krylov_iters"] for r, _ in alone)
+    print(f"{precision}: Krylov iterations alone {ks[0]}..{ks[-1]}", flush=True)
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == lpk.LP_OK
+        assert res[i]["krylov_iters"] == alone[i][0]["krylov_iters"]
+        assert np.array_equal(lpk.lp_get_state(p)[0], alone[i][1])
+        p.close()
