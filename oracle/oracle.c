@@ -402,10 +402,34 @@ static int abgmres(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t
     return ORC_OK;
 }
 
+/* The residual of the stopping rule of Sec. 4.2, ||f_hat - A_hat dw||, recomputed from dw  */
+/* (CGNE and MRNE also carry a recurrence for it, which drifts from this value in        */
+/* rounding; the stated criterion is on the residual itself).                           */
+static double true_residual(int64_t m, const int64_t* rp, const int32_t* ci, const double* ah,
+                            const double* fh, const double* dw, double* r) {
+    csr_mv(m, rp, ci, ah, dw, r);
+    for (int64_t i = 0; i < m; ++i) r[i] = fh[i] - r[i];
+    return nrm2(m, r);
+}
+
+/* Sec. 4.2: a solve that fails to meet its tolerance adopts the iterate with the least   */
+/* residual norm.  best_* hold that iterate (the initial dw_0 = 0 included); at the end, */
+/* if the tolerance was missed and an earlier iterate had a smaller residual, it         */
+/* replaces the last one.                                                                */
+static void keep_least_residual(int64_t m, int64_t n, double res, double* best_res,
+                                const double* dw, const double* dyh, double* bdw, double* bdyh) {
+    if (res < *best_res) {
+        *best_res = res;
+        memcpy(bdw, dw, (size_t)n * sizeof(double));
+        memcpy(bdyh, dyh, (size_t)m * sizeof(double));
+    }
+}
+
 /* CGNE preconditioned by inner iterations (Algorithm "CGNE method preconditioned by    */
 /* inner iterations"), dw_0 = 0, read with alpha_k in the update of dw.  The multiplier */
 /* vector dyh is carried along (dyh += alpha_k * multipliers of q_k) so that             */
-/* dw = A_hat^T dyh.  Stops when ||g_k|| <= eps ||f_hat|| or at kmax.                    */
+/* dw = A_hat^T dyh.  Stops when ||f_hat - A_hat dw_k|| <= eps ||f_hat|| or at kmax;     */
+/* when the tolerance is missed the least-residual iterate is returned (Sec. 4.2).      */
 static int cgne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* rp,
                 const int32_t* ci, const double* ah, const int32_t* perm, double omega_c,
                 const double* fh, double eps, int64_t kmax, double* dw, double* dyh,
@@ -421,12 +445,15 @@ static int cgne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
     double* q = (double*)malloc((size_t)n * sizeof(double));
     double* qm = (double*)malloc((size_t)m * sizeof(double));   /* multipliers of q */
     double* aq = (double*)malloc((size_t)m * sizeof(double));
+    double* rt = (double*)malloc((size_t)m * sizeof(double));
+    double* bdw = (double*)calloc((size_t)n, sizeof(double));
+    double* bdyh = (double*)calloc((size_t)m, sizeof(double));
     memcpy(g, fh, (size_t)m * sizeof(double));
     apply_inner(o, m, n, rp, ci, ah, perm, omega_c, g, uu, zz);
     memcpy(q, uu, (size_t)n * sizeof(double));
     memcpy(qm, zz, (size_t)m * sizeof(double));
     double gamma = dot(m, g, zz);
-    double res = beta;
+    double res = beta, best = beta;
     int64_t k = 0;
     while (k < kmax) {
         double qq = dot(n, q, q);
@@ -437,8 +464,9 @@ static int cgne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
         csr_mv(m, rp, ci, ah, q, aq);
         for (int64_t i = 0; i < m; ++i) g[i] -= alpha * aq[i];
         ++k;
-        res = nrm2(m, g);
+        res = true_residual(m, rp, ci, ah, fh, dw, rt);
         if (res <= eps * beta) break;
+        keep_least_residual(m, n, res, &best, dw, dyh, bdw, bdyh);
         apply_inner(o, m, n, rp, ci, ah, perm, omega_c, g, uu, zz);
         double gnew = dot(m, g, zz);
         double bk = gnew / gamma;
@@ -446,15 +474,23 @@ static int cgne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
         for (int64_t j = 0; j < n; ++j) q[j] = uu[j] + bk * q[j];
         for (int64_t i = 0; i < m; ++i) qm[i] = zz[i] + bk * qm[i];
     }
-    info->iters = k; info->res_est = res; info->failed = res > eps * beta;
-    free(g); free(zz); free(uu); free(q); free(qm); free(aq);
+    info->iters = k; info->failed = res > eps * beta;
+    if (info->failed && best < res) {
+        memcpy(dw, bdw, (size_t)n * sizeof(double));
+        memcpy(dyh, bdyh, (size_t)m * sizeof(double));
+        res = best;
+    }
+    info->res_est = res;
+    free(g); free(zz); free(uu); free(q); free(qm); free(aq); free(rt); free(bdw); free(bdyh);
     return ORC_OK;
 }
 
 /* MRNE preconditioned by inner iterations (Algorithm "MRNE method preconditioned by    */
 /* inner iterations"), read with consistent indices: dw_{k+1} = dw_k + alpha_k p_k,     */
 /* gamma_{k+1} = ||q_{k+1}||^2, p_{k+1} = q_{k+1} + beta_k p_k.  Multipliers of p and q */
-/* are carried so that dw = A_hat^T dyh.  Stops when ||g_k|| <= eps ||f_hat||.          */
+/* are carried so that dw = A_hat^T dyh.  Stops when ||f_hat - A_hat dw_k|| <=          */
+/* eps ||f_hat|| or at kmax; when the tolerance is missed the least-residual iterate is */
+/* returned (Sec. 4.2).                                                                 */
 static int mrne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* rp,
                 const int32_t* ci, const double* ah, const int32_t* perm, double omega_c,
                 const double* fh, double eps, int64_t kmax, double* dw, double* dyh,
@@ -472,12 +508,15 @@ static int mrne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
     double* t = (double*)malloc((size_t)m * sizeof(double));
     double* v = (double*)malloc((size_t)n * sizeof(double));
     double* vm = (double*)malloc((size_t)m * sizeof(double));
+    double* rt = (double*)malloc((size_t)m * sizeof(double));
+    double* bdw = (double*)calloc((size_t)n, sizeof(double));
+    double* bdyh = (double*)calloc((size_t)m, sizeof(double));
     memcpy(g, fh, (size_t)m * sizeof(double));
     apply_inner(o, m, n, rp, ci, ah, perm, omega_c, g, q, qm);   /* q_0 = A^T C g_0 */
     memcpy(pv, q, (size_t)n * sizeof(double));
     memcpy(pm, qm, (size_t)m * sizeof(double));
     double gamma = dot(n, q, q);
-    double res = beta;
+    double res = beta, best = beta;
     int64_t k = 0;
     while (k < kmax && gamma > 0.0) {
         csr_mv(m, rp, ci, ah, pv, t);                                /* t_k = A p_k */
@@ -491,16 +530,24 @@ static int mrne(const orc_solver_opts* o, int64_t m, int64_t n, const int64_t* r
         for (int64_t j = 0; j < n; ++j) q[j] -= alpha * v[j];
         for (int64_t i = 0; i < m; ++i) qm[i] -= alpha * vm[i];
         ++k;
-        res = nrm2(m, g);
+        res = true_residual(m, rp, ci, ah, fh, dw, rt);
         if (res <= eps * beta) break;
+        keep_least_residual(m, n, res, &best, dw, dyh, bdw, bdyh);
         double gnew = dot(n, q, q);
         double bk = gnew / gamma;
         gamma = gnew;
         for (int64_t j = 0; j < n; ++j) pv[j] = q[j] + bk * pv[j];
         for (int64_t i = 0; i < m; ++i) pm[i] = qm[i] + bk * pm[i];
     }
-    info->iters = k; info->res_est = res; info->failed = res > eps * beta;
-    free(g); free(q); free(qm); free(pv); free(pm); free(t); free(v); free(vm);
+    info->iters = k; info->failed = res > eps * beta;
+    if (info->failed && best < res) {
+        memcpy(dw, bdw, (size_t)n * sizeof(double));
+        memcpy(dyh, bdyh, (size_t)m * sizeof(double));
+        res = best;
+    }
+    info->res_est = res;
+    free(g); free(q); free(qm); free(pv); free(pm); free(t); free(v); free(vm); free(rt);
+    free(bdw); free(bdyh);
     return ORC_OK;
 }
 
