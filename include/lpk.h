@@ -118,7 +118,10 @@ typedef struct {
 typedef struct {
     int64_t iters;           /* Krylov iterations                                         */
     double beta;             /* ||f_hat||                                                  */
-    double res_est;          /* residual reported by the Krylov recurrence                */
+    double res_est;          /* residual of the stopping test for the returned iterate:   */
+                             /* AB-GMRES the Givens estimate |gamma_{k+1}|, BA-GMRES its  */
+                             /* preconditioned residual, CGNE / MRNE ||f_hat - A_hat dw|| */
+                             /* recomputed from dw                                        */
     double res_true;         /* ||f_hat - A_hat dw||, recomputed at exit                  */
     int32_t failed;          /* 1: tolerance not met within the limit (Sec. 4.2 rule)     */
     int32_t pad0;
@@ -236,7 +239,11 @@ lp_status ipm_step(lp_problem* p, lp_iter_info* info);
  * iterations from dw_0 = 0, stopping when ||f_hat - A_hat dw|| <= tol ||f_hat||.
  * d: n positive entries, or NULL for the current D = sqrt(x/s); f: m entries (R(A D)).
  * dw: n outputs; dy: m outputs or NULL.  ki may be NULL.  Krylov non-convergence is not
- * an error (ki->failed = 1; the last iterate, which has the least residual, is kept).
+ * an error: ki->failed = 1 and, as Sec. 4.2 prescribes for a solve that misses its
+ * tolerance, the iterate of least residual norm is returned.  For AB-GMRES and BA-GMRES
+ * that is the last iterate (their minimised residual does not grow); CGNE and MRNE, whose
+ * residual may grow, test ||f_hat - A_hat dw|| recomputed after every step and keep the
+ * least-residual iterate seen (dw_0 = 0 included).
  * Errors: LP_EINVAL (NULL f or dw, tol < 0), LP_ENONFINITE, LP_EDEVICE.                */
 lp_status direction_solve(lp_problem* p, const double* d, const double* f, double tol,
                           double* dw, double* dy, lp_krylov_info* ki);

@@ -88,7 +88,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
         z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(m, 4); z.add(2 * m, 4); z.add(m, 4);
     }
     for (int i = 0; i < (cg ? 15 : 12); ++i) z.add(m, 8);    // m-vectors
-    for (int i = 0; i < (cg ? 13 : 11); ++i) z.add(n, 8);    // n-vectors
+    for (int i = 0; i < (cg ? 14 : 11); ++i) z.add(n, 8);    // n-vectors
     if (o.max_correctors > 0) { z.add(n, 8); z.add(n, 8); }  // a corrector's dx, ds
     z.add(n, 4); z.add(m, 4);                     // z32, r32
     z.add(m * cols, 8); z.add(m * pcols, 8);      // V, P
@@ -448,8 +448,8 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     const int nv[] = {V_X, V_S, V_D, V_RD, V_TN, V_DXA, V_DSA, V_DW, V_TMPN, V_C, V_Z64};
     for (int q : nv) p->vec[q] = A.alloc<double>(n);
     if (cg) {
-        for (int q : {V_G, V_QM, V_PM}) p->vec[q] = A.alloc<double>(m);
-        for (int q : {V_Q, V_PV}) p->vec[q] = A.alloc<double>(n);
+        for (int q : {V_DYB, V_QM, V_PM}) p->vec[q] = A.alloc<double>(m);
+        for (int q : {V_Q, V_PV, V_DWB}) p->vec[q] = A.alloc<double>(n);
     }
     if (p->opt.max_correctors > 0)
         for (int q : {V_DXC, V_DSC}) p->vec[q] = A.alloc<double>(n);

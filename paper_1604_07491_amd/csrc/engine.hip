@@ -525,6 +525,13 @@ static void enqueue_gs(Batch& B, int64_t it, int parts) {
     if (parts & GS_FINISH) b_gs_finish(L);
 }
 
+// the residual f_hat - A_hat dw of the iterate a CGNE / MRNE step just formed, recomputed
+// (its squared norm as reduction partials), for the stopping test of Sec. 4.2
+static void enqueue_cg_residual(Batch& B, int64_t it) {
+    Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, [](const lp_problem* p) { return csr_bytes(p) + 8.0 * p->m; }));
+    b_spmv(B.L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, PM_ITER_DIR, true);
+}
+
 // one CGNE or MRNE iteration (Sec. 3.3): a preconditioner application (multipliers into
 // column 0 of P), its product with A_hat^T in FP64, one product with A_hat, and the
 // vector kernels
@@ -555,6 +562,7 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
             Prof pr(&B, LP_K_CG_VEC, it, vb(48.0, 24.0));
             b_cgne_step(L);
         }
+        enqueue_cg_residual(B, it);
         b_cg_check(L);
     } else {
         {
@@ -571,9 +579,10 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
             b_cg_dot(L, V_Z64, V_PV, 1);
         }
         {
-            Prof pr(&B, LP_K_CG_VEC, it, vb(64.0, 40.0));
+            Prof pr(&B, LP_K_CG_VEC, it, vb(40.0, 40.0));
             b_mrne_step(L);
         }
+        enqueue_cg_residual(B, it);
         b_cg_check(L);
         {
             Prof pr(&B, LP_K_CG_VEC, it, vb(24.0, 24.0));
@@ -667,6 +676,8 @@ static void enqueue_assembly(Batch& B, int pmask) {
         b_backsolve(L, pmask);
         b_combine(L, pmask);
         b_spmv(L, M_AH_CSC, V_DYH, V_DW, EPI_PLAIN, -1, -1, pmask, false);
+    } else {
+        b_cg_restore(L, pmask);
     }
     b_spmv(L, M_AH_CSR, V_DW, V_TMPM, EPI_B_MINUS, V_FH, -1, pmask, true);
     b_true_res(L, pmask);
@@ -699,6 +710,8 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
     }
     if (info) info->assign((size_t)B.cap, lp_krylov_info{});
     if (kmax_all == 0) return LP_OK;
+    // MRNE's first launch forms q_0 and takes no step, so kmax steps need kmax + 1
+    const int64_t extra = B.L.krylov == LP_MRNE ? 1 : 0;
     const int64_t sid = B.solve_id++;
     B.cur_solve = sid;
     if ((int64_t)B.solve_iters.size() <= sid) B.solve_iters.resize(sid + 1, 0);
@@ -712,7 +725,7 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
     int64_t enq = 0;
     int batch = poll_every > 0 ? poll_every : (B.last_iters > 2 ? (int)(B.last_iters - 1) : 4);
     for (;;) {
-        const int64_t todo = std::max<int64_t>(1, std::min<int64_t>(batch, kmax_all - enq));
+        const int64_t todo = std::max<int64_t>(1, std::min<int64_t>(batch, kmax_all + extra - enq));
         if (use_graph) {
             const int64_t launches = (todo + B.graph_iters - 1) / B.graph_iters;
             for (int64_t i = 0; i < launches; ++i) LPK_HIP(hipGraphLaunch(B.gexec, B.st));
@@ -727,7 +740,7 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
         bool all = true;
         for (int s = 0; s < B.cap; ++s)
             if (B.mem[s] && (B.h_param[s].mode & pmask) && !B.h_slot[s].ctl.done) all = false;
-        if (all || enq >= kmax_all) break;
+        if (all || enq >= kmax_all + extra) break;
         if (poll_every <= 0) batch = std::max(2, std::min(32, batch < 8 ? 4 : batch / 2));
     }
     enqueue_assembly(B, pmask);

@@ -33,15 +33,22 @@ struct KrylovCtl {
     double cg_gamma;
     double cg_beta;
     int32_t cg_phase;
-    int32_t pad0;
+    // CGNE / MRNE least-residual iterate (the failure rule of Sec. 4.2): CG_SAVE, the
+    // iterate now in dw, dyh has the least residual so far and the next step copies it to
+    // V_DWB, V_DYB before updating; CG_RESTORE, the solve missed its tolerance and the
+    // assembly puts the saved iterate back
+    int32_t cg_save;
+    double cg_best;     // least residual so far (dw_0 = 0 included)
+    double pad1;
 };
+constexpr int CG_SAVE = 1, CG_RESTORE = 2;
 
 // vectors of an instance, addressed by selector
 enum VecSel : int {
     V_X = 0, V_Y, V_S, V_D, V_RHO, V_RP, V_RD, V_TN, V_DXA, V_DSA, V_DYA, V_DYC, V_F, V_DW, V_DYH,
     V_TMPM, V_TMPN, V_B, V_C, V_FH, V_U, V_Z64, V_R64,
-    V_G, V_QM, V_PM,    // CGNE / MRNE m-vectors: residual (MRNE), multipliers of q and p
-    V_Q, V_PV,          // CGNE / MRNE n-vectors: q, p
+    V_DYB, V_QM, V_PM,  // CGNE / MRNE m-vectors: least-residual dyh, multipliers of q and p
+    V_Q, V_PV, V_DWB,   // CGNE / MRNE n-vectors: q, p, least-residual dw
     V_DXC, V_DSC,       // a centrality corrector's dx and ds (multiple correctors only)
     V_COUNT
 };
@@ -227,7 +234,9 @@ void b_cg_dot(const BLaunch& L, int xs, int ys, int nlen);
 void b_cgne_dir(const BLaunch& L);     // q = A_hat^T Cg + beta q (and multipliers); q.q
 void b_cgne_step(const BLaunch& L);    // alpha; dw, dyh += alpha (q, qm); g -= alpha A_hat q; g.g
 void b_mrne_step(const BLaunch& L);    // start: q_0; else alpha; dw, dyh, g, q, qm updates; g.g, q.q
-void b_cg_check(const BLaunch& L);     // res = ||g||, the stopping test, the next gamma (and beta)
+void b_cg_check(const BLaunch& L);     // res = ||f_hat - A_hat dw||, the stopping test, the least residual,
+                                       // the next gamma (and beta)
+void b_cg_restore(const BLaunch& L, int pmask);   // the least-residual iterate back after a failed solve
 void b_mrne_dir(const BLaunch& L);     // p = q + beta p, pm = qm + beta pm
 void b_gemv_col(const BLaunch& L);      // dense: u = G p_k
 // solve set-up (instances with a bit of pmask take part; the others are marked done)

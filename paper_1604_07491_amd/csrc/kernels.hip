@@ -884,15 +884,25 @@ void b_true_res(const BLaunch& L, int pmask) {
 // dw = A_hat^T dyh comes out of the iteration itself.
 //
 // Vectors.  CGNE: g (residual) = V_U, C g = P0, A_hat^T C g = V_Z64, q = V_Q with its
-// multipliers V_QM, A_hat q = V_TMPM.  MRNE: g = V_G, t = A_hat p = V_U, C t = P0,
-// v = A_hat^T C t = V_Z64, q = V_Q (multipliers V_QM), p = V_PV (multipliers V_PM).
+// multipliers V_QM, A_hat q = V_TMPM.  MRNE: t = A_hat p = V_U, C t = P0,
+// v = A_hat^T C t = V_Z64, q = V_Q (multipliers V_QM), p = V_PV (multipliers V_PM); MRNE's
+// residual recurrence g is not formed, since nothing reads it here.  Both: the
+// least-residual iterate in V_DWB, V_DYB.
+//
+// Stopping and failure (Sec. 4.2).  After each step the residual f_hat - A_hat dw is
+// recomputed by a CSR product (V_TMPM, its squared norm as partials of quantity 0 over
+// nbs blocks) and the check tests its norm against tol ||f_hat||.  The check also keeps
+// the least residual so far (dw_0 = 0 included): when the new iterate is the least, the
+// next step kernel first copies dw and dyh to V_DWB and V_DYB (CG_SAVE); when the solve
+// ends above the tolerance with an earlier iterate the least, the assembly copies that one
+// back (CG_RESTORE).
 //
 // Partials (Inst::part, nbr blocks each): CG_DOT the step's numerator or denominator
-// dot product, CG_QQ = q.q, CG_GG = g.g.  A multi-block kernel reads scalars only from
-// the control block (written by earlier launches) and from complete partials; only the
-// one-block check kernel writes the control block, so no block reads a scalar that
-// another block of the same launch writes.
-constexpr int CG_DOT = 1, CG_QQ = 2, CG_GG = 3;
+// dot product, CG_QQ = q.q.  A multi-block kernel reads scalars only from the control
+// block (written by earlier launches) and from complete partials; only the one-block
+// check kernel writes the control block, so no block reads a scalar that another block
+// of the same launch writes.
+constexpr int CG_DOT = 1, CG_QQ = 2;
 
 // the sum of the nb partials of quantity q in fixed order, on every thread of the block
 __device__ __forceinline__ double part_total(const Inst& in, int q, int nb, double* sh) {
@@ -905,8 +915,9 @@ __device__ __forceinline__ double part_total(const Inst& in, int q, int nb, doub
     return sh[0];
 }
 
-// start: dw = 0, dyh = 0, q = qm = p = pm = 0; the sweeps read t unscaled (1/h = 1) into
-// column k = 0; MRNE: g = f_hat (t starts as f_hat, written by the start of the solve)
+// start: dw = 0, dyh = 0 (also the least-residual copies: dw_0 has residual ||f_hat||),
+// q = qm = p = pm = 0; the sweeps read their input unscaled (1/h = 1) from column k = 0
+// (MRNE's start: f_hat, written by the start of the solve)
 __global__ __launch_bounds__(BLOCK) void k_cg_init(const Inst* __restrict__ I, int pmask, int mrne) {
     INST;
     if (!takes_part(in, pmask)) return;
@@ -914,14 +925,15 @@ __global__ __launch_bounds__(BLOCK) void k_cg_init(const Inst* __restrict__ I, i
     const int64_t t0 = (int64_t)bx * BLOCK + threadIdx.x;
     for (int64_t j = t0; j < in.n; j += stride) {
         in.vec[V_DW][j] = 0.0;
+        in.vec[V_DWB][j] = 0.0;
         in.vec[V_Q][j] = 0.0;
         in.vec[V_PV][j] = 0.0;
     }
     for (int64_t i = t0; i < in.m; i += stride) {
         in.vec[V_DYH][i] = 0.0;
+        in.vec[V_DYB][i] = 0.0;
         in.vec[V_QM][i] = 0.0;
         in.vec[V_PM][i] = 0.0;
-        if (mrne) in.vec[V_G][i] = in.vec[V_FH][i];
     }
     if (bx == 0 && threadIdx.x == 0) {
         KrylovCtl* ctl = in.ctl;
@@ -930,6 +942,8 @@ __global__ __launch_bounds__(BLOCK) void k_cg_init(const Inst* __restrict__ I, i
         ctl->cg_gamma = 0.0;
         ctl->cg_beta = 0.0;
         ctl->cg_phase = mrne ? 0 : 1;
+        ctl->cg_save = 0;
+        ctl->cg_best = ctl->beta;
     }
 }
 
@@ -984,16 +998,29 @@ void b_cgne_dir(const BLaunch& L) {
     hipLaunchKernelGGL(k_cgne_dir, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
+// the step kernels' first task: copy the iterate in dw, dyh to the least-residual
+// vectors when the last check found it the least so far
+__device__ __forceinline__ void cg_save_best(const Inst& in, int64_t t0, int64_t stride) {
+    if (in.ctl->cg_save != CG_SAVE) return;
+    const double* __restrict__ dw = in.vec[V_DW];
+    double* __restrict__ dwb = in.vec[V_DWB];
+    for (int64_t j = t0; j < in.n; j += stride) dwb[j] = dw[j];
+    const double* __restrict__ dyh = in.vec[V_DYH];
+    double* __restrict__ dyb = in.vec[V_DYB];
+    for (int64_t i = t0; i < in.m; i += stride) dyb[i] = dyh[i];
+}
+
 // CGNE step: alpha = gamma_new / q.q; dw += alpha q, dyh += alpha qm, g -= alpha A_hat q
-// (A_hat q in V_TMPM); g.g partials.  q.q = 0 ends the iteration (in the check).
+// (A_hat q in V_TMPM).  q.q = 0 ends the iteration (in the check).
 __global__ __launch_bounds__(BLOCK) void k_cgne_step(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
     INST;
     if (in.ctl->done || bx >= in.nbr) return;
+    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    cg_save_best(in, t0, stride);
     const double qq = part_total(in, CG_QQ, in.nbr, sh);
     if (qq == 0.0) return;
     const double alpha = part_total(in, CG_DOT, in.nbr, sh) / qq;
-    const int64_t stride = (int64_t)in.nbr * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
     const double* __restrict__ q = in.vec[V_Q];
     double* __restrict__ dw = in.vec[V_DW];
     for (int64_t j = t0; j < in.n; j += stride) dw[j] += alpha * q[j];
@@ -1001,24 +1028,19 @@ __global__ __launch_bounds__(BLOCK) void k_cgne_step(const Inst* __restrict__ I)
     const double* __restrict__ aq = in.vec[V_TMPM];
     double* __restrict__ dyh = in.vec[V_DYH];
     double* __restrict__ g = in.vec[V_U];
-    double gg = 0.0;
     for (int64_t i = t0; i < in.m; i += stride) {
         dyh[i] += alpha * qm[i];
-        const double v = g[i] - alpha * aq[i];
-        g[i] = v;
-        gg += v * v;
+        g[i] -= alpha * aq[i];
     }
-    write_part(in, bx, CG_GG, block_sum(gg, sh));
 }
 
 void b_cgne_step(const BLaunch& L) {
     hipLaunchKernelGGL(k_cgne_step, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
-// MRNE step.  Start (phase 0): q = A_hat^T C g, qm = C g; q.q partials.  Else, with
-// v = A_hat^T C t, t = A_hat p: alpha = gamma / v.p; dw += alpha p, dyh += alpha pm,
-// g -= alpha t, q -= alpha v, qm -= alpha C t; g.g and q.q partials.  v.p = 0 ends the
-// iteration (in the check).
+// MRNE step.  Start (phase 0): q = A_hat^T C f_hat, qm = C f_hat; q.q partials.  Else,
+// with v = A_hat^T C t, t = A_hat p: alpha = gamma / v.p; dw += alpha p, dyh += alpha pm,
+// q -= alpha v, qm -= alpha C t; q.q partials.  v.p = 0 ends the iteration (in the check).
 __global__ __launch_bounds__(BLOCK) void k_mrne_step(const Inst* __restrict__ I) {
     __shared__ double sh[BLOCK / 64];
     INST;
@@ -1038,6 +1060,7 @@ __global__ __launch_bounds__(BLOCK) void k_mrne_step(const Inst* __restrict__ I)
         write_part(in, bx, CG_QQ, block_sum(qq, sh));
         return;
     }
+    cg_save_best(in, t0, stride);
     const double vp = part_total(in, CG_DOT, in.nbr, sh);
     if (vp == 0.0) return;
     const double alpha = in.ctl->cg_gamma / vp;
@@ -1051,18 +1074,11 @@ __global__ __launch_bounds__(BLOCK) void k_mrne_step(const Inst* __restrict__ I)
         qq += w * w;
     }
     const double* __restrict__ pm = in.vec[V_PM];
-    const double* __restrict__ t = in.vec[V_U];
     double* __restrict__ dyh = in.vec[V_DYH];
-    double* __restrict__ g = in.vec[V_G];
-    double gg = 0.0;
     for (int64_t i = t0; i < in.m; i += stride) {
         dyh[i] += alpha * pm[i];
-        const double w = g[i] - alpha * t[i];
-        g[i] = w;
-        gg += w * w;
         qm[i] -= alpha * vm[i];
     }
-    write_part(in, bx, CG_GG, block_sum(gg, sh));
     write_part(in, bx, CG_QQ, block_sum(qq, sh));
 }
 
@@ -1070,11 +1086,25 @@ void b_mrne_step(const BLaunch& L) {
     hipLaunchKernelGGL(k_mrne_step, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 
-// One block per instance: the iteration count, res = ||g|| and the stopping test
-// ||g|| <= tol ||f_hat|| or the limit; a zero denominator stops the iteration where it
-// is.  CGNE: gamma = g . C g of this step (the next direction's reference).  MRNE:
+// One block per instance: the iteration count, res = ||f_hat - A_hat dw|| (from the
+// partials of the recomputed residual) and the stopping test res <= tol ||f_hat||, the
+// least-residual bookkeeping, or the limit; a zero denominator stops the iteration where
+// it is.  CGNE: gamma = g . C g of this step (the next direction's reference).  MRNE:
 // start: gamma = q_0 . q_0; after a step: beta = q.q / gamma and gamma = q.q, and
-// gamma = 0 stops the iteration.
+// gamma = 0 stops the iteration.  A solve that ends above the tolerance with an earlier
+// iterate of smaller residual is marked CG_RESTORE and reports that residual.
+__device__ __forceinline__ void cg_end(KrylovCtl* ctl, double res) {
+    ctl->done = 1;
+    ctl->failed = res > ctl->thresh;
+    if (ctl->failed && ctl->cg_best < res) {
+        ctl->cg_save = CG_RESTORE;
+        ctl->res = ctl->cg_best;
+    } else {
+        ctl->cg_save = 0;
+        ctl->res = res;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_cg_check(const Inst* __restrict__ I, int mrne) {
     __shared__ double sh[BLOCK / 64];
     INST;
@@ -1087,38 +1117,39 @@ __global__ __launch_bounds__(BLOCK) void k_cg_check(const Inst* __restrict__ I, 
         ctl->cg_gamma = gam;
         ctl->cg_beta = 0.0;
         ctl->cg_phase = 1;
-        if (!(gam > 0.0)) {
-            ctl->done = 1;
-            ctl->failed = ctl->res > ctl->thresh;
-        }
+        if (!(gam > 0.0)) cg_end(ctl, ctl->res);
         return;
     }
     const double den = part_total(in, mrne ? CG_DOT : CG_QQ, nb, sh);
-    const double gg = part_total(in, CG_GG, nb, sh);
+    double r2 = 0.0;
+    for (int c = threadIdx.x; c < in.nbs; c += blockDim.x) r2 += in.part[c];
+    r2 = block_sum(r2, sh);
     const double other = part_total(in, mrne ? CG_QQ : CG_DOT, nb, sh);
     if (threadIdx.x != 0) return;
     if (den == 0.0) {
-        ctl->done = 1;
-        ctl->failed = ctl->res > ctl->thresh;
+        cg_end(ctl, ctl->res);   // no step was taken: the iterate of the last check
         return;
     }
-    const double res = sqrt(gg);
+    const double res = sqrt(r2);
     const int it = ctl->iters + 1;
-    ctl->res = res;
     ctl->iters = it;
     if (!mrne) ctl->cg_gamma = other;
-    if (res <= ctl->thresh || it >= ctl->kmax) {
-        ctl->done = 1;
-        ctl->failed = res > ctl->thresh;
+    if (res <= ctl->thresh) {
+        cg_end(ctl, res);
+        return;
+    }
+    const bool least = res < ctl->cg_best;
+    if (least) ctl->cg_best = res;
+    ctl->cg_save = least ? CG_SAVE : 0;
+    ctl->res = res;
+    if (it >= ctl->kmax) {
+        cg_end(ctl, res);
         return;
     }
     if (mrne) {
         ctl->cg_beta = other / ctl->cg_gamma;
         ctl->cg_gamma = other;
-        if (!(other > 0.0)) {
-            ctl->done = 1;
-            ctl->failed = 1;
-        }
+        if (!(other > 0.0)) cg_end(ctl, res);
     }
 }
 
@@ -1143,6 +1174,25 @@ __global__ __launch_bounds__(BLOCK) void k_mrne_dir(const Inst* __restrict__ I) 
 
 void b_mrne_dir(const BLaunch& L) {
     hipLaunchKernelGGL(k_mrne_dir, dim3(L.max_nbr, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// assembly of a CGNE / MRNE solve that missed its tolerance: the least-residual iterate
+// replaces the last one (Sec. 4.2)
+__global__ __launch_bounds__(BLOCK) void k_cg_restore(const Inst* __restrict__ I, int pmask) {
+    INST;
+    if (!takes_part(in, pmask) || in.ctl->cg_save != CG_RESTORE) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK, t0 = (int64_t)bx * BLOCK + threadIdx.x;
+    const double* __restrict__ dwb = in.vec[V_DWB];
+    double* __restrict__ dw = in.vec[V_DW];
+    for (int64_t j = t0; j < in.n; j += stride) dw[j] = dwb[j];
+    const double* __restrict__ dyb = in.vec[V_DYB];
+    double* __restrict__ dyh = in.vec[V_DYH];
+    for (int64_t i = t0; i < in.m; i += stride) dyh[i] = dyb[i];
+}
+
+void b_cg_restore(const BLaunch& L, int pmask) {
+    const unsigned gx = capg(cdiv(L.max_m > L.max_n ? L.max_m : L.max_n, BLOCK), GRID_CAP);
+    hipLaunchKernelGGL(k_cg_restore, dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
 // ------------------------------------------------------------------------------------

@@ -15,16 +15,13 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_close, rel
 import paper_1604_07491_amd as lpk
 from paper_1604_07491_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 
-def _rel(a, b):
-    a = np.asarray(a.cpu() if hasattr(a, "cpu") else a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _case(name):
@@ -65,10 +62,10 @@ def test_bagmres_fixed_iterations(name, k, inner):
     odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0,
                                       oracle.solver_opts(krylov=oracle.BAGMRES, inner=INNER[inner], kmax=k))
     assert info["iters"] == oinfo["iters"] == k
-    assert _rel(dw, odw) <= 1e-9
+    assert_close(dw, odw, 1e-9)
     # dy is unique up to the null space of (A D)^T: compare (A D)^T dy
     AD = lp.to_dense() * d
-    assert _rel(AD.T @ np.asarray(dy), AD.T @ ody) <= 1e-9
+    assert_close(AD.T @ np.asarray(dy), AD.T @ ody, 1e-9)
     assert abs(info["beta"] - oinfo["beta"]) <= 1e-12 * oinfo["beta"]
     assert abs(info["res_est"] - oinfo["res_est"]) <= 1e-8 * oinfo["res_est"]
     assert abs(info["res_true"] - oinfo["res_true"]) <= 1e-9 * oinfo["beta"]
@@ -86,11 +83,11 @@ def test_bagmres_converged_is_min_norm(name, inner):
     AD = lp.to_dense() * d
     ref = np.linalg.pinv(AD) @ f
     print(f"iters {info['iters']} (oracle {oinfo['iters']}) res_true/beta {info['res_true'] / info['beta']:.2e} "
-          f"err {_rel(dw, ref):.2e}", flush=True)
+          f"err {rel(dw, ref):.2e}", flush=True)
     assert not info["failed"]
     assert abs(info["iters"] - oinfo["iters"]) <= 1
-    assert _rel(dw, ref) <= 1e-8
-    assert _rel(AD.T @ np.asarray(dy), ref) <= 1e-8
+    assert_close(dw, ref, 1e-8)
+    assert_close(AD.T @ np.asarray(dy), ref, 1e-8)
     assert info["res_true"] <= 1e-10 * info["beta"]
 
 
@@ -116,7 +113,7 @@ def test_bagmres_solves_the_corrector_least_squares_form():
         dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
     dy_ls = np.linalg.lstsq(AD.T, h, rcond=None)[0]
     assert not info["failed"]
-    assert _rel(dw, AD.T @ dy_ls) <= 1e-8
+    assert_close(dw, AD.T @ dy_ls, 1e-8)
 
 
 def test_bagmres_batch_matches_alone():

@@ -13,15 +13,11 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_close, rel, to_np
 import paper_1604_07491_amd as lpk
 from paper_1604_07491_amd import synth
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    a = np.asarray(a.cpu() if hasattr(a, "cpu") else a)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @functools.lru_cache(maxsize=None)
@@ -68,11 +64,11 @@ def test_fixed_iteration_direction_at_full_size(name, krylov, precision, k):
                             kmax=k, flexible=1 if krylov == "abgmres" else 0)
     odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, so)
     tol = 1e-9 if precision == "fp64" else 1e-4
-    e_dw = _rel(dw, odw)
     # dy is unique up to the null space of (A D)^T: compare (A D)^T dy = d o (A^T dy)
-    e_dy = _rel(d * oracle.csr_tmv(lp, np.asarray(dy.cpu() if hasattr(dy, "cpu") else dy)),
-                d * oracle.csr_tmv(lp, ody))
-    print(f"iters {info['iters']} dw err {e_dw:.2e} (A D)^T dy err {e_dy:.2e}", flush=True)
+    gdy = d * oracle.csr_tmv(lp, to_np(dy))
+    ody_w = d * oracle.csr_tmv(lp, ody)
+    print(f"iters {info['iters']} dw err {rel(dw, odw):.2e} (A D)^T dy err {rel(gdy, ody_w):.2e}", flush=True)
     assert info["iters"] == oinfo["iters"] == k
-    assert e_dw <= tol and e_dy <= tol
+    assert_close(dw, odw, tol)
+    assert_close(gdy, ody_w, tol)
     assert abs(info["res_true"] - oinfo["res_true"]) <= tol * oinfo["beta"]

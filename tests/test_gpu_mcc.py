@@ -79,10 +79,14 @@ def test_correctors_batch_matches_alone():
 
 @pytest.mark.parametrize("krylov,inner", [("cgne", "nessor"), ("mrne", "nessor"), ("bagmres", "nesor")])
 def test_correctors_with_other_krylov_methods(krylov, inner):
-    """The corrector solves run through whichever Krylov method the LP uses.  MRNE's
-    residual is a recurrence that drifts from the true residual at rounding level, so its
-    solves stop at slightly different iterates on the two sides and the step counts may
-    differ by two; the optimum may not."""
+    """The corrector solves run through whichever Krylov method the LP uses.  CGNE and MRNE
+    test the residual recomputed from their iterate on both sides (not a recurrence).  The
+    step counts agree to the one step a corrector decision within rounding of its threshold
+    may add, or else the side that stops first does so where the other side's gamma_rel is
+    within a factor 2 of eps_out = 1e-8: late solves stop at eps_in of a few 1e-8, so the
+    iterates, and gamma_rel with them, are determined only to about that level, and a side
+    just above the threshold may need two more steps (measured on this LP with MRNE: the
+    oracle's gamma_rel is 1.10e-8 after 10 steps and 2.38e-8 after 11)."""
     lp = _case("transport")
     kry = {"cgne": oracle.CGNE, "mrne": oracle.MRNE, "bagmres": oracle.BAGMRES}[krylov]
     inn = {"nessor": oracle.NESSOR, "nesor": oracle.NESOR}[inner]
@@ -96,4 +100,10 @@ def test_correctors_with_other_krylov_methods(krylov, inner):
           f"correctors {sum(L['correctors'] for L in o['log'])}", flush=True)
     assert r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8
     assert abs(r["pobj"] - o["pobj"]) <= 1e-7 * abs(o["pobj"])
-    assert abs(r["iters"] - o["iters"]) <= (2 if krylov == "mrne" else 1) and nc > 0
+    assert nc > 0
+    gl = [L["gamma_rel"] for L in log]
+    ol = [L["gamma_rel"] for L in o["log"]]
+    first, other = (gl, ol) if r["iters"] < o["iters"] else (ol, gl)
+    stop = min(r["iters"], o["iters"])
+    print(f"gamma_rel at step {stop}: gpu {gl[stop]:.3e} oracle {ol[stop]:.3e}", flush=True)
+    assert abs(r["iters"] - o["iters"]) <= 1 or other[stop] <= 2e-8

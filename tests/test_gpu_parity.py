@@ -12,16 +12,13 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_close, rel
 import paper_1604_07491_amd as lpk
 from paper_1604_07491_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 
-def _rel(a, b):
-    a = np.asarray(a.cpu() if hasattr(a, "cpu") else a)
-    b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _case(name):
@@ -64,12 +61,54 @@ def test_direction_solve_fixed_iterations(name, k):
     order = oracle.ORDER_NATURAL if name == "longrows" else oracle.ORDER_COLOUR
     odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, order=order))
     assert info["iters"] == oinfo["iters"] == min(k, lp.m)
-    assert _rel(dw, odw) <= 1e-9
+    assert_close(dw, odw, 1e-9)
     # dy is unique only up to the null space of (A D)^T (duplicated rows, the transportation
     # matrix's rank deficiency): compare (A D)^T dy, which is what the recurrence uses
     AD = lp.to_dense() * d
-    assert _rel(AD.T @ np.asarray(dy), AD.T @ ody) <= 1e-9
+    assert_close(AD.T @ np.asarray(dy), AD.T @ ody, 1e-9)
     assert abs(info["res_est"] - oinfo["res_est"]) <= 1e-9 * oinfo["beta"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
+                                  "transport_tall", "ldsz"])
+def test_one_iteration_at_kernel_tolerance(name, precision):
+    """At k = 1 the direction is one preconditioner application scaled by a scalar
+    (dw = y_1 A_hat^T C v_1, y_1 from one product and two norms), so it checks the sweep
+    and the products at their own tolerances: FP64 1e-12 (summation order and fused
+    multiply-add only), FP32 sweeps 1e-5 against the FP64 oracle, element by element."""
+    lp = _case(name)
+    d, f = _dir_problem(lp, 7)
+    print(f"case {name} k=1 {precision} m={lp.m} n={lp.n}", flush=True)
+    with lpk.from_lp(lp, lpk.options(krylov_max_iter=1, precision=precision)) as p:
+        dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
+    order = oracle.ORDER_NATURAL if name == "longrows" else oracle.ORDER_COLOUR
+    odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=1, flexible=1, order=order))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    print(f"dw err {rel(dw, odw):.2e}", flush=True)
+    assert info["iters"] == oinfo["iters"] == 1
+    assert_close(dw, odw, tol)
+    AD = lp.to_dense() * d
+    assert_close(AD.T @ np.asarray(dy), AD.T @ ody, tol)
+    assert abs(info["res_est"] - oinfo["res_est"]) <= tol * oinfo["beta"]
+
+
+@pytest.mark.parametrize("name", ["config0", "ragged", "transport", "transport_wide", "transport_sliced"])
+def test_starting_point_matches_the_oracle(name):
+    """The starting point (Mehrotra's heuristic, the reading of Sec. 4.2's LIPSOL start):
+    with ipm_max_iter = 0 the solve stops right after computing it.  x and s element by
+    element; y is unique only up to the null space of A^T, so A^T y."""
+    lp = _case(name)
+    print(f"case {name} starting point", flush=True)
+    ox, oy, os_ = oracle.init_point(lp)
+    with lpk.from_lp(lp, lpk.options(ipm_max_iter=0)) as p:
+        r = lpk.lp_solve(p)
+        x, y, s, st = lpk.lp_get_state(p)
+    assert r["status"] == lpk.LP_NOT_CONVERGED and r["iters"] == 0
+    print(f"x err {rel(x, ox):.2e} s err {rel(s, os_):.2e}", flush=True)
+    assert_close(x, ox, 1e-9)
+    assert_close(s, os_, 1e-9)
+    assert_close(oracle.csr_tmv(lp, np.asarray(y)), oracle.csr_tmv(lp, oy), 1e-9)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -83,9 +122,9 @@ def test_direction_solve_converged_is_min_norm(name, precision):
     AD = lp.to_dense() * d
     ref = np.linalg.pinv(AD) @ f
     assert not info["failed"]
-    assert _rel(dw, ref) <= 1e-8
+    assert_close(dw, ref, 1e-8)
     # dw = (A D)^T dy
-    assert _rel(AD.T @ np.asarray(dy), ref) <= 1e-8
+    assert_close(AD.T @ np.asarray(dy), ref, 1e-8)
     assert info["res_true"] <= 2e-12 * info["beta"]
 
 
@@ -98,11 +137,12 @@ def test_cimmino_direction_solve(precision):
             dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
         odw, ody, _ = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, inner=oracle.CIMMINO))
         tol = 1e-9 if precision == "fp64" else 1e-4
-        assert _rel(dw, odw) <= tol and _rel(dy, ody) <= tol
+        assert_close(dw, odw, tol)
+        assert_close(dy, ody, tol)
     with lpk.from_lp(lp, lpk.options(inner="cimmino", precision=precision)) as p:
         dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
     ref = np.linalg.pinv(lp.to_dense() * d) @ f
-    assert _rel(dw, ref) <= 1e-8
+    assert_close(dw, ref, 1e-8)
 
 
 def test_ipm_step_from_a_given_point():
@@ -120,7 +160,9 @@ def test_ipm_step_from_a_given_point():
             assert rc == 0 and not done
             assert info["k_af"] == L["k_af"] and info["k_cc"] == L["k_cc"]
             assert abs(info["alpha_p"] - L["alpha_p"]) <= 1e-9 and abs(info["alpha_d"] - L["alpha_d"]) <= 1e-9
-            assert _rel(gx, ox) <= 1e-9 and _rel(gs, os_) <= 1e-9 and _rel(gy, oy) <= 1e-8
+            assert_close(gx, ox, 1e-9)
+            assert_close(gs, os_, 1e-9)
+            assert_close(gy, oy, 1e-8)
             x, y, s = ox, oy, os_
 
 
@@ -189,9 +231,9 @@ def test_dense_gram_direction_solve_fixed_iterations(shape, k, precision):
     odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1, order=oracle.ORDER_NATURAL))
     assert info["iters"] == oinfo["iters"]
     tol = 1e-9 if precision == "fp64" else 2e-4
-    assert _rel(dw, odw) <= tol
+    assert_close(dw, odw, tol)
     AD = lp.dense * d
-    assert _rel(AD.T @ np.asarray(dy), AD.T @ ody) <= tol
+    assert_close(AD.T @ np.asarray(dy), AD.T @ ody, tol)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -201,7 +243,8 @@ def test_dense_gram_converged_min_norm(precision):
     with lpk.lp_create_dense(lp.dense, lp.b, lp.c, lpk.options(precision=precision)) as p:
         dw, dy, info = lpk.direction_solve(p, d, f, 1e-12)
     ref = np.linalg.pinv(lp.dense * d) @ f
-    assert not info["failed"] and _rel(dw, ref) <= 1e-8
+    assert not info["failed"]
+    assert_close(dw, ref, 1e-8)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -262,7 +305,7 @@ def test_direction_solve_beyond_1024_iterations():
         dw, dy, info = lpk.direction_solve(p, d, f, 0.0)
     odw, ody, oinfo = oracle.dirsolve(lp, d, f, 0.0, oracle.solver_opts(kmax=k, flexible=1))
     print(f"iters {info['iters']} res_true {info['res_true']:.3e} (oracle {oinfo['res_true']:.3e}) "
-          f"dw err {_rel(dw, odw):.2e}", flush=True)
+          f"dw err {rel(dw, odw):.2e}", flush=True)
     assert info["iters"] == oinfo["iters"] == k
-    assert _rel(dw, odw) <= 1e-6
+    assert_close(dw, odw, 1e-6)
     assert abs(info["res_true"] - oinfo["res_true"]) <= 1e-9 * oinfo["beta"]
