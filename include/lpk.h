@@ -248,6 +248,26 @@ lp_status ipm_step(lp_problem* p, lp_iter_info* info);
 lp_status direction_solve(lp_problem* p, const double* d, const double* f, double tol,
                           double* dw, double* dy, lp_krylov_info* ki);
 
+/* For callers that cannot allocate device memory during the call (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): direction_solve with
+ * every per-call device buffer -- the batch descriptors, the Krylov control block, the
+ * phase parameters, the reduction partials and the Krylov workspace (basis V, multiplier
+ * vectors P, Hessenberg matrix, Givens and Gram-Schmidt arrays) -- in one fixed device array
+ * of 32 MiB that the library holds on each GPU it runs on until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree, pinned host allocation or graph
+ * instantiation) and launches the kernels of direction_solve one by one, so its results
+ * are those of direction_solve.  d (n doubles, or NULL for the current D), f (m), dw (n)
+ * and dy (m, or NULL) are device pointers on the current device whatever
+ * lp_options.device_io says; the problem must have been created on this device.  The
+ * array is shared by every call on a GPU and keeps the last call's contents (each call
+ * sets up what it reads): calls that overlap on one GPU, from other threads or on other
+ * streams, race and must be serialised by the caller.
+ * Errors: those of direction_solve; LP_ETOOBIG when the workspace (for AB-GMRES about
+ * 16 m (kmax + 1) + 8 (kmax + 1)^2 bytes) exceeds the array (create the problem with a
+ * smaller krylov_max_iter); LP_EDEVICE when the current device is not the problem's.   */
+lp_status direction_solve_noalloc(lp_problem* p, const double* d, const double* f, double tol,
+                                  double* dw, double* dy, lp_krylov_info* ki);
+
 /* The whole interior-point solve: starting point (unless options.start == 1), then
  * ipm_step until gamma_rel <= eps_out or ipm_max_iter iterations (Sec. 4.2).  Returns the
  * final status (LP_OK, LP_NOT_CONVERGED, LP_DIVERGED or an error); r may be NULL.       */

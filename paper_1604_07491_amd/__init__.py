@@ -114,6 +114,7 @@ SIGNATURES = {
     "lp_destroy": (None, [_P]),
     "ipm_step": (C.c_int, [_P, C.POINTER(IterInfo)]),
     "direction_solve": (C.c_int, [_P, _P, _P, C.c_double, _P, _P, C.POINTER(KrylovInfo)]),
+    "direction_solve_noalloc": (C.c_int, [_P, _P, _P, C.c_double, _P, _P, C.POINTER(KrylovInfo)]),
     "lp_solve": (C.c_int, [_P, C.POINTER(Result)]),
     "lp_get_state": (C.c_int, [_P, _P, _P, _P, C.POINTER(IpmState)]),
     "lp_set_state": (C.c_int, [_P, _P, _P, _P, C.POINTER(IpmState)]),
@@ -407,6 +408,27 @@ def direction_solve(p: Problem, d, f, tol: float):
     ki = KrylovInfo()
     _check(lib().direction_solve(p.h, pd, pf, float(tol), pdw, pdy, C.byref(ki)), "direction_solve")
     return dw, dy, _dict(ki)
+
+
+def direction_solve_noalloc(p: Problem, d, f, tol: float, dw, dy=None) -> dict:
+    """direction_solve with no device allocation in the call; returns the info dict.  d
+    (n, or None: current D), f (m) and the outputs dw (n), dy (m or None) are the caller's
+    contiguous float64 CUDA tensors; dw and dy are written in place."""
+    def dev(t, size, name):
+        if t is None:
+            return None
+        import torch
+        if not (_is_torch(t) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == size):
+            raise ValueError(f"{name}: a contiguous float64 CUDA tensor of {size} entries is needed")
+        return t.data_ptr()
+    pd, pf = dev(d, p.n, "d"), dev(f, p.m, "f")
+    pdw, pdy = dev(dw, p.n, "dw"), dev(dy, p.m, "dy")
+    if pf is None or pdw is None:
+        raise ValueError("f and dw are needed")
+    ki = KrylovInfo()
+    _check(lib().direction_solve_noalloc(p.h, pd, pf, float(tol), pdw, pdy, C.byref(ki)), "direction_solve_noalloc")
+    return _dict(ki)
 
 
 def lp_solve(p: Problem) -> dict:

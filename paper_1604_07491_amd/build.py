@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpk.so")
-SOURCES = ["kernels.hip", "sweep.hip", "sweep_lds.hip", "engine.hip", "capi.hip", "profile.hip", "dense.hip", "server.hip", "colour.cpp", "bounds.cpp", "presolve.cpp"]
+SOURCES = ["kernels.hip", "sweep.hip", "sweep_lds.hip", "engine.hip", "capi.hip", "profile.hip", "dense.hip", "server.hip", "noalloc.hip", "colour.cpp", "bounds.cpp", "presolve.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions are generated
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -56,6 +56,7 @@ Batch::~Batch() {
     prof_release(*this);
     drop_graph();
     if (cap_st) (void)hipStreamDestroy(cap_st);
+    if (external) return;   // the storage is the caller's
     if (d_inst) (void)hipFree(d_inst);
     if (d_inst_c) (void)hipFree(d_inst_c);
     if (d_pad_slot) (void)hipFree(d_pad_slot);
@@ -102,6 +103,45 @@ lp_status Batch::init(int capacity, hipStream_t stream, bool own) {
     for (int i = 0; i < cap; ++i) h_slot[i].ctl.done = 1;
     LPK_HIP(hipMemcpyAsync(d_slot, h_slot, sizeof(Slot) * cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipMemcpyAsync(d_param, h_param, sizeof(Param) * cap, hipMemcpyHostToDevice, st));
+    LPK_HIP(hipStreamSynchronize(st));
+    dirty = true;
+    return LP_OK;
+}
+
+lp_status Batch::init_external(hipStream_t stream, unsigned char* dev, Slot* hs, Param* hp, Inst* hic) {
+    external = true;
+    cap = 1;
+    st = stream;
+    own_stream = false;
+    (void)hipGetDevice(&device);
+    mem.assign(1, nullptr);
+    h_inst.assign(1, Inst{});
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = dev + off;
+        off += align256(bytes);
+        return q;
+    };
+    d_inst = (Inst*)take(sizeof(Inst));
+    d_inst_c = (Inst*)take(sizeof(Inst));
+    d_pad_slot = (Slot*)take(sizeof(Slot));
+    d_pad_param = (Param*)take(sizeof(Param));
+    d_pad_part = (double*)take(sizeof(double) * RED_NQ * RED_MAXBLK);
+    d_slot = (Slot*)take(sizeof(Slot));
+    d_param = (Param*)take(sizeof(Param));
+    d_part = (double*)take(sizeof(double) * RED_NQ * RED_MAXBLK);
+    h_slot = hs;
+    h_param = hp;
+    h_inst_c = hic;
+    // the storage keeps an earlier call's contents: the control blocks (done = 1, as an
+    // empty slot) and the parameters start afresh; the partials are written before read
+    memset(h_slot, 0, sizeof(Slot));
+    memset(h_param, 0, sizeof(Param));
+    h_slot->ctl.done = 1;
+    LPK_HIP(hipMemcpyAsync(d_pad_slot, h_slot, sizeof(Slot), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(d_pad_param, h_param, sizeof(Param), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(d_slot, h_slot, sizeof(Slot), hipMemcpyHostToDevice, st));
+    LPK_HIP(hipMemcpyAsync(d_param, h_param, sizeof(Param), hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
     dirty = true;
     return LP_OK;

@@ -230,8 +230,15 @@ struct Batch {
     int64_t prof_launch[LP_K_COUNT] = {0};
     double prof_ms[LP_K_COUNT] = {0}, prof_bytes[LP_K_COUNT] = {0}, prof_flops[LP_K_COUNT] = {0};
 
+    // device arrays (d_inst, d_inst_c, d_pad_*, d_slot, d_param, d_part) and host mirrors
+    // (h_slot, h_param, h_inst_c) lent by the caller (init_external): never freed here
+    bool external = false;
+
     ~Batch();
     lp_status init(int capacity, hipStream_t stream, bool own);
+    // a batch of one on device memory at dev (BATCH_EXTERNAL_BYTES, 256-byte aligned) and
+    // the given host mirrors; allocates nothing, and captures no graph
+    lp_status init_external(hipStream_t stream, unsigned char* dev, Slot* hs, Param* hp, Inst* hic);
     int free_slot() const;
     int members() const;
     // make the device descriptors, launch maxima and graph match the membership
@@ -242,6 +249,13 @@ struct Batch {
     // read the control words and reduction results of every slot (synchronises the stream)
     lp_status get_slots();
 };
+
+// device bytes a batch of one takes in init_external: two descriptors, the padding slot,
+// parameters and partials, the slot, parameters and partials, each 256-byte aligned
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t BATCH_EXTERNAL_BYTES = 2 * align256(sizeof(Inst)) + 2 * align256(sizeof(Slot)) +
+                                        2 * align256(sizeof(Param)) +
+                                        2 * align256(sizeof(double) * RED_NQ * RED_MAXBLK);
 
 // homogeneity key: problems of one batch share these
 bool batch_compatible(const lp_problem* a, const lp_problem* b);
