@@ -56,10 +56,12 @@ typedef enum {
 } lp_status;
 
 /* LP_MIXED: FP32 inner sweeps (and their products) with the outer Krylov method, the true
- * residual and the interior-point update in FP64.  NE-SOR / NE-SSOR sweeps of an LP whose
- * FP64 z (n doubles) and colour table (2 ncolours + 1 ints) fit in 48 KiB run from LDS
- * and stream nothing from HBM, so they stay in FP64 (the LP then computes as with
- * LP_FP64).                                                                            */
+ * residual and the interior-point update in FP64, where FP32 pays: NE-SOR / NE-SSOR sweeps
+ * stay in FP64 when an LP's sweep runs in one workgroup from LDS in FP64 (z, v_k, p_k and
+ * the row pointers, and the rows if they fit, in the 160 KiB of LDS; the LP then computes
+ * as with LP_FP64), and run in FP32 otherwise (FP32 halves z, which may then fit in LDS,
+ * and the bytes streamed from memory).  Cimmino and the dense path run in FP32.  LPs whose
+ * sweeps run in different precisions share batches.                                    */
 typedef enum { LP_FP64 = 0, LP_MIXED = 1 } lp_precision;
 typedef enum { LP_ABGMRES = 0, LP_CGNE = 1, LP_MRNE = 2, LP_BAGMRES = 3 } lp_krylov;
 typedef enum { LP_NESOR = 0, LP_CIMMINO = 1, LP_NESSOR = 2, LP_GSOR = 3 } lp_inner;

@@ -24,8 +24,9 @@ extern "C" {
 #endif
 
 /* Solve `count` already-created problems, up to `width` of them in lockstep.  Problems
- * that share precision, inner iterations, sweeps and layout (sparse / dense) form one
- * group; groups run one after the other, each on a stream of its own (every problem's
+ * that share inner iterations, sweeps, Krylov method and layout (sparse / dense) form one
+ * group (FP32 and FP64 sweeps share a group: each launch serves the members of its
+ * precision); groups run one after the other, each on a stream of its own (every problem's
  * stream is synchronised first).  results[i] receives lp_solve's result for problems[i]
  * (seconds: from joining the batch to leaving it).  Returns LP_OK when every solve ran
  * (check results[i].status), else the first error.  Errors: LP_EINVAL (NULL arrays,
@@ -34,8 +35,8 @@ lp_status lp_solve_batch(lp_problem** problems, int32_t count, int32_t width, lp
 
 /* lp_time_kernel for a batch: the launches of kernel class cls for all `count` problems
  * together (one launch covers every problem), replayed `reps` times between two HIP
- * events.  bytes and flops are summed over the problems.  The problems must share
- * precision, inner iterations, sweeps and layout, and each needs a scaling (a solve ran).
+ * events.  bytes and flops are summed over the problems.  The problems must share inner
+ * iterations, sweeps, Krylov method and layout, and each needs a scaling (a solve ran).
  * Errors: LP_EINVAL, LP_EDEVICE.                                                          */
 lp_status lp_time_batch_kernel(lp_problem** problems, int32_t count, int32_t cls, int32_t reps,
                                double* us_per_launch, double* bytes_per_launch,

@@ -58,17 +58,40 @@ struct Sizes {
     }
 };
 
-bool fp32_sweeps(const lp_options& o, int64_t n, int64_t ncol, bool gsor) {
+bool fp32_sweeps(const lp_options& o, bool gsor, int kind64, int kind32) {
     if (o.precision != LP_MIXED) return false;
-    // NE-SOR / NE-SSOR sweeps whose FP64 z fits in LDS stream nothing from HBM: FP32
-    // would save no bandwidth there, and FP64 sweeps leave z_k = A_hat^T p_k for free
+    // FP32 pays where the FP64 NE-SOR / NE-SSOR sweep cannot run in one block from LDS: it
+    // then halves the bytes of z and of the row values that stream from memory, and may
+    // bring z (and the rows) into LDS.  FP64 sweeps leave z_k = A_hat^T p_k for free,
+    // where FP32 sweeps need a product in FP64; for a sweep already in LDS, whose colour
+    // steps are bound by latency, that product costs more than FP32 saves (measured on
+    // the serving mix: staging in FP32 only, 3 % slower).  Cimmino and the dense path: FP32.
+    (void)kind32;
     const bool sor = o.inner == LP_NESOR || o.inner == LP_NESSOR;
-    return gsor || !sor || lds_z_bytes(n, ncol, 8) > LDS_Z_MAX;
+    if (gsor || !sor) return true;
+    return kind64 == 0;
+}
+
+int sweep_kind(int64_t m, int64_t n, int64_t nnz, const std::vector<Colour>& cols, int tb) {
+    const int64_t nc = (int64_t)cols.size();
+    if (nc == 0) return 0;
+    if (lds_stage_bytes(m, n, nnz, nc, tb) <= LDS_STAGE_MAX) return 2;
+    if (lds_z_bytes(m, n, nc, tb) > LDS_Z_MAX) return 0;
+    for (const Colour& C : cols) {
+        const int64_t rounds = ((int64_t)(C.r1 - C.r0) * C.g + LDS_SWEEP_THREADS - 1) / LDS_SWEEP_THREADS;
+        if (rounds > LDS_ROUNDS_MAX || C.maxlen > 8 * C.g) return 0;
+    }
+    return 1;
 }
 
 uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     Sizes z;
-    const bool mixed = fp32_sweeps(o, n, 1, false);
+    // An upper bound.  NE-SOR / NE-SSOR sweeps staged in LDS in FP64 (the staged size with
+    // as many colours as rows still fits) run in FP64 from LDS: no FP32 copies, no row
+    // slices.  Otherwise LP_MIXED may keep FP32 copies and the sweeps may need slices.
+    const bool sor = o.inner == LP_NESOR || o.inner == LP_NESSOR;
+    const bool staged64 = sor && lds_stage_bytes(m, n, nnz, m, 8) <= LDS_STAGE_MAX;
+    const bool mixed = o.precision == LP_MIXED && !staged64;
     const int64_t kmax = plan_kmax(m, o);
     const int64_t cols = basis_cols(kmax, o), pcols = mult_cols(kmax, o);
     const bool cg = !is_gmres(o);
@@ -78,7 +101,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
     z.add(m, 4);                                  // permutation
     z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
-    if ((o.inner == LP_NESOR || o.inner == LP_NESSOR) && lds_z_bytes(n, m, 4) > LDS_Z_MAX) {
+    if (sor && !staged64) {
         // row slices: at most 5/4 of the nonzeros with columns and values (FP32 copy in
         // mixed precision); slice starts of the colours, slice offsets and lengths, row
         // positions, slice rows, the other rows
@@ -319,7 +342,6 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     } else {
         ncol = greedy_colour(m, n, rp, ci, colour.data(), p->perm.data());
     }
-    const bool mixed = p->mixed = fp32_sweeps(p->opt, n, ncol, p->gsor);
     std::vector<int32_t> prp((size_t)m + 1), pci((size_t)nnz);
     std::vector<double> pa((size_t)nnz), pb((size_t)m);
     prp[0] = 0;
@@ -346,17 +368,22 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         C.maxlen = 0;
         for (int64_t t = t0; t < t1; ++t) C.maxlen = std::max<int>(C.maxlen, prp[t + 1] - prp[t]);
         C.R = regs_for(C.maxlen, C.g);
-        // lane layout by cache-line count, for LPs swept colour by colour (z in HBM)
-        if (lds_z_bytes(n, ncol, mixed ? 4 : 8) > LDS_Z_MAX) choose_layout(C, prp.data(), pci.data(), mixed ? 4 : 8);
         p->colours.push_back(C);
         t0 = t1;
     }
+    // the sweep precision and where the sweeps run
+    const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
+    const int kind64 = sweep_kind(m, n, nnz, p->colours, 8), kind32 = sweep_kind(m, n, nnz, p->colours, 4);
+    const bool mixed = p->mixed = fp32_sweeps(p->opt, p->gsor, kind64, kind32);
+    p->lds_kind = (sor && !p->gsor && !p->dense) ? (mixed ? kind32 : kind64) : 0;
+    // lane layout by cache-line count, for LPs swept colour by colour (z in HBM)
+    if (p->lds_kind == 0)
+        for (Colour& C : p->colours) choose_layout(C, prp.data(), pci.data(), mixed ? 4 : 8);
     // slices for the colours whose neighbouring rows touch neighbouring columns (NE-SOR /
     // NE-SSOR swept colour by colour)
     std::vector<int32_t> h_cslice, h_soff, h_slen, h_srows, h_rsl, h_sidx, h_crow;
     {
-        const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
-        if (sor && !p->gsor && lds_z_bytes(n, ncol, mixed ? 4 : 8) > LDS_Z_MAX) {
+        if (sor && !p->gsor && p->lds_kind == 0) {
             h_cslice.assign(p->colours.size(), -1);
             h_rsl.assign((size_t)m, -1);
             bool any = false;

@@ -44,7 +44,8 @@ bool gs_fusable(int64_t m, int64_t kmax) { return gs_segments(m) <= 4 && kmax + 
 static inline int cdiv_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 bool batch_compatible(const lp_problem* a, const lp_problem* b) {
-    return a->mixed == b->mixed && a->opt.inner == b->opt.inner &&
+    // the sweep precision is per instance (Inst::fp32): FP32 and FP64 members share a batch
+    return a->opt.inner == b->opt.inner &&
            a->opt.krylov == b->opt.krylov &&
            a->gsor == b->gsor && a->opt.inner_sweeps == b->opt.inner_sweeps && a->device == b->device;
 }
@@ -200,8 +201,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.nbr = red_blocks(std::max(p->m, p->n));
     in.nbs = spmv_blocks(p->m, p->g_csr);
     in.zcover = p->zcover ? 1 : 0;
-    in.lds = (in.ncol > 0 && lds_z_bytes(p->n, in.ncol, mixed ? 4 : 8) <= LDS_Z_MAX) ? 1 : 0;
-    if (in.lds && lds_stage_bytes(p->m, p->n, p->nnz, in.ncol, mixed ? 4 : 8) <= LDS_STAGE_MAX) in.lds = 2;
+    in.lds = in.ncol > 0 ? p->lds_kind : 0;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
     in.ldp = p->ldh;   // kmax + 1 for AB-GMRES
@@ -249,6 +249,10 @@ static Inst make_inst(Batch& B, int slot) {
     in.omega = p->opt.omega;
     in.fpairs = p->fpairs;
     in.nfpairs = p->nfpairs;
+    in.fp32 = mixed ? 1 : 0;
+    // FP64 NE-SOR / NE-SSOR sweeps leave z_k = A_hat^T p_k for the product that follows
+    // (BA-GMRES has no such product: its sweeps end the iteration's operator)
+    in.keepz = (!mixed && sor && !p->gsor && p->opt.krylov != LP_BAGMRES) ? 1 : 0;
     return in;
 }
 
@@ -256,11 +260,12 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
                         const std::vector<int>& cb) {
     if (a.S != b.S || a.max_m != b.max_m || a.max_n != b.max_n || a.max_nbr != b.max_nbr ||
         a.max_nbs != b.max_nbs || a.max_ldp != b.max_ldp || a.gs_rpl != b.gs_rpl ||
-        a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.gs_dots_grid != b.gs_dots_grid || a.mixed != b.mixed ||
+        a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.gs_dots_grid != b.gs_dots_grid || a.any32 != b.any32 ||
+        a.any64 != b.any64 || a.any_nokeep != b.any_nokeep ||
         a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
         a.need_prep != b.need_prep ||
         a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.any_stage != b.any_stage ||
-        a.stage_bytes != b.stage_bytes || a.keep_z != b.keep_z || a.max_ncol_global != b.max_ncol_global ||
+        a.stage_bytes != b.stage_bytes || a.max_ncol_global != b.max_ncol_global ||
         a.grid_ahz != b.grid_ahz)
         return false;
     for (int i = 0; i < 4; ++i)
@@ -299,16 +304,16 @@ lp_status Batch::refresh() {
         if (!p) continue;
         const Inst& in = h_inst[s];
         if (first) {
-            L.mixed = p->mixed;
             L.inner = p->gsor ? 3 : p->opt.inner;
             L.ell = std::max(1, (int)p->opt.inner_sweeps);
             L.krylov = p->opt.krylov;
             L.ba = L.krylov == LP_BAGMRES;
-            // FP64 sweeps leave z_k = A_hat^T p_k for the product that follows (BA-GMRES
-            // has no such product: its sweeps end the iteration's operator)
-            L.keep_z = !L.mixed && !L.ba && (L.inner == LP_NESOR || L.inner == LP_NESSOR);
             first = false;
         }
+        // the sweep precision and whether the sweeps leave z_k are per instance
+        L.any32 = L.any32 || in.fp32;
+        L.any64 = L.any64 || !in.fp32;
+        L.any_nokeep = L.any_nokeep || !in.keepz;
         L.max_m = std::max(L.max_m, in.m);
         L.max_n = std::max(L.max_n, in.n);
         L.max_nbr = std::max(L.max_nbr, in.nbr);
@@ -334,10 +339,10 @@ lp_status Batch::refresh() {
         L.max_fpairs = std::max(L.max_fpairs, in.nfpairs);
         if (in.lds == 2) {
             L.any_stage = true;
-            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.ncol, L.mixed ? 4 : 8));
+            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.ncol, in.fp32 ? 4 : 8));
         } else if (in.lds) {
             L.any_lds = true;
-            L.lds_bytes = std::max<int>(L.lds_bytes, (int)lds_z_bytes(in.n, in.ncol, L.mixed ? 4 : 8));
+            L.lds_bytes = std::max<int>(L.lds_bytes, (int)lds_z_bytes(in.m, in.n, in.ncol, in.fp32 ? 4 : 8));
         } else {
             L.max_ncol_global = std::max(L.max_ncol_global, in.ncol);
             L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);
@@ -426,8 +431,13 @@ static double over_members(const Batch& B, F f) {
 }
 
 static double sweep_bytes_dense(const Batch& B) {
-    const double sv = B.L.mixed ? 4.0 : 8.0;
-    return over_members(B, [&](const lp_problem* p) { return (double)p->m * p->m * sv + 16.0 * p->m; });
+    return over_members(B, [&](const lp_problem* p) { return (double)p->m * p->m * (p->mixed ? 4.0 : 8.0) + 16.0 * p->m; });
+}
+
+// the sweeps of p leave z_k = A_hat^T p_k (FP64 NE-SOR / NE-SSOR, not BA-GMRES)
+static bool keeps_z(const lp_problem* p) {
+    const bool sor = p->opt.inner == LP_NESOR || p->opt.inner == LP_NESSOR;
+    return !p->mixed && sor && !p->gsor && p->opt.krylov != LP_BAGMRES;
 }
 
 // ------------------------------------------------------------------------------------
@@ -439,7 +449,8 @@ static double sweep_bytes_dense(const Batch& B) {
 // mode has a bit of pmask, whatever their control blocks say
 static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0) {
     const BLaunch& L = B.L;
-    const double sv = L.mixed ? 4.0 : 8.0;   // bytes of one A_hat value / z entry in the sweeps
+    // bytes of one A_hat value / z entry in the sweeps of p
+    auto sv = [](const lp_problem* p) { return p->mixed ? 4.0 : 8.0; };
     const int ell = L.ell;
     if (with_prep && L.need_prep) b_prep(L, pmask);
     if (L.inner == 3) {
@@ -450,17 +461,16 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0)
             const int first = sw == 0;
             {
                 const double by = over_members(B, [&](const lp_problem* p) {
-                    const double m = p->m, n = p->n, nnz = p->nnz;
-                    (void)n;
-                    return first ? m * (8.0 + sv + 16.0) : nnz * (sv + 4.0) + p->n * sv + m * (4.0 + 8.0 + sv + 16.0);
+                    const double m = p->m, nnz = p->nnz, t = sv(p);
+                    return first ? m * (8.0 + t + 16.0) : nnz * (t + 4.0) + p->n * t + m * (4.0 + 8.0 + t + 16.0);
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
                 b_cim_res(L, first);
             }
             if (sw + 1 < ell) {
                 const double by = over_members(B, [&](const lp_problem* p) {
-                    const double m = p->m, n = p->n, nnz = p->nnz;
-                    return nnz * (sv + 4.0) + m * sv + n * (4.0 + sv * (first ? 1.0 : 2.0));
+                    const double m = p->m, n = p->n, nnz = p->nnz, t = sv(p);
+                    return nnz * (t + 4.0) + m * t + n * (4.0 + t * (first ? 1.0 : 2.0));
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
                 b_cim_z(L, first);
@@ -471,27 +481,18 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0)
         const bool ssor = L.inner == LP_NESSOR;
         const int npass = ssor ? 2 * ell : ell;
         // the instances whose z fits in LDS: every pass and colour in one launch
-        auto lds_kind = [&](const lp_problem* p) {
-            const int64_t nc = (int64_t)p->colours.size();
-            if (lds_z_bytes(p->n, nc, L.mixed ? 4 : 8) > LDS_Z_MAX) return 0;
-            return lds_stage_bytes(p->m, p->n, p->nnz, nc, L.mixed ? 4 : 8) <= LDS_STAGE_MAX ? 2 : 1;
-        };
-        if (L.any_stage) {
-            // row data read once per application
+        auto lds_kind = [&](const lp_problem* p) { return p->lds_kind; };
+        if (L.any_stage || L.any_lds) {
+            // staged: the row data read once per application; otherwise on every pass; both:
+            // row pointers, u, v_k and p_k once, z written when kept
             const double by = over_members(B, [&](const lp_problem* p) {
-                if (lds_kind(p) != 2) return 0.0;
-                return p->nnz * (sv + 4.0) + (p->m + 1) * 4.0 + (double)p->m * (8.0 + 16.0) + (L.keep_z ? 8.0 * p->n : 0.0);
+                const int kd = lds_kind(p);
+                if (kd == 0) return 0.0;
+                return (kd == 2 ? 1 : npass) * p->nnz * (sv(p) + 4.0) + (p->m + 1) * 4.0 + (double)p->m * (8.0 + 16.0) +
+                       (keeps_z(p) ? 8.0 * p->n : 0.0);
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0, true, pmask);
-        }
-        if (L.any_lds) {
-            const double by = over_members(B, [&](const lp_problem* p) {
-                if (lds_kind(p) != 1) return 0.0;
-                return npass * (p->nnz * (sv + 4.0) + (double)p->m * (4.0 + 8.0 + 16.0)) + (L.keep_z ? 8.0 * p->n : 0.0);
-            });
-            Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0, false, pmask);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, pmask);
         }
         for (int sw = 0; sw < npass; ++sw) {
             const int dir = ssor ? (sw & 1) : 0;
@@ -499,10 +500,10 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0)
                 const int c = dir ? L.max_ncol_global - 1 - cc : cc;
                 const double by = over_members(B, [&](const lp_problem* p) {
                     const int nc = (int)p->colours.size();
-                    if (c >= nc || p->n * (L.mixed ? 4 : 8) <= LDS_Z_MAX) return 0.0;
+                    if (c >= nc || lds_kind(p) != 0) return 0.0;
                     const Colour& cl = p->colours[c];
-                    const int wz = L.keep_z || !(sw + 1 == npass && c == (dir ? 0 : nc - 1));
-                    return cl.nnz * (sv + 4.0) + cl.nnz * sv * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
+                    const int wz = keeps_z(p) || !(sw + 1 == npass && c == (dir ? 0 : nc - 1));
+                    return cl.nnz * (sv(p) + 4.0) + cl.nnz * sv(p) * (wz ? 2.0 : 1.0) + (double)(cl.r1 - cl.r0) * (4.0 + 8.0 + 16.0);
                 });
                 Prof pr(&B, LP_K_SWEEP, it, by);
                 b_nesor(L, c, sw, npass, dir, pmask);
@@ -514,6 +515,14 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0)
 static double csc_bytes(const lp_problem* p) { return p->nnz * 12.0 + p->m * 8.0 + p->n * 8.0 + (p->n + 1) * 4.0; }
 static double csr_bytes(const lp_problem* p) { return p->nnz * 12.0 + p->n * 8.0 + p->m * 8.0 + (p->m + 1) * 4.0; }
 
+// z_k = A_hat^T p_k in FP64 for the instances whose sweeps do not leave it (FP32 sweeps,
+// Cimmino): a product with the CSC copy
+static void enqueue_zk(Batch& B, int64_t it) {
+    if (!B.L.any_nokeep) return;
+    Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, [](const lp_problem* p) { return keeps_z(p) ? 0.0 : csc_bytes(p); }));
+    b_spmv(B.L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, PM_NOKEEP, false);
+}
+
 static void enqueue_products(Batch& B, int64_t it) {
     const BLaunch& L = B.L;
     if (L.inner == 3) {
@@ -524,10 +533,7 @@ static void enqueue_products(Batch& B, int64_t it) {
     }
     // outer operator in FP64: z_k = A_hat^T p_k (left by the FP64 sweeps, else by a
     // product with the CSC copy), u = A_hat z_k
-    if (!L.keep_z) {
-        Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
-        b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
-    }
+    enqueue_zk(B, it);
     {
         Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
         b_spmv(L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
@@ -582,10 +588,7 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
     };
     if (L.krylov == LP_CGNE) {
         enqueue_precond(B, it, true);   // C g (g in V_U)
-        if (!L.keep_z) {
-            Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
-            b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
-        }
+        enqueue_zk(B, it);
         {
             Prof pr(&B, LP_K_CG_VEC, it, vb(16.0, 0.0));
             b_cg_dot(L, V_U, V_PCOL, 0);
@@ -610,10 +613,7 @@ static void enqueue_cg_iteration(Batch& B, int64_t it) {
             b_spmv(L, M_AH_CSR, V_PV, V_U, EPI_PLAIN, -1, -1, PM_ITER_DIR, false);   // t = A_hat p
         }
         enqueue_precond(B, it, true);   // C t (at the start: C g)
-        if (!L.keep_z) {
-            Prof pr(&B, LP_K_SPMV_CSC, it, over_members(B, csc_bytes));
-            b_spmv(L, M_AH_CSC, V_PCOL, V_Z64, EPI_PLAIN, -1, -1, 0, false);
-        }
+        enqueue_zk(B, it);
         {
             Prof pr(&B, LP_K_CG_VEC, it, vb(0.0, 16.0));
             b_cg_dot(L, V_Z64, V_PV, 1);

@@ -131,7 +131,15 @@ __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
     if (pmask > 0) return (*to_global(in.mode) & pmask) != 0;
     const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
     if (pmask == PM_ITER_DIR) return ctl->done == 0 && ctl->cg_phase != 0;
+    if (pmask == PM_NOKEEP) return ctl->done == 0 && in.keepz == 0;
     return ctl->done == 0;   // 0: Krylov loop, still iterating
+}
+
+// a launch of the sweep kernels in precision T serves only the instances whose sweeps run
+// in that precision
+template <typename T>
+__device__ __forceinline__ bool other_precision(const Inst& in) {
+    return (sizeof(T) == 4) != (in.fp32 != 0);
 }
 
 __device__ __forceinline__ void write_part(const Inst& in, int bx, int q, double v) {

@@ -58,6 +58,9 @@ constexpr int V_VCOL = -2;   // column ctl->k of the Krylov basis V
 // pmask of the launches that take only the instances still iterating that have a search
 // direction (every CGNE instance, MRNE instances past their start)
 constexpr int PM_ITER_DIR = -1;
+// pmask of the product z_k = A_hat^T p_k in the Krylov loop: the instances still iterating
+// whose sweeps do not leave z_k themselves (Inst::keepz == 0)
+constexpr int PM_NOKEEP = -2;
 
 // matrices of an instance for the row-dot products
 enum MatSel : int { M_A_CSR = 0, M_A_CSC = 1, M_AH_CSR = 2, M_AH_CSC = 3 };
@@ -121,7 +124,7 @@ struct Inst {
     double omega;
     const int32_t* fpairs;                // split free variables: (x+ column, x- column) pairs
     int32_t nfpairs;                      // number of pairs (0 unless made with general bounds)
-    int32_t pad_f;
+    int32_t fp32;                         // 1: the inner sweeps run in FP32 (z32, ah32)
     // row slices of the colours whose neighbouring rows touch neighbouring columns (the
     // sinks of a transportation matrix): SL_ROWS rows stored slot-major, element (slot s,
     // row r) of slice q at soff[q] + s * SL_ROWS + r; NULL cslice: no such colour
@@ -136,7 +139,8 @@ struct Inst {
     int32_t nbc;                          // blocks of the CSR rows in the product with slices
     const int32_t* crow;                  // with slices: the rows kept in CSR form only
     int32_t ncrow;                        // their number
-    int32_t pad_c;
+    int32_t keepz;                        // 1: FP64 NE-SOR / NE-SSOR sweeps leave z_k = A_hat^T p_k
+                                          // in V_Z64 (no product with A_hat^T in the loop)
 };
 
 #ifndef LPK_SL_GROUPS
@@ -158,7 +162,9 @@ struct BLaunch {
     int gs_rpl, gs_nchunks; // largest rows per lane (template bound) and chunk count
     int gs_dots_grid;       // blocks per instance of the Gram-Schmidt dot launches
     bool gs_fused;          // every update block sums the dot partials itself
-    int mixed;              // FP32 inner iterations
+    bool any32, any64;      // some instance sweeps in FP32 / in FP64 (Inst::fp32); a launch of
+                            // either precision skips the instances of the other
+    bool any_nokeep;        // some instance needs z_k = A_hat^T p_k from a product (Inst::keepz 0)
     int inner;              // lp_inner of every instance (NE-SOR, Cimmino, NE-SSOR) or 3: dense SOR
     int ell;                // inner sweeps per preconditioner application
     int krylov;             // lp_krylov of every instance (0 AB-GMRES, 1 CGNE, 2 MRNE)
@@ -176,19 +182,27 @@ struct BLaunch {
     bool any_free;          // some instance has split free variables
     int grid_ahz;           // blocks of u = A_hat z with slices (0: no instance has slices)
     int max_fpairs;         // most split free variables of an instance
-    bool keep_z;            // FP64 NE-SOR / NE-SSOR: the sweeps leave z_k = A_hat^T p_k in
-                            // V_Z64, and the loop needs no product with A_hat^T
     int max_ncol_global;    // colours of the instances swept by per-colour launches
 };
 
-// an NE-SOR instance sweeps in one block with z in LDS when z fits in this many bytes,
-// and with its row data, v_k and p_k in LDS as well when all of them fit in LDS_STAGE_MAX
-constexpr int LDS_Z_MAX = 48 * 1024;
-constexpr int LDS_STAGE_MAX = 64 * 1024;
+// An NE-SOR / NE-SSOR instance sweeps in one block with all of its row values and column
+// indices, z, v_k, p_k, the row pointers and a colour table in LDS when they fit in
+// LDS_STAGE_MAX (lds_stage_bytes); with all but the row values and indices in LDS when
+// those fit in LDS_Z_MAX (lds_z_bytes), the rows then read from memory.  gfx950 gives a
+// workgroup 160 KiB of LDS.
+constexpr int LDS_BLOCK_MAX = 160 * 1024;
+constexpr int LDS_Z_MAX = LDS_BLOCK_MAX;
+constexpr int LDS_STAGE_MAX = LDS_BLOCK_MAX;
 // LDS of the one-block sweep: z with the colour table, and (staged) everything
-inline int64_t lds_z_bytes(int64_t n, int64_t ncol, int tbytes) { return n * tbytes + 4 * (2 * ncol + 1); }
+inline int64_t lds_z_bytes(int64_t m, int64_t n, int64_t ncol, int tbytes) {
+    return 16 * ncol + 16 * m + n * tbytes + 4 * (m + 1);
+}
+// threads of the one-block sweep, and the most rounds of them a colour's rows may take
+// when the rows are read from memory (each round is one dependent load step)
+constexpr int LDS_SWEEP_THREADS = 1024;
+constexpr int LDS_ROUNDS_MAX = 4;
 inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, int tbytes) {
-    return 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1) + 4 * (2 * ncol + 1);
+    return 16 * ncol + 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1);
 }
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------
@@ -214,7 +228,7 @@ void b_prep(const BLaunch& L, int pmask);
 void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir, int pmask);
 // every colour of every pass, one block per instance (ssor: passes alternate direction);
 // staged: the instances with Inst::lds == 2 (row data in LDS), else those with lds == 1
-void b_sweep_lds(const BLaunch& L, int npass, int ssor, bool staged, int pmask);
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, int pmask);   // every LDS-resident instance
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 // classical Gram-Schmidt, pass 0 and 1: dot partials, (reduce,) update u -= V h

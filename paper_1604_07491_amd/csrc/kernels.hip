@@ -180,7 +180,7 @@ void b_spmv(const BLaunch& L, int mat, int xsel, int outsel, int epi, int b1sel,
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cim_res(const Inst* __restrict__ I, int first) {
     INST;
-    if (in.ctl->done || in.gsor) return;
+    if (in.ctl->done || in.gsor || other_precision<T>(in)) return;
     const int g = in.g_csr;
     const int lane = threadIdx.x & (g - 1);
     const int64_t k = in.ctl->k;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_cim_res(const Inst* __restrict__ I, i
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cim_z(const Inst* __restrict__ I, int first) {
     INST;
-    if (in.ctl->done || in.gsor) return;
+    if (in.ctl->done || in.gsor || other_precision<T>(in)) return;
     const int g = in.g_csc;
     const int lane = threadIdx.x & (g - 1);
     const T* __restrict__ cval;
@@ -251,13 +251,13 @@ __global__ __launch_bounds__(BLOCK) void k_cim_z(const Inst* __restrict__ I, int
 
 void b_cim_res(const BLaunch& L, int first) {
     const unsigned gx = capg(L.grid_spmv[M_AH_CSR], GRID_CAP);
-    if (L.mixed) hipLaunchKernelGGL((k_cim_res<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
-    else hipLaunchKernelGGL((k_cim_res<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
+    if (L.any32) hipLaunchKernelGGL((k_cim_res<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
+    if (L.any64) hipLaunchKernelGGL((k_cim_res<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
 }
 void b_cim_z(const BLaunch& L, int first) {
     const unsigned gx = capg(L.grid_spmv[M_AH_CSC], GRID_CAP);
-    if (L.mixed) hipLaunchKernelGGL((k_cim_z<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
-    else hipLaunchKernelGGL((k_cim_z<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
+    if (L.any32) hipLaunchKernelGGL((k_cim_z<float>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
+    if (L.any64) hipLaunchKernelGGL((k_cim_z<double>), dim3(gx, L.S), dim3(BLOCK), 0, L.st, L.I, first);
 }
 
 // ------------------------------------------------------------------------------------
@@ -266,7 +266,7 @@ void b_cim_z(const BLaunch& L, int first) {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_apply_c(const Inst* __restrict__ I) {
     INST;
-    if (in.ctl->done || !in.gsor) return;
+    if (in.ctl->done || !in.gsor || other_precision<T>(in)) return;
     const int64_t k = in.ctl->k;
     const int m = in.m;
     const int i = bx * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -301,8 +301,8 @@ __global__ __launch_bounds__(BLOCK) void k_gemv_col(const Inst* __restrict__ I) 
 }
 
 void b_apply_c(const BLaunch& L) {
-    if (L.mixed) hipLaunchKernelGGL((k_apply_c<float>), dim3(cdiv(L.max_m, 4), L.S), dim3(BLOCK), 0, L.st, L.I);
-    else hipLaunchKernelGGL((k_apply_c<double>), dim3(cdiv(L.max_m, 4), L.S), dim3(BLOCK), 0, L.st, L.I);
+    if (L.any32) hipLaunchKernelGGL((k_apply_c<float>), dim3(cdiv(L.max_m, 4), L.S), dim3(BLOCK), 0, L.st, L.I);
+    if (L.any64) hipLaunchKernelGGL((k_apply_c<double>), dim3(cdiv(L.max_m, 4), L.S), dim3(BLOCK), 0, L.st, L.I);
 }
 void b_gemv_col(const BLaunch& L) {
     hipLaunchKernelGGL(k_gemv_col, dim3(cdiv(L.max_m, 4), L.S), dim3(BLOCK), 0, L.st, L.I);

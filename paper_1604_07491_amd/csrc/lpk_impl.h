@@ -30,9 +30,10 @@ int32_t greedy_colour(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci
 
 // device bytes lp_create allocates for these sizes and options
 uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o);
-// the sweeps of a problem with these options run in FP32: LP_MIXED, except NE-SOR and
-// NE-SSOR sweeps whose FP64 z (with the colour table of ncol colours) fits in LDS
-bool fp32_sweeps(const lp_options& o, int64_t n, int64_t ncol, bool gsor);
+// the sweeps of a problem with these options run in FP32 (LP_MIXED, where FP32 moves fewer
+// bytes from memory or lets the sweep run from LDS alone): kind64 / kind32 are sweep_kind
+// in FP64 / FP32
+bool fp32_sweeps(const lp_options& o, bool gsor, int kind64, int kind32);
 // host validation of lp_create's inputs (no device call)
 lp_status validate_inputs(int64_t m, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
                           const double* val, const double* b, const double* c);
@@ -87,6 +88,13 @@ struct Colour {
 // the lane layout of a colour's rows whose wave-wide loads touch fewer cache lines
 void choose_layout(Colour& C, const int32_t* rp, const int32_t* ci, int zbytes);
 
+// How the NE-SOR / NE-SSOR sweeps of an LP with these colours run (Inst::lds) with values
+// of tb bytes: 2, one block per LP with the row data, z, v_k and p_k in LDS; 1, one block
+// with z, v_k and p_k in LDS and the rows read from memory, when every colour's rows take
+// at most LDS_ROUNDS_MAX rounds of the block's threads at no more than 8 elements a lane;
+// 0, colour by colour over many blocks.
+int sweep_kind(int64_t m, int64_t n, int64_t nnz, const std::vector<Colour>& cols, int tb);
+
 // one timed launch: events a (before) and b (after) on the batch's stream
 struct ProfRec {
     int cls;
@@ -118,7 +126,8 @@ struct lp_problem {
     hipStream_t st = nullptr;
     int device = 0;
     bool dense = false;
-    bool mixed = false;                             // FP32 sweeps (LP_MIXED where they stream from HBM)
+    bool mixed = false;                             // FP32 sweeps (LP_MIXED where they pay)
+    int lds_kind = 0;                               // sweep_kind of the NE-SOR / NE-SSOR sweeps
     bool gsor = false;                              // dense: SOR on the Gram matrix
     double* G = nullptr;                            // m x m Gram matrix A_hat A_hat^T
     double* Wgram = nullptr;                        // split-K partial tiles of the Gram build

@@ -12,11 +12,11 @@ namespace lpk {
 // ------------------------------------------------------------------------------------
 // start of Krylov iteration k, NE-SOR instances whose colour 0 leaves some column
 // uncovered: z = 0 (the first sweep sets V[:,k] and p_k itself)
-__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int mixed, int pmask) {
+__global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int pmask) {
     INST;
     if (!takes_part(in, pmask) || in.gsor || in.zcover || in.lds || in.ncol == 0) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    if (mixed) {
+    if (in.fp32) {
         for (int64_t j = (int64_t)bx * BLOCK + threadIdx.x; j < in.n; j += stride) in.z32[j] = 0.0f;
     } else {
         double* __restrict__ z = in.vec[V_Z64];
@@ -25,8 +25,7 @@ __global__ __launch_bounds__(BLOCK) void k_prep(const Inst* __restrict__ I, int 
 }
 
 void b_prep(const BLaunch& L, int pmask) {
-    hipLaunchKernelGGL(k_prep, dim3(capg(cdiv(L.max_n, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I,
-                       L.mixed, pmask);
+    hipLaunchKernelGGL(k_prep, dim3(capg(cdiv(L.max_n, BLOCK), GRID_CAP), L.S), dim3(BLOCK), 0, L.st, L.I, pmask);
 }
 
 // ------------------------------------------------------------------------------------
@@ -56,7 +55,7 @@ template <typename T, int R>
 __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int c, int sw, int npass, int dir, int keepz, int pmask, int ba) {
     INST;
     const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
-    if (!takes_part(in, pmask) || in.gsor || in.lds || c >= in.ncol) return;
+    if (!takes_part(in, pmask) || in.gsor || in.lds || c >= in.ncol || other_precision<T>(in)) return;
     if (in.cslice && to_global(in.cslice)[c] >= 0) return;   // a sliced colour (k_nesor_sl)
     const LPK_GLOBAL int32_t* cstart = to_global(in.cstart);
     const int r0 = cstart[c], r1 = cstart[c + 1], gc = to_global(in.cg)[c];
@@ -75,7 +74,7 @@ __global__ __launch_bounds__(BLOCK) void k_nesor(const Inst* __restrict__ I, int
         lane = lw / il;
     }
     if (row >= r1) return;   // the same for every lane of the row; no block barrier below
-    const int write_z = keepz || !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
+    const int write_z = (keepz && in.keepz) || !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
     // colour 0 of the first sweep reads z = 0 and overwrites its columns when it covers
     // every column (no clearing pass needed)
     const int fresh = sw == 0 && c == 0 && in.zcover;
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(SL_THREADS) void k_nesor_sl(const Inst* __restrict_
     __shared__ T red[SL_THREADS / 64][SL_ROWS];
     INST;
     const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
-    if (!takes_part(in, pmask) || in.gsor || in.lds || c >= in.ncol || !in.cslice) return;
+    if (!takes_part(in, pmask) || in.gsor || in.lds || c >= in.ncol || !in.cslice || other_precision<T>(in)) return;
     const int q0 = to_global(in.cslice)[c];
     if (q0 < 0) return;
     const LPK_GLOBAL int32_t* cstart = to_global(in.cstart);
@@ -180,7 +179,7 @@ __global__ __launch_bounds__(SL_THREADS) void k_nesor_sl(const Inst* __restrict_
     const bool live = row < r1;
     const int off = to_global(in.soff)[q0 + bx];
     const int steps = to_global(in.slen)[q0 + bx] / SL_GROUPS;
-    const int write_z = keepz || !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
+    const int write_z = (keepz && in.keepz) || !(sw == npass - 1 && c == (dir ? 0 : in.ncol - 1));
     const int fresh = sw == 0 && c == 0 && in.zcover;
     const int64_t k = ctl->k;
     LPK_GLOBAL double* __restrict__ vk = to_global(ba ? in.vec[V_R64] : in.V + k * in.ldv);
@@ -281,18 +280,18 @@ static void launch_nesor_sl(const BLaunch& L, int R, dim3 gr, int colour, int pa
 // form, the sliced launch for those that slice it (each kernel skips the other kind)
 void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir, int pmask) {
     const int nc2 = L.max_ncol > 1 ? L.max_ncol : 1;
-    const int kz = (!L.mixed && L.keep_z) ? 1 : 0;
+    // FP64 launches write z on the last colour for the instances that keep it (Inst::keepz)
     if (L.grid_colour[colour] > 0) {
         const dim3 gr(capg(L.grid_colour[colour], 1 << 30), L.S);
         const int R = L.colour_r[colour];
-        if (L.mixed) launch_nesor<float>(L, R, gr, colour, pass, npass, dir, 0, pmask);
-        else launch_nesor<double>(L, R, gr, colour, pass, npass, dir, kz, pmask);
+        if (L.any32) launch_nesor<float>(L, R, gr, colour, pass, npass, dir, 0, pmask);
+        if (L.any64) launch_nesor<double>(L, R, gr, colour, pass, npass, dir, 1, pmask);
     }
     if (L.grid_colour[nc2 + colour] > 0) {
         const dim3 gr(capg(L.grid_colour[nc2 + colour], 1 << 30), L.S);
         const int R = L.colour_r[nc2 + colour];
-        if (L.mixed) launch_nesor_sl<float>(L, R, gr, colour, pass, npass, dir, 0, pmask);
-        else launch_nesor_sl<double>(L, R, gr, colour, pass, npass, dir, kz, pmask);
+        if (L.any32) launch_nesor_sl<float>(L, R, gr, colour, pass, npass, dir, 0, pmask);
+        if (L.any64) launch_nesor_sl<double>(L, R, gr, colour, pass, npass, dir, 1, pmask);
     }
 }
 

@@ -158,7 +158,8 @@ def test_centrality_correctors_option():
 
 
 def test_mixed_precision_allocates_fp32_copies_only_where_sweeps_stream():
-    """FP32 copies of A_hat exist only when z does not fit in LDS (n * 8 > 48 KiB)."""
+    """FP32 copies of A_hat exist only when the FP64 sweep cannot run from LDS alone (its
+    row data, z, v_k and p_k over the 160 KiB a gfx950 workgroup may use)."""
     small = (200, 500, 3000)
     assert lpk.lp_footprint_bytes(*small, lpk.options(precision="mixed")) == lpk.lp_footprint_bytes(*small)
     big = (600, 90000, 180000)

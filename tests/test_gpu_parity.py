@@ -278,8 +278,8 @@ def test_config2_basis_pursuit_full_size(precision):
 
 
 def test_mixed_small_lp_sweeps_in_fp64():
-    """LP_MIXED keeps the NE-SOR sweeps of an LP whose FP64 z fits in LDS in FP64: such an
-    LP computes exactly as with LP_FP64."""
+    """LP_MIXED keeps the NE-SOR sweeps of an LP whose whole FP64 sweep fits in LDS in FP64:
+    such an LP computes exactly as with LP_FP64."""
     lp = synth.config(0)
     out = {}
     for prec in ("fp64", "mixed"):

@@ -129,10 +129,13 @@ def test_server_admission_and_results():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_mixes_lds_and_per_colour_sweeps(precision):
-    """Small LPs sweep in one block from LDS alone (row data staged); a 302 x 2000 LP
-    keeps z in LDS and reads its rows from memory; a transportation LP with n = 8000 (z
-    over the LDS limit in FP64) sweeps colour by colour.  All three kinds in one batch give
-    each LP's result bitwise as alone, and the optimum matches the oracle's."""
+    """FP64: small LPs sweep in one block from LDS alone (row data staged); a 302 x 2000 LP
+    keeps z in LDS and reads its rows from memory; a transportation LP with
+    n = 8000 (each colour over 4 rounds of a block) sweeps colour by colour.  Mixed: the
+    transportation LP, whose FP64 sweep cannot run from LDS, sweeps in FP32 (staged in LDS,
+    where FP32 fits) while the others stay in FP64, in one batch whose launches each serve
+    the LPs of their precision.  Each LP's result is bitwise as alone, and the optimum
+    matches the oracle's."""
     lps = [synth.transport_lp(100, 80, seed=3)] + _mix(3, seed0=60) + [synth.sparse_lp(300, 2000, 6, 2, seed=61)]
     opts = lambda: lpk.options(precision=precision)
     alone = []
@@ -154,11 +157,11 @@ def test_batch_mixes_lds_and_per_colour_sweeps(precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_mixes_sliced_and_csr_colours(precision):
     """A transportation LP whose sink rows are stored in row slices (150 x 100), one whose
-    sinks stay in CSR form (100 x 80: slices would pad by more than a quarter) and a small
+    sinks stay in CSR form (100 x 90: slices would pad by more than a quarter) and a small
     sparse LP in one batch: colour 1 then runs both the sliced and the CSR sweep launch, each
     skipping the other kind's LPs.  Every LP's result is bitwise as alone, and the sliced
     LP's optimum matches the oracle's."""
-    lps = [synth.transport_lp(150, 100, seed=9), synth.transport_lp(100, 80, seed=3)] + _mix(1, seed0=70)
+    lps = [synth.transport_lp(150, 100, seed=9), synth.transport_lp(100, 90, seed=3)] + _mix(1, seed0=70)
     opts = lambda: lpk.options(precision=precision)
     alone = []
     for lp in lps:
