@@ -1,27 +1,29 @@
 """Benchmark: interior-point LP solves per second on one MI355X.
 
-One step solves B LPs of the workload's shape (distinct seeds; the first is the workload
-LP itself) to a relative duality gap of 1e-8, up to W of them in lockstep (lp_solve_batch:
-each phase of an interior-point iteration is one launch for the whole batch; a finished
-LP leaves and a waiting one joins).  Inputs are created on the device before the timed
-region (torch tensors handed to lp_create), so `value` excludes host-to-device copies.
-Prints one JSON line:
+Default workload: the serving mix.  256 sparse LPs (m ~ U{200..m_hi}, n = m U(2, 4), 4-10
+nonzeros per column, seeds 1000 + i) go to the library's server, which keeps up to W of
+them in one lockstep batch, admits new ones by HBM footprint and overlaps their work.
+The K timed steps are closed-loop runs (every LP submitted at t = 0); a warm-up run comes
+first.  Then an open-loop run offers 0.8 x that capacity as a seeded Poisson trace, for the
+latencies, and both runs repeat in the other precision.  Prints one JSON line:
 
-  value         LPs solved per second over the K timed steps (all B x K solves)
-  p50_ms/p99_ms per-LP latency inside the timed steps (joining the batch to leaving it)
-  roofline      the dominant kernel class of a profiled solve, timed for the batch as it
-                runs (lp_time_batch_kernel: one launch covers all W LPs) by replaying its
-                launches back-to-back between two HIP events on the library's stream;
-                achieved = algorithmic bytes per launch (summed over the W LPs) / mean
-                launch duration
-  cpu_baseline  the CPU FP64 oracle on the workload LP (one full solve, one core)
+  value         converged LPs (status OK, gamma_rel <= 1e-8) per second, closed loop
+  p50_ms/p99_ms latency from submission to completion in the open-loop run
+  roofline      the kernel class with the most time per Krylov iteration in the mix's
+                batch, timed by replaying its launches for W LPs back-to-back between two
+                HIP events on the library's stream (lp_time_batch_kernel); achieved =
+                algorithmic bytes per launch (summed over the LPs) / mean launch duration
+  cpu_baseline  the CPU FP64 oracle on a seeded sample of the mix (about 20 s, one core)
 
-Method flags: --krylov (abgmres, cgne, mrne, bagmres), --inner (nesor, nessor, cimmino),
---precision (fp64, mixed), --correctors K (multiple centrality correctors per step).
-Workloads: the default transportation 300x300 LP, sparse_200x500, bounded_200x500 (general
-bounds, reduced to the standard form by lp_create_bounded), basis_pursuit_1024x16384,
-sparse_120000x434580 (with --ipm-steps), serving_mix, streaming_1199000x4345800 (kernel
-bandwidth), copy_probe (counter calibration).
+The stated mix goes to m = 20,000; its whole-run cost is beyond any single-GPU run (the
+design notes give the oracle's Krylov counts), so m_hi is 1000 unless --m-hi says otherwise.
+
+Other workloads (--workload): transport_300x300 (64 transportation LPs per step, 64 in
+lockstep), sparse_200x500, bounded_200x500 (general bounds, reduced to the standard form by
+lp_create_bounded), basis_pursuit_1024x16384, sparse_120000x434580 (with --ipm-steps),
+streaming_1199000x4345800 (kernel bandwidth outside the Infinity Cache), copy_probe
+(counter calibration).  Method flags: --krylov (abgmres, cgne, mrne, bagmres), --inner
+(nesor, nessor, cimmino), --precision (fp64, mixed), --correctors K.
 """
 import argparse
 import json
@@ -85,9 +87,10 @@ def make_lps(workload, count):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (serving mix: closed-loop runs of the whole mix) [1; other workloads 3]")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="transport_300x300",
+    ap.add_argument("--workload", default="serving_mix",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
                              "sparse_120000x434580", "serving_mix", "streaming_1199000x4345800",
                              "bounded_200x500", "copy_probe"])
@@ -95,11 +98,14 @@ def main():
                     help="time this many interior-point steps of the first LP instead of whole solves")
     ap.add_argument("--krylov-cap", type=int, default=1500,
                     help="serving_mix: Krylov basis cap per solve (stated cap of the mix)")
-    ap.add_argument("--m-hi", type=int, default=20000, help="serving_mix: largest m of the mix")
+    ap.add_argument("--m-hi", type=int, default=1000,
+                    help="serving_mix: largest m of the mix (the stated mix goes to 20000; see the design notes)")
+    ap.add_argument("--precision-mix", default="mixed", choices=["fp64", "mixed"],
+                    help="serving_mix: the precision the value is quoted for (the other is run for comparison)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving_mix: offered load as a fraction of the closed-loop mixed throughput")
-    ap.add_argument("--batch", type=int, default=64, help="LPs per step")
-    ap.add_argument("--width", type=int, default=64, help="LPs in lockstep")
+    ap.add_argument("--batch", type=int, default=None, help="LPs per step [serving mix 256; others 64]")
+    ap.add_argument("--width", type=int, default=None, help="LPs in lockstep [serving mix 256; others 64]")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
@@ -112,8 +118,16 @@ def main():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
     args = ap.parse_args()
+    serving = args.workload == "serving_mix"
+    if args.steps is None:
+        args.steps = 1 if serving else 3
+    if args.batch is None:
+        args.batch = 256 if serving else 64
+    if args.width is None:
+        args.width = 256 if serving else 64
     if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (independent LPs would shard "
+                                   "across GPUs with no exchange; that path is not built)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -173,7 +187,8 @@ def main():
         print(f"step {step} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    ok = all(r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8 for r in res)
+    n_ok = sum(1 for r in res if r["status"] == lpk.LP_OK and r["gamma_rel"] <= 1e-8)
+    ok = n_ok == len(res)
 
     # one LP alone: its latency, and a profiled solve to find the dominant kernel class
     p0 = probs[0]
@@ -241,7 +256,7 @@ def main():
     lat_ms = np.array(lat) * 1e3
     line = {
         "metric": "LPs solved/s at rel. gap 1e-8 (p50/p99 latency; Krylov+NE-SOR kernel HBM GB/s)",
-        "value": len(res) / total,
+        "value": n_ok / total,
         "unit": "LPs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -372,8 +387,6 @@ def _serve_run(lps, arrivals, precision, width, cap):
             if delay > 0:
                 time.sleep(delay)
             tickets[srv.submit(lp)] = i
-            if (i + 1) % 32 == 0:
-                print(f"  submitted {i + 1}", file=sys.stderr, flush=True)
         done = []
         while len(done) < len(lps):
             srv.wait(len(lps) - len(done), 30.0)
@@ -384,38 +397,105 @@ def _serve_run(lps, arrivals, precision, width, cap):
     return done, wall
 
 
+def _converged(done):
+    import paper_1604_07491_amd as lpk
+    return [c for c in done if c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8]
+
+
+def _mix_roofline(lps, precision, width):
+    """The kernel classes of the serving mix timed as the batch runs them: every LP of the
+    mix created on the device, scaled by one short direction solve, then each class's
+    launches for `width` LPs replayed back-to-back between two HIP events on the library's
+    stream (lp_time_batch_kernel).  The dominant class is the one with the most time per
+    Krylov iteration (launches per iteration x duration)."""
+    import numpy as np
+    import torch
+    import paper_1604_07491_amd as lpk
+    dev = lambda a: torch.as_tensor(np.asarray(a)).cuda()
+    probs = []
+    for lp in lps[:width]:
+        p = lpk.lp_create(lp.m, lp.n, dev(lp.row_ptr), dev(lp.col_idx), dev(lp.val), dev(lp.b), dev(lp.c),
+                          lpk.options(precision=precision))
+        lpk.direction_solve(p, dev(np.ones(lp.n)), dev(lp.b), 0.5)   # one scaling (D = I)
+        probs.append(p)
+    torch.cuda.synchronize()
+    layouts = [p.sweep_layout() for p in probs]
+    per_iter = {"sweep": (lpk.LP_K_SWEEP, 1), "spmv_csr": (lpk.LP_K_SPMV_CSR, 1), "gs_dots": (lpk.LP_K_GS_DOTS, 2),
+                "gs_update": (lpk.LP_K_GS_UPDATE, 2)}
+    if any(f for f, _ in layouts):
+        per_iter["spmv_csc"] = (lpk.LP_K_SPMV_CSC, 1)
+    classes = {}
+    for name, (cls, k) in per_iter.items():
+        t = lpk.lp_time_batch_kernel(probs, cls, reps=20)
+        gbs = t["bytes_per_launch"] / (t["us_per_launch"] * 1e-6) / 1e9
+        classes[name] = {"us_per_launch": t["us_per_launch"], "bytes_per_launch": t["bytes_per_launch"],
+                         "launches_per_iteration": k, "us_per_iteration": k * t["us_per_launch"], "gbs": gbs,
+                         "frac": gbs / HBM_PEAK_GBS}
+        print(f"  {name}: {classes[name]}", file=sys.stderr, flush=True)
+    for p in probs:
+        p.close()
+    dom = max(classes, key=lambda k: classes[k]["us_per_iteration"])
+    c = classes[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": c["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": c["frac"], "traffic": None, "us_per_launch": c["us_per_launch"],
+                "bytes_per_launch": c["bytes_per_launch"], "lps_per_launch": len(probs),
+                "timing": "lp_time_batch_kernel replay, 20 x group, HIP events on the library stream"}
+    if dom == "sweep":
+        roofline["note"] = ("one workgroup per LP sweeps every colour with block barriers between them: a "
+                            "chain of 2 x colours dependent steps of 1.2-2 us, bound by latency, not bandwidth")
+    kinds = {k: sum(1 for _, kk in layouts if kk == k) for k in (0, 1, 2)}
+    return roofline, classes, {"fp32_sweeps": sum(f for f, _ in layouts), "staged_in_lds": kinds[2],
+                               "z_in_lds_rows_from_memory": kinds[1], "colour_by_colour": kinds[0]}
+
+
 def serve_main(args):
-    """Serving mix: LPs of different sizes arrive as a Poisson process; the server keeps
-    up to `width` of them in one lockstep batch and admits new ones by HBM footprint as
-    others finish.  Closed loop (every LP submitted at t = 0) measures the capacity; the
-    open-loop run offers `load` times the mixed-precision capacity with seeded arrivals;
-    both precisions replay the same trace."""
+    """Serving mix: LPs of different sizes arrive; the server keeps up to `width` of them in
+    one lockstep batch, admits new ones by HBM footprint as others finish, and overlaps
+    their work.  value: closed-loop capacity (every LP submitted at t = 0), converged LPs
+    per second over the timed runs.  Latency: an open-loop run offering `load` times that
+    capacity as a seeded Poisson trace, p50 / p99 from submission to completion.  Both
+    precisions run the same LPs and the same trace."""
     import numpy as np
     import paper_1604_07491_amd as lpk
     from paper_1604_07491_amd import synth
     count = args.batch
+    width = min(args.width, count)
     lps, unit = synth.serving_mix(count=count, m_hi=args.m_hi, rate=1.0)
     print(f"generated {count} LPs (m {min(l.m for l in lps)}..{max(l.m for l in lps)})", file=sys.stderr,
           flush=True)
-    out = {}
+    prec = args.precision_mix
+    for _ in range(args.warmup):
+        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap)
+        print(f"warm-up closed loop {prec}: {len(_converged(done)) / wall:.2f} LPs/s", file=sys.stderr, flush=True)
     closed = {}
-    for prec in ("mixed", "fp64"):
-        done, wall = _serve_run(lps, np.zeros(count), prec, args.width, args.krylov_cap)
-        closed[prec] = {"lps_per_s": count / wall, "wall_s": wall,
-                        "converged": sum(c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8 for c in done)}
-        print(f"closed loop {prec}: {closed[prec]}", file=sys.stderr, flush=True)
-    rate = args.load * closed["mixed"]["lps_per_s"]
+    walls, conv = [], []
+    for step in range(args.steps):
+        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap)
+        walls.append(wall)
+        conv.append(len(_converged(done)))
+        print(f"step {step}: closed loop {prec} {conv[-1] / wall:.2f} LPs/s", file=sys.stderr, flush=True)
+    closed[prec] = {"lps_per_s": sum(conv) / sum(walls), "wall_s": sum(walls) / len(walls),
+                    "converged": min(conv), "lps": count,
+                    "krylov_iters_total": int(sum(c["krylov_iters"] for c in done))}
+    other = "fp64" if prec == "mixed" else "mixed"
+    done, wall = _serve_run(lps, np.zeros(count), other, width, args.krylov_cap)
+    closed[other] = {"lps_per_s": len(_converged(done)) / wall, "wall_s": wall, "converged": len(_converged(done)),
+                     "lps": count, "krylov_iters_total": int(sum(c["krylov_iters"] for c in done))}
+    print(f"closed loop {other}: {closed[other]}", file=sys.stderr, flush=True)
+    rate = args.load * closed[prec]["lps_per_s"]
     arrivals = unit / rate          # unit-rate Poisson trace scaled to the offered rate
-    for prec in ("mixed", "fp64"):
-        done, wall = _serve_run(lps, arrivals, prec, args.width, args.krylov_cap)
+    out = {}
+    for pr in (prec, other):
+        done, wall = _serve_run(lps, arrivals, pr, width, args.krylov_cap)
         lat = np.array([c["t_done"] - c["t_submit"] for c in done]) * 1e3
-        ok = [c for c in done if c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8]
-        out[prec] = {"lps_per_s": count / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
-                     "p99_ms": float(np.percentile(lat, 99)), "converged": len(ok),
-                     "max_gamma_rel": max(c["gamma_rel"] for c in done),
-                     "krylov_iters_total": int(sum(c["krylov_iters"] for c in done)),
-                     "ipm_iters_total": int(sum(c["iters"] for c in done))}
-        print(f"open loop {prec}: {out[prec]}", file=sys.stderr, flush=True)
+        ok = _converged(done)
+        out[pr] = {"lps_per_s": len(ok) / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                   "p99_ms": float(np.percentile(lat, 99)), "converged": len(ok),
+                   "max_gamma_rel": max(c["gamma_rel"] for c in done),
+                   "krylov_iters_total": int(sum(c["krylov_iters"] for c in done)),
+                   "ipm_iters_total": int(sum(c["iters"] for c in done))}
+        print(f"open loop {pr}: {out[pr]}", file=sys.stderr, flush=True)
+    roofline, classes, layout = _mix_roofline(sorted(lps, key=lambda l: -l.m), prec, width)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -431,18 +511,24 @@ def serve_main(args):
         tcpu = time.perf_counter() - tc
         cpu = {"value": done_cpu / tcpu, "unit": "LPs/s", "cores": 1, "kind": "oracle",
                "sample": f"{done_cpu} LPs of the mix in seeded random order, one core, {tcpu:.1f} s"}
-    m = out["mixed"]
+    c = closed[prec]
+    o = out[prec]
     line = {
         "metric": "LPs solved/s at rel. gap 1e-8 (p50/p99 latency), serving mix",
-        "value": m["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": m["wall_s"] * 1e3, "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"],
+        "value": c["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": c["wall_s"] * 1e3, "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 sweeps + f64", "data": "synthetic",
+        "dtype": "f64" if layout["fp32_sweeps"] == 0 else "f32 sweeps + f64", "data": "synthetic",
+        "all_converged": c["converged"] == count and o["converged"] == count,
         "config": {"workload": "serving_mix", "lps": count, "m_range": [200, args.m_hi],
-                   "arrival": "Poisson, seed 4242", "rate_per_s": rate, "offered_load": args.load,
-                   "lps_in_lockstep": args.width, "krylov_cap": args.krylov_cap},
-        "open_loop": out, "closed_loop": closed,
-        "mixed_over_fp64": out["mixed"]["lps_per_s"] / out["fp64"]["lps_per_s"],
+                   "stated_m_range": [200, 20000], "n": "m x U(2, 4)", "nnz_per_column": "U{4..10}",
+                   "seeds": "1000 + i", "arrival": "Poisson, seed 4242", "offered_load": args.load,
+                   "rate_per_s": rate, "lps_in_lockstep": width, "precision": prec, "krylov": "AB-GMRES",
+                   "inner": "NE-SOR", "inner_sweeps": 2, "omega": 1.0, "krylov_cap": args.krylov_cap,
+                   "sweep_layout": layout},
+        "closed_loop": closed, "open_loop": out,
+        "mixed_over_fp64": closed["mixed"]["lps_per_s"] / closed["fp64"]["lps_per_s"],
+        "roofline": roofline, "batch_kernels": classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

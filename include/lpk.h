@@ -299,6 +299,14 @@ lp_status lp_get_log(const lp_problem* p, lp_iter_info* info, int32_t cap, int32
 lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options* o,
                              uint64_t* bytes);
 
+/* How the inner-iteration sweeps of p run (either pointer may be NULL): *fp32 = 1 when
+ * they run in FP32 (LP_MIXED where it pays, see lp_precision), and for NE-SOR / NE-SSOR on
+ * sparse rows *kind = 2 when each preconditioner application runs in one workgroup with
+ * the rows, z, v_k and p_k in LDS, 1 when z, v_k and p_k are in LDS and the rows are read
+ * from memory, 0 when the sweeps run colour by colour over many workgroups (and for the
+ * other inner iterations).  Host only.  Errors: LP_EINVAL (NULL p).                    */
+lp_status lp_sweep_layout(const lp_problem* p, int32_t* fp32, int32_t* kind);
+
 /* Number of colours of the row colouring and the colour sizes (sizes may be NULL).      */
 lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, int32_t cap);
 

@@ -122,6 +122,7 @@ SIGNATURES = {
     "lp_footprint_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.POINTER(Options),
                                      C.POINTER(C.c_uint64)]),
     "lp_colouring": (C.c_int, [_P, C.POINTER(C.c_int32), _P, C.c_int32]),
+    "lp_sweep_layout": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lp_colour_rows": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
     "lp_profile": (C.c_int, [_P, C.c_uint32]),
     "lp_profile_read": (C.c_int, [_P, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
@@ -249,6 +250,13 @@ class Problem:
             return t, t.data_ptr()
         a = np.zeros(size)
         return a, a.ctypes.data
+
+    def sweep_layout(self):
+        """(fp32, kind): the sweeps run in FP32; kind 2 one workgroup from LDS alone, 1 one
+        workgroup with the rows read from memory, 0 colour by colour."""
+        f, k = C.c_int32(0), C.c_int32(0)
+        _check(lib().lp_sweep_layout(self.h, C.byref(f), C.byref(k)), "lp_sweep_layout")
+        return int(f.value), int(k.value)
 
     def colouring(self):
         nc = C.c_int32(0)

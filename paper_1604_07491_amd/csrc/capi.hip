@@ -1048,6 +1048,13 @@ lp_status lp_footprint_bytes(int64_t m, int64_t n, int64_t nnz, const lp_options
     return LP_OK;
 }
 
+lp_status lp_sweep_layout(const lp_problem* p, int32_t* fp32, int32_t* kind) {
+    if (!p) return fail(LP_EINVAL, "NULL problem");
+    if (fp32) *fp32 = p->mixed ? 1 : 0;
+    if (kind) *kind = p->lds_kind;
+    return LP_OK;
+}
+
 lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, int32_t cap) {
     if (!p || !ncolours) return fail(LP_EINVAL, "NULL argument");
     *ncolours = (int32_t)p->colours.size();

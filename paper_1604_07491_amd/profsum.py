@@ -2,12 +2,16 @@
 
     python -m paper_1604_07491_amd.profsum trace <rocprof output dir> <out.json>
     python -m paper_1604_07491_amd.profsum pmc   <rocprof output dir> <out.json>
+    python -m paper_1604_07491_amd.profsum window <rocprof output dir> <out.json> <kernel> <grid y> <count>
 
 trace: per (kernel, grid) launch counts and mean durations from the kernel trace, and for
 each batch width the mean duration of the NE-SOR sweep launches of the timing replay (the
 sweep launches after the last back-substitution of that width: bench.py replays the
 dominant kernel last).  pmc: per (kernel, grid) mean counter value, and the mean over the
-last 800 batched sweep dispatches (the replay window of bench.py's kernel table).
+last 800 batched sweep dispatches (the replay window of bench.py's kernel table).  window:
+the mean duration of the last <count> launches of the kernel whose name contains <kernel>
+with grid y = <grid y> (bench.py replays its dominant kernel for the serving mix's batch
+last of all its launches of that grid), with the per-kernel table of the whole trace.
 """
 import collections
 import csv
@@ -70,6 +74,28 @@ def pmc_summary(d):
     return res
 
 
+def window_summary(d, kernel, grid_y, count):
+    rows = list(csv.DictReader(open(_one(d, "*kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = [r for r in rows if kernel in r["Kernel_Name"] and int(r["Grid_Size_Y"]) == grid_y][-count:]
+    us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+    res = {"kernel": kernel, "grid_y": grid_y, "n": len(us), "avg_us": sum(us) / max(1, len(us)),
+           "min_us": min(us) if us else None, "max_us": max(us) if us else None}
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        key = r["Kernel_Name"].split("(")[0][:48]
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    total = sum(v[1] for v in agg.values())
+    res["kernels"] = [[k, n, us / 1e3, us / n, us / total]
+                      for k, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:15]]
+    return res
+
+
 if __name__ == "__main__":
     kind, d, out = sys.argv[1:4]
-    json.dump(trace_summary(d) if kind == "trace" else pmc_summary(d), open(out, "w"), indent=1)
+    if kind == "window":
+        res = window_summary(d, sys.argv[4], int(sys.argv[5]), int(sys.argv[6]))
+    else:
+        res = trace_summary(d) if kind == "trace" else pmc_summary(d)
+    json.dump(res, open(out, "w"), indent=1)
