@@ -106,6 +106,8 @@ def main():
                     help="serving_mix: offered load as a fraction of the closed-loop mixed throughput")
     ap.add_argument("--batch", type=int, default=None, help="LPs per step [serving mix 256; others 64]")
     ap.add_argument("--width", type=int, default=None, help="LPs in lockstep [serving mix 256; others 64]")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="serving mix: lockstep batches the width is split into, each on its own stream [1]")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
@@ -374,12 +376,12 @@ def steps_main(args):
     p.close()
 
 
-def _serve_run(lps, arrivals, precision, width, cap):
+def _serve_run(lps, arrivals, precision, width, cap, lanes=1):
     """Submit every LP at its arrival time (seconds from the first) to a server; return the
     completions and the wall time from the first arrival to the last completion."""
     import paper_1604_07491_amd as lpk
     solver = lpk.options(precision=precision, krylov_max_iter=cap)
-    with lpk.Server(slots=width, solver=solver) as srv:
+    with lpk.Server(slots=width, solver=solver, lanes=lanes) as srv:
         t0 = time.perf_counter()
         tickets = {}
         for i, (lp, ta) in enumerate(zip(lps, arrivals)):
@@ -465,12 +467,12 @@ def serve_main(args):
           flush=True)
     prec = args.precision_mix
     for _ in range(args.warmup):
-        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap)
+        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap, args.lanes)
         print(f"warm-up closed loop {prec}: {len(_converged(done)) / wall:.2f} LPs/s", file=sys.stderr, flush=True)
     closed = {}
     walls, conv = [], []
     for step in range(args.steps):
-        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap)
+        done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap, args.lanes)
         walls.append(wall)
         conv.append(len(_converged(done)))
         print(f"step {step}: closed loop {prec} {conv[-1] / wall:.2f} LPs/s", file=sys.stderr, flush=True)
@@ -478,7 +480,7 @@ def serve_main(args):
                     "converged": min(conv), "lps": count,
                     "krylov_iters_total": int(sum(c["krylov_iters"] for c in done))}
     other = "fp64" if prec == "mixed" else "mixed"
-    done, wall = _serve_run(lps, np.zeros(count), other, width, args.krylov_cap)
+    done, wall = _serve_run(lps, np.zeros(count), other, width, args.krylov_cap, args.lanes)
     closed[other] = {"lps_per_s": len(_converged(done)) / wall, "wall_s": wall, "converged": len(_converged(done)),
                      "lps": count, "krylov_iters_total": int(sum(c["krylov_iters"] for c in done))}
     print(f"closed loop {other}: {closed[other]}", file=sys.stderr, flush=True)
@@ -486,7 +488,7 @@ def serve_main(args):
     arrivals = unit / rate          # unit-rate Poisson trace scaled to the offered rate
     out = {}
     for pr in (prec, other):
-        done, wall = _serve_run(lps, arrivals, pr, width, args.krylov_cap)
+        done, wall = _serve_run(lps, arrivals, pr, width, args.krylov_cap, args.lanes)
         lat = np.array([c["t_done"] - c["t_submit"] for c in done]) * 1e3
         ok = _converged(done)
         out[pr] = {"lps_per_s": len(ok) / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
@@ -523,7 +525,7 @@ def serve_main(args):
         "config": {"workload": "serving_mix", "lps": count, "m_range": [200, args.m_hi],
                    "stated_m_range": [200, 20000], "n": "m x U(2, 4)", "nnz_per_column": "U{4..10}",
                    "seeds": "1000 + i", "arrival": "Poisson, seed 4242", "offered_load": args.load,
-                   "rate_per_s": rate, "lps_in_lockstep": width, "precision": prec, "krylov": "AB-GMRES",
+                   "rate_per_s": rate, "lps_in_lockstep": width, "lanes": args.lanes, "precision": prec, "krylov": "AB-GMRES",
                    "inner": "NE-SOR", "inner_sweeps": 2, "omega": 1.0, "krylov_cap": args.krylov_cap,
                    "sweep_layout": layout},
         "closed_loop": closed, "open_loop": out,

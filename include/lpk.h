@@ -316,13 +316,31 @@ lp_status lp_colouring(const lp_problem* p, int32_t* ncolours, int32_t* sizes, i
  * a_ij / a_i0 to tol (relative; tol = 0 asks for equality), lambda = a_k0 / a_i0.
  * keep[m] receives 0 for those rows and 1 for the others, *m_keep the rows kept; the
  * caller builds the reduced LP from the kept rows (the duals of the dropped rows may be
- * taken as 0).  Linear dependencies among three or more rows are left in place: the
- * min-norm formulation (Sec. 2.2) solves rank-deficient problems as they are.
+ * taken as 0).  Dependencies among three or more rows are left in place here (the
+ * min-norm formulation of Sec. 2.2 solves rank-deficient problems as they are); the
+ * general search is lp_presolve_dependent_rows.
  * Errors: LP_EINVAL (malformed CSR, NULL, tol < 0, or a dropped row whose right-hand
  * side is not lambda times its partner's to tol: the LP is infeasible),
  * LP_ENONFINITE, LP_EDIM.                                                              */
 lp_status lp_presolve_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                            const double* val, const double* b, double tol, int32_t* keep, int64_t* m_keep);
+
+/* Presolve of general dependent rows (the conclusions' "detect and remove linear
+ * dependencies"), host only: keep[k] = 0 exactly when row k of A is in the span of rows
+ * 0..k-1, so the kept rows are the first row basis in the given order and number rank(A);
+ * *m_keep receives that count.  Found by sparse elimination, one row at a time: a row is
+ * dependent when its remainder after elimination against the kept rows is at most tol times
+ * its largest entry (relative; 1e-9 suits data of moderate condition).  Its right-hand side,
+ * eliminated alongside, must vanish to tol relative to the terms that formed it, else the LP
+ * is infeasible.  Rows that are multiples of another (lp_presolve_rows) are among those
+ * found; so is the transportation matrix's single dependency (one of its rows).  The caller
+ * builds the reduced LP from the kept rows; the dropped rows' duals may be taken as 0.
+ * Errors: LP_EINVAL (malformed CSR, NULL, tol < 0, contradicting right-hand side),
+ * LP_ENONFINITE, LP_EDIM, LP_ETOOBIG (the elimination would store more than
+ * max(32 nnz, 4M) entries), LP_ENOMEM.                                                  */
+lp_status lp_presolve_dependent_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                     const double* val, const double* b, double tol, int32_t* keep,
+                                     int64_t* m_keep);
 
 /* Greedy row colouring on the host alone (no device needed): colour[m] and the
  * colour-major sweep order perm[m] (rows ascending inside each colour).

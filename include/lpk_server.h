@@ -45,9 +45,16 @@ lp_status lp_time_batch_kernel(lp_problem** problems, int32_t count, int32_t cls
 typedef struct lp_server lp_server;
 
 typedef struct {
-    int32_t slots;           /* LPs in the lockstep batch, [1, 256] [32]                    */
+    int32_t slots;           /* LPs solved at once, over all lanes, [1, 256] [32]           */
     int32_t max_skip;        /* FIFO with bounded skip: later requests that may start ahead
                                 of a head request that does not fit yet [8]                */
+    int32_t lanes;           /* lockstep batches the slots are split into, [1, 8] [1].  Each
+                                lane runs on a stream of its own and the engine thread keeps
+                                every lane's next round queued, so one lane's latency-bound
+                                launches (a small LP's one-block sweep lasts as long as its
+                                chain of colour steps) overlap another lane's bandwidth-bound
+                                ones.  Every LP's arithmetic is the same in any lane.      */
+    int32_t pad0;
     uint64_t hbm_budget;     /* device bytes the admitted problems may hold together, by
                                 lp_footprint_bytes [0: 80% of the free memory at create]     */
     lp_options solver;       /* options for every request (device_io and stream ignored)    */
@@ -65,7 +72,9 @@ typedef struct {
 
 lp_status lp_server_options_default(lp_server_options* o);
 
-/* Start `slots` workers on the current HIP device.  Errors: LP_EINVAL, LP_EDEVICE.     */
+/* Start the server on the current HIP device: a preparer thread (admission, lp_create, and
+ * lp_destroy of finished problems, whose device memory is released to the budget then) and
+ * an engine thread that runs the lanes.  Errors: LP_EINVAL, LP_EDEVICE.                  */
 lp_status lp_server_create(const lp_server_options* o, lp_server** out);
 
 /* Queue one LP (host arrays, validated and copied now; same layout as lp_create).  A

@@ -85,8 +85,8 @@ class Result(C.Structure):
 
 
 class ServerOptions(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("max_skip", C.c_int32), ("hbm_budget", C.c_uint64),
-                ("solver", Options)]
+    _fields_ = [("slots", C.c_int32), ("max_skip", C.c_int32), ("lanes", C.c_int32), ("pad0", C.c_int32),
+                ("hbm_budget", C.c_uint64), ("solver", Options)]
 
 
 class Completion(C.Structure):
@@ -111,6 +111,8 @@ SIGNATURES = {
                                           C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                           _P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
     "lp_presolve_rows": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, C.c_double, _P, C.POINTER(C.c_int64)]),
+    "lp_presolve_dependent_rows": (C.c_int, [C.c_int64, C.c_int64, _P, _P, _P, _P, C.c_double, _P,
+                                             C.POINTER(C.c_int64)]),
     "lp_destroy": (None, [_P]),
     "ipm_step": (C.c_int, [_P, C.POINTER(IterInfo)]),
     "direction_solve": (C.c_int, [_P, _P, _P, C.c_double, _P, _P, C.POINTER(KrylovInfo)]),
@@ -351,6 +353,19 @@ def lp_presolve_rows(m, n, row_ptr, col_idx, val, b, tol: float = 1e-12):
     return keep.astype(bool)
 
 
+def lp_presolve_dependent_rows(m, n, row_ptr, col_idx, val, b, tol: float = 1e-9):
+    """``lp_presolve_dependent_rows``: a 0/1 mask of the rows to keep (the rows in the span
+    of the rows before them are dropped: the kept rows are the first row basis)."""
+    arrs = [np.ascontiguousarray(a, dt) for a, dt in ((row_ptr, np.int64), (col_idx, np.int32),
+                                                     (val, np.float64), (b, np.float64))]
+    keep = np.zeros(int(m), np.int32)
+    mk = C.c_int64(0)
+    _check(lib().lp_presolve_dependent_rows(int(m), int(n), *[a.ctypes.data for a in arrs], float(tol),
+                                            keep.ctypes.data, C.byref(mk)), "lp_presolve_dependent_rows")
+    assert mk.value == int(keep.sum())
+    return keep.astype(bool)
+
+
 def lp_create_bounded(m, n, row_ptr, col_idx, val, b, c, lo, hi, opts: Optional[Options] = None,
                       **kw) -> Problem:
     """``lp_create_bounded`` (general bounds, reduced to the standard form on the host).
@@ -521,10 +536,10 @@ class Server:
     """The request server of include/lpk_server.h (lockstep batch, continuous admission by
     HBM footprint)."""
 
-    def __init__(self, slots=32, max_skip=8, hbm_budget=0, solver: Optional[Options] = None, **kw):
+    def __init__(self, slots=32, max_skip=8, hbm_budget=0, solver: Optional[Options] = None, lanes=1, **kw):
         o = ServerOptions()
         lib().lp_server_options_default(C.byref(o))
-        o.slots, o.max_skip, o.hbm_budget = int(slots), int(max_skip), int(hbm_budget)
+        o.slots, o.max_skip, o.hbm_budget, o.lanes = int(slots), int(max_skip), int(hbm_budget), int(lanes)
         o.solver = solver if solver is not None else options(**kw)
         h = C.c_void_p(None)
         _check(lib().lp_server_create(C.byref(o), C.byref(h)), "lp_server_create")

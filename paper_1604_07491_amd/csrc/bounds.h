@@ -44,4 +44,15 @@ void bounds_recover(const BoundMap& map, const double* xs, double* x);
 bool presolve_parallel_rows(int64_t m, const int64_t* rp, const int32_t* ci, const double* val,
                             const double* b, double tol, int32_t* keep, int64_t* m_keep, std::string& err);
 
+// Presolve: every row in the span of the rows before it (to tol) gets keep = 0; false with
+// a message when such a row's right-hand side contradicts, or when the elimination would
+// store more than max_fill entries.
+bool presolve_dependent_rows(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                             const double* b, double tol, int64_t max_fill, int32_t* keep, int64_t* m_keep,
+                             std::string& err);
+// The same on the dense Gram matrix (m^2 doubles), when the elimination fills.
+bool presolve_dependent_rows_gram(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci,
+                                  const double* val, const double* b, double tol, int32_t* keep,
+                                  int64_t* m_keep, std::string& err);
+
 }  // namespace lpk

@@ -1103,6 +1103,37 @@ lp_status lp_presolve_rows(int64_t m, int64_t n, const int64_t* row_ptr, const i
     return LP_OK;
 }
 
+// rows up to which the dependency search may fall back to the dense Gram matrix (8 m^2
+// bytes, m^3 / 3 multiply-adds)
+static constexpr int64_t PRESOLVE_GRAM_MAX_M = 4096;
+
+lp_status lp_presolve_dependent_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                     const double* val, const double* b, double tol, int32_t* keep,
+                                     int64_t* m_keep) {
+    g_err.clear();
+    if (!row_ptr || !col_idx || !val || !b || !keep || !m_keep) return fail(LP_EINVAL, "NULL argument");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(LP_EINVAL, "tol must be finite and >= 0");
+    if (m < 1 || n < 1) return fail(LP_EDIM, "m and n must be positive");
+    lp_status rc = validate(m, n, row_ptr[m], row_ptr, col_idx, val, false);
+    if (rc != LP_OK) return rc;
+    if ((rc = check_vec(b, m, "b")) != LP_OK) return rc;
+    std::string err;
+    const int64_t max_fill = std::max<int64_t>(32 * row_ptr[m], (int64_t)1 << 22);
+    try {
+        if (presolve_dependent_rows(m, n, row_ptr, col_idx, val, b, tol, max_fill, keep, m_keep, err)) return LP_OK;
+        if (err.find("fill limit") == std::string::npos) return fail(LP_EINVAL, err);
+        // the elimination filled: the dense Gram matrix, where it fits
+        if (m > PRESOLVE_GRAM_MAX_M)
+            return fail(LP_ETOOBIG, err + ", and m exceeds the dense fallback's " +
+                                        std::to_string(PRESOLVE_GRAM_MAX_M) + " rows");
+        err.clear();
+        if (presolve_dependent_rows_gram(m, n, row_ptr, col_idx, val, b, tol, keep, m_keep, err)) return LP_OK;
+        return fail(LP_EINVAL, err);
+    } catch (const std::bad_alloc&) {
+        return fail(LP_ENOMEM, "host memory for the dependency search");
+    }
+}
+
 lp_status lp_colour_rows(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                          int32_t* colour, int32_t* perm, int32_t* ncolours) {
     g_err.clear();

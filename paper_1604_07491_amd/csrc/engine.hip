@@ -1065,8 +1065,17 @@ static void next_corrector(Engine::Member& mb, Param& pr, const lp_options& o) {
 }
 
 lp_status Engine::round() {
+    const lp_status rc = issue();
+    if (rc != LP_OK) return rc;
+    return complete();
+}
+
+bool Engine::ready() const { return !issued || hipStreamQuery(B->st) != hipErrorNotReady; }
+
+lp_status Engine::issue() {
     Batch& b = *B;
     lp_status rc;
+    if (issued) return LP_OK;
 #define LPK_RC(x)                         \
     do {                                  \
         if ((rc = (x)) != LP_OK) {        \
@@ -1096,7 +1105,7 @@ lp_status Engine::round() {
     }
     if (sched == 1) uniform = true;
     if (sched == 2) uniform = false;
-    const bool hold = uniform && iterating > 0;   // phases wait for the others' solves
+    hold = uniform && iterating > 0;   // phases wait for the others' solves
     bool has[ST_COUNT] = {false};
     bool has_add = false;
     int live = 0, solving = 0, waiting = 0;
@@ -1316,7 +1325,26 @@ lp_status Engine::round() {
             if (solve_phase(mb.state)) mb.enq += todo;
         LPK_HIP(hipGetLastError());
     }
-    LPK_RC(b.get_slots());
+    // the control words and reduction results come back with the round's work; the host
+    // state machines advance in complete()
+    LPK_HIP(hipMemcpyAsync(b.h_slot, b.d_slot, sizeof(Slot) * b.cap, hipMemcpyDeviceToHost, b.st));
+    issued = true;
+#undef LPK_RC
+    return LP_OK;
+}
+
+lp_status Engine::complete() {
+    Batch& b = *B;
+    if (!issued) return LP_OK;
+    issued = false;
+    {
+        const hipError_t e = hipStreamSynchronize(b.st);
+        if (e != hipSuccess) {
+            error = LP_EDEVICE;
+            return hip_fail(e, "hipStreamSynchronize");
+        }
+    }
+    b.param_inflight = false;
 
     // transitions (held members keep their state)
     for (int s = 0; s < b.cap; ++s) {
@@ -1488,7 +1516,6 @@ lp_status Engine::round() {
         }
     }
     if (b.prof_recs.size() > 200000) prof_collect(b);
-#undef LPK_RC
     return LP_OK;
 }
 

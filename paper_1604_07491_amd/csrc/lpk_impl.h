@@ -326,11 +326,20 @@ struct Engine {
     std::vector<Member> mem;
     lp_status error = LP_OK;          // a device error stops the whole batch
     bool stepwise = false;            // ipm_step: the update round does not evaluate the next point
+    bool issued = false;              // a round's work is queued and complete() has not run
+    bool hold = false;                // this round's phases wait for the others' solves
 
     void attach(Batch* b);
     // join a free slot: start with the starting point, or from the point it holds
     int join(lp_problem* p, bool from_point, int32_t limit_k);
+    // one round: issue() queues every launch of the round and the copy of the control words
+    // on the batch's stream without waiting; complete() waits for them and advances each
+    // member's state machine.  round() is the two in a row.  Members join and leave only
+    // between complete() and the next issue().
     lp_status round();
+    lp_status issue();
+    lp_status complete();
+    bool ready() const;               // nothing issued, or the issued round has finished
     bool any_live() const;
     void leave(int slot);             // empty a slot
 };

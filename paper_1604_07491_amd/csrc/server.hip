@@ -139,6 +139,8 @@ struct lp_server {
     std::condition_variable cv_work, cv_ready, cv_done;
     std::deque<std::unique_ptr<Request>> queue;   // submitted, not admitted
     std::deque<Ready> ready;                      // admitted and created, not joined
+    std::deque<std::pair<lp_problem*, uint64_t>> retire;   // finished: destroy, then release
+    bool engine_done = false;
     int32_t preparing = 0;
     std::deque<lp_completion> done;
     std::map<uint64_t, Solution> solutions;
@@ -177,6 +179,8 @@ static std::unique_ptr<Request> take_admissible(lp_server* s) {
     return nullptr;
 }
 
+// publish a completion; fp is released from the budget now, or (fp = 0 here) by the
+// preparer once it has destroyed the problem
 static void complete(lp_server* s, lp_completion cpl, uint64_t fp, Solution sol, bool was_running) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -198,15 +202,39 @@ static void prep_main(lp_server* s) {
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
     for (;;) {
         std::unique_ptr<Request> r;
+        std::deque<std::pair<lp_problem*, uint64_t>> retire;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] {
-                if (s->stop && s->queue.empty()) return true;
+                if (!s->retire.empty()) return true;
+                if (s->stop && s->queue.empty() && s->engine_done) return true;
                 return !s->queue.empty() && (r = take_admissible(s)) != nullptr;
             });
-            if (!r) break;   // stopping and nothing queued
-            s->in_use += r->footprint;
-            s->preparing += 1;
+            retire.swap(s->retire);
+            if (r) {
+                s->in_use += r->footprint;
+                s->preparing += 1;
+            }
+        }
+        // Finished problems are destroyed here, not on the engine thread: freeing device
+        // memory waits for the work queued on the device, and the engine keeps the other
+        // lanes' rounds queued meanwhile.  Their memory returns to the budget afterwards.
+        if (!retire.empty()) {
+            uint64_t freed = 0;
+            for (auto& q : retire) {
+                lp_destroy(q.first);
+                freed += q.second;
+            }
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->in_use -= freed;
+            }
+            s->cv_work.notify_all();
+        }
+        if (!r) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->retire.empty() && s->stop && s->queue.empty() && s->engine_done) break;
+            continue;
         }
         lp_options o = s->opt.solver;
         o.device_io = 0;
@@ -244,81 +272,150 @@ static void prep_main(lp_server* s) {
     (void)hipStreamDestroy(st);
 }
 
-// the lockstep batch: join ready problems into free slots at tick boundaries, tick, and
-// complete the members that finished
-static void engine_main(lp_server* s) {
-    if (hipSetDevice(s->device) != hipSuccess) return;
+// One lane: a lockstep batch on a stream of its own, and the requests of its members.
+struct Lane {
     hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
     Batch B;
-    if (B.init(s->opt.slots, st, true) != LP_OK) return;
     Engine E;
-    E.attach(&B);
-    std::vector<Ready> held((size_t)B.cap);
-    std::vector<double> t_start((size_t)B.cap, 0.0);
-    for (;;) {
-        std::vector<Ready> joining;
+    std::vector<Ready> held;
+    std::vector<double> t_start;
+};
+
+// Complete the lane's members that finished (or, after a device error, every member;
+// nothing of the lane is in flight when this runs):
+// copy the solution out, publish the completion, and hand the problem to the preparer to
+// destroy (its budget is released then).
+static void drain_lane(lp_server* s, Lane& L, lp_status trc) {
+    for (int slot = 0; slot < L.B.cap; ++slot) {
+        Engine::Member& mb = L.E.mem[slot];
+        if (mb.state != Engine::DONE && !(trc != LP_OK && mb.state != Engine::EMPTY)) continue;
+        Ready& rd = L.held[slot];
+        lp_completion cpl;
+        memset(&cpl, 0, sizeof(cpl));
+        cpl.ticket = rd.req->ticket;
+        cpl.t_submit = rd.req->t_submit;
+        cpl.t_start = L.t_start[slot];
+        cpl.footprint = rd.req->footprint;
+        Solution sol;
+        if (trc != LP_OK) {
+            cpl.status = trc;
+        } else {
+            lp_result res;
+            fill_result(mb, &res);
+            cpl.status = res.status;
+            cpl.iters = res.iters;
+            cpl.pobj = res.pobj;
+            cpl.dobj = res.dobj;
+            cpl.gamma_rel = res.gamma_rel;
+            cpl.krylov_iters = res.krylov_iters;
+            sol.x.resize((size_t)rd.req->n);
+            sol.y.resize((size_t)rd.req->m);
+            sol.s.resize((size_t)rd.req->n);
+            const lp_status rc2 = lp_get_state(rd.p, sol.x.data(), sol.y.data(), sol.s.data(), nullptr);
+            if (rc2 != LP_OK) cpl.status = rc2;
+        }
+        cpl.t_done = s->now();
+        L.E.leave(slot);
+        // the lane's stream is idle here and outlives no retired problem: the problem is
+        // destroyed without it
+        rd.p->st = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->retire.emplace_back(rd.p, rd.req->footprint);
+        }
+        L.held[slot] = Ready();
+        complete(s, cpl, 0, std::move(sol), true);
+    }
+}
+
+// The lanes: join ready problems into a lane's free slots whenever its previous round has
+// completed, queue its next round, and complete the members that finished.  All launches
+// come from this one thread.  While one lane's round runs on the GPU the others' rounds
+// are queued on their streams, so their kernels overlap.
+static void engine_main(lp_server* s) {
+    bool ok = hipSetDevice(s->device) == hipSuccess;
+    const int nl = std::max(1, std::min<int>(s->opt.lanes, s->opt.slots));
+    std::vector<std::unique_ptr<Lane>> lanes;
+    for (int l = 0; ok && l < nl; ++l) {
+        std::unique_ptr<Lane> L(new Lane());
+        if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess) {
+            ok = false;
+            break;
+        }
+        // slots split as evenly as they go, the first lanes taking the remainder
+        const int cap = s->opt.slots / nl + (l < s->opt.slots % nl ? 1 : 0);
+        if (L->B.init(cap, L->st, true) != LP_OK) {
+            ok = false;
+            break;
+        }
+        L->E.attach(&L->B);
+        L->held.resize((size_t)L->B.cap);
+        L->t_start.assign((size_t)L->B.cap, 0.0);
+        lanes.push_back(std::move(L));
+    }
+    auto busy = [&]() {
+        for (auto& L : lanes)
+            if (L->E.issued || L->E.any_live()) return true;
+        return false;
+    };
+    while (ok) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_ready.wait(lk, [&] {
-                if (E.any_live()) return true;
+                if (busy()) return true;
                 if (!s->ready.empty()) return true;
                 return s->stop && s->queue.empty() && s->ready.empty() && s->preparing == 0;
             });
-            int free = 0;
-            for (int i = 0; i < B.cap; ++i) free += B.mem[i] == nullptr;
-            while (free > 0 && !s->ready.empty()) {
-                joining.push_back(std::move(s->ready.front()));
-                s->ready.pop_front();
-                --free;
-                s->running += 1;
+            if (!busy() && s->ready.empty()) break;
+        }
+        bool progressed = false;
+        for (auto& Lp : lanes) {
+            Lane& L = *Lp;
+            if (L.E.issued) {
+                if (!L.E.ready()) continue;
+                const lp_status trc = L.E.complete();
+                drain_lane(s, L, trc);
+                progressed = true;
             }
-            if (joining.empty() && !E.any_live()) break;
-        }
-        for (Ready& rd : joining) {
-            // the problem was created (and synchronised) on the preparer's stream
-            rd.p->st = st;
-            const int slot = E.join(rd.p, false, rd.p->opt.ipm_max_iter);
-            t_start[slot] = s->now();
-            held[slot] = std::move(rd);
-        }
-        const lp_status trc = E.round();
-        for (int slot = 0; slot < B.cap; ++slot) {
-            Engine::Member& mb = E.mem[slot];
-            if (mb.state != Engine::DONE && !(trc != LP_OK && mb.state != Engine::EMPTY)) continue;
-            Ready& rd = held[slot];
-            lp_completion cpl;
-            memset(&cpl, 0, sizeof(cpl));
-            cpl.ticket = rd.req->ticket;
-            cpl.t_submit = rd.req->t_submit;
-            cpl.t_start = t_start[slot];
-            cpl.footprint = rd.req->footprint;
-            Solution sol;
+            std::vector<Ready> joining;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                int free = 0;
+                for (int i = 0; i < L.B.cap; ++i) free += L.B.mem[i] == nullptr;
+                while (free > 0 && !s->ready.empty()) {
+                    joining.push_back(std::move(s->ready.front()));
+                    s->ready.pop_front();
+                    --free;
+                    s->running += 1;
+                }
+            }
+            for (Ready& rd : joining) {
+                // the problem was created (and synchronised) on the preparer's stream
+                rd.p->st = L.st;
+                const int slot = L.E.join(rd.p, false, rd.p->opt.ipm_max_iter);
+                L.t_start[slot] = s->now();
+                L.held[slot] = std::move(rd);
+            }
+            if (!L.E.any_live()) continue;
+            const lp_status trc = L.E.issue();
             if (trc != LP_OK) {
-                cpl.status = trc;
-            } else {
-                lp_result res;
-                fill_result(mb, &res);
-                cpl.status = res.status;
-                cpl.iters = res.iters;
-                cpl.pobj = res.pobj;
-                cpl.dobj = res.dobj;
-                cpl.gamma_rel = res.gamma_rel;
-                cpl.krylov_iters = res.krylov_iters;
-                sol.x.resize((size_t)rd.req->n);
-                sol.y.resize((size_t)rd.req->m);
-                sol.s.resize((size_t)rd.req->n);
-                const lp_status rc2 = lp_get_state(rd.p, sol.x.data(), sol.y.data(), sol.s.data(), nullptr);
-                if (rc2 != LP_OK) cpl.status = rc2;
+                // what was queued before the error ends before the members leave
+                (void)hipStreamSynchronize(L.st);
+                L.E.issued = false;
+                drain_lane(s, L, trc);
             }
-            cpl.t_done = s->now();
-            E.leave(slot);
-            lp_destroy(rd.p);
-            const uint64_t fp = rd.req->footprint;
-            held[slot] = Ready();
-            complete(s, cpl, fp, std::move(sol), true);
+            progressed = true;
         }
+        // every queued round still running: wait a little before looking again
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
+    for (auto& L : lanes) (void)hipStreamSynchronize(L->st);
+    lanes.clear();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->engine_done = true;
+    }
+    s->cv_work.notify_all();
 }
 
 extern "C" {
@@ -328,6 +425,7 @@ lp_status lp_server_options_default(lp_server_options* o) {
     memset(o, 0, sizeof(*o));
     o->slots = 32;
     o->max_skip = 8;
+    o->lanes = 1;
     o->hbm_budget = 0;
     return lp_options_default(&o->solver);
 }
@@ -335,8 +433,8 @@ lp_status lp_server_options_default(lp_server_options* o) {
 lp_status lp_server_create(const lp_server_options* o, lp_server** out) {
     if (!o || !out) return LP_EINVAL;
     *out = nullptr;
-    if (o->slots < 1 || o->slots > 256 || o->max_skip < 0) {
-        set_error("slots must be in [1, 256] and max_skip >= 0");
+    if (o->slots < 1 || o->slots > 256 || o->max_skip < 0 || o->lanes < 1 || o->lanes > 8) {
+        set_error("slots must be in [1, 256], lanes in [1, 8] and max_skip >= 0");
         return LP_EINVAL;
     }
     int count = 0;
@@ -456,9 +554,11 @@ lp_status lp_server_destroy(lp_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    s->prep.join();
     s->cv_ready.notify_all();
+    // the engine first: it may still wait for problems the preparer creates, and the
+    // preparer destroys what the engine retires until the engine is done
     s->engine.join();
+    s->prep.join();
     delete s;
     return LP_OK;
 }

@@ -127,6 +127,37 @@ def test_server_admission_and_results():
             srv.result(tickets[0])      # released after the first fetch
 
 
+def test_server_lanes_keep_results_bitwise():
+    """The slots split into lanes (lockstep batches on streams of their own, rounds queued
+    from one thread): every LP's solution is bitwise the same with 1, 2 and 3 lanes (3: an
+    uneven split of 8 slots), and the same as alone."""
+    lps = _mix(12, seed0=300)
+    alone = []
+    for lp in lps[:3]:
+        with lpk.from_lp(lp) as p:
+            lpk.lp_solve(p)
+            alone.append(lpk.lp_get_state(p)[0])
+    got = {}
+    for lanes in (1, 2, 3):
+        print(f"lanes {lanes}", flush=True)
+        with lpk.Server(slots=8, lanes=lanes) as srv:
+            tickets = [srv.submit(lp) for lp in lps]
+            assert srv.wait(len(tickets), 300.0)
+            done = {c["ticket"]: c for c in srv.poll()}
+            assert set(done) == set(tickets)
+            res = []
+            for t in tickets:
+                assert done[t]["status"] == lpk.LP_OK and done[t]["gamma_rel"] <= 1e-8
+                res.append((done[t]["iters"], done[t]["krylov_iters"], srv.result(t)[0]))
+            got[lanes] = res
+    for lanes in (2, 3):
+        for a, b in zip(got[1], got[lanes]):
+            assert a[0] == b[0] and a[1] == b[1]
+            assert np.array_equal(a[2], b[2])
+    for i in range(3):
+        assert np.array_equal(got[2][i][2], alone[i])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_mixes_lds_and_per_colour_sweeps(precision):
     """FP64: small LPs sweep in one block from LDS alone (row data staged); a 302 x 2000 LP
