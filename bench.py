@@ -2,7 +2,8 @@
 
 Default workload: the serving mix.  256 sparse LPs (m ~ U{200..m_hi}, n = m U(2, 4), 4-10
 nonzeros per column, seeds 1000 + i) go to the library's server, which keeps up to W of
-them in one lockstep batch, admits new ones by HBM footprint and overlaps their work.
+them at once, split into L lockstep batches (lanes, each on its own stream, default 4),
+admits new ones by HBM footprint and overlaps their work.
 The K timed steps are closed-loop runs (every LP submitted at t = 0); a warm-up run comes
 first.  Then an open-loop run offers 0.8 x that capacity as a seeded Poisson trace, for the
 latencies, and both runs repeat in the other precision.  Prints one JSON line:
@@ -106,8 +107,8 @@ def main():
                     help="serving_mix: offered load as a fraction of the closed-loop mixed throughput")
     ap.add_argument("--batch", type=int, default=None, help="LPs per step [serving mix 256; others 64]")
     ap.add_argument("--width", type=int, default=None, help="LPs in lockstep [serving mix 256; others 64]")
-    ap.add_argument("--lanes", type=int, default=1,
-                    help="serving mix: lockstep batches the width is split into, each on its own stream [1]")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="serving mix: lockstep batches the width is split into, each on its own stream [4]")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--inner", default="nesor", choices=["nesor", "nessor", "cimmino"])
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
@@ -422,13 +423,14 @@ def _mix_roofline(lps, precision, width):
         probs.append(p)
     torch.cuda.synchronize()
     layouts = [p.sweep_layout() for p in probs]
-    per_iter = {"sweep": (lpk.LP_K_SWEEP, 1), "spmv_csr": (lpk.LP_K_SPMV_CSR, 1), "gs_dots": (lpk.LP_K_GS_DOTS, 2),
-                "gs_update": (lpk.LP_K_GS_UPDATE, 2)}
+    per_iter = {"sweep": lpk.LP_K_SWEEP, "spmv_csr": lpk.LP_K_SPMV_CSR, "gs_dots": lpk.LP_K_GS_DOTS,
+                "gs_update": lpk.LP_K_GS_UPDATE}
     if any(f for f, _ in layouts):
-        per_iter["spmv_csc"] = (lpk.LP_K_SPMV_CSC, 1)
+        per_iter["spmv_csc"] = lpk.LP_K_SPMV_CSC
     classes = {}
-    for name, (cls, k) in per_iter.items():
+    for name, cls in per_iter.items():
         t = lpk.lp_time_batch_kernel(probs, cls, reps=20)
+        k = t["launches_per_group"]   # the class's launches in one Krylov iteration
         gbs = t["bytes_per_launch"] / (t["us_per_launch"] * 1e-6) / 1e9
         classes[name] = {"us_per_launch": t["us_per_launch"], "bytes_per_launch": t["bytes_per_launch"],
                          "launches_per_iteration": k, "us_per_iteration": k * t["us_per_launch"], "gbs": gbs,

@@ -120,8 +120,8 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     if (cg) {
         z.add(nchunks, 8);
     } else {
-        z.add(std::max<int64_t>(nchunks, (int64_t)gs_segments(m) * cols), 8);
-        z.add((int64_t)gs_segments(m) * cols, 8);
+        z.add(std::max<int64_t>(nchunks, (int64_t)gs_segments(m) * (cols + 1)), 8);
+        z.add((int64_t)gs_segments(m) * (cols + 1), 8);
     }
     // the problem's batch of one: descriptor, control words, parameters, partials
     z.add(1, sizeof(Inst)); z.add(1, sizeof(Slot)); z.add(1, sizeof(Param));
@@ -493,8 +493,9 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     if (cg) {
         p->gpart = A.alloc<double>(p->nchunks);
     } else {
-        p->gpart = A.alloc<double>(std::max<int64_t>(p->nchunks, (int64_t)gs_segments(m) * cols));
-        p->gpart2 = A.alloc<double>((int64_t)gs_segments(m) * cols);
+        // Gram-Schmidt dot partials: segments x (cols + 1) (the delayed form adds u . u)
+        p->gpart = A.alloc<double>(std::max<int64_t>(p->nchunks, (int64_t)gs_segments(m) * (cols + 1)));
+        p->gpart2 = A.alloc<double>((int64_t)gs_segments(m) * (cols + 1));
     }
     if (p->gsor) {
         p->G = A.alloc<double>(m * m);

@@ -204,7 +204,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.lds = in.ncol > 0 ? p->lds_kind : 0;
     in.ldv = p->ldv;
     in.ldh = p->ldh;
-    in.ldp = p->ldh;   // kmax + 1 for AB-GMRES
+    in.ldp = p->ldh + 1;   // kmax + 2 for AB-GMRES: the dots of columns 0..kmax and u . u
     in.kmax = p->kmax;
     in.rp = p->rp;
     in.ci = p->ci;
@@ -571,6 +571,33 @@ static void enqueue_gs(Batch& B, int64_t it, int parts) {
     if (parts & GS_FINISH) b_gs_finish(L);
 }
 
+// AB-GMRES: Gram-Schmidt twice with the second pass delayed by one iteration (one pass of
+// dots and one of updates over V per iteration) and the Givens step of the column the
+// iteration completes
+static void enqueue_dgs(Batch& B, int64_t it, int parts) {
+    const BLaunch& L = B.L;
+    const double kk = (double)(it + 1);
+    // V once (k + 1 columns), v~_k and u once, the partials (segments x (k + 2)) once
+    auto dots_b = [&]() {
+        return over_members(B, [&](const lp_problem* p) {
+            return kk * p->m * 8.0 + 2.0 * p->m * 8.0 + gs_segments(p->m) * (kk + 1.0) * 16.0;
+        });
+    };
+    // V once (k columns), v~_k and u read and written, the coefficients
+    auto upd_b = [&]() {
+        return over_members(B, [&](const lp_problem* p) { return (kk - 1.0) * p->m * 8.0 + p->m * 32.0 + kk * 16.0; });
+    };
+    if (parts & GS_DOTS) {
+        Prof pr(&B, LP_K_GS_DOTS, it, dots_b());
+        b_dgs_dots(L);
+    }
+    if (parts & GS_FINISH) b_dgs_finish(L);
+    if (parts & GS_UPDATES) {
+        Prof pr(&B, LP_K_GS_UPDATE, it, upd_b());
+        b_dgs_update(L);
+    }
+}
+
 // the residual f_hat - A_hat dw of the iterate a CGNE / MRNE step just formed, recomputed
 // (its squared norm as reduction partials), for the stopping test of Sec. 4.2
 static void enqueue_cg_residual(Batch& B, int64_t it) {
@@ -661,8 +688,8 @@ static void enqueue_iteration(Batch& B, int64_t it) {
     }
     enqueue_precond(B, it, true);
     enqueue_products(B, it);
-    // CGS2 + Givens; the host iteration index equals the device one while the solve runs
-    enqueue_gs(B, it, GS_DOTS | GS_UPDATES | GS_FINISH);
+    // delayed CGS2 + Givens; the host iteration index equals the device one while the solve runs
+    enqueue_dgs(B, it, GS_DOTS | GS_UPDATES | GS_FINISH);
 }
 
 // capture `iters` Krylov iterations for the current membership; every kernel argument is
@@ -750,8 +777,9 @@ lp_status krylov_batch(Batch& B, int pmask, std::vector<lp_krylov_info>* info) {
     }
     if (info) info->assign((size_t)B.cap, lp_krylov_info{});
     if (kmax_all == 0) return LP_OK;
-    // MRNE's first launch forms q_0 and takes no step, so kmax steps need kmax + 1
-    const int64_t extra = B.L.krylov == LP_MRNE ? 1 : 0;
+    // MRNE's first launch forms q_0 and takes no step, and AB-GMRES completes column k - 1
+    // in iteration k (the delayed Gram-Schmidt pass): kmax steps need kmax + 1 launches
+    const int64_t extra = (B.L.krylov == LP_MRNE || (B.L.krylov == LP_ABGMRES && !B.L.ba)) ? 1 : 0;
     const int64_t sid = B.solve_id++;
     B.cur_solve = sid;
     if ((int64_t)B.solve_iters.size() <= sid) B.solve_iters.resize(sid + 1, 0);
@@ -1571,8 +1599,10 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
             t.done = 0;
             t.active = 1;
             t.kmax = 1;
-            t.k = gs ? (int32_t)kg : 0;
+            // the delayed form's update works on column k - 1 of the last finish
+            t.k = gs ? (int32_t)kg + (cls == LP_K_GS_UPDATE && !B.L.ba ? 1 : 0) : 0;
             t.inv_h = 1.0;
+            t.dg_nu = 1.0;
             t.omega_c = B.mem[s]->omega_c;
         }
         B.h_slot[s].ctl = t;
@@ -1596,7 +1626,8 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
         if (cls == LP_K_SWEEP) {
             enqueue_precond(B, -1, false);
         } else if (gs) {
-            enqueue_gs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
+            if (B.L.ba) enqueue_gs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
+            else enqueue_dgs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
         } else if (cls == LP_K_SPMV_CSC) {
             if (B.L.inner != 3) {
                 Prof pr(&B, LP_K_SPMV_CSC, -1, over_members(B, csc_bytes));

@@ -39,7 +39,11 @@ struct KrylovCtl {
     // assembly puts the saved iterate back
     int32_t cg_save;
     double cg_best;     // least residual so far (dw_0 = 0 included)
-    double pad1;
+    // AB-GMRES with the delayed second Gram-Schmidt pass: eta of the vector the next
+    // iteration preconditions, and the last finish's nu and s_k for its update
+    double dg_eta;
+    double dg_nu;
+    double dg_sk;
 };
 constexpr int CG_SAVE = 1, CG_RESTORE = 2;
 
@@ -236,6 +240,10 @@ void b_gs_dots(const BLaunch& L, int pass);
 void b_gs_reduce(const BLaunch& L, int pass);
 void b_gs_update(const BLaunch& L, int pass);
 void b_gs_finish(const BLaunch& L);
+// AB-GMRES: Gram-Schmidt twice with the second pass delayed one iteration (kernels.hip)
+void b_dgs_dots(const BLaunch& L);
+void b_dgs_finish(const BLaunch& L);
+void b_dgs_update(const BLaunch& L);
 void b_apply_c(const BLaunch& L);       // dense: P[:,k] = C v_k
 
 // ---- CGNE and MRNE preconditioned by inner iterations (Sec. 3.3) ------------------------

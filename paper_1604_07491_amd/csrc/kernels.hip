@@ -510,27 +510,25 @@ void b_gs_reduce(const BLaunch& L, int pass) {
 // composed maps stay bounded).
 constexpr int GF_CH = 1024;
 
-__global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I) {
-    __shared__ double sh[BLOCK / 64];
-    __shared__ double hb[GF_CH], cb[GF_CH], sb[GF_CH], ob[GF_CH];
-    __shared__ double sA[BLOCK], sB[BLOCK];
-    __shared__ double carry_s;
-    INST;
-    KrylovCtl* ctl = in.ctl;
-    if (ctl->done) return;
-    double q = 0.0;
-    for (int c = threadIdx.x; c < in.nchunks; c += BLOCK) q += in.gpart[c];
-    const double nrm2 = block_sum(q, sh);
-    const int k = ctl->k;
-    double* hk = in.H + (int64_t)k * in.ldh;
-    if (threadIdx.x == 0) carry_s = hk[0];
-    for (int base = 0; base < k; base += GF_CH) {
-        const int len = k - base < GF_CH ? k - base : GF_CH;
+struct GivensLds {
+    double hb[GF_CH], cb[GF_CH], sb[GF_CH], ob[GF_CH];
+    double sA[BLOCK], sB[BLOCK];
+    double carry;
+};
+
+// Column kc of H (hk, entries 0..kc; h_{kc+1,kc} = hn): the earlier rotations 0..kc-1,
+// then the rotation that zeroes hn, and gamma.  Every thread of the block calls it; thread
+// 0 gets the return value: false when that rotation degenerates (r = 0), else true with
+// *res = |gamma_{kc+1}|.
+__device__ bool givens_column(const Inst& in, double* hk, int kc, double hn, GivensLds& g, double* res) {
+    if (threadIdx.x == 0) g.carry = hk[0];
+    for (int base = 0; base < kc; base += GF_CH) {
+        const int len = kc - base < GF_CH ? kc - base : GF_CH;
         __syncthreads();
         for (int t = threadIdx.x; t < len; t += BLOCK) {
-            hb[t] = hk[base + t + 1];
-            cb[t] = in.cs[base + t];
-            sb[t] = in.sn[base + t];
+            g.hb[t] = hk[base + t + 1];
+            g.cb[t] = in.cs[base + t];
+            g.sb[t] = in.sn[base + t];
         }
         __syncthreads();
         // this thread's entries [i0, i1) and the composition of their maps, x -> A x + B
@@ -540,62 +538,89 @@ __global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I)
         const int i1 = i0 + per < len ? i0 + per : len;
         double A = 1.0, B = 0.0;
         for (int i = i0; i < i1; ++i) {
-            const double a = -sb[i], b = cb[i] * hb[i];
+            const double a = -g.sb[i], b = g.cb[i] * g.hb[i];
             B = a * B + b;
             A = a * A;
         }
         // inclusive scan over the threads: after it, (A, B) composes the maps of threads 0..t
-        sA[t] = A;
-        sB[t] = B;
+        g.sA[t] = A;
+        g.sB[t] = B;
         __syncthreads();
         for (int d = 1; d < BLOCK; d <<= 1) {
             double pa = 1.0, pb = 0.0;
             if (t >= d) {
-                pa = sA[t - d];
-                pb = sB[t - d];
+                pa = g.sA[t - d];
+                pb = g.sB[t - d];
             }
             __syncthreads();
             if (t >= d) {
                 B = A * pb + B;
                 A = A * pa;
-                sA[t] = A;
-                sB[t] = B;
+                g.sA[t] = A;
+                g.sB[t] = B;
             }
             __syncthreads();
         }
-        // starting carry of this thread's entries: the maps of threads 0..t-1 on carry_s
-        double carry = carry_s;
-        if (t > 0) carry = sA[t - 1] * carry + sB[t - 1];
+        // starting carry of this thread's entries: the maps of threads 0..t-1 on the carry
+        double carry = g.carry;
+        if (t > 0) carry = g.sA[t - 1] * carry + g.sB[t - 1];
         for (int i = i0; i < i1; ++i) {
-            const double bv = hb[i], c = cb[i], s = sb[i];
-            ob[i] = c * carry + s * bv;
-            carry = -s * carry + c * bv;
+            const double bv = g.hb[i], c = g.cb[i], sv = g.sb[i];
+            g.ob[i] = c * carry + sv * bv;
+            carry = -sv * carry + c * bv;
         }
-        __syncthreads();   // every thread has read carry_s
-        if (i0 < i1 && i1 == len) carry_s = carry;
+        __syncthreads();   // every thread has read the carry
+        if (i0 < i1 && i1 == len) g.carry = carry;
         __syncthreads();
-        for (int q2 = threadIdx.x; q2 < len; q2 += BLOCK) hk[base + q2] = ob[q2];
+        for (int q2 = threadIdx.x; q2 < len; q2 += BLOCK) hk[base + q2] = g.ob[q2];
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    const double hn = sqrt(nrm2);
-    const double a = carry_s, b = hn;
+    if (threadIdx.x != 0) return false;
+    const double a = g.carry, b = hn;
     const double r = hypot(a, b);
-    if (r == 0.0) {
+    if (r == 0.0) return false;
+    const double c = a / r, sv = b / r;
+    in.cs[kc] = c;
+    in.sn[kc] = sv;
+    hk[kc] = r;
+    hk[kc + 1] = 0.0;
+    const double gk = in.gam[kc];
+    in.gam[kc + 1] = -sv * gk;
+    in.gam[kc] = c * gk;
+    *res = fabs(in.gam[kc + 1]);
+    return true;
+}
+
+// ||u||^2 from the chunk partials, h_{k+1,k} = ||u||, the Givens step on column k, and
+// the test |gamma_{k+1}| <= tol * beta.  Rotation i maps (carry_i, h_{i+1}) to the output
+// entry c_i carry_i + s_i h_{i+1} and the next carry -s_i carry_i + c_i h_{i+1}: the carries
+// follow the first-order linear recurrence carry_{i+1} = a_i carry_i + b_i (a_i = -s_i,
+// b_i = c_i h_{i+1}).  Column k and the coefficients are staged through LDS in chunks;
+// inside a chunk each thread composes the affine maps of its consecutive entries, a
+// block-wide scan composes the threads' maps, and each thread then replays its entries from
+// its starting carry.  The depth is log2(BLOCK) barrier steps instead of a chain of length
+// k (|a_i| <= 1, so the composed maps stay bounded).
+__global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    __shared__ GivensLds g;
+    INST;
+    KrylovCtl* ctl = in.ctl;
+    if (ctl->done) return;
+    double q = 0.0;
+    for (int c = threadIdx.x; c < in.nchunks; c += BLOCK) q += in.gpart[c];
+    const double nrm2 = block_sum(q, sh);
+    const int k = ctl->k;
+    double* hk = in.H + (int64_t)k * in.ldh;
+    double res = 0.0;
+    const double hn = sqrt(nrm2);   // thread 0's value is the one used
+    const bool ok = givens_column(in, hk, k, hn, g, &res);
+    if (threadIdx.x != 0) return;
+    if (!ok) {
         ctl->done = 1;
         ctl->iters = k;
         ctl->failed = ctl->res > ctl->thresh;
         return;
     }
-    const double c = a / r, s = b / r;
-    in.cs[k] = c;
-    in.sn[k] = s;
-    hk[k] = r;
-    hk[k + 1] = 0.0;
-    const double gk = in.gam[k];
-    in.gam[k + 1] = -s * gk;
-    in.gam[k] = c * gk;
-    const double res = fabs(in.gam[k + 1]);
     ctl->res = res;
     ctl->k = k + 1;
     ctl->iters = k + 1;
@@ -608,6 +633,277 @@ __global__ __launch_bounds__(BLOCK) void k_gs_finish(const Inst* __restrict__ I)
 
 void b_gs_finish(const BLaunch& L) {
     hipLaunchKernelGGL(k_gs_finish, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// ------------------------------------------------------------------------------------
+// AB-GMRES orthogonalisation with the second pass delayed by one iteration (classical
+// Gram-Schmidt twice, reorganised so that each iteration reads the basis twice instead of
+// four times).  Iteration k enters with columns 0..k-1 of V orthonormal and column k
+// holding v~_k = u~_{k-1} / eta_k: the previous iteration's vector after one projection,
+// scaled by an estimate eta_k of its norm, which is what the preconditioner was applied to
+// (flexible form: p_k = C v~_k, u_k = A_hat A_hat^T p_k).  Then:
+//  * dots: a_j = v_j . v~_k and b_j = v_j . u_k for j < k, c = v~_k . v~_k, d = v~_k . u_k,
+//    e = u_k . u_k, all in one pass over V (k_dgs_dots; segment partials as in k_gs_dots);
+//  * finish (one block per instance): the second pass of v~_k, t = (a_j), nu^2 = c - ||t||^2,
+//    v_k = (v~_k - V t) / nu; so u_{k-1} = V (s' + eta_k t) + eta_k nu v_k, which completes
+//    column k-1 of H (s' its first-pass entries), and its Givens step gives the residual
+//    after k iterations and the stopping test.  Then u_k's first pass against v_0..v_k:
+//    s_j = b_j (j < k), s_k = (d - t . b) / nu, stored as column k of H, and
+//    eta_{k+1}^2 = e - ||s||^2 for the next iteration's scaling;
+//  * update: v_k = (v~_k - V t) / nu and u~_k = u_k - V s - s_k v_k in one pass over V.
+// For k = 0, v_0 = f_hat / beta is exact: no second pass, nu = 1.  Each iteration ends one
+// column behind classical Gram-Schmidt twice: the test after k iterations runs in iteration
+// k, so a solve runs one more preconditioner application and product than it reports.
+// Column k of H needs k < kmax; at k = kmax the iteration only completes column kmax - 1.
+__global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_dgs_dots(const Inst* __restrict__ I) {
+    INST;
+    if (in.ctl->done) return;
+    const int k = in.ctl->k;
+    const int nseg = in.nseg;
+    const int64_t m = in.m;
+    const int tasks = nseg * (k + 2);   // columns 0..k, then u . u
+    const int lane = threadIdx.x & 63;
+    const int nw = (int)gridDim.x * GS_DOT_WAVES;
+    const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
+    const LPK_GLOBAL double* __restrict__ vk = to_global(in.V + (int64_t)k * in.ldv);
+    for (int t = bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
+        const int j = nseg == 1 ? t : t / nseg;
+        const int sg = t - j * nseg;
+        const int64_t r0 = (int64_t)sg * GS_SEG;
+        const int64_t r1 = r0 + GS_SEG < m ? r0 + GS_SEG : m;
+        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+        int64_t i = r0 + lane;
+        if (j <= k) {
+            const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)j * in.ldv);
+            for (; i + 64 < r1; i += 128) {
+                const double x0 = vj[i], x1 = vj[i + 64];
+                a0 += x0 * vk[i];
+                b0 += x0 * u[i];
+                a1 += x1 * vk[i + 64];
+                b1 += x1 * u[i + 64];
+            }
+            for (; i < r1; i += 64) {
+                const double x0 = vj[i];
+                a0 += x0 * vk[i];
+                b0 += x0 * u[i];
+            }
+        } else {
+            for (; i + 64 < r1; i += 128) {
+                a0 += u[i] * u[i];
+                a1 += u[i + 64] * u[i + 64];
+            }
+            for (; i < r1; i += 64) a0 += u[i] * u[i];
+        }
+        const double a = wave_sum(a0 + a1);
+        const double b = wave_sum(b0 + b1);
+        if (lane == 0) {
+            in.gpart[(int64_t)sg * in.ldp + j] = a;
+            if (j <= k) in.gpart2[(int64_t)sg * in.ldp + j] = b;
+        }
+    }
+}
+
+void b_dgs_dots(const BLaunch& L) {
+    hipLaunchKernelGGL(k_dgs_dots, dim3(L.gs_dots_grid, L.S), dim3(64 * GS_DOT_WAVES), 0, L.st, L.I);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dgs_finish(const Inst* __restrict__ I) {
+    __shared__ double sh[BLOCK / 64];
+    __shared__ GivensLds g;
+    __shared__ double sc[4];
+    INST;
+    KrylovCtl* ctl = in.ctl;
+    if (ctl->done) return;
+    const int k = ctl->k;
+    const int nseg = in.nseg;
+    double* __restrict__ ta = in.gpart;    // row 0: a_j (j <= k), then e at k + 1
+    double* __restrict__ tb = in.gpart2;   // row 0: b_j (j <= k)
+    // the segment sums, in place in row 0, in a fixed order
+    if (nseg > 1)
+        for (int j = threadIdx.x; j <= k + 1; j += BLOCK) {
+            double sa = 0.0, sb = 0.0;
+            for (int c = 0; c < nseg; ++c) {
+                sa += ta[(int64_t)c * in.ldp + j];
+                if (j <= k) sb += tb[(int64_t)c * in.ldp + j];
+            }
+            ta[j] = sa;
+            if (j <= k) tb[j] = sb;
+        }
+    __syncthreads();
+    // ||t||^2, t . b and sum_{j<k} b_j^2
+    double q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    for (int j = threadIdx.x; j < k; j += BLOCK) {
+        const double a = ta[j], b = tb[j];
+        q1 += a * a;
+        q2 += a * b;
+        q3 += b * b;
+    }
+    q1 = block_sum(q1, sh);
+    q2 = block_sum(q2, sh);
+    q3 = block_sum(q3, sh);
+    if (threadIdx.x == 0) {
+        const double c = ta[k], d = tb[k];
+        double nu = 1.0, sk = d;
+        if (k > 0) {
+            const double nu2 = c - q1;
+            nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+            sk = nu > 0.0 ? (d - q2) / nu : 0.0;
+        }
+        sc[0] = nu;
+        sc[1] = sk;
+        sc[2] = q3 + sk * sk;   // ||s||^2
+        sc[3] = ta[k + 1];      // e
+    }
+    __syncthreads();
+    const double nu = sc[0], sk = sc[1];
+    if (k > 0) {
+        // column k-1: s' (stored there last iteration) + eta_k t, h_{k,k-1} = eta_k nu
+        const double eta = ctl->dg_eta;
+        double* hc = in.H + (int64_t)(k - 1) * in.ldh;
+        for (int j = threadIdx.x; j < k; j += BLOCK) hc[j] += eta * ta[j];
+        __syncthreads();
+        double res = 0.0;
+        const double hn = eta * nu;
+        const bool ok = givens_column(in, hc, k - 1, hn, g, &res);
+        if (threadIdx.x == 0) {
+            if (!ok) {
+                ctl->done = 1;
+                ctl->iters = k - 1;
+                ctl->failed = ctl->res > ctl->thresh;
+            } else {
+                ctl->res = res;
+                ctl->iters = k;
+                if (res <= ctl->thresh || hn == 0.0 || k >= ctl->kmax) {
+                    ctl->done = 1;
+                    ctl->failed = res > ctl->thresh;
+                }
+            }
+            sc[0] = ctl->done;
+        }
+        __syncthreads();
+        if (sc[0] != 0.0) return;
+    }
+    // u_k's first pass: column k of H, the next scaling, and the update's coefficients
+    double* hk = in.H + (int64_t)k * in.ldh;
+    for (int j = threadIdx.x; j < k; j += BLOCK) hk[j] = tb[j];
+    if (threadIdx.x == 0) {
+        hk[k] = sk;
+        const double e = sc[3];
+        double eta2 = e - sc[2];
+        if (eta2 < 1e-24 * e) eta2 = 1e-24 * e;   // cancellation: the next pass rescales
+        const double eta = sqrt(eta2);
+        ctl->dg_eta = eta;
+        ctl->dg_nu = nu;
+        ctl->dg_sk = sk;
+        ctl->inv_h = eta > 0.0 ? 1.0 / eta : 0.0;
+        ctl->k = k + 1;
+    }
+}
+
+void b_dgs_finish(const BLaunch& L) {
+    hipLaunchKernelGGL(k_dgs_finish, dim3(1, L.S), dim3(BLOCK), 0, L.st, L.I);
+}
+
+// acc_t[r] += sum_j V[i_r, j] t_j and acc_s[r] += sum_j V[i_r, j] s_j over the wave's
+// columns j (w, w + GS_WAVES, ... < kk, increasing), one load of V for both (half the
+// single-vector unroll: two accumulators per row)
+template <int RPL>
+__device__ __forceinline__ void chunk_axpy2(const Inst& in, int kk, int w, int lane, int64_t base, int rpl,
+                                            const double* tc, const double* scf, double (&at)[RPL],
+                                            double (&as)[RPL]) {
+    constexpr int U = gs_unroll<RPL>() >= 2 ? gs_unroll<RPL>() / 2 : 1;
+    const int64_t m = in.m;
+    int j = w;
+    for (; j + (U - 1) * GS_WAVES < kk; j += U * GS_WAVES) {
+        double v[U][RPL], tq[U], sq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            tq[q] = tc[j + q * GS_WAVES];
+            sq[q] = scf[j + q * GS_WAVES];
+            const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)(j + q * GS_WAVES) * in.ldv);
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const int64_t i = base + lane + 64 * t;
+                v[q][t] = (t < rpl && i < m) ? vj[i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                at[t] += v[q][t] * tq[q];
+                as[t] += v[q][t] * sq[q];
+            }
+    }
+    for (; j < kk; j += GS_WAVES) {
+        const double tj = tc[j], sj = scf[j];
+        const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)j * in.ldv);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int64_t i = base + lane + 64 * t;
+            const double x = (t < rpl && i < m) ? vj[i] : 0.0;
+            at[t] += x * tj;
+            as[t] += x * sj;
+        }
+    }
+}
+
+template <int RPL>
+__global__ __launch_bounds__(64 * GS_WAVES) void k_dgs_update(const Inst* __restrict__ I) {
+    __shared__ double red[GS_WAVES][64 * RPL];
+    __shared__ double tl[GS_HLDS / 2], sl[GS_HLDS / 2];
+    INST;
+    const KrylovCtl* ctl = in.ctl;
+    if (ctl->done || bx >= in.nchunks) return;
+    const int kk = ctl->k - 1;   // the iteration whose finish ran
+    const int rpl = in.rpl;
+    const int64_t m = in.m;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)bx * 64 * rpl;
+    const double* tc = in.gpart;
+    const double* scf = in.gpart2;
+    if (kk <= GS_HLDS / 2) {
+        for (int j = threadIdx.x; j < kk; j += blockDim.x) {
+            tl[j] = tc[j];
+            sl[j] = scf[j];
+        }
+        __syncthreads();
+        tc = tl;
+        scf = sl;
+    }
+    double at[RPL], as[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) at[t] = as[t] = 0.0;
+    chunk_axpy2<RPL>(in, kk, w, lane, base, rpl, tc, scf, at, as);
+    // the waves' partial sums, one vector after the other through the same LDS
+    const int r = threadIdx.x;
+    double st = 0.0, ss = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = at[t];
+    __syncthreads();
+    if (r < 64 * rpl)
+        for (int ww = 0; ww < GS_WAVES; ++ww) st += red[ww][r];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = as[t];
+    __syncthreads();
+    if (r < 64 * rpl) {
+        const int64_t i = base + r;
+        for (int ww = 0; ww < GS_WAVES; ++ww) ss += red[ww][r];
+        if (i < m) {
+            LPK_GLOBAL double* __restrict__ vk = to_global(in.V + (int64_t)kk * in.ldv);
+            LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
+            const double v = (vk[i] - st) / ctl->dg_nu;
+            vk[i] = v;
+            u[i] = u[i] - ss - v * ctl->dg_sk;
+        }
+    }
+}
+
+void b_dgs_update(const BLaunch& L) {
+#define LPK_GU(R) hipLaunchKernelGGL((k_dgs_update<R>), dim3(L.gs_nchunks, L.S), dim3(64 * GS_WAVES), 0, L.st, L.I)
+    LPK_SWITCH_RPL(LPK_GU)
+#undef LPK_GU
 }
 
 // ------------------------------------------------------------------------------------

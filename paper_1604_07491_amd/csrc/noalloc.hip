@@ -70,8 +70,8 @@ static size_t carve_workspace(const lp_problem* p, unsigned char* base, Workspac
     x.ykr = take(cols + 1);
     x.h2 = take(cols + 1);
     if (gmres) {
-        x.gpart = take(std::max<int64_t>(p->nchunks, segs * cols));
-        x.gpart2 = take(segs * cols);
+        x.gpart = take(std::max<int64_t>(p->nchunks, segs * (cols + 1)));
+        x.gpart2 = take(segs * (cols + 1));
     } else {
         x.gpart = take(p->nchunks);
         x.gpart2 = nullptr;
