@@ -328,11 +328,13 @@ lp_status Batch::refresh() {
         L.gs_rpl = std::max(L.gs_rpl, in.rpl);
         L.gs_nchunks = std::max(L.gs_nchunks, in.nchunks);
         L.gs_fused = L.gs_fused && gs_fusable(p->m, p->kmax);
-        // dot tasks: (k + 1) columns x segments, at most 128 blocks of 4 waves per instance,
-        // 64 in batches of 64 or more (the blocks beyond a short basis's tasks return at
-        // once but still cost dispatch: transportation x64, 73.4 -> 74.5 LPs/s)
+        // dot tasks: segments x columns (or groups of 4 columns for long bases in wide
+        // batches), at most 128 blocks of 4 waves per instance, 64 in batches of 64 or more
+        // (the blocks beyond a short basis's tasks return at once but still cost dispatch:
+        // transportation x64, 73.4 -> 74.5 LPs/s)
         const int dcap = std::min(128, std::max(64, 4096 / std::max(1, cap)));
-        L.gs_dots_grid = std::max<int>(L.gs_dots_grid, (int)std::min<int64_t>(dcap, cdiv_i((int64_t)in.nseg * (p->kmax + 1), 4)));
+        const int64_t dtasks = (int64_t)in.nseg * (p->kmax + 1);
+        L.gs_dots_grid = std::max<int>(L.gs_dots_grid, (int)std::min<int64_t>(dcap, cdiv_i(dtasks, 4)));
         L.max_ncol = std::max(L.max_ncol, in.ncol);
         L.any_free = L.any_free || in.nfpairs > 0;
         if (in.nsl > 0) L.grid_ahz = std::max(L.grid_ahz, in.nbc + in.nsl);

@@ -655,52 +655,94 @@ void b_gs_finish(const BLaunch& L) {
 // column behind classical Gram-Schmidt twice: the test after k iterations runs in iteration
 // k, so a solve runs one more preconditioner application and product than it reports.
 // Column k of H needs k < kmax; at k = kmax the iteration only completes column kmax - 1.
-__global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_dgs_dots(const Inst* __restrict__ I) {
-    INST;
-    if (in.ctl->done) return;
-    const int k = in.ctl->k;
+// one DPP lane move inside each row of 16 lanes (ctrl: a quad_perm or row-mirror code)
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes, in every lane: inside each row of 16 lanes by DPP moves
+// (quad_perm [1,0,3,2], [2,3,0,1], then the half-row and row mirrors, whose partners hold
+// the same partial sums as the xor-4 and xor-8 partners), then across rows by two shuffles
+__device__ __forceinline__ double wave_sum_rows(double v) {
+    v += dpp_row_move<0xB1>(v);
+    v += dpp_row_move<0x4E>(v);
+    v += dpp_row_move<0x141>(v);
+    v += dpp_row_move<0x140>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// A task is C consecutive columns of one segment: u and v~_k are loaded once per row for
+// all of them.  Column k + 1 stands for u itself (its dot with u is u . u).  C = 4 when the
+// launch has enough tasks for it (at least 16384 / 4 per 64-wide slice of instances: the
+// serving mix's long bases), else C = 1 (short bases: more, shorter tasks keep more loads in
+// flight).
+template <int C>
+__device__ __forceinline__ void dgs_dots_tasks(const Inst& in, int k, int blk) {
     const int nseg = in.nseg;
     const int64_t m = in.m;
-    const int tasks = nseg * (k + 2);   // columns 0..k, then u . u
+    const int ngrp = (k + 2 + C - 1) / C;   // columns 0..k, then u . u
+    const int tasks = nseg * ngrp;
     const int lane = threadIdx.x & 63;
     const int nw = (int)gridDim.x * GS_DOT_WAVES;
     const LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
     const LPK_GLOBAL double* __restrict__ vk = to_global(in.V + (int64_t)k * in.ldv);
-    for (int t = bx * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
-        const int j = nseg == 1 ? t : t / nseg;
-        const int sg = t - j * nseg;
+    for (int t = blk * GS_DOT_WAVES + (threadIdx.x >> 6); t < tasks; t += nw) {
+        const int q = nseg == 1 ? t : t / nseg;
+        const int sg = t - q * nseg;
+        const int c0 = q * C;
         const int64_t r0 = (int64_t)sg * GS_SEG;
         const int64_t r1 = r0 + GS_SEG < m ? r0 + GS_SEG : m;
-        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-        int64_t i = r0 + lane;
-        if (j <= k) {
-            const LPK_GLOBAL double* __restrict__ vj = to_global(in.V + (int64_t)j * in.ldv);
-            for (; i + 64 < r1; i += 128) {
-                const double x0 = vj[i], x1 = vj[i + 64];
-                a0 += x0 * vk[i];
-                b0 += x0 * u[i];
-                a1 += x1 * vk[i + 64];
-                b1 += x1 * u[i + 64];
-            }
-            for (; i < r1; i += 64) {
-                const double x0 = vj[i];
-                a0 += x0 * vk[i];
-                b0 += x0 * u[i];
-            }
-        } else {
-            for (; i + 64 < r1; i += 128) {
-                a0 += u[i] * u[i];
-                a1 += u[i + 64] * u[i + 64];
-            }
-            for (; i < r1; i += 64) a0 += u[i] * u[i];
+        const LPK_GLOBAL double* __restrict__ x[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j = c0 + c;
+            x[c] = j <= k ? to_global(in.V + (int64_t)j * in.ldv) : u;   // past k + 1: unused
         }
-        const double a = wave_sum(a0 + a1);
-        const double b = wave_sum(b0 + b1);
-        if (lane == 0) {
-            in.gpart[(int64_t)sg * in.ldp + j] = a;
-            if (j <= k) in.gpart2[(int64_t)sg * in.ldp + j] = b;
+        const int nc = k + 2 - c0 < C ? k + 2 - c0 : C;
+        double a[C], b[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = b[c] = 0.0;
+        constexpr int UNR = C == 1 ? 2 : 1;
+#pragma unroll UNR
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            const double ui = u[i], wi = vk[i];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c < nc) {
+                    const double xi = x[c][i];
+                    a[c] += xi * wi;
+                    b[c] += xi * ui;
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (c >= nc) break;
+            const int j = c0 + c;
+            const double sb = wave_sum_rows(b[c]);
+            if (j <= k) {
+                const double sa = wave_sum_rows(a[c]);
+                if (lane == 0) {
+                    in.gpart[(int64_t)sg * in.ldp + j] = sa;
+                    in.gpart2[(int64_t)sg * in.ldp + j] = sb;
+                }
+            } else if (lane == 0) {
+                in.gpart[(int64_t)sg * in.ldp + j] = sb;   // u . u
+            }
         }
     }
+}
+
+__global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_dgs_dots(const Inst* __restrict__ I) {
+    INST;
+    if (in.ctl->done) return;
+    const int k = in.ctl->k;
+    if ((int64_t)(k + 2) * gridDim.y >= 16384) dgs_dots_tasks<4>(in, k, bx);
+    else dgs_dots_tasks<1>(in, k, bx);
 }
 
 void b_dgs_dots(const BLaunch& L) {
