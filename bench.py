@@ -39,26 +39,26 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
-def kernels_digest():
+def kernels_digest(files=("sweep.hip", "kernels.h")):
     """sha256 of the sweep kernels' source and of the header that sizes their launches, which
-    the committed counter runs were taken on."""
+    the committed counter runs were taken on (the one-block sweep: sweep_lds.hip)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "kernels.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1604_07491_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def counter_traffic(args, kernel, width):
+def counter_traffic(args, kernel, width, precision=None, files=("sweep.hip", "kernels.h")):
     """HBM bytes per launch of `kernel` from the committed counter runs, if they were taken
     for this workload and batch width on the kernels as they are now (else None)."""
     if not args.traffic or not os.path.exists(args.traffic):
         return None
-    key = f"{args.workload}/{args.precision}/w{width}/{kernel}"
+    key = f"{args.workload}/{precision or args.precision}/w{width}/{kernel}"
     if args.inner != "nesor" or args.krylov != "abgmres":
         key += f"/{args.inner}/{args.krylov}"
     rec = json.load(open(args.traffic)).get(key)
-    if not rec or rec.get("kernels_sha256") != kernels_digest():
+    if not rec or rec.get("kernels_sha256") != kernels_digest(files):
         return None
     return rec["bytes_per_launch"]
 
@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--correctors", type=int, default=0,
                     help="multiple centrality correctors per interior-point step (0: Mehrotra's method)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--replay-only", action="store_true",
+                    help="serving mix: only the kernel-class replay of the roofline (for counter runs)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="counter-derived HBM bytes per launch (FETCH_SIZE/WRITE_SIZE runs)")
     args = ap.parse_args()
@@ -405,7 +407,7 @@ def _converged(done):
     return [c for c in done if c["status"] == lpk.LP_OK and c["gamma_rel"] <= 1e-8]
 
 
-def _mix_roofline(lps, precision, width):
+def _mix_roofline(lps, precision, width, args=None):
     """The kernel classes of the serving mix timed as the batch runs them: every LP of the
     mix created on the device, scaled by one short direction solve, then each class's
     launches for `width` LPs replayed back-to-back between two HIP events on the library's
@@ -440,8 +442,12 @@ def _mix_roofline(lps, precision, width):
         p.close()
     dom = max(classes, key=lambda k: classes[k]["us_per_iteration"])
     c = classes[dom]
+    # HBM bytes per launch from the committed counter runs of this replay (FETCH_SIZE and
+    # WRITE_SIZE, scaled by a plain copy's), while the sweep kernels are unchanged
+    files = ("sweep_lds.hip", "kernels.h") if all(kk != 0 for _, kk in layouts) else ("sweep.hip", "sweep_lds.hip", "kernels.h")
+    traffic = counter_traffic(args, dom, len(probs), precision, files) if args is not None else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": c["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": c["frac"], "traffic": None, "us_per_launch": c["us_per_launch"],
+                "frac": c["frac"], "traffic": traffic, "us_per_launch": c["us_per_launch"],
                 "bytes_per_launch": c["bytes_per_launch"], "lps_per_launch": len(probs),
                 "timing": "lp_time_batch_kernel replay, 20 x group, HIP events on the library stream"}
     if dom == "sweep":
@@ -468,6 +474,10 @@ def serve_main(args):
     print(f"generated {count} LPs (m {min(l.m for l in lps)}..{max(l.m for l in lps)})", file=sys.stderr,
           flush=True)
     prec = args.precision_mix
+    if args.replay_only:
+        roofline, classes, layout = _mix_roofline(sorted(lps, key=lambda l: -l.m), prec, width, args)
+        print(json.dumps({"roofline": roofline, "batch_kernels": classes, "sweep_layout": layout}), flush=True)
+        return
     for _ in range(args.warmup):
         done, wall = _serve_run(lps, np.zeros(count), prec, width, args.krylov_cap, args.lanes)
         print(f"warm-up closed loop {prec}: {len(_converged(done)) / wall:.2f} LPs/s", file=sys.stderr, flush=True)
@@ -499,7 +509,7 @@ def serve_main(args):
                    "krylov_iters_total": int(sum(c["krylov_iters"] for c in done)),
                    "ipm_iters_total": int(sum(c["iters"] for c in done))}
         print(f"open loop {pr}: {out[pr]}", file=sys.stderr, flush=True)
-    roofline, classes, layout = _mix_roofline(sorted(lps, key=lambda l: -l.m), prec, width)
+    roofline, classes, layout = _mix_roofline(sorted(lps, key=lambda l: -l.m), prec, width, args)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

@@ -328,6 +328,20 @@ static void drain_lane(lp_server* s, Lane& L, lp_status trc) {
     }
 }
 
+// A lane's stream on a hardware queue of its own.  Streams otherwise share the process's few
+// hardware queues (GPU_MAX_HW_QUEUES) with every other stream, the preparer's and the graph
+// captures' included, and two lanes on one queue run their rounds in turn.  A stream created
+// with a CU mask gets a queue of its own; the mask here covers every compute unit.
+static hipError_t create_lane_stream(int device, hipStream_t* st) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
+        std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0xFFFFFFFFu);
+        if (cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+        if (hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) == hipSuccess) return hipSuccess;
+    }
+    return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
 // The lanes: join ready problems into a lane's free slots whenever its previous round has
 // completed, queue its next round, and complete the members that finished.  All launches
 // come from this one thread.  While one lane's round runs on the GPU the others' rounds
@@ -338,7 +352,7 @@ static void engine_main(lp_server* s) {
     std::vector<std::unique_ptr<Lane>> lanes;
     for (int l = 0; ok && l < nl; ++l) {
         std::unique_ptr<Lane> L(new Lane());
-        if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess) {
+        if (create_lane_stream(s->device, &L->st) != hipSuccess) {
             ok = false;
             break;
         }

@@ -3,6 +3,7 @@
     python -m paper_1604_07491_amd.profsum trace <rocprof output dir> <out.json>
     python -m paper_1604_07491_amd.profsum pmc   <rocprof output dir> <out.json>
     python -m paper_1604_07491_amd.profsum window <rocprof output dir> <out.json> <kernel> <grid y> <count>
+    python -m paper_1604_07491_amd.profsum pmcwindow <rocprof output dir> <out.json> <kernel> <grid threads> <count>
 
 trace: per (kernel, grid) launch counts and mean durations from the kernel trace, and for
 each batch width the mean duration of the NE-SOR sweep launches of the timing replay (the
@@ -12,6 +13,8 @@ last 800 batched sweep dispatches (the replay window of bench.py's kernel table)
 the mean duration of the last <count> launches of the kernel whose name contains <kernel>
 with grid y = <grid y> (bench.py replays its dominant kernel for the serving mix's batch
 last of all its launches of that grid), with the per-kernel table of the whole trace.
+pmcwindow: the mean counter value over the last <count> dispatches of the kernel whose name
+contains <kernel> with <grid threads> threads in all (a counter run of that replay).
 """
 import collections
 import csv
@@ -92,9 +95,23 @@ def window_summary(d, kernel, grid_y, count):
     return res
 
 
+def pmc_window(d, kernel, grid_threads, count):
+    rows = list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
+    sel = [r for r in rows if kernel in r["Kernel_Name"] and int(r["Grid_Size"]) == grid_threads]
+    sel.sort(key=lambda r: int(r["Dispatch_Id"]))
+    out = {}
+    for name in sorted({r["Counter_Name"] for r in sel}):
+        v = [float(r["Counter_Value"]) for r in sel if r["Counter_Name"] == name][-count:]
+        out[name] = {"n": len(v), "mean": sum(v) / max(1, len(v)), "min": min(v) if v else None,
+                     "max": max(v) if v else None}
+    return {"kernel": kernel, "grid_threads": grid_threads, "counters": out}
+
+
 if __name__ == "__main__":
     kind, d, out = sys.argv[1:4]
-    if kind == "window":
+    if kind == "pmcwindow":
+        res = pmc_window(d, sys.argv[4], int(sys.argv[5]), int(sys.argv[6]))
+    elif kind == "window":
         res = window_summary(d, sys.argv[4], int(sys.argv[5]), int(sys.argv[6]))
     else:
         res = trace_summary(d) if kind == "trace" else pmc_summary(d)
