@@ -199,14 +199,14 @@ constexpr int LDS_Z_MAX = LDS_BLOCK_MAX;
 constexpr int LDS_STAGE_MAX = LDS_BLOCK_MAX;
 // LDS of the one-block sweep: z with the colour table, and (staged) everything
 inline int64_t lds_z_bytes(int64_t m, int64_t n, int64_t ncol, int tbytes) {
-    return 16 * ncol + 16 * m + n * tbytes + 4 * (m + 1);
+    return 16 * ncol + 16 * m + (n + 1) * tbytes + 4 * (m + 1);
 }
 // threads of the one-block sweep, and the most rounds of them a colour's rows may take
 // when the rows are read from memory (each round is one dependent load step)
 constexpr int LDS_SWEEP_THREADS = 1024;
 constexpr int LDS_ROUNDS_MAX = 4;
 inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, int tbytes) {
-    return 16 * ncol + 16 * m + nnz * (tbytes + 4) + n * tbytes + 4 * (m + 1);
+    return 16 * ncol + 16 * m + nnz * (tbytes + 4) + (n + 1) * tbytes + 4 * (m + 1);
 }
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------

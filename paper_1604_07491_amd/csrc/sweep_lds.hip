@@ -26,8 +26,8 @@ namespace lpk {
 // multipliers go to V_U.  1024 threads per block measured as fast as 256 and twice as fast
 // as 64 on the 200 x 500 LPs.
 // LDS layout: colour table (ncol int4), p (m doubles), v (m doubles), [STAGED: values (nnz
-// T)], z (n T), row pointers (m + 1 ints), [STAGED: column indices (nnz ints)]:
-// lds_stage_bytes / lds_z_bytes.
+// T)], z (n + 1 T: entry n takes the stores of the lanes past a row's end), row pointers
+// (m + 1 ints), [STAGED: column indices (nnz ints)]: lds_stage_bytes / lds_z_bytes.
 constexpr int NT = LDS_SWEEP_THREADS;
 
 // one DPP lane move inside each row of 16 lanes (ctrl a quad_perm or row-mirror code)
@@ -78,7 +78,7 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     double* vl = pl + m;                               // v_k
     T* sv = reinterpret_cast<T*>(vl + m);              // STAGED: the row values
     T* z = STAGED ? sv + nnz : sv;
-    int32_t* srp = reinterpret_cast<int32_t*>(z + n);
+    int32_t* srp = reinterpret_cast<int32_t*>(z + n + 1);
     int32_t* si = srp + (m + 1);                       // STAGED: the column indices
     if constexpr (STAGED) {
 #pragma unroll 4
@@ -91,15 +91,20 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     for (int t = tid; t <= m; t += NT) srp[t] = grp[t];
 #pragma unroll 4
     for (int t = tid; t < m; t += NT) vl[t] = u[t] * ih;
-    // A colour whose rows fit in one wave (rows x lanes <= 64) runs on wave 0 alone, and a
-    // run of such colours needs no block barrier: the LDS accesses of one wave complete in
-    // program order.
+    for (int j = tid; j <= n; j += NT) z[j] = 0;
+    __syncthreads();
+    // The colour table.  A colour whose rows fit in one wave (rows x lanes <= 64) runs on
+    // wave 0 alone, and a run of such colours needs no block barrier: the LDS accesses of
+    // one wave complete in program order.  Each colour also records its slots per lane, the
+    // element slots its longest row needs (ceil(longest / g), at most R in the slot path).
     for (int c = tid; c < ncol; c += NT) {
         const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
         const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
-        ctab[c] = make_int4(r0, r1, g, (r1 - r0) * g <= 64 ? 1 : 0);
+        int longest = 0;
+        for (int r = r0; r < r1; ++r) longest = max(longest, srp[r + 1] - srp[r]);
+        const int slots = (longest + g - 1) / g;
+        ctab[c] = make_int4(r0, r1, g, ((r1 - r0) * g <= 64 ? 1 : 0) | (slots << 1));
     }
-    for (int j = tid; j < n; j += NT) z[j] = 0;
     __syncthreads();
     const T om = (T)in.omega;
     constexpr int R = 8;
@@ -111,14 +116,16 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
         for (int cc = 0; cc < ncol; ++cc) {
             const int4 ct = ctab[dir ? ncol - 1 - cc : cc];
             const int r0 = ct.x, r1 = ct.y, g = ct.z;
-            const bool small = ct.w != 0;
+            const bool small = (ct.w & 1) != 0;
+            const int slots = ct.w >> 1;   // element slots per lane of the colour's longest row
             const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
             const int lane = tid & (g - 1);
+            const int lg = __builtin_ctz(g);   // g is a power of two
             if (!small && prev_small) __syncthreads();
             const int nth = small ? 64 : NT;
-            const int per = nth / g;
+            const int per = nth >> lg;
             for (int base = r0; base < r1 && tid < nth; base += per) {
-                const int row = base + tid / g;
+                const int row = base + (tid >> lg);
                 if (row >= r1) continue;   // uniform inside the sub-group
                 const double vrow = vl[row];
                 const int s = srp[row], e = srp[row + 1];
@@ -126,30 +133,48 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
                 if (e - s <= g * R) {
                     // the row's values and indices are loaded together, then its z values;
                     // those are kept for the update: no other row of the colour touches
-                    // these columns, so they are still current
+                    // these columns, so they are still current.  The colour's slot count is
+                    // uniform over the block, so slots past it are skipped by a scalar branch;
+                    // inside it, a slot past the row's end loads the row's last element
+                    // (rows are never empty), counts as 0, and stores to z[n].  Skipping the
+                    // zero terms leaves acc unchanged (it starts at +0 and never becomes -0).
                     T a[R], zv[R];
                     int jj[R];
+                    bool ok[R];
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
+                        if (t >= slots) break;
                         const int kk = s + lane + t * g;
+                        ok[t] = kk < e;
+                        const int kc = ok[t] ? kk : e - 1;
                         if constexpr (STAGED) {
-                            a[t] = kk < e ? sv[kk] : (T)0;
-                            jj[t] = kk < e ? si[kk] : 0;
+                            a[t] = sv[kc];
+                            jj[t] = si[kc];
                         } else {
-                            a[t] = kk < e ? gval[kk] : (T)0;
-                            jj[t] = kk < e ? gci[kk] : 0;
+                            a[t] = gval[kc];
+                            jj[t] = gci[kc];
                         }
                     }
 #pragma unroll
-                    for (int t = 0; t < R; ++t) zv[t] = s + lane + t * g < e ? z[jj[t]] : (T)0;
+                    for (int t = 0; t < R; ++t) {
+                        if (t >= slots) break;
+                        a[t] = ok[t] ? a[t] : (T)0;
+                        const T zt = z[jj[t]];
+                        zv[t] = ok[t] ? zt : (T)0;
+                    }
 #pragma unroll
-                    for (int t = 0; t < R; ++t) acc += a[t] * zv[t];
+                    for (int t = 0; t < R; ++t) {
+                        if (t >= slots) break;
+                        acc += a[t] * zv[t];
+                    }
                     acc = sg_sum_lds(acc, g);
                     delta = om * ((T)vrow - acc);
                     if (write_z) {
 #pragma unroll
-                        for (int t = 0; t < R; ++t)
-                            if (s + lane + t * g < e) z[jj[t]] = zv[t] + delta * a[t];
+                        for (int t = 0; t < R; ++t) {
+                            if (t >= slots) break;
+                            z[ok[t] ? jj[t] : n] = zv[t] + delta * a[t];
+                        }
                     }
                 } else {
                     for (int kk = s + lane; kk < e; kk += g) {
