@@ -678,9 +678,8 @@ __device__ __forceinline__ double wave_sum_rows(double v) {
 
 // A task is C consecutive columns of one segment: u and v~_k are loaded once per row for
 // all of them.  Column k + 1 stands for u itself (its dot with u is u . u).  C = 4 when the
-// launch has enough tasks for it (at least 16384 / 4 per 64-wide slice of instances: the
-// serving mix's long bases), else C = 1 (short bases: more, shorter tasks keep more loads in
-// flight).
+// launch has at least 16384 columns over its instances (the serving mix's long bases), 2 from
+// 8192, else 1 (short bases: more, shorter tasks keep more loads in flight).
 template <int C>
 __device__ __forceinline__ void dgs_dots_tasks(const Inst& in, int k, int blk) {
     const int nseg = in.nseg;
@@ -707,7 +706,7 @@ __device__ __forceinline__ void dgs_dots_tasks(const Inst& in, int k, int blk) {
         double a[C], b[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) a[c] = b[c] = 0.0;
-        constexpr int UNR = C == 1 ? 2 : 1;
+        constexpr int UNR = C == 1 ? 2 : 1;   // rows in flight per lane
 #pragma unroll UNR
         for (int64_t i = r0 + lane; i < r1; i += 64) {
             const double ui = u[i], wi = vk[i];
@@ -741,7 +740,9 @@ __global__ __launch_bounds__(64 * GS_DOT_WAVES) void k_dgs_dots(const Inst* __re
     INST;
     if (in.ctl->done) return;
     const int k = in.ctl->k;
-    if ((int64_t)(k + 2) * gridDim.y >= 16384) dgs_dots_tasks<4>(in, k, bx);
+    const int64_t work = (int64_t)(k + 2) * gridDim.y;
+    if (work >= 16384) dgs_dots_tasks<4>(in, k, bx);
+    else if (work >= 8192) dgs_dots_tasks<2>(in, k, bx);
     else dgs_dots_tasks<1>(in, k, bx);
 }
 
@@ -848,7 +849,7 @@ void b_dgs_finish(const BLaunch& L) {
 
 // acc_t[r] += sum_j V[i_r, j] t_j and acc_s[r] += sum_j V[i_r, j] s_j over the wave's
 // columns j (w, w + GS_WAVES, ... < kk, increasing), one load of V for both (half the
-// single-vector unroll: two accumulators per row)
+// single-vector unroll: two accumulators per row; the full unroll measured slower)
 template <int RPL>
 __device__ __forceinline__ void chunk_axpy2(const Inst& in, int kk, int w, int lane, int64_t base, int rpl,
                                             const double* tc, const double* scf, double (&at)[RPL],
@@ -892,7 +893,10 @@ __device__ __forceinline__ void chunk_axpy2(const Inst& in, int kk, int w, int l
 
 template <int RPL>
 __global__ __launch_bounds__(64 * GS_WAVES) void k_dgs_update(const Inst* __restrict__ I) {
-    __shared__ double red[GS_WAVES][64 * RPL];
+    // the waves' partial sums of both vectors in one pass through LDS when they fit in
+    // 16 KiB (RPL <= 2), else one vector after the other through the same LDS
+    constexpr bool ONE = RPL <= 2;
+    __shared__ double red[ONE ? 2 : 1][GS_WAVES][64 * RPL];
     __shared__ double tl[GS_HLDS / 2], sl[GS_HLDS / 2];
     INST;
     const KrylovCtl* ctl = in.ctl;
@@ -917,21 +921,35 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_dgs_update(const Inst* __rest
 #pragma unroll
     for (int t = 0; t < RPL; ++t) at[t] = as[t] = 0.0;
     chunk_axpy2<RPL>(in, kk, w, lane, base, rpl, tc, scf, at, as);
-    // the waves' partial sums, one vector after the other through the same LDS
     const int r = threadIdx.x;
     double st = 0.0, ss = 0.0;
+    if constexpr (ONE) {
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = at[t];
-    __syncthreads();
-    if (r < 64 * rpl)
-        for (int ww = 0; ww < GS_WAVES; ++ww) st += red[ww][r];
-    __syncthreads();
+        for (int t = 0; t < RPL; ++t) {
+            red[0][w][lane + 64 * t] = at[t];
+            red[ONE ? 1 : 0][w][lane + 64 * t] = as[t];
+        }
+        __syncthreads();
+        if (r < 64 * rpl)
+            for (int ww = 0; ww < GS_WAVES; ++ww) {
+                st += red[0][ww][r];
+                ss += red[ONE ? 1 : 0][ww][r];
+            }
+    } else {
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) red[w][lane + 64 * t] = as[t];
-    __syncthreads();
+        for (int t = 0; t < RPL; ++t) red[0][w][lane + 64 * t] = at[t];
+        __syncthreads();
+        if (r < 64 * rpl)
+            for (int ww = 0; ww < GS_WAVES; ++ww) st += red[0][ww][r];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) red[0][w][lane + 64 * t] = as[t];
+        __syncthreads();
+        if (r < 64 * rpl)
+            for (int ww = 0; ww < GS_WAVES; ++ww) ss += red[0][ww][r];
+    }
     if (r < 64 * rpl) {
         const int64_t i = base + r;
-        for (int ww = 0; ww < GS_WAVES; ++ww) ss += red[ww][r];
         if (i < m) {
             LPK_GLOBAL double* __restrict__ vk = to_global(in.V + (int64_t)kk * in.ldv);
             LPK_GLOBAL double* __restrict__ u = to_global(in.vec[V_U]);
