@@ -433,6 +433,10 @@ def _mix_roofline(lps, precision, width, args=None):
     for name, cls in per_iter.items():
         t = lpk.lp_time_batch_kernel(probs, cls, reps=20)
         k = t["launches_per_group"]   # the class's launches in one Krylov iteration
+        if k == 0:
+            # the product u = A_hat z_k of LPs whose one-block sweep forms it: no launch
+            print(f"  {name}: no launches (formed inside the sweep)", file=sys.stderr, flush=True)
+            continue
         gbs = t["bytes_per_launch"] / (t["us_per_launch"] * 1e-6) / 1e9
         classes[name] = {"us_per_launch": t["us_per_launch"], "bytes_per_launch": t["bytes_per_launch"],
                          "launches_per_iteration": k, "us_per_iteration": k * t["us_per_launch"], "gbs": gbs,

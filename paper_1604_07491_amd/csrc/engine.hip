@@ -253,6 +253,8 @@ static Inst make_inst(Batch& B, int slot) {
     // FP64 NE-SOR / NE-SSOR sweeps leave z_k = A_hat^T p_k for the product that follows
     // (BA-GMRES has no such product: its sweeps end the iteration's operator)
     in.keepz = (!mixed && sor && !p->gsor && p->opt.krylov != LP_BAGMRES) ? 1 : 0;
+    // AB-GMRES with an FP64 one-block sweep: the sweep also forms u = A_hat z_k
+    in.fuse_u = (in.keepz && in.lds != 0 && p->opt.krylov == LP_ABGMRES) ? 1 : 0;
     return in;
 }
 
@@ -261,7 +263,7 @@ static bool same_launch(const BLaunch& a, const BLaunch& b, const std::vector<in
     if (a.S != b.S || a.max_m != b.max_m || a.max_n != b.max_n || a.max_nbr != b.max_nbr ||
         a.max_nbs != b.max_nbs || a.max_ldp != b.max_ldp || a.gs_rpl != b.gs_rpl ||
         a.gs_nchunks != b.gs_nchunks || a.gs_fused != b.gs_fused || a.gs_dots_grid != b.gs_dots_grid || a.any32 != b.any32 ||
-        a.any64 != b.any64 || a.any_nokeep != b.any_nokeep ||
+        a.any64 != b.any64 || a.any_nokeep != b.any_nokeep || a.any_fuse != b.any_fuse || a.all_fuse != b.all_fuse ||
         a.inner != b.inner || a.ell != b.ell || a.krylov != b.krylov || a.max_ncol != b.max_ncol ||
         a.need_prep != b.need_prep ||
         a.any_lds != b.any_lds || a.lds_bytes != b.lds_bytes || a.any_stage != b.any_stage ||
@@ -297,6 +299,8 @@ lp_status Batch::refresh() {
     L.any_stage = false;
     L.stage_bytes = 0;
     L.max_ncol_global = 0;
+    L.any_fuse = false;
+    L.all_fuse = true;
     bool first = true;
     for (int s = 0; s < cap; ++s) {
         h_inst[s] = make_inst(*this, s);
@@ -314,6 +318,8 @@ lp_status Batch::refresh() {
         L.any32 = L.any32 || in.fp32;
         L.any64 = L.any64 || !in.fp32;
         L.any_nokeep = L.any_nokeep || !in.keepz;
+        L.any_fuse = L.any_fuse || in.fuse_u;
+        L.all_fuse = L.all_fuse && in.fuse_u;
         L.max_m = std::max(L.max_m, in.m);
         L.max_n = std::max(L.max_n, in.n);
         L.max_nbr = std::max(L.max_nbr, in.nbr);
@@ -442,6 +448,11 @@ static bool keeps_z(const lp_problem* p) {
     return !p->mixed && sor && !p->gsor && p->opt.krylov != LP_BAGMRES;
 }
 
+// the one-block sweep of p's AB-GMRES iterations also forms u = A_hat z_k (Inst::fuse_u)
+static bool fuses_u(const lp_problem* p) {
+    return keeps_z(p) && p->lds_kind != 0 && !p->colours.empty() && p->opt.krylov == LP_ABGMRES;
+}
+
 // ------------------------------------------------------------------------------------
 // Krylov iterations
 
@@ -449,7 +460,7 @@ static bool keeps_z(const lp_problem* p) {
 // flag from each instance's control block), with the start-of-iteration preparation.
 // pmask > 0 (the start of a BA-GMRES solve, NE-SOR / NE-SSOR only): the instances whose
 // mode has a bit of pmask, whatever their control blocks say
-static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0) {
+static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0, int fuse = 0) {
     const BLaunch& L = B.L;
     // bytes of one A_hat value / z entry in the sweeps of p
     auto sv = [](const lp_problem* p) { return p->mixed ? 4.0 : 8.0; };
@@ -490,11 +501,13 @@ static void enqueue_precond(Batch& B, int64_t it, bool with_prep, int pmask = 0)
             const double by = over_members(B, [&](const lp_problem* p) {
                 const int kd = lds_kind(p);
                 if (kd == 0) return 0.0;
+                // with the product fused: u written, and the rows read once more unless staged
+                const double fu = (fuse && fuses_u(p)) ? 8.0 * p->m + (kd == 2 ? 0.0 : p->nnz * (sv(p) + 4.0)) : 0.0;
                 return (kd == 2 ? 1 : npass) * p->nnz * (sv(p) + 4.0) + (p->m + 1) * 4.0 + (double)p->m * (8.0 + 16.0) +
-                       (keeps_z(p) ? 8.0 * p->n : 0.0);
+                       (keeps_z(p) ? 8.0 * p->n : 0.0) + fu;
             });
             Prof pr(&B, LP_K_SWEEP, it, by);
-            b_sweep_lds(L, npass, ssor ? 1 : 0, pmask);
+            b_sweep_lds(L, npass, ssor ? 1 : 0, pmask, fuse);
         }
         for (int sw = 0; sw < npass; ++sw) {
             const int dir = ssor ? (sw & 1) : 0;
@@ -534,11 +547,13 @@ static void enqueue_products(Batch& B, int64_t it) {
         return;
     }
     // outer operator in FP64: z_k = A_hat^T p_k (left by the FP64 sweeps, else by a
-    // product with the CSC copy), u = A_hat z_k
+    // product with the CSC copy), u = A_hat z_k (formed by the one-block sweep itself for
+    // the instances with Inst::fuse_u: no launch when every instance has it)
     enqueue_zk(B, it);
+    if (L.all_fuse) return;
     {
-        Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, csr_bytes));
-        b_spmv(L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
+        Prof pr(&B, LP_K_SPMV_CSR, it, over_members(B, [](const lp_problem* p) { return fuses_u(p) ? 0.0 : csr_bytes(p); }));
+        b_spmv(L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, L.any_fuse ? PM_NOFUSE : 0, false);
     }
 }
 
@@ -688,7 +703,7 @@ static void enqueue_iteration(Batch& B, int64_t it) {
         enqueue_cg_iteration(B, it);
         return;
     }
-    enqueue_precond(B, it, true);
+    enqueue_precond(B, it, true, 0, 1);
     enqueue_products(B, it);
     // delayed CGS2 + Givens; the host iteration index equals the device one while the solve runs
     enqueue_dgs(B, it, GS_DOTS | GS_UPDATES | GS_FINISH);
@@ -1609,6 +1624,14 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
         }
         B.h_slot[s].ctl = t;
     }
+    if (cls == LP_K_SPMV_CSR && B.L.inner != 3 && B.L.all_fuse) {
+        // every instance's sweep forms u itself: this class has no launch
+        *us_per_launch = 0.0;
+        if (bytes_per_launch) *bytes_per_launch = 0.0;
+        if (flops_per_launch) *flops_per_launch = 0.0;
+        if (launches_per_group) *launches_per_group = 0;
+        return LP_OK;
+    }
     hipStream_t st = B.st;
     LPK_HIP(hipMemcpyAsync(B.d_slot, B.h_slot, sizeof(Slot) * B.cap, hipMemcpyHostToDevice, st));
     LPK_HIP(hipStreamSynchronize(st));
@@ -1626,7 +1649,8 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
     hipError_t e = hipStreamBeginCapture(B.cap_st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         if (cls == LP_K_SWEEP) {
-            enqueue_precond(B, -1, false);
+            // as the AB-GMRES iteration launches it (with the product where fused)
+            enqueue_precond(B, -1, false, 0, (B.L.krylov == LP_ABGMRES && !B.L.ba) ? 1 : 0);
         } else if (gs) {
             if (B.L.ba) enqueue_gs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
             else enqueue_dgs(B, kg, cls == LP_K_GS_DOTS ? GS_DOTS : GS_UPDATES);
@@ -1638,9 +1662,11 @@ static lp_status time_kernel(Batch& B, int32_t cls, int32_t reps, double* us_per
         } else if (cls == LP_K_SPMV_CSR) {
             if (B.L.inner == 3) {
                 enqueue_products(B, -1);   // the dense path's only product, u = G p_k
-            } else {
-                Prof pr(&B, LP_K_SPMV_CSR, -1, over_members(B, csr_bytes));
-                b_spmv(B.L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, 0, false);
+            } else if (!B.L.all_fuse) {
+                // the instances whose sweep does not form u itself
+                Prof pr(&B, LP_K_SPMV_CSR, -1,
+                        over_members(B, [](const lp_problem* p) { return fuses_u(p) ? 0.0 : csr_bytes(p); }));
+                b_spmv(B.L, M_AH_CSR, V_Z64, V_U, EPI_PLAIN, -1, -1, B.L.any_fuse ? PM_NOFUSE : 0, false);
             }
         } else {
             for (int s = 0; s < B.cap; ++s)

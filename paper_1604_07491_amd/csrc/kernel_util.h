@@ -132,6 +132,7 @@ __device__ __forceinline__ bool takes_part(const Inst& in, int pmask) {
     const LPK_GLOBAL KrylovCtl* ctl = to_global(in.ctl);
     if (pmask == PM_ITER_DIR) return ctl->done == 0 && ctl->cg_phase != 0;
     if (pmask == PM_NOKEEP) return ctl->done == 0 && in.keepz == 0;
+    if (pmask == PM_NOFUSE) return ctl->done == 0 && in.fuse_u == 0;
     return ctl->done == 0;   // 0: Krylov loop, still iterating
 }
 

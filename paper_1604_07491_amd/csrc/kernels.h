@@ -65,6 +65,9 @@ constexpr int PM_ITER_DIR = -1;
 // pmask of the product z_k = A_hat^T p_k in the Krylov loop: the instances still iterating
 // whose sweeps do not leave z_k themselves (Inst::keepz == 0)
 constexpr int PM_NOKEEP = -2;
+// pmask: the instances inside a solve whose one-block sweep does not also form u = A_hat z_k
+// (Inst::fuse_u 0)
+constexpr int PM_NOFUSE = -3;
 
 // matrices of an instance for the row-dot products
 enum MatSel : int { M_A_CSR = 0, M_A_CSC = 1, M_AH_CSR = 2, M_AH_CSC = 3 };
@@ -145,6 +148,8 @@ struct Inst {
     int32_t ncrow;                        // their number
     int32_t keepz;                        // 1: FP64 NE-SOR / NE-SSOR sweeps leave z_k = A_hat^T p_k
                                           // in V_Z64 (no product with A_hat^T in the loop)
+    int32_t fuse_u;                       // 1: the one-block sweep of an AB-GMRES iteration also
+                                          // forms u = A_hat z_k into V_U (no product launch)
 };
 
 #ifndef LPK_SL_GROUPS
@@ -169,6 +174,7 @@ struct BLaunch {
     bool any32, any64;      // some instance sweeps in FP32 / in FP64 (Inst::fp32); a launch of
                             // either precision skips the instances of the other
     bool any_nokeep;        // some instance needs z_k = A_hat^T p_k from a product (Inst::keepz 0)
+    bool any_fuse, all_fuse;// some / every instance forms u = A_hat z_k in its sweep (Inst::fuse_u)
     int inner;              // lp_inner of every instance (NE-SOR, Cimmino, NE-SSOR) or 3: dense SOR
     int ell;                // inner sweeps per preconditioner application
     int krylov;             // lp_krylov of every instance (0 AB-GMRES, 1 CGNE, 2 MRNE)
@@ -232,7 +238,7 @@ void b_prep(const BLaunch& L, int pmask);
 void b_nesor(const BLaunch& L, int colour, int pass, int npass, int dir, int pmask);
 // every colour of every pass, one block per instance (ssor: passes alternate direction);
 // staged: the instances with Inst::lds == 2 (row data in LDS), else those with lds == 1
-void b_sweep_lds(const BLaunch& L, int npass, int ssor, int pmask);   // every LDS-resident instance
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, int pmask, int fuse = 0);   // every LDS-resident instance
 void b_cim_res(const BLaunch& L, int first);
 void b_cim_z(const BLaunch& L, int first);
 // classical Gram-Schmidt, pass 0 and 1: dot partials, (reduce,) update u -= V h

@@ -58,7 +58,8 @@ __device__ __forceinline__ T sg_sum_lds(T v, int g) {
 }
 
 template <typename T, bool STAGED>
-__device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* lds_raw, int npass, int ssor, int ba) {
+__device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* lds_raw, int npass, int ssor, int ba,
+                                               int fuse) {
     const int m = in.m, n = in.n, nnz = in.nnz, ncol = in.ncol;
     const int keepz = in.keepz;
     const int tid = threadIdx.x;
@@ -204,32 +205,67 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
         double* __restrict__ zo = in.vec[V_Z64];
         for (int j = tid; j < n; j += NT) zo[j] = (double)z[j];
     }
+    // AB-GMRES: u = A_hat z_k from the z this block holds, one row per thread, the row's
+    // elements in index order (z is complete: keepz), instead of a product launch
+    if (fuse && in.fuse_u) {
+        LPK_GLOBAL double* __restrict__ uo = to_global(in.vec[V_U]);
+        for (int row = tid; row < m; row += NT) {
+            const int s = srp[row], e = srp[row + 1];
+            double acc = 0.0;
+            int kk = s;
+            // eight elements' loads, then their gathers, then the products in index order
+            for (; kk + 8 <= e; kk += 8) {
+                T a[8], zv[8];
+                int jj[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if constexpr (STAGED) {
+                        a[q] = sv[kk + q];
+                        jj[q] = si[kk + q];
+                    } else {
+                        a[q] = gval[kk + q];
+                        jj[q] = gci[kk + q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) zv[q] = z[jj[q]];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc += (double)a[q] * (double)zv[q];
+            }
+            for (; kk < e; ++kk) {
+                if constexpr (STAGED) acc += (double)sv[kk] * (double)z[si[kk]];
+                else acc += (double)gval[kk] * (double)z[gci[kk]];
+            }
+            uo[row] = acc;
+        }
+    }
 }
 
 // One launch serves every instance that sweeps from LDS, whatever its mode (STAGED or
 // streamed) and precision: the branch is uniform per block, and separate launches per kind
 // would run one after the other, each as long as its largest instance.
-__global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int pmask, int ba) {
+__global__ __launch_bounds__(NT) void k_sweep_lds(const Inst* __restrict__ I, int npass, int ssor, int pmask, int ba,
+                                                  int fuse) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     INST;
     if (!takes_part(in, pmask) || in.lds == 0) return;
     if (in.fp32) {
-        if (in.lds == 2) sweep_lds_body<float, true>(in, lds_raw, npass, ssor, ba);
-        else sweep_lds_body<float, false>(in, lds_raw, npass, ssor, ba);
+        if (in.lds == 2) sweep_lds_body<float, true>(in, lds_raw, npass, ssor, ba, fuse);
+        else sweep_lds_body<float, false>(in, lds_raw, npass, ssor, ba, fuse);
     } else {
-        if (in.lds == 2) sweep_lds_body<double, true>(in, lds_raw, npass, ssor, ba);
-        else sweep_lds_body<double, false>(in, lds_raw, npass, ssor, ba);
+        if (in.lds == 2) sweep_lds_body<double, true>(in, lds_raw, npass, ssor, ba, fuse);
+        else sweep_lds_body<double, false>(in, lds_raw, npass, ssor, ba, fuse);
     }
 }
 
-void b_sweep_lds(const BLaunch& L, int npass, int ssor, int pmask) {
+void b_sweep_lds(const BLaunch& L, int npass, int ssor, int pmask, int fuse) {
     // LDS beyond 64 KiB per block is asked for once (gfx950: 160 KiB)
     static bool big_lds = false;
     if (!big_lds)
         big_lds = hipFuncSetAttribute((const void*)k_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BLOCK_MAX) ==
                   hipSuccess;
     const int by = std::max(L.stage_bytes, L.lds_bytes);
-    hipLaunchKernelGGL(k_sweep_lds, dim3(1, L.S), dim3(NT), by, L.st, L.I, npass, ssor, pmask, L.ba ? 1 : 0);
+    hipLaunchKernelGGL(k_sweep_lds, dim3(1, L.S), dim3(NT), by, L.st, L.I, npass, ssor, pmask, L.ba ? 1 : 0, fuse);
 }
 
 }  // namespace lpk
