@@ -455,8 +455,9 @@ def _mix_roofline(lps, precision, width, args=None):
                 "bytes_per_launch": c["bytes_per_launch"], "lps_per_launch": len(probs),
                 "timing": "lp_time_batch_kernel replay, 20 x group, HIP events on the library stream"}
     if dom == "sweep":
-        roofline["note"] = ("one workgroup per LP sweeps every colour with block barriers between them: a "
-                            "chain of 2 x colours dependent steps of 1.2-2 us, bound by latency, not bandwidth")
+        roofline["note"] = ("one workgroup per LP sweeps every colour with block barriers between them (a "
+                            "chain of 2 x colours dependent steps of 1-2 us, bound by latency, not bandwidth), "
+                            "then forms u = A_hat z_k from its z for AB-GMRES")
     kinds = {k: sum(1 for _, kk in layouts if kk == k) for k in (0, 1, 2)}
     return roofline, classes, {"fp32_sweeps": sum(f for f, _ in layouts), "staged_in_lds": kinds[2],
                                "z_in_lds_rows_from_memory": kinds[1], "colour_by_colour": kinds[0]}
