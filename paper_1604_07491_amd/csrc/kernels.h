@@ -211,6 +211,8 @@ inline int64_t lds_z_bytes(int64_t m, int64_t n, int64_t ncol, int tbytes) {
 // when the rows are read from memory (each round is one dependent load step)
 constexpr int LDS_SWEEP_THREADS = 1024;
 constexpr int LDS_ROUNDS_MAX = 4;
+// element slots per lane held in registers by the one-block sweep
+constexpr int LDS_SLOTS = 16;
 inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, int tbytes) {
     return 16 * ncol + 16 * m + nnz * (tbytes + 4) + (n + 1) * tbytes + 4 * (m + 1);
 }

@@ -42,19 +42,96 @@ __device__ __forceinline__ float dpp_move(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+// v + (v of lane ^ 16) and v + (v of lane ^ 32) for every lane, by the gfx950 lane swaps:
+// permlane16_swap(x, x) returns, in every lane, the even row's and the odd row's x of its
+// pair of 16-lane rows, and permlane32_swap(x, x) the lower and the upper half's x of its
+// lane (a 32-bit swap, applied to both halves of a double); their sum is the butterfly
+// step's sum (addition commutes), with no LDS round trip.
+__device__ __forceinline__ double xor16_add(double v) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ float xor16_add(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor32_add(double v) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ float xor32_add(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // sum over the g consecutive lanes of a row (g a power of two, the row's lanes all
 // active).  Inside 16 lanes the partners come from DPP moves: quad_perm [1,0,3,2] and
 // [2,3,0,1] (xor 1, xor 2), then the half-row and row mirrors, whose partners hold the
-// same partial sums as the xor-4 and xor-8 partners; so the result is bitwise that of the
-// xor butterfly, without an LDS round trip per step.  Wider rows finish with shuffles.
+// same partial sums as the xor-4 and xor-8 partners; rows of 32 and 64 lanes finish with
+// the lane swaps (xor 16, xor 32).  So the result is bitwise that of the xor butterfly,
+// without an LDS round trip.
 template <typename T>
 __device__ __forceinline__ T sg_sum_lds(T v, int g) {
     if (g >= 2) v += dpp_move<0xB1>(v);
     if (g >= 4) v += dpp_move<0x4E>(v);
     if (g >= 8) v += dpp_move<0x141>(v);
     if (g >= 16) v += dpp_move<0x140>(v);
-    for (int o = 16; o < g; o <<= 1) v += __shfl_xor(v, o, g);
+    if (g >= 32) v = xor16_add(v);
+    if (g >= 64) v = xor32_add(v);
     return v;
+}
+
+// One row of a colour whose longest row needs at most S element slots per lane (S a
+// compile-time count, so the loads are straight-line code with no branch between them):
+// the row's values and indices are loaded together, then its z values; those are kept
+// for the update: no other row of the colour touches these columns, so they are still
+// current.  A slot past the row's end loads the row's last element (rows are never
+// empty), counts as 0, and stores to z[n]; the zero terms leave acc unchanged (it starts
+// at +0 and never becomes -0), so the result does not depend on S beyond the row's need.
+// Returns the row's delta.
+template <typename T, bool STAGED, int S>
+__device__ __forceinline__ T row_step(const T* sv, const int32_t* si, const LPK_GLOBAL T* __restrict__ gval,
+                                      const LPK_GLOBAL int32_t* __restrict__ gci, T* z, int n, int s, int e,
+                                      int lane, int g, T om, double vrow, bool write_z) {
+    T a[S], zv[S];
+    int jj[S];
+    bool ok[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const int kk = s + lane + t * g;
+        ok[t] = kk < e;
+        const int kc = ok[t] ? kk : e - 1;
+        if constexpr (STAGED) {
+            a[t] = sv[kc];
+            jj[t] = si[kc];
+        } else {
+            a[t] = gval[kc];
+            jj[t] = gci[kc];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        a[t] = ok[t] ? a[t] : (T)0;
+        const T zt = z[jj[t]];
+        zv[t] = ok[t] ? zt : (T)0;
+    }
+    T acc = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc += a[t] * zv[t];
+    acc = sg_sum_lds(acc, g);
+    const T delta = om * ((T)vrow - acc);
+    if (write_z) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) z[ok[t] ? jj[t] : n] = zv[t] + delta * a[t];
+    }
+    return delta;
+}
+
+// the slot counts compiled: a colour's count is rounded up to the next of these
+__host__ __device__ constexpr int slot_class(int slots) {
+    return slots <= 4 ? slots : slots <= 6 ? 6 : slots <= 8 ? 8 : slots <= 12 ? 12 : slots <= 16 ? 16 : slots;
 }
 
 template <typename T, bool STAGED>
@@ -96,29 +173,32 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     __syncthreads();
     // The colour table.  A colour whose rows fit in one wave (rows x lanes <= 64) runs on
     // wave 0 alone, and a run of such colours needs no block barrier: the LDS accesses of
-    // one wave complete in program order.  Each colour also records its slots per lane, the
-    // element slots its longest row needs (ceil(longest / g), at most R in the slot path).
+    // one wave complete in program order.  Each colour also records its slots per lane: the
+    // element slots its longest row needs, ceil(longest / g), rounded up to a compiled count
+    // (slot_class); a colour needing more than R takes the element loop instead.
     for (int c = tid; c < ncol; c += NT) {
         const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
         const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
         int longest = 0;
         for (int r = r0; r < r1; ++r) longest = max(longest, srp[r + 1] - srp[r]);
-        const int slots = (longest + g - 1) / g;
+        const int slots = slot_class((longest + g - 1) / g);
         ctab[c] = make_int4(r0, r1, g, ((r1 - r0) * g <= 64 ? 1 : 0) | (slots << 1));
     }
     __syncthreads();
     const T om = (T)in.omega;
-    constexpr int R = 8;
+    constexpr int R = LDS_SLOTS;
     // A barrier precedes a whole-block colour that follows wave-0 colours and ends every
     // whole-block colour.
     bool prev_small = false;
     for (int sw = 0; sw < npass; ++sw) {
         const int dir = ssor ? (sw & 1) : 0;
         for (int cc = 0; cc < ncol; ++cc) {
+            // the colour's entry is the same in every lane: scalar registers, scalar branches
             const int4 ct = ctab[dir ? ncol - 1 - cc : cc];
-            const int r0 = ct.x, r1 = ct.y, g = ct.z;
-            const bool small = (ct.w & 1) != 0;
-            const int slots = ct.w >> 1;   // element slots per lane of the colour's longest row
+            const int r0 = __builtin_amdgcn_readfirstlane(ct.x), r1 = __builtin_amdgcn_readfirstlane(ct.y);
+            const int g = __builtin_amdgcn_readfirstlane(ct.z), cw = __builtin_amdgcn_readfirstlane(ct.w);
+            const bool small = (cw & 1) != 0;
+            const int slots = cw >> 1;   // element slots per lane of the colour's longest row
             const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
             const int lane = tid & (g - 1);
             const int lg = __builtin_ctz(g);   // g is a power of two
@@ -131,51 +211,15 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
                 const double vrow = vl[row];
                 const int s = srp[row], e = srp[row + 1];
                 T acc = 0, delta;
-                if (e - s <= g * R) {
-                    // the row's values and indices are loaded together, then its z values;
-                    // those are kept for the update: no other row of the colour touches
-                    // these columns, so they are still current.  The colour's slot count is
-                    // uniform over the block, so slots past it are skipped by a scalar branch;
-                    // inside it, a slot past the row's end loads the row's last element
-                    // (rows are never empty), counts as 0, and stores to z[n].  Skipping the
-                    // zero terms leaves acc unchanged (it starts at +0 and never becomes -0).
-                    T a[R], zv[R];
-                    int jj[R];
-                    bool ok[R];
-#pragma unroll
-                    for (int t = 0; t < R; ++t) {
-                        if (t >= slots) break;
-                        const int kk = s + lane + t * g;
-                        ok[t] = kk < e;
-                        const int kc = ok[t] ? kk : e - 1;
-                        if constexpr (STAGED) {
-                            a[t] = sv[kc];
-                            jj[t] = si[kc];
-                        } else {
-                            a[t] = gval[kc];
-                            jj[t] = gci[kc];
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < R; ++t) {
-                        if (t >= slots) break;
-                        a[t] = ok[t] ? a[t] : (T)0;
-                        const T zt = z[jj[t]];
-                        zv[t] = ok[t] ? zt : (T)0;
-                    }
-#pragma unroll
-                    for (int t = 0; t < R; ++t) {
-                        if (t >= slots) break;
-                        acc += a[t] * zv[t];
-                    }
-                    acc = sg_sum_lds(acc, g);
-                    delta = om * ((T)vrow - acc);
-                    if (write_z) {
-#pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            if (t >= slots) break;
-                            z[ok[t] ? jj[t] : n] = zv[t] + delta * a[t];
-                        }
+                if (slots <= R) {
+                    switch (slots) {
+#define LPK_RS(S_)                                                                                    \
+    case S_:                                                                                          \
+        delta = row_step<T, STAGED, S_>(sv, si, gval, gci, z, n, s, e, lane, g, om, vrow, write_z != 0); \
+        break;
+                        LPK_RS(1) LPK_RS(2) LPK_RS(3) LPK_RS(4) LPK_RS(6) LPK_RS(8) LPK_RS(12) LPK_RS(16)
+#undef LPK_RS
+                        default: delta = 0; break;
                     }
                 } else {
                     for (int kk = s + lane; kk < e; kk += g) {
