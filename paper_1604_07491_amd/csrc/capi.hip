@@ -75,8 +75,8 @@ bool fp32_sweeps(const lp_options& o, bool gsor, int kind64, int kind32) {
 int sweep_kind(int64_t m, int64_t n, int64_t nnz, const std::vector<Colour>& cols, int tb) {
     const int64_t nc = (int64_t)cols.size();
     if (nc == 0) return 0;
-    if (lds_stage_bytes(m, n, nnz, nc, tb) <= LDS_STAGE_MAX) return 2;
-    if (lds_z_bytes(m, n, nc, tb) > LDS_Z_MAX) return 0;
+    if (lds_stage_bytes(m, n, nnz, tb) <= LDS_STAGE_MAX) return 2;
+    if (lds_z_bytes(m, n, tb) > LDS_Z_MAX) return 0;
     for (const Colour& C : cols) {
         const int64_t rounds = ((int64_t)(C.r1 - C.r0) * C.g + LDS_SWEEP_THREADS - 1) / LDS_SWEEP_THREADS;
         if (rounds > LDS_ROUNDS_MAX || C.maxlen > 8 * C.g) return 0;
@@ -90,7 +90,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     // as many colours as rows still fits) run in FP64 from LDS: no FP32 copies, no row
     // slices.  Otherwise LP_MIXED may keep FP32 copies and the sweeps may need slices.
     const bool sor = o.inner == LP_NESOR || o.inner == LP_NESSOR;
-    const bool staged64 = sor && lds_stage_bytes(m, n, nnz, m, 8) <= LDS_STAGE_MAX;
+    const bool staged64 = sor && lds_stage_bytes(m, n, nnz, 8) <= LDS_STAGE_MAX;
     const bool mixed = o.precision == LP_MIXED && !staged64;
     const int64_t kmax = plan_kmax(m, o);
     const int64_t cols = basis_cols(kmax, o), pcols = mult_cols(kmax, o);
@@ -101,6 +101,7 @@ uint64_t footprint(int64_t m, int64_t n, int64_t nnz, const lp_options& o) {
     if (mixed) { z.add(nnz, 4); z.add(nnz, 4); }
     z.add(m, 4);                                  // permutation
     z.add(m + 1, 4); z.add(m, 4);                 // colour ranges and lanes (at most m colours)
+    z.add(4 * m, 4);                              // the one-block sweep's colour table
     if (sor && !staged64) {
         // row slices: at most 5/4 of the nonzeros with columns and values (FP32 copy in
         // mixed precision); slice starts of the colours, slice offsets and lengths, row
@@ -455,6 +456,7 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     p->perm_d = A.alloc<int32_t>(m);
     p->cstart = A.alloc<int32_t>((int64_t)p->colours.size() + 1);
     p->cg = A.alloc<int32_t>((int64_t)p->colours.size());
+    if (p->lds_kind != 0) p->ctab = A.alloc<int32_t>(4 * (int64_t)p->colours.size());
     if (!h_cslice.empty()) {
         p->cslice = A.alloc<int32_t>((int64_t)h_cslice.size());
         p->soff = A.alloc<int32_t>((int64_t)h_soff.size());
@@ -518,6 +520,19 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
         p->h_cg[cl] = p->colours[cl].il ? -p->colours[cl].g : p->colours[cl].g;
     }
     p->h_cstart[p->colours.size()] = (int32_t)m;
+    if (p->ctab) {
+        std::vector<int32_t>& h_ctab = p->h_ctab;
+        h_ctab.assign(4 * p->colours.size(), 0);
+        for (size_t cl = 0; cl < p->colours.size(); ++cl) {
+            const Colour& C = p->colours[cl];
+            const int slots = slot_class((C.maxlen + C.g - 1) / C.g);
+            h_ctab[4 * cl] = C.r0;
+            h_ctab[4 * cl + 1] = C.r1;
+            h_ctab[4 * cl + 2] = C.g;
+            h_ctab[4 * cl + 3] = ((int64_t)(C.r1 - C.r0) * C.g <= 64 ? 1 : 0) | (slots << 1);
+        }
+        LPK_HIP(hipMemcpyAsync(p->ctab, h_ctab.data(), sizeof(int32_t) * h_ctab.size(), hipMemcpyHostToDevice, st));
+    }
     LPK_HIP(hipMemcpyAsync(p->cstart, p->h_cstart.data(), sizeof(int32_t) * p->h_cstart.size(), hipMemcpyHostToDevice, st));
     if (!p->h_cg.empty())
         LPK_HIP(hipMemcpyAsync(p->cg, p->h_cg.data(), sizeof(int32_t) * p->h_cg.size(), hipMemcpyHostToDevice, st));

@@ -212,6 +212,7 @@ static Inst make_inst(Batch& B, int slot) {
     in.ri = p->ri;
     in.cstart = p->cstart;
     in.cg = p->cg;
+    in.ctab = p->ctab;
     in.cslice = p->cslice;
     in.soff = p->soff;
     in.slen = p->slen;
@@ -347,10 +348,10 @@ lp_status Batch::refresh() {
         L.max_fpairs = std::max(L.max_fpairs, in.nfpairs);
         if (in.lds == 2) {
             L.any_stage = true;
-            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.ncol, in.fp32 ? 4 : 8));
+            L.stage_bytes = std::max<int>(L.stage_bytes, (int)lds_stage_bytes(in.m, in.n, in.nnz, in.fp32 ? 4 : 8));
         } else if (in.lds) {
             L.any_lds = true;
-            L.lds_bytes = std::max<int>(L.lds_bytes, (int)lds_z_bytes(in.m, in.n, in.ncol, in.fp32 ? 4 : 8));
+            L.lds_bytes = std::max<int>(L.lds_bytes, (int)lds_z_bytes(in.m, in.n, in.fp32 ? 4 : 8));
         } else {
             L.max_ncol_global = std::max(L.max_ncol_global, in.ncol);
             L.need_prep = L.need_prep || (in.ncol > 0 && !in.zcover);

@@ -115,6 +115,7 @@ struct Inst {
     int64_t ldv, ldh, ldp, kmax;
     const int32_t *rp, *ci, *cp, *ri;     // CSR and CSC of the row-permuted A
     const int32_t *cstart, *cg;           // colour row ranges (ncol+1), lanes per row by colour
+    const int32_t* ctab;                  // one-block sweep: colour table (4 ints per colour)
     const double *a, *ac;                 // A values (CSR, CSC)
     double *ah, *ahc;                     // A_hat values (CSR, CSC)
     float *ah32, *ahc32;                  // FP32 copies (mixed precision)
@@ -204,8 +205,8 @@ constexpr int LDS_BLOCK_MAX = 160 * 1024;
 constexpr int LDS_Z_MAX = LDS_BLOCK_MAX;
 constexpr int LDS_STAGE_MAX = LDS_BLOCK_MAX;
 // LDS of the one-block sweep: z with the colour table, and (staged) everything
-inline int64_t lds_z_bytes(int64_t m, int64_t n, int64_t ncol, int tbytes) {
-    return 16 * ncol + 16 * m + (n + 1) * tbytes + 4 * (m + 1);
+inline int64_t lds_z_bytes(int64_t m, int64_t n, int tbytes) {
+    return 16 * m + (n + 1) * tbytes + 4 * (m + 1);
 }
 // threads of the one-block sweep, and the most rounds of them a colour's rows may take
 // when the rows are read from memory (each round is one dependent load step)
@@ -213,8 +214,16 @@ constexpr int LDS_SWEEP_THREADS = 1024;
 constexpr int LDS_ROUNDS_MAX = 4;
 // element slots per lane held in registers by the one-block sweep
 constexpr int LDS_SLOTS = 16;
-inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int64_t ncol, int tbytes) {
-    return 16 * ncol + 16 * m + nnz * (tbytes + 4) + (n + 1) * tbytes + 4 * (m + 1);
+inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int tbytes) {
+    return 16 * m + nnz * (tbytes + 4) + (n + 1) * tbytes + 4 * (m + 1);
+}
+// The one-block sweep's colour table, four ints per colour in device memory, read by
+// scalar loads: first and last row, lanes per row g, and (bit 0) whether the colour runs
+// on wave 0 alone (rows x g <= 64) with (bits 1..) the element slots per lane its longest
+// row needs, ceil(longest / g), rounded up to a count the kernel compiles (slot_class); a
+// colour needing more than LDS_SLOTS takes the element loop.
+__host__ __device__ constexpr int slot_class(int slots) {
+    return slots <= 4 ? slots : slots <= 6 ? 6 : slots <= 8 ? 8 : slots <= 12 ? 12 : slots <= 16 ? 16 : slots;
 }
 
 // ---- row-dot products (CSR A x, CSC A^T y) --------------------------------------------

@@ -138,7 +138,7 @@ struct lp_problem {
     // host-side structure
     std::vector<int32_t> perm;        // permuted row t is original row perm[t]
     std::vector<lpk::Colour> colours;
-    std::vector<int32_t> h_cstart, h_cg;
+    std::vector<int32_t> h_cstart, h_cg, h_ctab;
     int g_csr = 64, g_csc = 1;
     int rpl = 1, nchunks = 1;
     bool zcover = false;                            // colour 0 covers every column
@@ -147,6 +147,7 @@ struct lp_problem {
     // structure and data (permuted rows)
     int32_t *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr, *perm_d = nullptr;
     int32_t *cstart = nullptr, *cg = nullptr;
+    int32_t* ctab = nullptr;                        // one-block sweep colour table (lds_kind != 0)
     int32_t *cslice = nullptr, *soff = nullptr, *slen = nullptr, *rsl = nullptr, *sl_idx = nullptr, *srows = nullptr;
     int32_t nsl = 0;                                // slices over all colours
     int32_t* crow = nullptr;                        // rows not in slices

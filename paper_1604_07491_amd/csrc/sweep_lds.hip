@@ -14,9 +14,8 @@ namespace lpk {
 // A whole NE-SOR or NE-SSOR application (every pass over every colour) for instances
 // whose z fits in LDS: one block of NT = 1024 threads per instance, z zeroed and kept in
 // LDS, a block barrier between colours instead of a kernel launch.  v_k (formed from u at
-// the start), the multipliers p_k, the row pointers and a table of the colours (first and
-// last row, lanes per row, and whether the colour runs on wave 0 alone) sit in LDS too;
-// v_k and p_k are written back at the end.  STAGED (Inst::lds == 2): the row values and
+// the start), the multipliers p_k and the row pointers sit in LDS too; the colour table
+// (Inst::ctab) is read from device memory by scalar loads.  v_k and p_k are written back at the end.  STAGED (Inst::lds == 2): the row values and
 // column indices are copied into LDS as well, in one coalesced pass, so the colour steps,
 // each a dependent chain of loads, run on LDS alone; otherwise (Inst::lds == 1) they are
 // read from memory (the instance's rows stay in the L2 cache over the passes).  Each row
@@ -25,9 +24,10 @@ namespace lpk {
 // A_hat^T p_k).  ba (BA-GMRES): the input is V_U as it is, kept in V_R64, and the
 // multipliers go to V_U.  1024 threads per block measured as fast as 256 and twice as fast
 // as 64 on the 200 x 500 LPs.
-// LDS layout: colour table (ncol int4), p (m doubles), v (m doubles), [STAGED: values (nnz
-// T)], z (n + 1 T: entry n takes the stores of the lanes past a row's end), row pointers
-// (m + 1 ints), [STAGED: column indices (nnz ints)]: lds_stage_bytes / lds_z_bytes.
+// LDS layout: p (m doubles), v (m doubles), [STAGED: values (nnz T)], z (n + 1 T: entry n
+// takes the stores of the lanes past a row's end), row pointers (m + 1 ints), [STAGED:
+// column indices (nnz ints)]: lds_stage_bytes / lds_z_bytes.  The colour table (first and
+// last row, lanes per row, wave 0 alone, slots per lane) stays in device memory.
 constexpr int NT = LDS_SWEEP_THREADS;
 
 // one DPP lane move inside each row of 16 lanes (ctrl a quad_perm or row-mirror code)
@@ -129,11 +129,6 @@ __device__ __forceinline__ T row_step(const T* sv, const int32_t* si, const LPK_
     return delta;
 }
 
-// the slot counts compiled: a colour's count is rounded up to the next of these
-__host__ __device__ constexpr int slot_class(int slots) {
-    return slots <= 4 ? slots : slots <= 6 ? 6 : slots <= 8 ? 8 : slots <= 12 ? 12 : slots <= 16 ? 16 : slots;
-}
-
 template <typename T, bool STAGED>
 __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* lds_raw, int npass, int ssor, int ba,
                                                int fuse) {
@@ -151,8 +146,10 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     else gval = to_global((const T*)in.ah);
     const LPK_GLOBAL int32_t* __restrict__ gci = to_global(in.ci);
     const LPK_GLOBAL int32_t* __restrict__ grp = to_global(in.rp);
-    int4* ctab = reinterpret_cast<int4*>(lds_raw);     // per colour: r0, r1, g, wave-0 only
-    double* pl = reinterpret_cast<double*>(ctab + ncol);   // multipliers being accumulated
+    // the colour table (device memory, read-only): its entries are loaded by scalar loads
+    const __attribute__((address_space(4))) int32_t* __restrict__ ctab =
+        (const __attribute__((address_space(4))) int32_t*)in.ctab;
+    double* pl = reinterpret_cast<double*>(lds_raw);   // multipliers being accumulated
     double* vl = pl + m;                               // v_k
     T* sv = reinterpret_cast<T*>(vl + m);              // STAGED: the row values
     T* z = STAGED ? sv + nnz : sv;
@@ -171,20 +168,9 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     for (int t = tid; t < m; t += NT) vl[t] = u[t] * ih;
     for (int j = tid; j <= n; j += NT) z[j] = 0;
     __syncthreads();
-    // The colour table.  A colour whose rows fit in one wave (rows x lanes <= 64) runs on
-    // wave 0 alone, and a run of such colours needs no block barrier: the LDS accesses of
-    // one wave complete in program order.  Each colour also records its slots per lane: the
-    // element slots its longest row needs, ceil(longest / g), rounded up to a compiled count
-    // (slot_class); a colour needing more than R takes the element loop instead.
-    for (int c = tid; c < ncol; c += NT) {
-        const int r0 = in.cstart[c], r1 = in.cstart[c + 1];
-        const int g = in.cg[c] > 0 ? in.cg[c] : -in.cg[c];   // consecutive lanes here
-        int longest = 0;
-        for (int r = r0; r < r1; ++r) longest = max(longest, srp[r + 1] - srp[r]);
-        const int slots = slot_class((longest + g - 1) / g);
-        ctab[c] = make_int4(r0, r1, g, ((r1 - r0) * g <= 64 ? 1 : 0) | (slots << 1));
-    }
-    __syncthreads();
+    // A colour whose rows fit in one wave (rows x lanes <= 64) runs on wave 0 alone, and a
+    // run of such colours needs no block barrier: the LDS accesses of one wave complete in
+    // program order.
     const T om = (T)in.omega;
     constexpr int R = LDS_SLOTS;
     // A barrier precedes a whole-block colour that follows wave-0 colours and ends every
@@ -193,10 +179,9 @@ __device__ __forceinline__ void sweep_lds_body(const Inst& in, unsigned char* ld
     for (int sw = 0; sw < npass; ++sw) {
         const int dir = ssor ? (sw & 1) : 0;
         for (int cc = 0; cc < ncol; ++cc) {
-            // the colour's entry is the same in every lane: scalar registers, scalar branches
-            const int4 ct = ctab[dir ? ncol - 1 - cc : cc];
-            const int r0 = __builtin_amdgcn_readfirstlane(ct.x), r1 = __builtin_amdgcn_readfirstlane(ct.y);
-            const int g = __builtin_amdgcn_readfirstlane(ct.z), cw = __builtin_amdgcn_readfirstlane(ct.w);
+            // the colour's entry, uniform: scalar registers, scalar branches
+            const int c4 = 4 * (dir ? ncol - 1 - cc : cc);
+            const int r0 = ctab[c4], r1 = ctab[c4 + 1], g = ctab[c4 + 2], cw = ctab[c4 + 3];
             const bool small = (cw & 1) != 0;
             const int slots = cw >> 1;   // element slots per lane of the colour's longest row
             const int write_z = keepz || !(sw == npass - 1 && cc == ncol - 1);
