@@ -38,7 +38,31 @@ def _case(name):
         return synth.transport_lp(1100, 32, seed=10)
     if name == "ldsz":             # z in LDS, rows too many to stage there
         return synth.sparse_lp(300, 2000, 6, 2, seed=61)
+    if name == "rows32":           # one-block sweep, rows of about 24 elements: 32 lanes a row
+        return synth.sparse_lp(298, 900, 8, 2, seed=72)
+    if name == "rows64":           # about 40 elements a row: 64 lanes, sums over the whole wave
+        return synth.sparse_lp(298, 1200, 10, 2, seed=71)
+    if name == "slots12":          # a few long rows among short ones: 6 and 12 slots a lane
+        return _hetero_rows(5, 160, 640, 8, 96, 3)
+    if name == "slots16":          # 4, 8 and 16 slots a lane
+        return _hetero_rows(5, 200, 800, 6, 120, 3)
     raise ValueError(name)
+
+
+def _hetero_rows(seed, m, n, long_every, long_len, short_len):
+    """Rows of short_len elements with every long_every-th row long_len long, so that a
+    colour's longest row needs many element slots per lane at the lanes its mean length
+    gives; primal and dual feasible by construction."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((m, n))
+    for i in range(m):
+        L = long_len if i % long_every == 0 else short_len
+        cols = rng.choice(n, L, replace=False)
+        A[i, cols] = rng.standard_normal(L)
+    for j in np.where(np.abs(A).sum(axis=0) == 0)[0]:
+        A[rng.integers(0, m), j] = rng.standard_normal()
+    x0, y0, s0 = rng.uniform(0.5, 1.5, n), rng.standard_normal(m), rng.uniform(0.5, 1.5, n)
+    return synth.from_dense(A, A @ x0, A.T @ y0 + s0, name=f"hetero_{m}x{n}", seed=seed, x0=x0, y0=y0, s0=s0)
 
 
 def _dir_problem(lp, seed=0):
@@ -50,7 +74,7 @@ def _dir_problem(lp, seed=0):
 
 
 @pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
-                                  "transport_tall", "ldsz"])
+                                  "transport_tall", "ldsz", "rows32", "rows64", "slots12", "slots16"])
 @pytest.mark.parametrize("k", [1, 4, 13])
 def test_direction_solve_fixed_iterations(name, k):
     lp = _case(name)
@@ -71,7 +95,7 @@ def test_direction_solve_fixed_iterations(name, k):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
-                                  "transport_tall", "ldsz"])
+                                  "transport_tall", "ldsz", "rows32", "rows64", "slots12", "slots16"])
 def test_one_iteration_at_kernel_tolerance(name, precision):
     """At k = 1 the direction is one preconditioner application scaled by a scalar
     (dw = y_1 A_hat^T C v_1, y_1 from one product and two norms), so it checks the sweep
@@ -91,6 +115,30 @@ def test_one_iteration_at_kernel_tolerance(name, precision):
     AD = lp.to_dense() * d
     assert_close(AD.T @ np.asarray(dy), AD.T @ ody, tol)
     assert abs(info["res_est"] - oinfo["res_est"]) <= tol * oinfo["beta"]
+
+
+@pytest.mark.parametrize("name,want", [("rows32", "g32"), ("rows64", "g64"), ("slots12", "s12"), ("slots16", "s16")])
+def test_one_block_cases_reach_their_layouts(name, want):
+    """The cases above that target the one-block sweep reach it, with the lane counts and
+    slot counts they are named for: a colour's lanes per row are the power of two at or
+    above its mean row length (at most 64), its slots per lane ceil(longest / lanes),
+    rounded up to a compiled count (1-4, 6, 8, 12, 16)."""
+    lp = _case(name)
+    with lpk.from_lp(lp) as p:
+        _, kind = p.sweep_layout()
+    assert kind in (1, 2)
+    colour, perm, ncol = oracle.colour(lp)
+    lens = np.diff(lp.row_ptr)
+    lanes, classes = set(), set()
+    for c in range(ncol):
+        rows = np.where(colour == c)[0]
+        mean = lens[rows].mean()
+        g = 1 if mean <= 2 else min(64, 1 << int(np.ceil(np.log2(mean))))
+        sl = -(-int(lens[rows].max()) // g)
+        lanes.add(g)
+        classes.add(next(k for k in (1, 2, 3, 4, 6, 8, 12, 16, 1 << 30) if sl <= k))
+    print(f"case {name}: lanes {sorted(lanes)}, slot classes {sorted(classes)}", flush=True)
+    assert (int(want[1:]) in lanes) if want[0] == "g" else (int(want[1:]) in classes)
 
 
 @pytest.mark.parametrize("name", ["config0", "ragged", "transport", "transport_wide", "transport_sliced"])
