@@ -89,7 +89,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (serving mix: closed-loop runs of the whole mix) [1; other workloads 3]")
+                    help="timed steps (serving mix: closed-loop runs of the whole mix) [3]")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="serving_mix",
                     choices=["transport_300x300", "sparse_200x500", "basis_pursuit_1024x16384",
@@ -125,7 +125,7 @@ def main():
     args = ap.parse_args()
     serving = args.workload == "serving_mix"
     if args.steps is None:
-        args.steps = 1 if serving else 3
+        args.steps = 3
     if args.batch is None:
         args.batch = 256 if serving else 64
     if args.width is None:
