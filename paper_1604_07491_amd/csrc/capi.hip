@@ -377,6 +377,11 @@ static lp_status setup(lp_problem* p, const int64_t* rp, const int32_t* ci, cons
     const int kind64 = sweep_kind(m, n, nnz, p->colours, 8), kind32 = sweep_kind(m, n, nnz, p->colours, 4);
     const bool mixed = p->mixed = fp32_sweeps(p->opt, p->gsor, kind64, kind32);
     p->lds_kind = (sor && !p->gsor && !p->dense) ? (mixed ? kind32 : kind64) : 0;
+    // one-block sweeps: at most LDS_LANES_MAX lanes a row when the longest row then needs at
+    // most LDS_SLOTS slots a lane (fewer waves per colour, and a row's sum stays in DPP moves)
+    if (p->lds_kind != 0)
+        for (Colour& C : p->colours)
+            if (C.g > LDS_LANES_MAX && (C.maxlen + LDS_LANES_MAX - 1) / LDS_LANES_MAX <= LDS_SLOTS) C.g = LDS_LANES_MAX;
     // lane layout by cache-line count, for LPs swept colour by colour (z in HBM)
     if (p->lds_kind == 0)
         for (Colour& C : p->colours) choose_layout(C, prp.data(), pci.data(), mixed ? 4 : 8);

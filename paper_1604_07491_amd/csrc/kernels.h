@@ -212,8 +212,12 @@ inline int64_t lds_z_bytes(int64_t m, int64_t n, int tbytes) {
 // when the rows are read from memory (each round is one dependent load step)
 constexpr int LDS_SWEEP_THREADS = 1024;
 constexpr int LDS_ROUNDS_MAX = 4;
-// element slots per lane held in registers by the one-block sweep
+// element slots per lane held in registers by the one-block sweep, and the most lanes it
+// gives a row whose longest row fits in that many slots (colours of the one-block sweep take
+// min(lanes_for(mean length), LDS_LANES_MAX) lanes a row then; measured on the serving mix:
+// 16 lanes 160 us per 256-LP launch, 8 lanes 170 us, up to 64 lanes 185 us)
 constexpr int LDS_SLOTS = 16;
+constexpr int LDS_LANES_MAX = 16;
 inline int64_t lds_stage_bytes(int64_t m, int64_t n, int64_t nnz, int tbytes) {
     return 16 * m + nnz * (tbytes + 4) + (n + 1) * tbytes + 4 * (m + 1);
 }

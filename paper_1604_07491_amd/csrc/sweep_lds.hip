@@ -18,9 +18,10 @@ namespace lpk {
 // (Inst::ctab) is read from device memory by scalar loads.  v_k and p_k are written back at the end.  STAGED (Inst::lds == 2): the row values and
 // column indices are copied into LDS as well, in one coalesced pass, so the colour steps,
 // each a dependent chain of loads, run on LDS alone; otherwise (Inst::lds == 1) they are
-// read from memory (the instance's rows stay in the L2 cache over the passes).  Each row
-// is handled exactly as in k_nesor (same lanes per row, same element-to-lane assignment,
-// same sub-group sum).  keepz (Inst::keepz): z is copied out to V_Z64 at the end (z_k =
+// read from memory (the instance's rows stay in the L2 cache over the passes).  A row takes
+// its colour's lanes (at most LDS_LANES_MAX here when its longest row fits in LDS_SLOTS
+// slots a lane), element kk on lane (kk - s) mod g in slot (kk - s) / g, each lane's
+// elements summed in slot order, then the xor butterfly over the row's lanes.  keepz (Inst::keepz): z is copied out to V_Z64 at the end (z_k =
 // A_hat^T p_k).  ba (BA-GMRES): the input is V_U as it is, kept in V_R64, and the
 // multipliers go to V_U.  1024 threads per block measured as fast as 256 and twice as fast
 // as 64 on the 200 x 500 LPs.

@@ -38,14 +38,18 @@ def _case(name):
         return synth.transport_lp(1100, 32, seed=10)
     if name == "ldsz":             # z in LDS, rows too many to stage there
         return synth.sparse_lp(300, 2000, 6, 2, seed=61)
-    if name == "rows32":           # one-block sweep, rows of about 24 elements: 32 lanes a row
-        return synth.sparse_lp(298, 900, 8, 2, seed=72)
-    if name == "rows64":           # about 40 elements a row: 64 lanes, sums over the whole wave
-        return synth.sparse_lp(298, 1200, 10, 2, seed=71)
+    # one-block sweeps: a colour takes lanes_for(its mean row length) lanes a row, at most 16
+    # when its longest row fits in 16 slots a lane
+    if name == "lanes32":          # rows of 300 among rows of 12: colours at 32 and 64 lanes
+        return _hetero_rows(3, 200, 3000, 10, 300, 12)
+    if name == "lanes64":          # every row 300 long: 64 lanes, sums over the whole wave
+        return _hetero_rows(3, 60, 2000, 1, 300, 300)
     if name == "slots12":          # a few long rows among short ones: 6 and 12 slots a lane
         return _hetero_rows(5, 160, 640, 8, 96, 3)
-    if name == "slots16":          # 4, 8 and 16 slots a lane
+    if name == "slots16":          # 8 and 16 slots a lane
         return _hetero_rows(5, 200, 800, 6, 120, 3)
+    if name == "slotsloop":        # a colour's longest row past 16 slots: the element loop
+        return _hetero_rows(6, 200, 800, 8, 200, 3)
     raise ValueError(name)
 
 
@@ -74,7 +78,8 @@ def _dir_problem(lp, seed=0):
 
 
 @pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
-                                  "transport_tall", "ldsz", "rows32", "rows64", "slots12", "slots16"])
+                                  "transport_tall", "ldsz", "lanes32", "lanes64", "slots12", "slots16",
+                                  "slotsloop"])
 @pytest.mark.parametrize("k", [1, 4, 13])
 def test_direction_solve_fixed_iterations(name, k):
     lp = _case(name)
@@ -95,7 +100,8 @@ def test_direction_solve_fixed_iterations(name, k):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["config0", "ragged", "longrows", "transport", "transport_wide", "transport_sliced",
-                                  "transport_tall", "ldsz", "rows32", "rows64", "slots12", "slots16"])
+                                  "transport_tall", "ldsz", "lanes32", "lanes64", "slots12", "slots16",
+                                  "slotsloop"])
 def test_one_iteration_at_kernel_tolerance(name, precision):
     """At k = 1 the direction is one preconditioner application scaled by a scalar
     (dw = y_1 A_hat^T C v_1, y_1 from one product and two norms), so it checks the sweep
@@ -117,12 +123,14 @@ def test_one_iteration_at_kernel_tolerance(name, precision):
     assert abs(info["res_est"] - oinfo["res_est"]) <= tol * oinfo["beta"]
 
 
-@pytest.mark.parametrize("name,want", [("rows32", "g32"), ("rows64", "g64"), ("slots12", "s12"), ("slots16", "s16")])
+@pytest.mark.parametrize("name,want", [("lanes32", "g32"), ("lanes64", "g64"), ("slots12", "s12"), ("slots16", "s16"),
+                                       ("slotsloop", "s99")])
 def test_one_block_cases_reach_their_layouts(name, want):
     """The cases above that target the one-block sweep reach it, with the lane counts and
     slot counts they are named for: a colour's lanes per row are the power of two at or
-    above its mean row length (at most 64), its slots per lane ceil(longest / lanes),
-    rounded up to a compiled count (1-4, 6, 8, 12, 16)."""
+    above its mean row length (at most 64), lowered to 16 when its longest row then fits
+    in 16 slots a lane; its slots per lane ceil(longest / lanes), rounded up to a compiled
+    count (1-4, 6, 8, 12, 16; past 16 the element loop, s99 here)."""
     lp = _case(name)
     with lpk.from_lp(lp) as p:
         _, kind = p.sweep_layout()
@@ -133,10 +141,13 @@ def test_one_block_cases_reach_their_layouts(name, want):
     for c in range(ncol):
         rows = np.where(colour == c)[0]
         mean = lens[rows].mean()
+        longest = int(lens[rows].max())
         g = 1 if mean <= 2 else min(64, 1 << int(np.ceil(np.log2(mean))))
-        sl = -(-int(lens[rows].max()) // g)
+        if g > 16 and -(-longest // 16) <= 16:
+            g = 16
+        sl = -(-longest // g)
         lanes.add(g)
-        classes.add(next(k for k in (1, 2, 3, 4, 6, 8, 12, 16, 1 << 30) if sl <= k))
+        classes.add(next((k for k in (1, 2, 3, 4, 6, 8, 12, 16) if sl <= k), 99))
     print(f"case {name}: lanes {sorted(lanes)}, slot classes {sorted(classes)}", flush=True)
     assert (int(want[1:]) in lanes) if want[0] == "g" else (int(want[1:]) in classes)
 
