@@ -88,35 +88,36 @@ __device__ __forceinline__ T sg_sum_lds(T v, int g) {
 // compile-time count, so the loads are straight-line code with no branch between them):
 // the row's values and indices are loaded together, then its z values; those are kept
 // for the update: no other row of the colour touches these columns, so they are still
-// current.  A slot past the row's end loads the row's last element (rows are never
-// empty), counts as 0, and stores to z[n]; the zero terms leave acc unchanged (it starts
-// at +0 and never becomes -0), so the result does not depend on S beyond the row's need.
-// Returns the row's delta.
+// current.  A slot past the row's end counts value 0 at the sink column n, whose z entry
+// is 0 from the start and stays 0 (its updates add delta x 0): its term is +0, which
+// leaves acc unchanged (it starts at +0 and never becomes -0), so the result does not
+// depend on S beyond the row's need.  Its loads stay in bounds: in device memory at the
+// row's last element; in LDS as they fall (an LDS read cannot fault, and its value is
+// not used).  Returns the row's delta.
 template <typename T, bool STAGED, int S>
 __device__ __forceinline__ T row_step(const T* sv, const int32_t* si, const LPK_GLOBAL T* __restrict__ gval,
                                       const LPK_GLOBAL int32_t* __restrict__ gci, T* z, int n, int s, int e,
                                       int lane, int g, T om, double vrow, bool write_z) {
     T a[S], zv[S];
     int jj[S];
-    bool ok[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) {
         const int kk = s + lane + t * g;
-        ok[t] = kk < e;
-        const int kc = ok[t] ? kk : e - 1;
         if constexpr (STAGED) {
-            a[t] = sv[kc];
-            jj[t] = si[kc];
+            a[t] = sv[kk];
+            jj[t] = si[kk];
         } else {
+            const int kc = kk < e ? kk : e - 1;
             a[t] = gval[kc];
             jj[t] = gci[kc];
         }
     }
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        a[t] = ok[t] ? a[t] : (T)0;
-        const T zt = z[jj[t]];
-        zv[t] = ok[t] ? zt : (T)0;
+        const bool ok = s + lane + t * g < e;
+        a[t] = ok ? a[t] : (T)0;
+        jj[t] = ok ? jj[t] : n;
+        zv[t] = z[jj[t]];
     }
     T acc = 0;
 #pragma unroll
@@ -125,7 +126,7 @@ __device__ __forceinline__ T row_step(const T* sv, const int32_t* si, const LPK_
     const T delta = om * ((T)vrow - acc);
     if (write_z) {
 #pragma unroll
-        for (int t = 0; t < S; ++t) z[ok[t] ? jj[t] : n] = zv[t] + delta * a[t];
+        for (int t = 0; t < S; ++t) z[jj[t]] = zv[t] + delta * a[t];
     }
     return delta;
 }
