@@ -1025,15 +1025,47 @@ void b_init_ctl(const BLaunch& L, int pmask, int64_t kcap) {
 
 // R y = gamma(1:iters), R the upper triangle of the rotated Hessenberg matrix, by
 // columns from the last: y_i = g_i / R_ii, then g_t -= R_ti y_i for t < i.  Up to BS_REG
-// iterations, the block stages panels of BS_PANEL doubles of H (the columns [c0, c1), rows
-// up to c1) into LDS with all its threads, loads in flight together; then wave 0 applies
-// the panel's columns, lane l holding g_t for t = l + 64 r in registers and y_i reaching
-// every lane by a shuffle from its owner, so a step waits only on LDS.  Longer solves
-// take the same steps with g in memory.  Every entry sees the same operations in the
-// same order either way.
+// iterations, the block stages panels of up to BS_PANEL doubles of H (the columns [c0, c1),
+// rows up to c1) into LDS with all its threads, loads in flight together; then wave 0
+// applies the panel's columns, lane l holding g_t for t = l + 64 r in registers.  The
+// columns of one block of 64 (i >> 6 = RI) run in a loop compiled for RI: y_i's owner is
+// register RI, read by every lane with readlane, and only registers r <= RI (rows t < 64
+// (RI + 1)) are updated; the others hold rows past i, which the step leaves alone.  Longer
+// solves take the same steps with g in memory.  Every entry sees the same operations in
+// the same order either way.
 constexpr int BS_NR = 16;
 constexpr int BS_REG = 64 * BS_NR;
-constexpr int BS_PANEL = 8192;
+constexpr int BS_PANEL = 18432;   // 144 KiB of LDS (gfx950 gives a workgroup 160 KiB)
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// columns i = ihi down to ilo (all in the block RI) of the panel starting at column c0 with
+// column stride c1
+template <int RI>
+__device__ __forceinline__ void bs_columns(double (&g)[BS_NR], const double* panel, int c0, int c1, int ihi, int ilo,
+                                           int lane) {
+    for (int i = ihi; i >= ilo; --i) {
+        const double* col = panel + (i - c0) * c1;
+        const double yi = readlane_f64(g[RI], i & 63) / col[i];
+        // every lane of a register loads (rows t >= i read the diagonal, unused) and selects
+        double cv[RI + 1];
+#pragma unroll
+        for (int r = 0; r <= RI; ++r) {
+            const int t = lane + 64 * r;
+            cv[r] = col[t < i ? t : i];
+        }
+#pragma unroll
+        for (int r = 0; r <= RI; ++r) {
+            const int t = lane + 64 * r;
+            const double upd = g[r] - cv[r] * yi;
+            g[r] = t == i ? yi : (t < i ? upd : g[r]);
+        }
+    }
+}
 
 __global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I, int pmask) {
     __shared__ double panel[BS_PANEL];
@@ -1085,29 +1117,19 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(const Inst* __restrict__ I,
         }
         __syncthreads();
         if (solver) {
-            for (int i = c1 - 1; i >= c0; --i) {
-                const double* col = panel + (i - c0) * c1;
-                const int ri = i >> 6;
-                double gi = 0.0;
-#pragma unroll
-                for (int r = 0; r < BS_NR; ++r)
-                    if (r == ri) gi = g[r];
-                gi = __shfl(gi, i & 63, 64);
-                const double yi = gi / col[i];
-                // branch-free: every lane loads (rows t >= i read the diagonal, unused) and
-                // selects, so the step is one batch of LDS loads and no divergent code
-                double cv[BS_NR];
-#pragma unroll
-                for (int r = 0; r < BS_NR; ++r) {
-                    const int t = lane + 64 * r;
-                    cv[r] = col[t < i ? t : i];
+            // the panel's columns by blocks of 64 (at most two blocks: cb <= 64)
+            for (int ihi = c1 - 1; ihi >= c0;) {
+                const int ri = ihi >> 6;
+                const int ilo = std::max(c0, ri * 64);
+                switch (ri) {
+#define LPK_BS(R_) \
+    case R_: bs_columns<R_>(g, panel, c0, c1, ihi, ilo, lane); break;
+                    LPK_BS(0) LPK_BS(1) LPK_BS(2) LPK_BS(3) LPK_BS(4) LPK_BS(5) LPK_BS(6) LPK_BS(7)
+                    LPK_BS(8) LPK_BS(9) LPK_BS(10) LPK_BS(11) LPK_BS(12) LPK_BS(13) LPK_BS(14) LPK_BS(15)
+#undef LPK_BS
+                    default: break;
                 }
-#pragma unroll
-                for (int r = 0; r < BS_NR; ++r) {
-                    const int t = lane + 64 * r;
-                    const double upd = g[r] - cv[r] * yi;
-                    g[r] = t == i ? yi : (t < i ? upd : g[r]);
-                }
+                ihi = ilo - 1;
             }
         }
         c1 = c0;
