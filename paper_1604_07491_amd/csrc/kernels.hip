@@ -512,7 +512,7 @@ constexpr int GF_CH = 1024;
 
 struct GivensLds {
     double hb[GF_CH], cb[GF_CH], sb[GF_CH], ob[GF_CH];
-    double sA[BLOCK], sB[BLOCK];
+    double sA[BLOCK / 64], sB[BLOCK / 64];   // the waves' composed maps
     double carry;
 };
 
@@ -542,28 +542,37 @@ __device__ bool givens_column(const Inst& in, double* hk, int kc, double hn, Giv
             B = a * B + b;
             A = a * A;
         }
-        // inclusive scan over the threads: after it, (A, B) composes the maps of threads 0..t
-        g.sA[t] = A;
-        g.sB[t] = B;
-        __syncthreads();
-        for (int d = 1; d < BLOCK; d <<= 1) {
-            double pa = 1.0, pb = 0.0;
-            if (t >= d) {
-                pa = g.sA[t - d];
-                pb = g.sB[t - d];
-            }
-            __syncthreads();
-            if (t >= d) {
+        // inclusive scan over the threads: inside each wave by shuffles, then across the
+        // waves through LDS; after it, (A, B) composes the maps of threads 0..t
+        const int lane = t & 63, w = t >> 6;
+        for (int d = 1; d < 64; d <<= 1) {
+            const double pa = __shfl_up(A, d, 64), pb = __shfl_up(B, d, 64);
+            if (lane >= d) {
                 B = A * pb + B;
                 A = A * pa;
-                g.sA[t] = A;
-                g.sB[t] = B;
             }
-            __syncthreads();
         }
+        if (lane == 63) {
+            g.sA[w] = A;
+            g.sB[w] = B;
+        }
+        __syncthreads();
+        double PA = 1.0, PB = 0.0;   // the maps of the earlier waves
+        for (int q = 0; q < w; ++q) {
+            const double a = g.sA[q], b = g.sB[q];
+            PB = a * PB + b;
+            PA = a * PA;
+        }
+        B = A * PB + B;
+        A = A * PA;
         // starting carry of this thread's entries: the maps of threads 0..t-1 on the carry
+        double EA = __shfl_up(A, 1, 64), EB = __shfl_up(B, 1, 64);
+        if (lane == 0) {
+            EA = PA;
+            EB = PB;
+        }
         double carry = g.carry;
-        if (t > 0) carry = g.sA[t - 1] * carry + g.sB[t - 1];
+        if (t > 0) carry = EA * carry + EB;
         for (int i = i0; i < i1; ++i) {
             const double bv = g.hb[i], c = g.cb[i], sv = g.sb[i];
             g.ob[i] = c * carry + sv * bv;
@@ -751,7 +760,7 @@ void b_dgs_dots(const BLaunch& L) {
 }
 
 __global__ __launch_bounds__(BLOCK) void k_dgs_finish(const Inst* __restrict__ I) {
-    __shared__ double sh[BLOCK / 64];
+    __shared__ double sh3[BLOCK / 64][3];
     __shared__ GivensLds g;
     __shared__ double sc[4];
     INST;
@@ -781,10 +790,27 @@ __global__ __launch_bounds__(BLOCK) void k_dgs_finish(const Inst* __restrict__ I
         q2 += a * b;
         q3 += b * b;
     }
-    q1 = block_sum(q1, sh);
-    q2 = block_sum(q2, sh);
-    q3 = block_sum(q3, sh);
+    // the three block sums together (each the same butterfly and wave order as block_sum)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double x1 = __shfl_xor(q1, o, 64), x2 = __shfl_xor(q2, o, 64), x3 = __shfl_xor(q3, o, 64);
+        q1 += x1;
+        q2 += x2;
+        q3 += x3;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh3[threadIdx.x >> 6][0] = q1;
+        sh3[threadIdx.x >> 6][1] = q2;
+        sh3[threadIdx.x >> 6][2] = q3;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        q1 = q2 = q3 = 0.0;
+        for (int i = 0; i < BLOCK / 64; ++i) {
+            q1 += sh3[i][0];
+            q2 += sh3[i][1];
+            q3 += sh3[i][2];
+        }
         const double c = ta[k], d = tb[k];
         double nu = 1.0, sk = d;
         if (k > 0) {
