@@ -685,6 +685,33 @@ __device__ __forceinline__ double wave_sum_rows(double v) {
     return v;
 }
 
+// The sums over the 64 lanes of eight values at once, each lane keeping half of its values
+// at each of the first three levels: lanes 32 apart by permlane32_swap, 16 apart by
+// permlane16_swap (gfx950), 8 apart by a row rotation; then xor 1 and xor 2 inside quads and
+// the half-row mirror (whose partner then holds the xor-4 partner's sum).  Afterwards the
+// eight lanes 8q..8q+7 all hold the sum of v[q].
+__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+    double w[4], x[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v[i]), __double2loint(v[i + 4]), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v[i]), __double2hiint(v[i + 4]), false, false);
+        w[i] = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(w[i]), __double2loint(w[i + 2]), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(w[i]), __double2hiint(w[i + 2]), false, false);
+        x[i] = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    }
+    const bool b3 = (threadIdx.x & 8) != 0;
+    double y = (b3 ? x[1] : x[0]) + dpp_row_move<0x128>(b3 ? x[0] : x[1]);   // row_ror:8
+    y += dpp_row_move<0xB1>(y);
+    y += dpp_row_move<0x4E>(y);
+    y += dpp_row_move<0x141>(y);
+    return y;
+}
+
 // A task is C consecutive columns of one segment: u and v~_k are loaded once per row for
 // all of them.  Column k + 1 stands for u itself (its dot with u is u . u).  C = 4 when the
 // launch has at least 16384 columns over its instances (the serving mix's long bases), 2 from
@@ -726,6 +753,22 @@ __device__ __forceinline__ void dgs_dots_tasks(const Inst& in, int k, int blk) {
                     a[c] += xi * wi;
                     b[c] += xi * ui;
                 }
+        }
+        if constexpr (C == 4) {
+            // the task's eight sums in one pass: lane 8q holds a[q] (q < 4) or b[q - 4]
+            const double vv[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+            const double y = wave_sum8(vv);
+            const int q = lane >> 3, c = q & 3, j = c0 + c;
+            if ((lane & 7) == 0 && c < nc) {
+                if (q < 4) {
+                    if (j <= k) in.gpart[(int64_t)sg * in.ldp + j] = y;
+                } else if (j <= k) {
+                    in.gpart2[(int64_t)sg * in.ldp + j] = y;
+                } else {
+                    in.gpart[(int64_t)sg * in.ldp + j] = y;   // u . u
+                }
+            }
+            continue;
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
