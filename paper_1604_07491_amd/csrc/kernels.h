@@ -197,14 +197,14 @@ struct BLaunch {
 };
 
 // An NE-SOR / NE-SSOR instance sweeps in one block with all of its row values and column
-// indices, z, v_k, p_k, the row pointers and a colour table in LDS when they fit in
+// indices, z, v_k, p_k and the row pointers in LDS when they fit in
 // LDS_STAGE_MAX (lds_stage_bytes); with all but the row values and indices in LDS when
 // those fit in LDS_Z_MAX (lds_z_bytes), the rows then read from memory.  gfx950 gives a
 // workgroup 160 KiB of LDS.
 constexpr int LDS_BLOCK_MAX = 160 * 1024;
 constexpr int LDS_Z_MAX = LDS_BLOCK_MAX;
 constexpr int LDS_STAGE_MAX = LDS_BLOCK_MAX;
-// LDS of the one-block sweep: z with the colour table, and (staged) everything
+// LDS of the one-block sweep: z, v_k, p_k and the row pointers, and (staged) the rows too
 inline int64_t lds_z_bytes(int64_t m, int64_t n, int tbytes) {
     return 16 * m + (n + 1) * tbytes + 4 * (m + 1);
 }
