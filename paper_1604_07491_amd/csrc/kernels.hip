@@ -672,19 +672,6 @@ __device__ __forceinline__ double dpp_row_move(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// sum over the 64 lanes, in every lane: inside each row of 16 lanes by DPP moves
-// (quad_perm [1,0,3,2], [2,3,0,1], then the half-row and row mirrors, whose partners hold
-// the same partial sums as the xor-4 and xor-8 partners), then across rows by two shuffles
-__device__ __forceinline__ double wave_sum_rows(double v) {
-    v += dpp_row_move<0xB1>(v);
-    v += dpp_row_move<0x4E>(v);
-    v += dpp_row_move<0x141>(v);
-    v += dpp_row_move<0x140>(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
-
 // The sums over the 64 lanes of eight values at once, each lane keeping half of its values
 // at each of the first three levels: lanes 32 apart by permlane32_swap, 16 apart by
 // permlane16_swap (gfx950), 8 apart by a row rotation; then xor 1 and xor 2 inside quads and
@@ -710,6 +697,28 @@ __device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
     y += dpp_row_move<0x4E>(y);
     y += dpp_row_move<0x141>(y);
     return y;
+}
+
+// The sum over the 64 lanes of one value by the same tree as each of wave_sum8's eight:
+// lanes 32 apart, then 16, then 8 (a row rotation), then xor 1, xor 2 and the half-row
+// mirror.  Every lane gets the sum; a column's dot is then the same bits whether its task
+// reduced one, two or four columns (the column count per task follows the launch width).
+__device__ __forceinline__ double wave_sum_tree(double v) {
+    {
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+        v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    }
+    {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+        v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+    }
+    v = v + dpp_row_move<0x128>(v);   // row_ror:8
+    v += dpp_row_move<0xB1>(v);
+    v += dpp_row_move<0x4E>(v);
+    v += dpp_row_move<0x141>(v);
+    return v;
 }
 
 // A task is C consecutive columns of one segment: u and v~_k are loaded once per row for
@@ -774,9 +783,9 @@ __device__ __forceinline__ void dgs_dots_tasks(const Inst& in, int k, int blk) {
         for (int c = 0; c < C; ++c) {
             if (c >= nc) break;
             const int j = c0 + c;
-            const double sb = wave_sum_rows(b[c]);
+            const double sb = wave_sum_tree(b[c]);
             if (j <= k) {
-                const double sa = wave_sum_rows(a[c]);
+                const double sa = wave_sum_tree(a[c]);
                 if (lane == 0) {
                     in.gpart[(int64_t)sg * in.ldp + j] = sa;
                     in.gpart2[(int64_t)sg * in.ldp + j] = sb;

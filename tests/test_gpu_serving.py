@@ -233,3 +233,31 @@ def test_narrow_graphs_keep_results_bitwise(precision):
         assert res[i]["krylov_iters"] == alone[i][0]["krylov_iters"]
         assert np.array_equal(lpk.lp_get_state(p)[0], alone[i][1])
         p.close()
+
+
+def test_dots_task_width_keeps_results_bitwise():
+    """The Gram-Schmidt dots reduce one, two or four basis columns per task, chosen by the
+    launch width times the basis size; every column's dot takes the same reduction tree
+    either way.  An LP whose late solves pass 254 iterations is solved alone (one column a
+    task) and as 64 copies in one batch (four columns a task once k >= 254, two from 126):
+    every copy's iterate is bitwise the alone one, with the same Krylov count."""
+    lp = synth.sparse_lp(598, 1800, 6, 2, seed=7)
+    with lpk.from_lp(lp) as p:
+        ks = []
+        for _ in range(99):
+            info = lpk.ipm_step(p)
+            ks += [info["k_af"], info["k_cc"]]
+            if info["converged"]:
+                break
+    print(f"largest solve {max(ks)} iterations", flush=True)
+    assert max(ks) >= 254
+    with lpk.from_lp(lp) as p:
+        r0 = lpk.lp_solve(p)
+        x0 = lpk.lp_get_state(p)[0]
+    probs = [lpk.from_lp(lp) for _ in range(64)]
+    res = lpk.lp_solve_batch(probs, width=64)
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == lpk.LP_OK
+        assert res[i]["krylov_iters"] == r0["krylov_iters"]
+        assert np.array_equal(lpk.lp_get_state(p)[0], x0)
+        p.close()
